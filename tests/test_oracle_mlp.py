@@ -1,0 +1,112 @@
+"""Pins of the proposal-network oracle (FP64): gradients against central
+finite differences, the first AdamW step against its closed form, textbook
+values of the normal CDF, and the degenerate settings of the proposal rule
+that must reduce to the plain full-K selection."""
+import math
+
+import numpy as np
+import pytest
+
+import fepll_synth as fs
+from oracle import mlp64 as M
+
+
+def small_params(seed=1, d=7, h=6, K=5):
+    g = fs.rng(seed)
+    return {"W1": g.normal(0, 0.5, (h, d)), "b1": g.normal(0, 0.1, h),
+            "W2": g.normal(0, 0.5, (h, h)), "b2": g.normal(0, 0.1, h),
+            "W3": g.normal(0, 0.5, (K, h)), "b3": g.normal(0, 0.1, K)}
+
+
+def test_gradients_match_central_differences():
+    p = small_params()
+    g = fs.rng(2)
+    X = g.normal(0, 1, (9, 7))
+    t = g.integers(0, 5, 9)
+    _, grad = M.loss_and_grad(p, X, t)
+    h = 1e-6
+    for name in M.NAMES:
+        fd = np.zeros_like(p[name])
+        for idx in np.ndindex(p[name].shape):
+            keep = p[name][idx]
+            p[name][idx] = keep + h
+            lp = M.softmax_xent(M.forward(p, X)[0], t)[0]
+            p[name][idx] = keep - h
+            lm = M.softmax_xent(M.forward(p, X)[0], t)[0]
+            p[name][idx] = keep
+            fd[idx] = (lp - lm) / (2 * h)
+        err = np.abs(fd - grad[name]).max() / max(1e-12, np.abs(fd).max())
+        assert err < 1e-6, (name, err)
+
+
+def test_full_size_gradient_spot_check():
+    p = fs.mlp_init(200, 3)
+    g = fs.rng(4)
+    X = g.normal(0, 1, (16, 65))
+    t = g.integers(0, 200, 16)
+    _, grad = M.loss_and_grad(p, X, t)
+    h = 1e-6
+    for name, idx in [("W1", (3, 64)), ("b1", (17,)), ("W2", (100, 7)),
+                      ("b2", (255,)), ("W3", (t[0], 5)), ("b3", (t[1],))]:
+        keep = p[name][idx]
+        p[name][idx] = keep + h
+        lp = M.softmax_xent(M.forward(p, X)[0], t)[0]
+        p[name][idx] = keep - h
+        lm = M.softmax_xent(M.forward(p, X)[0], t)[0]
+        p[name][idx] = keep
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grad[name][idx]) <= 1e-6 * max(1e-3, abs(fd)), (name, fd, grad[name][idx])
+
+
+def test_adamw_first_step_closed_form():
+    """After one step from zero moments, m_hat = g and v_hat = g^2, so each
+    parameter moves by lr * (g / (|g| + eps) + wd * p)."""
+    p = small_params(5)
+    p0 = {k: v.copy() for k, v in p.items()}
+    g = {k: fs.rng(6 + i).normal(0, 1, v.shape) for i, (k, v) in enumerate(p.items())}
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(x) for k, x in p.items()}
+    lr, eps, wd = 0.01, 1e-8, 0.05
+    M.adamw_step(p, g, m, v, 1, lr=lr, eps=eps, wd=wd)
+    for k in M.NAMES:
+        want = p0[k] - lr * (g[k] / (np.abs(g[k]) + eps) + wd * p0[k])
+        np.testing.assert_allclose(p[k], want, rtol=1e-12, atol=1e-15)
+
+
+def test_gelu_textbook_values():
+    # GELU(x) = x Phi(x); Phi(1) = 0.8413447460685429, Phi(-1) = 0.15865525393145707
+    np.testing.assert_allclose(M.gelu(np.array([1.0, -1.0, 0.0])),
+                               [0.8413447460685429, -0.15865525393145707, 0.0], rtol=1e-15)
+    np.testing.assert_allclose(M.gelu(np.array([12.0, -12.0])), [12.0, 0.0], atol=1e-30)
+    x = np.linspace(-4, 4, 17)
+    fd = (M.gelu(x + 1e-6) - M.gelu(x - 1e-6)) / 2e-6
+    np.testing.assert_allclose(M.gelu_grad(x), fd, atol=1e-8)
+
+
+def test_xent_uniform_logits_is_log_K():
+    for K in (2, 7, 200):
+        loss, g = M.softmax_xent(np.zeros((3, K)), np.array([0, 1, K - 1]))
+        assert abs(loss - math.log(K)) < 1e-14
+        np.testing.assert_allclose(g.sum(axis=1), 0, atol=1e-15)
+
+
+def test_topm_ties_to_lower_index():
+    lg = np.array([[1.0, 3.0, 3.0, 0.5, 3.0]])
+    np.testing.assert_array_equal(M.topm(lg, 3), [[1, 2, 4]])
+
+
+def test_proposal_degenerate_settings_give_full_argmin():
+    g = fs.rng(9)
+    costs = g.normal(0, 5, (50, 12))
+    logits = g.normal(0, 1, (50, 12))
+    full = np.argmin(costs, axis=1)
+    lab, fb = M.propose_select(costs, M.topm(logits, 8), math.inf)
+    np.testing.assert_array_equal(lab, full)
+    assert fb.all()
+    lab, _ = M.propose_select(costs, M.topm(logits, 12), 0.5)
+    np.testing.assert_array_equal(lab, full)
+    lab, fb = M.propose_select(costs, M.topm(logits, 3), -math.inf)
+    assert not fb.any()
+    cand = M.topm(logits, 3)
+    want = cand[np.arange(50), np.argmin(np.take_along_axis(costs, cand, 1), 1)]
+    np.testing.assert_array_equal(lab, want)
