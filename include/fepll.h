@@ -1,0 +1,170 @@
+/*
+ * fepll.h -- C ABI of the MI355X (gfx950) EPLL denoising library.
+ *
+ * The library restores an image y = x + w (white Gaussian noise of standard
+ * deviation sigma, A = identity) under a zero-mean Gaussian-mixture prior on
+ * DC-removed 8x8 patches, by half-quadratic splitting: every iteration runs
+ * the five steps of Algorithm 1 of Parameswaran, Deledalle, Denis & Nguyen,
+ * "Accelerating GMM-based patch priors for image restoration: three
+ * ingredients for a 100x speed-up" (arXiv 1710.08124) -- patch extraction,
+ * Gaussian selection, patch estimation, patch reprojection, image
+ * estimation -- with selection and estimation in each component's
+ * eigenbasis (Sec. 2.1, eq:projection_eigenspace / eq:selection_eigenspace).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - A patch is the 8x8 block whose top-left pixel is (r, c); its vector index
+ *   is 8*dy + dx.  The patch set is every block fully inside the image,
+ *   Np = (H-7)*(W-7) patches, numbered r*(W-7) + c.
+ * - Images are float32, row-major, `row_stride` elements between rows.
+ * - GMM parameters come in float64 (they are set up once); the hot path runs
+ *   in float32 (or bf16 / fp8 for the projections, see fepll_options).
+ * - The "cost" of component k for a patch is the selection objective of
+ *   Alg. 1, iota_k + sum_j (log nu_kj + c_j^2 / nu_kj), c = U_k^t z~,
+ *   iota_k = -2 log w_k, nu_kj = lambda_kj + 1/beta.  The chosen component is
+ *   the smallest cost, ties going to the lowest index.
+ * - Every call returns a fepll_status; on failure nothing the caller owns has
+ *   been written unless stated, and fepll_last_error() gives a message
+ *   (thread-local, valid until the next call on the same thread).
+ * - Calls on the same fepll_gmm handle must not run concurrently (the handle
+ *   owns the scratch memory the restoration uses).
+ * - Device work is enqueued on fepll_options.stream (a hipStream_t; NULL =
+ *   the default stream).  Entry points that take host buffers synchronise the
+ *   stream before returning; entry points that take only device buffers do
+ *   not, unless stated.
+ */
+#ifndef FEPLL_H
+#define FEPLL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fepll_gmm fepll_gmm; /* opaque; owns its device copies */
+
+typedef enum {
+  FEPLL_OK = 0,
+  FEPLL_EINVAL = -1,       /* an argument is out of its documented range   */
+  FEPLL_ENOMEM = -2,       /* a device or host allocation failed            */
+  FEPLL_EDEVICE = -3,      /* a HIP runtime call failed                     */
+  FEPLL_EUNSUPPORTED = -4, /* a valid request this build does not implement */
+  FEPLL_ECHECKSUM = -5     /* a serialized blob failed its integrity check  */
+} fepll_status;
+
+enum { FEPLL_FP32 = 0, FEPLL_BF16 = 1, FEPLL_FP8 = 2 };
+
+typedef struct {
+  float* data;         /* first pixel                                   */
+  int32_t height;      /* H >= 8                                        */
+  int32_t width;       /* W >= 8                                        */
+  int64_t row_stride;  /* elements between rows, >= width               */
+  int32_t on_device;   /* 1: data is device memory, 0: host memory      */
+} fepll_image;
+
+typedef struct {
+  /* Arithmetic of the projection c = U_k^t z~ in the selection step:
+   * FEPLL_FP32 (default), FEPLL_BF16 or FEPLL_FP8 (e4m3), always with float32
+   * accumulation; log-determinant terms, patch estimation, reprojection and
+   * image estimation stay float32.                                         */
+  int32_t precision;
+  /* FEPLL_FP32 only: every patch whose float32 selection is not certified
+   * by the rounding-error bound of its costs is re-selected in float64, so
+   * the labels equal those of an exact evaluation (default 1).             */
+  int32_t recheck;
+  /* Learned proposal (needs fepll_gmm_load_proposal): score only the top_m
+   * components proposed by the network, fall back to all K when half the
+   * exact gap between the two best proposed costs is below margin_nats.    */
+  int32_t use_proposal;
+  int32_t top_m;          /* 1..K, default 8                                */
+  double margin_nats;     /* default 0.5; +inf = always fall back           */
+  /* Start of the iterations; NULL = y (Alg. 1 starts from x = y).          */
+  const fepll_image* init;
+  void* stream;           /* hipStream_t; NULL = default stream             */
+  /* Nonzero: bracket every kernel stage with HIP events on `stream` and
+   * accumulate the stage times in the handle (read with fepll_profile).    */
+  int32_t profile;
+} fepll_options;
+
+/* Fill *opt with the defaults above. */
+void fepll_options_default(fepll_options* opt);
+
+/*
+ * Create a GMM handle from the eigendecomposition Sigma_k = U_k S_k U_k^t
+ * (Sec. 2.1, computed offline in the paper).
+ *   U:      K x d x d float64, host, row-major: U[(k*d + p)*d + j] is entry p
+ *           of the j-th eigenvector of Sigma_k (columns are eigenvectors);
+ *           each U_k must be orthonormal (max |U^t U - I| <= 1e-8).
+ *   lambda: K x d float64, host, the diagonal of S_k, finite and >= 0.
+ *   w:      K float64, host, the mixture weights (eq:prior): w_k > 0 and
+ *           |sum w - 1| <= 1e-6 (never renormalised).
+ *   K:      1..1024.   d: must be 64 (8x8 patches).
+ * The library copies what it keeps.  EINVAL on any violated condition,
+ * ENOMEM / EDEVICE on allocation or copy failure; *out is set only on OK.
+ */
+fepll_status fepll_gmm_create(const double* U, const double* lambda, const double* w,
+                              int32_t K, int32_t d, fepll_gmm** out);
+
+/* Release a handle (NULL is a no-op).  Synchronises the device first. */
+void fepll_gmm_destroy(fepll_gmm* g);
+
+/*
+ * Restore y by T iterations of Alg. 1 (denoising: A = identity).
+ *   y:      noisy image (host or device).  Finite values only (EINVAL).
+ *   H:      the degradation operator A; only NULL (identity) is supported,
+ *           anything else returns EUNSUPPORTED.
+ *   sigma:  noise standard deviation on the image's scale, > 0.
+ *   beta_schedule: T absolute values of beta (the HQS coupling weight of
+ *           eq:qhs), each > 0; NULL = {1, 4, 8, 16, 32} / sigma^2 with T = 5
+ *           (T must then be 5 or 0, where 0 means 5).
+ *   T:      1..16 iterations.
+ *   out:    H x W output (host or device); may alias y.
+ *   opt:    NULL = defaults.
+ *   labels_out: optional int32 buffer of T * Np entries, iteration-major; in
+ *           the same memory space as y; receives the chosen component of
+ *           every patch at every iteration.
+ * Host images are copied in and out and the call returns after the result
+ * is in `out`.  Device images: the work is enqueued and the call returns.
+ */
+fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* H, double sigma,
+                           const double* beta_schedule, int32_t T, fepll_image* out,
+                           const fepll_options* opt, int32_t* labels_out);
+
+/*
+ * One Gaussian-selection step (Alg. 1, "Gaussian selection", eigenspace
+ * form) on every patch of the device image x for one beta, without
+ * estimation or reprojection.  Device buffers of Np entries each:
+ *   labels (int32, required), best and second (float32, optional: the two
+ *   smallest float32 costs), flags (int32, optional: 1 where the float32
+ *   selection was not certified and, with recheck on, was redone in float64).
+ * Used to check the selection against an exact evaluation and to record
+ * the labels the proposal network is trained on.
+ */
+fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta,
+                          int32_t* labels, float* best, float* second, int32_t* flags,
+                          const fepll_options* opt);
+
+/*
+ * Stage timing of the calls made with options.profile set since the last
+ * read.  Stages: 0 selection (float32 E-step), 1 float64 re-selection,
+ * 2 bucketing, 3 patch estimation, 4 reprojection + image estimation,
+ * 5 per-beta constants.  ms[s] receives the summed event time of stage s in
+ * milliseconds and launches[s] the number of timed launches (either pointer
+ * may be NULL); n is the number of entries provided (at most 6 are written).
+ * Synchronises with the recorded events, then clears the accumulators.
+ */
+fepll_status fepll_profile(fepll_gmm* g, double* ms, int32_t* launches, int32_t n);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* fepll_last_error(void);
+
+/* Library version string. */
+const char* fepll_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEPLL_H */

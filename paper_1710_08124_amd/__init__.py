@@ -1,0 +1,221 @@
+"""Python binding of libfepll.so, the gfx950 EPLL denoising library.
+
+Argument marshalling only: every step of the restoration runs in the HIP
+kernels behind the C ABI declared in include/fepll.h.  PyTorch supplies
+device memory and the current stream.  There is no fallback: if the shared
+library is missing, importing the binding's functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+__all__ = ["FepllError", "GMM", "restore", "select", "profile", "library_path", "FP32", "BF16",
+           "FP8"]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfepll.so")
+
+FP32, BF16, FP8 = 0, 1, 2
+_PREC = {"fp32": FP32, "bf16": BF16, "fp8": FP8}
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EUNSUPPORTED",
+           -5: "ECHECKSUM"}
+
+
+class FepllError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("data", c_void_p), ("height", c_int32), ("width", c_int32),
+                ("row_stride", c_int64), ("on_device", c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("recheck", c_int32), ("use_proposal", c_int32),
+                ("top_m", c_int32), ("margin_nats", c_double), ("init", POINTER(Image)),
+                ("stream", c_void_p), ("profile", c_int32)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    L.fepll_options_default.argtypes = [POINTER(Options)]
+    L.fepll_options_default.restype = None
+    L.fepll_last_error.restype = c_char_p
+    L.fepll_version.restype = c_char_p
+    L.fepll_gmm_create.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                   POINTER(c_void_p)]
+    L.fepll_gmm_create.restype = c_int32
+    L.fepll_gmm_destroy.argtypes = [c_void_p]
+    L.fepll_gmm_destroy.restype = None
+    L.fepll_restore.argtypes = [c_void_p, POINTER(Image), c_void_p, c_double, c_void_p, c_int32,
+                                POINTER(Image), POINTER(Options), c_void_p]
+    L.fepll_restore.restype = c_int32
+    L.fepll_select.argtypes = [c_void_p, POINTER(Image), c_double, c_void_p, c_void_p, c_void_p,
+                               c_void_p, POINTER(Options)]
+    L.fepll_select.restype = c_int32
+    L.fepll_profile.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32), c_int32]
+    L.fepll_profile.restype = c_int32
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != 0:
+        raise FepllError(st, lib().fepll_last_error().decode())
+
+
+def _ptr(a) -> int:
+    """Data pointer of a torch tensor or a C-contiguous numpy array."""
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _image(t) -> Image:
+    import torch
+    if isinstance(t, np.ndarray):
+        if t.dtype != np.float32 or t.ndim != 2 or t.strides[1] != 4:
+            raise ValueError("image must be a 2-D float32 array with unit column stride")
+        return Image(t.ctypes.data, t.shape[0], t.shape[1], t.strides[0] // 4, 0)
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.dim() != 2 \
+            or t.stride(1) != 1:
+        raise ValueError("image must be a 2-D float32 tensor with unit column stride")
+    return Image(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0), 1 if t.is_cuda else 0)
+
+
+STAGES = ("select", "recheck", "bucket", "wiener", "ola_update", "prep")
+
+
+def _options(precision="fp32", recheck=True, init=None, stream=None, profile=False) -> Options:
+    o = Options()
+    lib().fepll_options_default(ctypes.byref(o))
+    o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+    o.recheck = 1 if recheck else 0
+    if init is not None:
+        o._init_img = _image(init)  # keep alive with the struct
+        o.init = ctypes.pointer(o._init_img)
+    o.stream = stream
+    o.profile = 1 if profile else 0
+    return o
+
+
+def _stream_of(t):
+    import torch
+    if isinstance(t, torch.Tensor) and t.is_cuda:
+        return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+    return None
+
+
+class GMM:
+    """Device-resident mixture: U (K,64,64) eigenvectors as columns,
+    lam (K,64) eigenvalues, w (K,) weights -- all float64 on the host."""
+
+    def __init__(self, U, lam, w):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        lam = np.ascontiguousarray(lam, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        K = w.shape[0]
+        if U.shape != (K, 64, 64) or lam.shape != (K, 64):
+            raise ValueError("U must be (K,64,64), lam (K,64), w (K,)")
+        h = c_void_p()
+        _check(lib().fepll_gmm_create(U.ctypes.data, lam.ctypes.data, w.ctypes.data, K, 64,
+                                      ctypes.byref(h)))
+        self._h = h
+        self.K = K
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fepll_gmm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def profile(gmm: GMM):
+    """Stage times (ms) and launch counts accumulated since the last read."""
+    ms = (c_double * 6)()
+    n = (c_int32 * 6)()
+    _check(lib().fepll_profile(gmm.handle, ms, n, 6))
+    return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
+
+
+def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
+            recheck=True, return_labels=False, out=None, profile=False):
+    """Denoise y (2-D float32 torch tensor, CUDA or CPU, or numpy array).
+
+    betas: absolute beta values (default {1,4,8,16,32}/sigma^2).
+    Returns the restored image (same kind and device as y) and, with
+    return_labels, the (T, Np) int32 labels of every iteration.
+    """
+    import torch
+    yi = _image(y)
+    if out is None:
+        out = torch.empty_like(y) if isinstance(y, torch.Tensor) else np.empty_like(y)
+    oi = _image(out)
+    o = _options(precision, recheck, init, _stream_of(y), profile)
+    if betas is None:
+        bptr, T = None, 0
+        Tn = 5
+    else:
+        b = np.ascontiguousarray(betas, dtype=np.float64)
+        bptr, T = b.ctypes.data, b.size
+        Tn = T
+    labels = None
+    lptr = None
+    if return_labels:
+        Np = (y.shape[0] - 7) * (y.shape[1] - 7)
+        if isinstance(y, torch.Tensor):
+            labels = torch.empty((Tn, Np), dtype=torch.int32, device=y.device)
+        else:
+            labels = np.empty((Tn, Np), dtype=np.int32)
+        lptr = _ptr(labels)
+    _check(lib().fepll_restore(gmm.handle, ctypes.byref(yi), None, float(sigma), bptr, T,
+                               ctypes.byref(oi), ctypes.byref(o), lptr))
+    return (out, labels) if return_labels else out
+
+
+def select(gmm: GMM, x, beta: float, recheck=True, precision="fp32"):
+    """One Gaussian-selection step on the CUDA image x.
+    Returns (labels int32, best f32, second f32, flags int32), each of
+    length (H-7)*(W-7)."""
+    import torch
+    xi = _image(x)
+    Np = (x.shape[0] - 7) * (x.shape[1] - 7)
+    dev = x.device
+    lab = torch.empty(Np, dtype=torch.int32, device=dev)
+    best = torch.empty(Np, dtype=torch.float32, device=dev)
+    second = torch.empty(Np, dtype=torch.float32, device=dev)
+    flags = torch.empty(Np, dtype=torch.int32, device=dev)
+    o = _options(precision, recheck, None, _stream_of(x))
+    _check(lib().fepll_select(gmm.handle, ctypes.byref(xi), float(beta), lab.data_ptr(),
+                              best.data_ptr(), second.data_ptr(), flags.data_ptr(),
+                              ctypes.byref(o)))
+    return lab, best, second, flags

@@ -1,0 +1,67 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+//
+// Layout of the per-beta constant tables the kernels read (all in device
+// memory, built once per beta schedule by prep.hip):
+//
+//  * Ut   float,  [T][K][2][8][64][4]: the E-step MFMA A operand.  For
+//    iteration t, component k, eigen block jb (0/1), MFMA step s = 4*i + e
+//    (i = 0..7, e = 0..3) and lane l, the float at [t][k][jb][i][l][e] is
+//    U_k[p][j] / sqrt(nu_kj) with p = 2*s + (l >> 5) and j = 32*jb + (l & 31).
+//    Scaling the eigenvectors by nu^-1/2 turns the Mahalanobis term
+//    sum_j c_j^2 / nu_kj of the selection cost into a plain sum of squares.
+//  * Wt   float,  [T][K][2][8][64][4]: the patch-estimation A operand,
+//    entry W_k[q][p] with q = 32*qb + (l & 31), p = 2*s + (l >> 5), where
+//    W_k = U_k diag(gamma_k) U_k^t (the Wiener filter of Alg. 1, patch
+//    estimation, written back in pixel space).
+//  * L32  float,  [T][K]: L_k = iota_k + sum_j log nu_kj rounded from float64.
+//  * L64  double, [T][K] and invnu64 double [T][K][64]: the same terms in
+//    float64 for the re-selection of uncertified patches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fepll {
+
+constexpr int kP = 64;          // pixels per patch
+constexpr int kTileStride = 4096;  // floats per (t, k) operand table
+constexpr int kMaxT = 16;
+constexpr int kMaxK = 1024;
+
+struct Schedule {
+  int T;
+  double beta[kMaxT];
+};
+
+// ------------------------------------------------------------ launches
+// Every launcher returns hipSuccess or the launch error; none synchronises.
+
+hipError_t launch_prep(const double* U64, const double* lam64, const double* w64, int K,
+                       const Schedule& sch, float* Ut, float* Wt, float* L32, double* L64,
+                       double* invnu64, hipStream_t st);
+
+hipError_t launch_estep_f32(const float* x, int H, int W, const float* Ut_t, const float* L32_t,
+                            int K, double beta, int32_t* labels, float* best, float* second,
+                            int32_t* flags, int32_t* list_count, int32_t* list, hipStream_t st);
+
+hipError_t launch_recheck_f64(const float* x, int H, int W, const double* U64,
+                              const double* invnu64_t, const double* L64_t, int K,
+                              const int32_t* list_count, const int32_t* list, int32_t* labels,
+                              int max_list, hipStream_t st);
+
+// Counting sort of patch indices by label (stable) and the Wiener tile list.
+// hist: [K][nb] int32, nb = ceil(Np / kSortBlock); seg: [3*(K+1)+1] int32
+// laid out as start[K+1], count[K], tile_prefix[K+1], total_tiles.
+constexpr int kSortBlock = 1024;
+constexpr int kWienerTile = 64;
+hipError_t launch_bucket(const int32_t* labels, int Np, int K, int32_t* hist, int32_t* seg,
+                         int32_t* perm, hipStream_t st);
+
+hipError_t launch_wiener_f32(const float* x, int H, int W, const float* Wt_t, int K,
+                             const int32_t* seg, const int32_t* perm, float* Zhat,
+                             hipStream_t st);
+
+hipError_t launch_ola_update(const float* Zhat, const float* y, int H, int W, double b,
+                             float* xnew, hipStream_t st);
+
+}  // namespace fepll

@@ -1,0 +1,65 @@
+// Per-beta constants of the eigenspace formulation (Sec. 2.1, the terms
+// defined after eq:selection_eigenspace): nu_kj = lambda_kj + 1/beta,
+// gamma_kj = lambda_kj / nu_kj, iota_k = -2 log w_k.  Computed in float64
+// from the float64 eigendecomposition, then rounded once to float32 in the
+// operand layouts the MFMA kernels read (see common.h).
+#include "common.h"
+
+namespace fepll {
+
+__global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U64,
+                                                   const double* __restrict__ lam,
+                                                   const double* __restrict__ w, int K,
+                                                   Schedule sch, float* __restrict__ Ut,
+                                                   float* __restrict__ Wt,
+                                                   float* __restrict__ L32,
+                                                   double* __restrict__ L64,
+                                                   double* __restrict__ invnu64) {
+  const int k = blockIdx.x;
+  const int t = blockIdx.y;
+  const double beta = sch.beta[t];
+  __shared__ double Us[kP * kP];  // U_k[p][j]
+  __shared__ double nu[kP], gam[kP], rs[kP];
+  for (int i = threadIdx.x; i < kP * kP; i += blockDim.x) Us[i] = U64[(size_t)k * kP * kP + i];
+  if (threadIdx.x < kP) {
+    const int j = threadIdx.x;
+    const double l = lam[k * kP + j];
+    const double n = l + 1.0 / beta;
+    nu[j] = n;
+    gam[j] = l / n;
+    rs[j] = 1.0 / sqrt(n);
+    invnu64[((size_t)t * K + k) * kP + j] = 1.0 / n;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = -2.0 * log(w[k]);
+    for (int j = 0; j < kP; ++j) s += log(nu[j]);
+    L64[t * K + k] = s;
+    L32[t * K + k] = (float)s;
+  }
+  float* ut = Ut + ((size_t)t * K + k) * kTileStride;
+  float* wt = Wt + ((size_t)t * K + k) * kTileStride;
+  for (int idx = threadIdx.x; idx < kTileStride; idx += blockDim.x) {
+    const int e = idx & 3, l = (idx >> 2) & 63, i = (idx >> 8) & 7, jb = idx >> 11;
+    const int s = 4 * i + e;
+    const int p = 2 * s + (l >> 5);
+    const int j = 32 * jb + (l & 31);
+    ut[idx] = (float)(Us[p * kP + j] * rs[j]);
+    // Wiener operand: row q of W_k = U_k diag(gamma) U_k^t, column p
+    const int q = j;
+    double acc = 0.0;
+    for (int jj = 0; jj < kP; ++jj) acc += Us[q * kP + jj] * gam[jj] * Us[p * kP + jj];
+    wt[idx] = (float)acc;
+  }
+}
+
+hipError_t launch_prep(const double* U64, const double* lam64, const double* w64, int K,
+                       const Schedule& sch, float* Ut, float* Wt, float* L32, double* L64,
+                       double* invnu64, hipStream_t st) {
+  dim3 grid(K, sch.T);
+  hipLaunchKernelGGL(prep_kernel, grid, dim3(256), 0, st, U64, lam64, w64, K, sch, Ut, Wt, L32,
+                     L64, invnu64);
+  return hipGetLastError();
+}
+
+}  // namespace fepll

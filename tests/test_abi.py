@@ -1,0 +1,114 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/fepll.h declares, and rejects invalid arguments before touching the
+device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import fepll_synth as fs
+import paper_1710_08124_amd as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fepll.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fepll_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared()
+    assert "fepll_restore" in names and "fepll_gmm_create" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", F.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = F.lib()
+    for n in names:
+        getattr(L, n)
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(F.Image) == 32
+    assert ctypes.sizeof(F.Options) == 48
+
+
+def test_options_defaults_and_version():
+    o = F.Options()
+    F.lib().fepll_options_default(ctypes.byref(o))
+    assert (o.precision, o.recheck, o.use_proposal, o.top_m) == (0, 1, 0, 8)
+    assert o.margin_nats == 0.5
+    assert F.lib().fepll_version().decode().startswith("fepll")
+
+
+def _create(U, lam, w, d=64):
+    h = ctypes.c_void_p()
+    st = F.lib().fepll_gmm_create(U.ctypes.data, lam.ctypes.data, w.ctypes.data, w.shape[0], d,
+                                  ctypes.byref(h))
+    return st, h
+
+
+@pytest.fixture(scope="module")
+def gmm3():
+    return fs.gmm(3, 1)
+
+
+def test_create_rejects_wrong_dimension(gmm3):
+    U, lam, w = gmm3
+    st, h = _create(U, lam, w, d=49)
+    assert st == -1 and not h.value
+    assert b"64" in F.lib().fepll_last_error()
+
+
+def test_create_rejects_bad_weights(gmm3):
+    U, lam, w = gmm3
+    st, _ = _create(U, lam, w * 1.01)
+    assert st == -1 and b"sum" in F.lib().fepll_last_error()
+    w2 = w.copy()
+    w2[0] = -w2[0]
+    assert _create(U, lam, w2)[0] == -1
+    w3 = w.copy()
+    w3[1] = np.nan
+    assert _create(U, lam, w3)[0] == -1
+
+
+def test_create_rejects_bad_eigenvalues(gmm3):
+    U, lam, w = gmm3
+    l2 = lam.copy()
+    l2[1, 5] = -1.0
+    assert _create(U, l2, w)[0] == -1
+    l2[1, 5] = np.inf
+    assert _create(U, l2, w)[0] == -1
+
+
+def test_create_rejects_non_orthonormal_basis(gmm3):
+    U, lam, w = gmm3
+    U2 = U.copy()
+    U2[2, 3, 4] += 1e-6
+    st, _ = _create(U2, lam, w)
+    assert st == -1 and b"orthonormal" in F.lib().fepll_last_error()
+
+
+def test_create_rejects_K_out_of_range():
+    U, lam, w = fs.gmm(1, 2)
+    h = ctypes.c_void_p()
+    assert F.lib().fepll_gmm_create(U.ctypes.data, lam.ctypes.data, w.ctypes.data, 0, 64,
+                                    ctypes.byref(h)) == -1
+    assert F.lib().fepll_gmm_create(None, lam.ctypes.data, w.ctypes.data, 1, 64,
+                                    ctypes.byref(h)) == -1
+
+
+def test_restore_rejects_null_handle():
+    y = np.zeros((16, 16), np.float32)
+    yi = F._image(y)
+    oi = F._image(np.zeros_like(y))
+    st = F.lib().fepll_restore(None, ctypes.byref(yi), None, 10.0, None, 0, ctypes.byref(oi),
+                               None, None)
+    assert st == -1
