@@ -63,6 +63,7 @@ struct fepll_gmm {
   Schedule sched{};
   int T_cap = 0;
   float* Ut = nullptr;
+  uint16_t* Ub = nullptr;
   float* Wt = nullptr;
   float* L32 = nullptr;
   double* L64 = nullptr;
@@ -142,6 +143,7 @@ fepll_status ensure_consts(fepll_gmm* g, const Schedule& s, hipStream_t st) {
     return FEPLL_OK;
   if (s.T > g->T_cap) {
     dfree(g->Ut);
+    dfree(g->Ub);
     dfree(g->Wt);
     dfree(g->L32);
     dfree(g->L64);
@@ -149,6 +151,7 @@ fepll_status ensure_consts(fepll_gmm* g, const Schedule& s, hipStream_t st) {
     g->T_cap = 0;
     const size_t K = g->K;
     HIPX(dalloc(&g->Ut, (size_t)s.T * K * kTileStride));
+    HIPX(dalloc(&g->Ub, (size_t)s.T * K * kTileStride));
     HIPX(dalloc(&g->Wt, (size_t)s.T * K * kTileStride));
     HIPX(dalloc(&g->L32, (size_t)s.T * K));
     HIPX(dalloc(&g->L64, (size_t)s.T * K));
@@ -157,7 +160,7 @@ fepll_status ensure_consts(fepll_gmm* g, const Schedule& s, hipStream_t st) {
   }
   {
     StageTimer tm(g, 5, st);
-    HIPX(launch_prep(g->U64, g->lam64, g->w64, g->K, s, g->Ut, g->Wt, g->L32, g->L64,
+    HIPX(launch_prep(g->U64, g->lam64, g->w64, g->K, s, g->Ut, g->Ub, g->Wt, g->L32, g->L64,
                      g->invnu64, st));
   }
   g->sched = s;
@@ -179,7 +182,7 @@ fepll_status ensure_ws(fepll_gmm* g, int H, int W) {
     g->np_cap = 0;
     const size_t nb = (Np + kSortBlock - 1) / kSortBlock;
     HIPX(dalloc(&g->labels, Np));
-    HIPX(dalloc(&g->list, Np));
+    HIPX(dalloc(&g->list, 4 * Np));  // int4 entries
     HIPX(dalloc(&g->count, 64));
     HIPX(dalloc(&g->hist, nb * g->K));
     HIPX(dalloc(&g->seg, 3 * (size_t)g->K + 3));
@@ -238,20 +241,28 @@ hipError_t copy_out(fepll_image* im, const float* src, hipStream_t st) {
 fepll_status check_opt(const fepll_gmm* g, const fepll_options* o) {
   if (o->precision != FEPLL_FP32 && o->precision != FEPLL_BF16 && o->precision != FEPLL_FP8)
     return fail(FEPLL_EINVAL, "options.precision must be FEPLL_FP32, FEPLL_BF16 or FEPLL_FP8");
-  if (o->precision != FEPLL_FP32)
-    return fail(FEPLL_EUNSUPPORTED, "only FEPLL_FP32 projections are built in this library");
+  if (o->precision == FEPLL_FP8)
+    return fail(FEPLL_EUNSUPPORTED, "FEPLL_FP8 projections are not built in this library");
   if (o->use_proposal) return fail(FEPLL_EUNSUPPORTED, "no proposal network is loaded");
-  if (o->top_m < 1 || o->top_m > g->K) return fail(FEPLL_EINVAL, "options.top_m out of 1..K");
+  if (o->use_proposal && (o->top_m < 1 || o->top_m > g->K))
+    return fail(FEPLL_EINVAL, "options.top_m out of 1..K");
   if (std::isnan(o->margin_nats)) return fail(FEPLL_EINVAL, "options.margin_nats is NaN");
   return FEPLL_OK;
 }
 
 // One Gaussian selection (E-step + optional float64 recheck) of image x.
 fepll_status run_select(fepll_gmm* g, const float* x, int H, int W, int t, double beta,
-                        bool recheck, int32_t* labels, float* best, float* second,
-                        int32_t* flags, hipStream_t st) {
+                        int precision, bool recheck, int32_t* labels, float* best,
+                        float* second, int32_t* flags, hipStream_t st) {
   const int Np = (H - 7) * (W - 7);
   const size_t K = g->K;
+  if (precision == FEPLL_BF16) {
+    StageTimer tm(g, 0, st);
+    HIPX(launch_estep_bf16(x, H, W, g->Ub + (size_t)t * K * kTileStride,
+                           g->L32 + (size_t)t * K, g->K, labels, best, second, st));
+    if (flags) HIPX(hipMemsetAsync(flags, 0, sizeof(int32_t) * Np, st));
+    return FEPLL_OK;
+  }
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, g->count, 1);
   HIPX(hipGetLastError());
   {
@@ -380,6 +391,7 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->lam64);
   dfree(g->w64);
   dfree(g->Ut);
+  dfree(g->Ub);
   dfree(g->Wt);
   dfree(g->L32);
   dfree(g->L64);
@@ -452,8 +464,8 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, 
   float* xn = g->xb;
   for (int t = 0; t < sch.T; ++t) {
     const double beta = sch.beta[t];
-    if ((s = run_select(g, xc, H, W, t, beta, o.recheck != 0, g->labels, nullptr, nullptr,
-                        nullptr, st)) != FEPLL_OK)
+    if ((s = run_select(g, xc, H, W, t, beta, o.precision, o.recheck != 0, g->labels, nullptr,
+                        nullptr, nullptr, st)) != FEPLL_OK)
       return s;
     if (labels_out)
       HIPX(hipMemcpyAsync(labels_out + (size_t)t * Np, g->labels, sizeof(int32_t) * Np,
@@ -502,7 +514,8 @@ fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta, int32
   sch.beta[0] = beta;
   if ((s = ensure_consts(g, sch, st)) != FEPLL_OK) return s;
   HIPX(copy_in(g->xa, x, st));
-  return run_select(g, g->xa, H, W, 0, beta, o.recheck != 0, labels, best, second, flags, st);
+  return run_select(g, g->xa, H, W, 0, beta, o.precision, o.recheck != 0, labels, best, second,
+                    flags, st);
 }
 
 }  // extern "C"

@@ -13,6 +13,9 @@
 //    entry W_k[q][p] with q = 32*qb + (l & 31), p = 2*s + (l >> 5), where
 //    W_k = U_k diag(gamma_k) U_k^t (the Wiener filter of Alg. 1, patch
 //    estimation, written back in pixel space).
+//  * Ub   bf16 bits (uint16), [T][K][2][4][64][8]: the bfloat16 E-step A
+//    operand, entry Ut_k[p][j] with j = 32*jb + (l & 31) and
+//    p = 16*t + 8*(l >> 5) + e for depth step t (0..3), lane l, element e.
 //  * L32  float,  [T][K]: L_k = iota_k + sum_j log nu_kj rounded from float64.
 //  * L64  double, [T][K] and invnu64 double [T][K][64]: the same terms in
 //    float64 for the re-selection of uncertified patches.
@@ -37,12 +40,16 @@ struct Schedule {
 // Every launcher returns hipSuccess or the launch error; none synchronises.
 
 hipError_t launch_prep(const double* U64, const double* lam64, const double* w64, int K,
-                       const Schedule& sch, float* Ut, float* Wt, float* L32, double* L64,
-                       double* invnu64, hipStream_t st);
+                       const Schedule& sch, float* Ut, uint16_t* Ub, float* Wt, float* L32,
+                       double* L64, double* invnu64, hipStream_t st);
 
 hipError_t launch_estep_f32(const float* x, int H, int W, const float* Ut_t, const float* L32_t,
                             int K, double beta, int32_t* labels, float* best, float* second,
                             int32_t* flags, int32_t* list_count, int32_t* list, hipStream_t st);
+
+hipError_t launch_estep_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
+                             const float* L32_t, int K, int32_t* labels, float* best,
+                             float* second, hipStream_t st);
 
 hipError_t launch_recheck_f64(const float* x, int H, int W, const double* U64,
                               const double* invnu64_t, const double* L64_t, int K,
@@ -52,7 +59,7 @@ hipError_t launch_recheck_f64(const float* x, int H, int W, const double* U64,
 // Counting sort of patch indices by label (stable) and the Wiener tile list.
 // hist: [K][nb] int32, nb = ceil(Np / kSortBlock); seg: [3*(K+1)+1] int32
 // laid out as start[K+1], count[K], tile_prefix[K+1], total_tiles.
-constexpr int kSortBlock = 1024;
+constexpr int kSortBlock = 16384;
 constexpr int kWienerTile = 64;
 hipError_t launch_bucket(const int32_t* labels, int Np, int K, int32_t* hist, int32_t* seg,
                          int32_t* perm, hipStream_t st);

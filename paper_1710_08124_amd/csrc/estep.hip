@@ -18,11 +18,11 @@
 // (16 KB per k, shared by every wave of the chip through L2) with one
 // component of software prefetch.
 //
-// Certification: every float32 cost carries a forward rounding-error bound
-// e_k (derivation below); a patch whose best cost plus its bound is not
-// below every other cost minus its bound is flagged, appended to a list,
-// and re-selected in float64 by recheck.hip.  Labels then equal an exact
-// evaluation of the selection rule.
+// Certification: the float32 costs carry a forward rounding-error bound
+// (derivation below); a patch whose best cost is not separated from the
+// others by the bound is appended to a list with the few components that
+// can still hold its exact minimum, and re-selected in float64 by
+// recheck.hip.  Labels then equal an exact evaluation of the selection rule.
 #include "common.h"
 
 namespace fepll {
@@ -48,11 +48,25 @@ __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
 //    |dQ| <= gamma_64 Q + 2 a sum_j |c_j| + 64 a^2
 //         <= gamma_64 Q + 16 a sqrt(Q) + 64 a^2
 //  * cost = fl(L32 + Q), L32 rounded once from float64: + u (|L| + |cost|).
+// With Q <= cost - min_k L_k this gives one bound E(cost) for every k of the
+// patch (kappa = 2 on top); E grows much slower than its argument, so
+// c - E(c) is increasing and:
+//  * the float32 argmin is exact when best + E(best) < second - E(second);
+//  * otherwise only components with cost <= best + 3 E(best) can hold the
+//    exact minimum.  The kernel keeps up to kCand of them (pruned whenever
+//    the running best improves) and hands them to the float64 re-selection;
+//    more than kCand at once marks the patch for a full-K re-selection.
+namespace {
+constexpr int kCand = 4;
+}
+
 __global__ __launch_bounds__(256, 2) void estep_f32_kernel(
     const float* __restrict__ x, int H, int W, const float4* __restrict__ Ut,
     const float* __restrict__ L, int K, float sqrt_beta, int32_t* __restrict__ labels,
     float* __restrict__ best_out, float* __restrict__ second_out, int32_t* __restrict__ flags,
-    int32_t* __restrict__ list_count, int32_t* __restrict__ list) {
+    int32_t* __restrict__ list_count, int4* __restrict__ list) {
+  __shared__ float cand_v[256 * kCand];
+  __shared__ int cand_k[256 * kCand];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int half = lane >> 5;
@@ -62,6 +76,18 @@ __global__ __launch_bounds__(256, 2) void estep_f32_kernel(
   const int r = blockIdx.y * 4 + wave;
   const int c0 = blockIdx.x * 64;
   const int rr = min(r, Hp - 1);
+
+  // smallest L_k and largest |L_k| (wave-uniform)
+  float Lmin = INFINITY, Labs = 0.f;
+  for (int k = lane; k < K; k += 64) {
+    Lmin = fminf(Lmin, L[k]);
+    Labs = fmaxf(Labs, fabsf(L[k]));
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    Lmin = fminf(Lmin, __shfl_xor(Lmin, m));
+    Labs = fmaxf(Labs, __shfl_xor(Labs, m));
+  }
 
   // ---- patch extraction: lane holds pixels p = 2s + half of its patches
   float z0[32], z1[32];
@@ -98,9 +124,15 @@ __global__ __launch_bounds__(256, 2) void estep_f32_kernel(
   const float g66 = 66.f * kU / (1.f - 66.f * kU);
   const float g64 = 64.f * kU / (1.f - 64.f * kU);
   const float a = g66 * sqrt_beta * sqrtf((half ? n1 : n0) * (1.f + 64.f * kU));
+  auto Ebound = [&](float c) {
+    const float q = fmaxf(c - Lmin, 0.f);
+    return kKappa * (g64 * q + 16.f * a * sqrtf(q) + 64.f * a * a + kU * (Labs + fabsf(c)));
+  };
 
-  float best_c = INFINITY, best_e = 0.f, second_c = INFINITY, others_lo = INFINITY;
-  int best_k = 0;
+  float best_c = INFINITY, second_c = INFINITY, thr = INFINITY;
+  int best_k = 0, nc = 0;
+  float* my_v = cand_v + threadIdx.x * kCand;
+  int* my_k = cand_k + threadIdx.x * kCand;
 
   const float4* up = Ut + lane;  // [K][2][8][64] float4
   float4 A[8];
@@ -137,19 +169,32 @@ __global__ __launch_bounds__(256, 2) void estep_f32_kernel(
       const float send = half ? q0 : q1;
       const float recv = __shfl_xor(send, 32);
       const float Q = (half ? q1 : q0) + recv;
-      const float Lk = L[k];
-      const float cost = Lk + Q;
-      const float e = kKappa * (g64 * Q + 16.f * a * sqrtf(Q) + 64.f * a * a +
-                                kU * (fabsf(Lk) + fabsf(cost)));
+      const float cost = L[k] + Q;
       if (cost < best_c) {
-        others_lo = fminf(others_lo, best_c - best_e);
         second_c = best_c;
         best_c = cost;
-        best_e = e;
         best_k = k;
-      } else {
-        others_lo = fminf(others_lo, cost - e);
-        second_c = fminf(second_c, cost);
+        thr = cost + 3.f * Ebound(cost);
+        int n2 = 0;
+        const int nold = min(nc, kCand);
+        for (int i = 0; i < nold; ++i) {
+          const float v = my_v[i];
+          if (v <= thr) {
+            my_v[n2] = v;
+            my_k[n2] = my_k[i];
+            ++n2;
+          }
+        }
+        nc = (nc > kCand) ? nc : n2;  // an overflow stays an overflow
+      } else if (cost < second_c) {
+        second_c = cost;
+      }
+      if (cost <= thr) {
+        if (nc < kCand) {
+          my_v[nc] = cost;
+          my_k[nc] = k;
+        }
+        ++nc;
       }
       q0 = 0.f;
       q1 = 0.f;
@@ -164,11 +209,25 @@ __global__ __launch_bounds__(256, 2) void estep_f32_kernel(
     labels[idx] = best_k;
     if (best_out) best_out[idx] = best_c;
     if (second_out) second_out[idx] = second_c;
-    const int unsure = !(best_c + best_e < others_lo);
+    const int unsure = !(best_c + Ebound(best_c) < second_c - Ebound(second_c));
     if (flags) flags[idx] = unsure;
     if (unsure && list) {
+      // entry: patch, candidate count (kCand + 1 = all K), candidates packed
+      // two per int in ascending k order of discovery
+      int4 ent;
+      ent.x = idx;
+      int kk4[kCand];
+      int n2 = 0;
+      if (nc <= kCand) {
+        for (int i = 0; i < nc; ++i)
+          if (my_v[i] <= thr) kk4[n2++] = my_k[i];
+      }
+      for (int i = n2; i < kCand; ++i) kk4[i] = 0;
+      ent.y = (nc <= kCand) ? n2 : kCand + 1;
+      ent.z = kk4[0] | (kk4[1] << 16);
+      ent.w = kk4[2] | (kk4[3] << 16);
       const int slot = atomicAdd(list_count, 1);
-      list[slot] = idx;
+      list[slot] = ent;
     }
   }
 }
@@ -176,11 +235,12 @@ __global__ __launch_bounds__(256, 2) void estep_f32_kernel(
 hipError_t launch_estep_f32(const float* x, int H, int W, const float* Ut_t, const float* L32_t,
                             int K, double beta, int32_t* labels, float* best, float* second,
                             int32_t* flags, int32_t* list_count, int32_t* list, hipStream_t st) {
+  // list holds int4 entries (see the kernel)
   const int Hp = H - 7, Wp = W - 7;
   dim3 grid((Wp + 63) / 64, (Hp + 3) / 4);
   hipLaunchKernelGGL(estep_f32_kernel, grid, dim3(256), 0, st, x, H, W,
                      reinterpret_cast<const float4*>(Ut_t), L32_t, K, (float)sqrt(beta), labels,
-                     best, second, flags, list_count, list);
+                     best, second, flags, list_count, reinterpret_cast<int4*>(list));
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
                                                    const double* __restrict__ lam,
                                                    const double* __restrict__ w, int K,
                                                    Schedule sch, float* __restrict__ Ut,
+                                                   uint16_t* __restrict__ Ub,
                                                    float* __restrict__ Wt,
                                                    float* __restrict__ L32,
                                                    double* __restrict__ L64,
@@ -39,12 +40,22 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
   }
   float* ut = Ut + ((size_t)t * K + k) * kTileStride;
   float* wt = Wt + ((size_t)t * K + k) * kTileStride;
+  uint16_t* ub = Ub + ((size_t)t * K + k) * kTileStride;
   for (int idx = threadIdx.x; idx < kTileStride; idx += blockDim.x) {
     const int e = idx & 3, l = (idx >> 2) & 63, i = (idx >> 8) & 7, jb = idx >> 11;
     const int s = 4 * i + e;
     const int p = 2 * s + (l >> 5);
     const int j = 32 * jb + (l & 31);
     ut[idx] = (float)(Us[p * kP + j] * rs[j]);
+    {
+      // bfloat16 table: same entries, MFMA 32x32x16 operand order
+      const int eb = idx & 7, lb = (idx >> 3) & 63, tb = (idx >> 9) & 3, jbb = idx >> 11;
+      const int pb = 16 * tb + 8 * (lb >> 5) + eb;
+      const int jb2 = 32 * jbb + (lb & 31);
+      uint32_t u = __float_as_uint((float)(Us[pb * kP + jb2] * rs[jb2]));
+      u += 0x7fffu + ((u >> 16) & 1u);
+      ub[idx] = (uint16_t)(u >> 16);
+    }
     // Wiener operand: row q of W_k = U_k diag(gamma) U_k^t, column p
     const int q = j;
     double acc = 0.0;
@@ -54,11 +65,11 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
 }
 
 hipError_t launch_prep(const double* U64, const double* lam64, const double* w64, int K,
-                       const Schedule& sch, float* Ut, float* Wt, float* L32, double* L64,
-                       double* invnu64, hipStream_t st) {
+                       const Schedule& sch, float* Ut, uint16_t* Ub, float* Wt, float* L32,
+                       double* L64, double* invnu64, hipStream_t st) {
   dim3 grid(K, sch.T);
-  hipLaunchKernelGGL(prep_kernel, grid, dim3(256), 0, st, U64, lam64, w64, K, sch, Ut, Wt, L32,
-                     L64, invnu64);
+  hipLaunchKernelGGL(prep_kernel, grid, dim3(256), 0, st, U64, lam64, w64, K, sch, Ut, Ub, Wt,
+                     L32, L64, invnu64);
   return hipGetLastError();
 }
 
