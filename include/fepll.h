@@ -137,8 +137,10 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* H, do
  * form) on every patch of the device image x for one beta, without
  * estimation or reprojection.  Device buffers of Np entries each:
  *   labels (int32, required), best and second (float32, optional: the two
- *   smallest float32 costs), flags (int32, optional: 1 where the float32
- *   selection was not certified and, with recheck on, was redone in float64).
+ *   smallest costs scored), flags (int32, optional: FEPLL_FP32 -- 1 where the
+ *   float32 selection was not certified and, with recheck on, was redone in
+ *   float64; with options.use_proposal -- 1 where the patch fell back to the
+ *   full-K search; otherwise 0).
  * Used to check the selection against an exact evaluation and to record
  * the labels the proposal network is trained on.
  */
@@ -148,14 +150,86 @@ fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta,
 
 /*
  * Stage timing of the calls made with options.profile set since the last
- * read.  Stages: 0 selection (float32 E-step), 1 float64 re-selection,
- * 2 bucketing, 3 patch estimation, 4 reprojection + image estimation,
- * 5 per-beta constants.  ms[s] receives the summed event time of stage s in
- * milliseconds and launches[s] the number of timed launches (either pointer
- * may be NULL); n is the number of entries provided (at most 6 are written).
+ * read.  Stages: 0 selection (E-step; with the proposal: exact rescoring of
+ * the candidates), 1 float64 re-selection, 2 bucketing, 3 patch
+ * estimation, 4 reprojection + image estimation, 5 per-beta constants,
+ * 6 proposal network, 7 full-K selection of the fallback patches.  ms[s]
+ * receives the summed event time of stage s in milliseconds and
+ * launches[s] the number of timed launches (either pointer may be NULL); n
+ * is the number of entries provided (at most 8 are written).
  * Synchronises with the recorded events, then clears the accumulators.
  */
 fepll_status fepll_profile(fepll_gmm* g, double* ms, int32_t* launches, int32_t n);
+
+/* ------------------------------------------------------------------------
+ * Component-proposal network.  Not part of the paper: the paper limits the
+ * components scored by a search tree (Sec. 3.2) and reviews a gating network
+ * that approximates the selection score (Sec. 5); here a network
+ * [z~/128, log sigma_beta] (65) -> 256 -> 256 -> K, exact-erf GELU after the
+ * hidden layers, proposes components that the selection step then rescores
+ * with the exact cost.  Parameters are one float32 vector
+ * W1 (256x65) b1 (256) W2 (256x256) b2 (256) W3 (Kx256) b3 (K), every W
+ * stored (out, in) row-major.  All buffers below are device memory unless
+ * stated; work is enqueued on `stream` (hipStream_t, NULL = default).
+ * ---------------------------------------------------------------------- */
+typedef struct fepll_mlp fepll_mlp;
+
+typedef struct {
+  double lr, beta1, beta2, eps, weight_decay; /* AdamW, decoupled decay */
+} fepll_adamw;
+
+/* Number of float32 parameters of the network for K components. */
+int64_t fepll_mlp_param_count(int32_t K);
+
+/* Create a network with K outputs (1..1024) from `params` (host,
+ * fepll_mlp_param_count(K) floats); max_batch (>= 1) bounds the rows of
+ * one loss/gradient evaluation (forward passes are chunked). */
+fepll_status fepll_mlp_create(int32_t K, const float* params, int32_t max_batch,
+                              fepll_mlp** out);
+void fepll_mlp_destroy(fepll_mlp* m);
+
+/* Copy the current parameters to host memory (synchronises). */
+fepll_status fepll_mlp_get_params(fepll_mlp* m, float* params);
+
+/* logits (n x K, float32) of the n feature rows X (n x 65, float32). */
+fepll_status fepll_mlp_forward(fepll_mlp* m, const float* X, int32_t n, float* logits,
+                               void* stream);
+
+/* Mean softmax cross-entropy of X against labels (n <= max_batch rows,
+ * int32 in 0..K-1) into *loss (device float, optional) and its gradient
+ * into grads (device, param_count floats, optional). */
+fepll_status fepll_mlp_loss_grad(fepll_mlp* m, const float* X, const int32_t* labels,
+                                 int32_t n, float* grads, float* loss, void* stream);
+
+/* One AdamW step on a minibatch of n <= max_batch rows; *loss as above.
+ * rows == NULL: the first n rows of X / labels; otherwise rows (device,
+ * n int32) lists the rows of X / labels that form the minibatch. */
+fepll_status fepll_mlp_train_step(fepll_mlp* m, const float* X, const int32_t* labels,
+                                  const int32_t* rows, int32_t n, const fepll_adamw* hp,
+                                  float* loss, void* stream);
+
+/* Network input of every patch of the device image x at coupling beta:
+ * X (Np x 65 float32) row i = [z~_i / 128, -0.5 log beta], z~_i the
+ * DC-removed patch i (numbered as in fepll_restore). */
+fepll_status fepll_features(const fepll_image* x, double beta, float* X, void* stream);
+
+/* Serialize the parameters into buf (host): a 64-byte header (magic
+ * "FEPLLMLP", version, K, widths, input scale, GELU variant, parameter
+ * count, FNV-1a-64 checksum of the parameter bytes) followed by the
+ * parameters.  With buf = NULL only *nbytes is set.  Synchronises. */
+fepll_status fepll_mlp_serialize(fepll_mlp* m, void* buf, size_t cap, size_t* nbytes);
+
+/* Attach a serialized network to a mixture for options.use_proposal.
+ * EINVAL on a malformed header or a K different from the mixture's,
+ * ECHECKSUM when the checksum does not match. */
+fepll_status fepll_gmm_load_proposal(fepll_gmm* g, const void* blob, size_t nbytes);
+
+/* The top_m (1..8) components the attached network proposes for every
+ * patch of the device image x at coupling beta: cand (device, Np x 8
+ * uint16) row i lists them by decreasing logit (ties to the lower index),
+ * 0xffff after the top_m-th.  EINVAL without a loaded network. */
+fepll_status fepll_propose(fepll_gmm* g, const fepll_image* x, double beta, int32_t top_m,
+                           uint16_t* cand, void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* fepll_last_error(void);

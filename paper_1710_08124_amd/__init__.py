@@ -43,6 +43,11 @@ class Options(ctypes.Structure):
                 ("stream", c_void_p), ("profile", c_int32)]
 
 
+class AdamW(ctypes.Structure):
+    _fields_ = [("lr", c_double), ("beta1", c_double), ("beta2", c_double), ("eps", c_double),
+                ("weight_decay", c_double)]
+
+
 _lib = None
 
 
@@ -75,6 +80,31 @@ def lib():
     L.fepll_select.restype = c_int32
     L.fepll_profile.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32), c_int32]
     L.fepll_profile.restype = c_int32
+    L.fepll_mlp_param_count.argtypes = [c_int32]
+    L.fepll_mlp_param_count.restype = c_int64
+    L.fepll_mlp_create.argtypes = [c_int32, c_void_p, c_int32, POINTER(c_void_p)]
+    L.fepll_mlp_create.restype = c_int32
+    L.fepll_mlp_destroy.argtypes = [c_void_p]
+    L.fepll_mlp_destroy.restype = None
+    L.fepll_mlp_get_params.argtypes = [c_void_p, c_void_p]
+    L.fepll_mlp_get_params.restype = c_int32
+    L.fepll_mlp_forward.argtypes = [c_void_p, c_void_p, c_int32, c_void_p, c_void_p]
+    L.fepll_mlp_forward.restype = c_int32
+    L.fepll_mlp_loss_grad.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                      c_void_p]
+    L.fepll_mlp_loss_grad.restype = c_int32
+    L.fepll_mlp_train_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32,
+                                       POINTER(AdamW), c_void_p, c_void_p]
+    L.fepll_mlp_train_step.restype = c_int32
+    L.fepll_features.argtypes = [POINTER(Image), c_double, c_void_p, c_void_p]
+    L.fepll_features.restype = c_int32
+    L.fepll_mlp_serialize.argtypes = [c_void_p, c_void_p, ctypes.c_size_t,
+                                      POINTER(ctypes.c_size_t)]
+    L.fepll_mlp_serialize.restype = c_int32
+    L.fepll_gmm_load_proposal.argtypes = [c_void_p, c_void_p, ctypes.c_size_t]
+    L.fepll_gmm_load_proposal.restype = c_int32
+    L.fepll_propose.argtypes = [c_void_p, POINTER(Image), c_double, c_int32, c_void_p, c_void_p]
+    L.fepll_propose.restype = c_int32
     _lib = L
     return L
 
@@ -103,10 +133,11 @@ def _image(t) -> Image:
     return Image(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0), 1 if t.is_cuda else 0)
 
 
-STAGES = ("select", "recheck", "bucket", "wiener", "ola_update", "prep")
+STAGES = ("select", "recheck", "bucket", "wiener", "ola_update", "prep", "propose", "fallback")
 
 
-def _options(precision="fp32", recheck=True, init=None, stream=None, profile=False) -> Options:
+def _options(precision="fp32", recheck=True, init=None, stream=None, profile=False,
+             proposal=False, top_m=8, margin=0.5) -> Options:
     o = Options()
     lib().fepll_options_default(ctypes.byref(o))
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
@@ -116,6 +147,9 @@ def _options(precision="fp32", recheck=True, init=None, stream=None, profile=Fal
         o.init = ctypes.pointer(o._init_img)
     o.stream = stream
     o.profile = 1 if profile else 0
+    o.use_proposal = 1 if proposal else 0
+    o.top_m = int(top_m)
+    o.margin_nats = float(margin)
     return o
 
 
@@ -147,6 +181,11 @@ class GMM:
     def handle(self):
         return self._h
 
+    def load_proposal(self, blob: bytes):
+        """Attach a serialized proposal network (see MLP.serialize)."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _check(lib().fepll_gmm_load_proposal(self._h, buf, len(blob)))
+
     def close(self):
         if getattr(self, "_h", None):
             lib().fepll_gmm_destroy(self._h)
@@ -161,14 +200,15 @@ class GMM:
 
 def profile(gmm: GMM):
     """Stage times (ms) and launch counts accumulated since the last read."""
-    ms = (c_double * 6)()
-    n = (c_int32 * 6)()
-    _check(lib().fepll_profile(gmm.handle, ms, n, 6))
+    ms = (c_double * 8)()
+    n = (c_int32 * 8)()
+    _check(lib().fepll_profile(gmm.handle, ms, n, 8))
     return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
 
 
 def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
-            recheck=True, return_labels=False, out=None, profile=False):
+            recheck=True, return_labels=False, out=None, profile=False, proposal=False,
+            top_m=8, margin=0.5):
     """Denoise y (2-D float32 torch tensor, CUDA or CPU, or numpy array).
 
     betas: absolute beta values (default {1,4,8,16,32}/sigma^2).
@@ -180,7 +220,7 @@ def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
     if out is None:
         out = torch.empty_like(y) if isinstance(y, torch.Tensor) else np.empty_like(y)
     oi = _image(out)
-    o = _options(precision, recheck, init, _stream_of(y), profile)
+    o = _options(precision, recheck, init, _stream_of(y), profile, proposal, top_m, margin)
     if betas is None:
         bptr, T = None, 0
         Tn = 5
@@ -202,7 +242,8 @@ def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
     return (out, labels) if return_labels else out
 
 
-def select(gmm: GMM, x, beta: float, recheck=True, precision="fp32"):
+def select(gmm: GMM, x, beta: float, recheck=True, precision="fp32", proposal=False, top_m=8,
+           margin=0.5):
     """One Gaussian-selection step on the CUDA image x.
     Returns (labels int32, best f32, second f32, flags int32), each of
     length (H-7)*(W-7)."""
@@ -214,8 +255,116 @@ def select(gmm: GMM, x, beta: float, recheck=True, precision="fp32"):
     best = torch.empty(Np, dtype=torch.float32, device=dev)
     second = torch.empty(Np, dtype=torch.float32, device=dev)
     flags = torch.empty(Np, dtype=torch.int32, device=dev)
-    o = _options(precision, recheck, None, _stream_of(x))
+    o = _options(precision, recheck, None, _stream_of(x), False, proposal, top_m, margin)
     _check(lib().fepll_select(gmm.handle, ctypes.byref(xi), float(beta), lab.data_ptr(),
                               best.data_ptr(), second.data_ptr(), flags.data_ptr(),
                               ctypes.byref(o)))
     return lab, best, second, flags
+
+
+def propose(gmm: GMM, x, beta: float, top_m: int = 8):
+    """Candidates of the attached network for every patch of the CUDA image x:
+    (Np, 8) int32, -1 after the top_m-th."""
+    import torch
+    xi = _image(x)
+    Np = (x.shape[0] - 7) * (x.shape[1] - 7)
+    cand = torch.empty((Np, 8), dtype=torch.int16, device=x.device)
+    _check(lib().fepll_propose(gmm.handle, ctypes.byref(xi), float(beta), int(top_m),
+                               cand.data_ptr(), _stream_of(x)))
+    c = cand.to(torch.int32) & 0xFFFF
+    c[c == 0xFFFF] = -1
+    return c
+
+
+def features(x, beta: float):
+    """Network input [z~/128, log sigma_beta] of every patch of CUDA image x."""
+    import torch
+    xi = _image(x)
+    Np = (x.shape[0] - 7) * (x.shape[1] - 7)
+    X = torch.empty((Np, 65), dtype=torch.float32, device=x.device)
+    _check(lib().fepll_features(ctypes.byref(xi), float(beta), X.data_ptr(), _stream_of(x)))
+    return X
+
+
+PARAM_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+
+def flatten_params(p: dict) -> np.ndarray:
+    """W1 b1 W2 b2 W3 b3 (W as (out, in)) into one float32 vector."""
+    return np.concatenate([np.asarray(p[k], np.float32).ravel() for k in PARAM_NAMES])
+
+
+def unflatten_params(v: np.ndarray, K: int) -> dict:
+    shapes = {"W1": (256, 65), "b1": (256,), "W2": (256, 256), "b2": (256,), "W3": (K, 256),
+              "b3": (K,)}
+    out, o = {}, 0
+    for k in PARAM_NAMES:
+        n = int(np.prod(shapes[k]))
+        out[k] = np.asarray(v[o:o + n]).reshape(shapes[k])
+        o += n
+    return out
+
+
+class MLP:
+    """Proposal network handle (float32 parameters on the device)."""
+
+    def __init__(self, K: int, params, max_batch: int = 4096):
+        v = params if isinstance(params, np.ndarray) else flatten_params(params)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        if v.size != lib().fepll_mlp_param_count(K):
+            raise ValueError("parameter vector has the wrong length")
+        h = c_void_p()
+        _check(lib().fepll_mlp_create(K, v.ctypes.data, int(max_batch), ctypes.byref(h)))
+        self._h = h
+        self.K = K
+        self.max_batch = max_batch
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fepll_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        v = np.empty(lib().fepll_mlp_param_count(self.K), np.float32)
+        _check(lib().fepll_mlp_get_params(self._h, v.ctypes.data))
+        return v
+
+    def forward(self, X):
+        import torch
+        n = X.shape[0]
+        out = torch.empty((n, self.K), dtype=torch.float32, device=X.device)
+        _check(lib().fepll_mlp_forward(self._h, X.data_ptr(), n, out.data_ptr(), _stream_of(X)))
+        return out
+
+    def loss_grad(self, X, y):
+        import torch
+        g = torch.empty(lib().fepll_mlp_param_count(self.K), dtype=torch.float32,
+                        device=X.device)
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(lib().fepll_mlp_loss_grad(self._h, X.data_ptr(), y.data_ptr(), X.shape[0],
+                                         g.data_ptr(), loss.data_ptr(), _stream_of(X)))
+        return loss, g
+
+    def train_step(self, X, y, rows=None, n=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                   weight_decay=1e-4, loss=None):
+        hp = AdamW(lr, beta1, beta2, eps, weight_decay)
+        if n is None:
+            n = rows.shape[0] if rows is not None else X.shape[0]
+        _check(lib().fepll_mlp_train_step(self._h, X.data_ptr(), y.data_ptr(),
+                                          rows.data_ptr() if rows is not None else None, int(n),
+                                          ctypes.byref(hp),
+                                          loss.data_ptr() if loss is not None else None,
+                                          _stream_of(X)))
+
+    def serialize(self) -> bytes:
+        nb = ctypes.c_size_t()
+        _check(lib().fepll_mlp_serialize(self._h, None, 0, ctypes.byref(nb)))
+        buf = ctypes.create_string_buffer(nb.value)
+        _check(lib().fepll_mlp_serialize(self._h, buf, nb.value, ctypes.byref(nb)))
+        return buf.raw[:nb.value]

@@ -12,45 +12,31 @@
 
 #include "common.h"
 #include "fepll.h"
+#include "internal.h"
+#include "propose.h"
 
 using namespace fepll;
 
-namespace {
-
-thread_local std::string g_err;
-
-fepll_status fail(fepll_status s, const std::string& msg) {
-  g_err = msg;
-  return s;
+namespace fepll {
+fepll_status parse_proposal_blob(const void* blob, size_t nbytes, int K, std::vector<float>& params);
 }
 
-#define HIPX(call)                                                                        \
-  do {                                                                                    \
-    hipError_t e_ = (call);                                                               \
-    if (e_ != hipSuccess)                                                                 \
-      return fail(e_ == hipErrorOutOfMemory ? FEPLL_ENOMEM : FEPLL_EDEVICE,               \
-                  std::string(#call) + ": " + hipGetErrorString(e_));                     \
-  } while (0)
+namespace {
+thread_local std::string g_err;
 
 __global__ void zero_i32_kernel(int32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
 }
-
-template <class T>
-hipError_t dalloc(T** p, size_t n) {
-  *p = nullptr;
-  if (n == 0) return hipSuccess;
-  return hipMalloc((void**)p, n * sizeof(T));
-}
-
-template <class T>
-void dfree(T*& p) {
-  if (p) (void)hipFree(p);
-  p = nullptr;
-}
-
 }  // namespace
+
+namespace fepll {
+fepll_status fail(fepll_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+void clear_error() { g_err.clear(); }
+}  // namespace fepll
 
 struct fepll_gmm {
   int K = 0;
@@ -80,6 +66,12 @@ struct fepll_gmm {
   float* ybuf = nullptr;
   float* xa = nullptr;
   float* xb = nullptr;
+  // proposal network (bfloat16 inference layout) and its scratch
+  uint16_t* pWb = nullptr;
+  float* pbias = nullptr;
+  bool has_proposal = false;
+  uint16_t* cand = nullptr;   // Np x 8
+  int32_t* fb_list = nullptr;  // Np
   hipStream_t last_stream = nullptr;
   bool used = false;
   // profiling: events recorded around stages, resolved in fepll_profile
@@ -94,7 +86,7 @@ struct fepll_gmm {
 
 namespace {
 
-constexpr int kStages = 6;
+constexpr int kStages = 8;
 
 hipEvent_t take_event(fepll_gmm* g) {
   if (!g->pool.empty()) {
@@ -179,6 +171,8 @@ fepll_status ensure_ws(fepll_gmm* g, int H, int W) {
     dfree(g->seg);
     dfree(g->perm);
     dfree(g->Zhat);
+    dfree(g->cand);
+    dfree(g->fb_list);
     g->np_cap = 0;
     const size_t nb = (Np + kSortBlock - 1) / kSortBlock;
     HIPX(dalloc(&g->labels, Np));
@@ -188,6 +182,8 @@ fepll_status ensure_ws(fepll_gmm* g, int H, int W) {
     HIPX(dalloc(&g->seg, 3 * (size_t)g->K + 3));
     HIPX(dalloc(&g->perm, Np));
     HIPX(dalloc(&g->Zhat, Np * kP));
+    HIPX(dalloc(&g->cand, Np * 8));
+    HIPX(dalloc(&g->fb_list, Np));
     g->np_cap = Np;
   }
   if (px > g->px_cap) {
@@ -243,24 +239,74 @@ fepll_status check_opt(const fepll_gmm* g, const fepll_options* o) {
     return fail(FEPLL_EINVAL, "options.precision must be FEPLL_FP32, FEPLL_BF16 or FEPLL_FP8");
   if (o->precision == FEPLL_FP8)
     return fail(FEPLL_EUNSUPPORTED, "FEPLL_FP8 projections are not built in this library");
-  if (o->use_proposal) return fail(FEPLL_EUNSUPPORTED, "no proposal network is loaded");
-  if (o->use_proposal && (o->top_m < 1 || o->top_m > g->K))
-    return fail(FEPLL_EINVAL, "options.top_m out of 1..K");
+  if (o->use_proposal) {
+    if (!g->has_proposal) return fail(FEPLL_EINVAL, "no proposal network is loaded");
+    if (o->top_m < 1 || o->top_m > 8 || o->top_m > g->K)
+      return fail(FEPLL_EINVAL, "options.top_m out of 1..min(8, K)");
+    if (o->precision != FEPLL_BF16)
+      return fail(FEPLL_EUNSUPPORTED, "the proposal path runs with FEPLL_BF16 projections");
+  }
   if (std::isnan(o->margin_nats)) return fail(FEPLL_EINVAL, "options.margin_nats is NaN");
   return FEPLL_OK;
 }
 
 // One Gaussian selection (E-step + optional float64 recheck) of image x.
+__global__ void mark_kernel(const int32_t* count, const int32_t* list, int32_t* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < *count) flags[list[i]] = 1;
+}
+
 fepll_status run_select(fepll_gmm* g, const float* x, int H, int W, int t, double beta,
-                        int precision, bool recheck, int32_t* labels, float* best,
-                        float* second, int32_t* flags, hipStream_t st) {
+                        int precision, bool recheck, const fepll_options* prop, int32_t* labels,
+                        float* best, float* second, int32_t* flags, hipStream_t st) {
   const int Np = (H - 7) * (W - 7);
   const size_t K = g->K;
   if (precision == FEPLL_BF16) {
-    StageTimer tm(g, 0, st);
-    HIPX(launch_estep_bf16(x, H, W, g->Ub + (size_t)t * K * kTileStride,
-                           g->L32 + (size_t)t * K, g->K, labels, best, second, st));
-    if (flags) HIPX(hipMemsetAsync(flags, 0, sizeof(int32_t) * Np, st));
+    if (flags) {
+      hipLaunchKernelGGL(zero_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, flags, Np);
+      HIPX(hipGetLastError());
+    }
+    if (!prop) {
+      StageTimer tm(g, 0, st);
+      HIPX(launch_estep_bf16(x, H, W, g->Ub + (size_t)t * K * kTileStride,
+                             g->L32 + (size_t)t * K, g->K, labels, best, second, st));
+      return FEPLL_OK;
+    }
+    {
+      StageTimer tm(g, 6, st);
+      HIPX(launch_propose_bf16(x, H, W, beta, g->pWb, g->pbias, g->K, prop->top_m, g->cand, st));
+    }
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, g->count, 1);
+    HIPX(hipGetLastError());
+    BF16Args a{};
+    a.x = x;
+    a.H = H;
+    a.W = W;
+    a.Ub = g->Ub + (size_t)t * K * kTileStride;
+    a.L = g->L32 + (size_t)t * K;
+    a.K = g->K;
+    a.labels = labels;
+    a.best = best;
+    a.second = second;
+    a.cand = reinterpret_cast<const uint4*>(g->cand);
+    a.margin = (float)prop->margin_nats;
+    a.fb_count = g->count;
+    a.fb_list = g->fb_list;
+    a.list_count = g->count;
+    a.list = g->fb_list;
+    {
+      StageTimer tm(g, 0, st);
+      HIPX(launch_estep_bf16_mode(kModeSpatialCand, a, st));
+    }
+    {
+      StageTimer tm(g, 7, st);
+      HIPX(launch_estep_bf16_mode(kModeListFull, a, st));
+    }
+    if (flags) {
+      hipLaunchKernelGGL(mark_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, g->count,
+                         g->fb_list, flags);
+      HIPX(hipGetLastError());
+    }
     return FEPLL_OK;
   }
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, g->count, 1);
@@ -403,6 +449,10 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->seg);
   dfree(g->perm);
   dfree(g->Zhat);
+  dfree(g->cand);
+  dfree(g->fb_list);
+  dfree(g->pWb);
+  dfree(g->pbias);
   dfree(g->ybuf);
   dfree(g->xa);
   dfree(g->xb);
@@ -464,8 +514,9 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, 
   float* xn = g->xb;
   for (int t = 0; t < sch.T; ++t) {
     const double beta = sch.beta[t];
-    if ((s = run_select(g, xc, H, W, t, beta, o.precision, o.recheck != 0, g->labels, nullptr,
-                        nullptr, nullptr, st)) != FEPLL_OK)
+    if ((s = run_select(g, xc, H, W, t, beta, o.precision, o.recheck != 0,
+                        o.use_proposal ? &o : nullptr, g->labels, nullptr, nullptr, nullptr,
+                        st)) != FEPLL_OK)
       return s;
     if (labels_out)
       HIPX(hipMemcpyAsync(labels_out + (size_t)t * Np, g->labels, sizeof(int32_t) * Np,
@@ -488,6 +539,47 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, 
   HIPX(copy_out(out, xc, st));
   if (!out->on_device || !y->on_device || (labels_out && !y->on_device))
     HIPX(hipStreamSynchronize(st));
+  return FEPLL_OK;
+}
+
+fepll_status fepll_gmm_load_proposal(fepll_gmm* g, const void* blob, size_t nbytes) {
+  g_err.clear();
+  if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
+  std::vector<float> params;
+  fepll_status s = parse_proposal_blob(blob, nbytes, g->K, params);
+  if (s != FEPLL_OK) return s;
+  std::vector<uint16_t> wb(proposal_wb_count(g->K));
+  std::vector<float> bias(proposal_bias_count(g->K));
+  pack_proposal(params.data(), g->K, wb.data(), bias.data());
+  HIPX(hipDeviceSynchronize());
+  dfree(g->pWb);
+  dfree(g->pbias);
+  g->has_proposal = false;
+  HIPX(dalloc(&g->pWb, wb.size()));
+  HIPX(dalloc(&g->pbias, bias.size()));
+  HIPX(hipMemcpy(g->pWb, wb.data(), wb.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  HIPX(hipMemcpy(g->pbias, bias.data(), bias.size() * sizeof(float), hipMemcpyHostToDevice));
+  g->has_proposal = true;
+  return FEPLL_OK;
+}
+
+fepll_status fepll_propose(fepll_gmm* g, const fepll_image* x, double beta, int32_t top_m,
+                           uint16_t* cand, void* stream) {
+  g_err.clear();
+  if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
+  fepll_status s;
+  if ((s = check_image(x, "x")) != FEPLL_OK) return s;
+  if (!x->on_device) return fail(FEPLL_EINVAL, "fepll_propose takes a device image");
+  if (!cand) return fail(FEPLL_EINVAL, "cand is NULL");
+  if (!g->has_proposal) return fail(FEPLL_EINVAL, "no proposal network is loaded");
+  if (top_m < 1 || top_m > 8 || top_m > g->K) return fail(FEPLL_EINVAL, "top_m out of range");
+  if (!(beta > 0.0) || !std::isfinite(beta)) return fail(FEPLL_EINVAL, "beta must be > 0");
+  const int H = x->height, W = x->width;
+  hipStream_t st = (hipStream_t)stream;
+  if ((s = use_stream(g, st)) != FEPLL_OK) return s;
+  if ((s = ensure_ws(g, H, W)) != FEPLL_OK) return s;
+  HIPX(copy_in(g->xa, x, st));
+  HIPX(launch_propose_bf16(g->xa, H, W, beta, g->pWb, g->pbias, g->K, top_m, cand, st));
   return FEPLL_OK;
 }
 
@@ -514,8 +606,8 @@ fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta, int32
   sch.beta[0] = beta;
   if ((s = ensure_consts(g, sch, st)) != FEPLL_OK) return s;
   HIPX(copy_in(g->xa, x, st));
-  return run_select(g, g->xa, H, W, 0, beta, o.precision, o.recheck != 0, labels, best, second,
-                    flags, st);
+  return run_select(g, g->xa, H, W, 0, beta, o.precision, o.recheck != 0,
+                    o.use_proposal ? &o : nullptr, labels, best, second, flags, st);
 }
 
 }  // extern "C"

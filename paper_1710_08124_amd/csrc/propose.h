@@ -1,0 +1,45 @@
+// Internal declarations of the proposal path (bfloat16 selection modes and
+// the fused network inference).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace fepll {
+
+enum { kModeSpatialFull = 0, kModeSpatialCand = 1, kModeListFull = 2 };
+
+struct BF16Args {
+  const float* x;         // current image, H x W contiguous
+  int H, W;
+  const uint16_t* Ub;     // bfloat16 operand table of this beta
+  const float* L;         // L_k of this beta
+  int K;
+  int32_t* labels;        // Np
+  float* best;            // Np or NULL
+  float* second;          // Np or NULL
+  const uint4* cand;      // candidates mode: Np x 8 uint16 (0xffff = none)
+  float margin;           // candidates mode: fallback when half the gap < margin
+  int32_t* fb_count;      // candidates mode: fallback list length (device)
+  int32_t* fb_list;       // candidates mode: fallback list (Np)
+  const int32_t* list_count;  // list mode: list length (device)
+  const int32_t* list;        // list mode: patch indices
+};
+
+hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st);
+
+// Network inference + top-m: cand[i] gets the m best classes of patch i in
+// decreasing logit order (ties to the lower class), 0xffff after the m-th.
+// Wb / bias: see propose.hip.
+hipError_t launch_propose_bf16(const float* x, int H, int W, double beta, const uint16_t* Wb,
+                               const float* bias, int K, int m, uint16_t* cand, hipStream_t st);
+
+// Host-side packing of float32 parameters into the inference layouts.
+// Returns the number of uint16 entries of Wb and fills wb / bias.
+void pack_proposal(const float* params, int K, uint16_t* wb, float* bias);
+size_t proposal_wb_count(int K);
+size_t proposal_bias_count(int K);
+
+}  // namespace fepll

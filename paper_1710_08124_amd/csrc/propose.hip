@@ -1,0 +1,252 @@
+// Proposal network inference (bfloat16 MFMA, float32 accumulation) fused
+// with the top-m selection of its logits.
+//
+// The three layers run in transposed form, H^t = W X^t: hidden units (or
+// classes) on the MFMA rows, 32 patches on the columns.  The 32x32 output of
+// v_mfma_f32_32x32x16_bf16 leaves lane l with patch (l & 31) and units
+// 8 g + 4 (l >> 5) + e (g, e = 0..3); the next layer's B operand needs units
+// 16 s + 8 (l >> 5) + 0..7, so one exchange between lanes l and l ^ 32 per
+// group pair re-packs every activation in registers: no activation ever
+// leaves the wave.  The layer-1 B operand is the patch itself (one 8-pixel
+// patch row per depth step, as in the selection kernels) plus the
+// log sigma_beta feature.
+//
+// A workgroup of 8 waves owns 256 patches (8 patch rows x 32 columns) and
+// streams the 23 weight slabs (one slab = one 32-row block of a layer, all
+// depth steps, already in MFMA operand order) through double-buffered LDS,
+// so each weight byte read from L2 serves 256 patches.
+//
+// Top-m: each lane keeps the 8 largest ranking keys (logit, then lower
+// class) of its 112 classes in sorted registers, then merges with lane
+// l ^ 32.
+#include "common.h"
+#include "mlp.h"
+#include "propose.h"
+
+namespace fepll {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+__device__ __forceinline__ uint32_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ __forceinline__ uint32_t pack2(float a, float b) {
+  return bf16_rne(a) | (bf16_rne(b) << 16);
+}
+__device__ __forceinline__ f32x16 mfma_bf16(uint4 a, uint4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ float gelu(float a) {
+  return 0.5f * a * (1.f + erff(a * 0.70710678118654752f));
+}
+
+// Ranking key of a logit: an order-preserving map of the float to uint32,
+// its 10 low bits replaced by (1023 - class).  Keys compare like
+// (logit, -class) with the logit truncated to 22 significant bits of its
+// order (sign, exponent, 13 mantissa bits): ties within 2^-13 relative go to
+// the lower class.  Every compare-exchange is then one max and one min.
+__device__ __forceinline__ uint32_t rank_key(float v, int cls) {
+  const uint32_t u = __float_as_uint(v);
+  const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return (o & ~1023u) | (uint32_t)(1023 - cls);
+}
+__device__ __forceinline__ int key_class(uint32_t k) { return 1023 - (int)(k & 1023u); }
+
+struct Top8 {
+  uint32_t t[8];  // descending
+  __device__ void init() {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) t[i] = 0u;
+  }
+  __device__ void insert(uint32_t x) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const uint32_t hi = max(t[i], x);
+      x = min(t[i], x);
+      t[i] = hi;
+    }
+  }
+};
+
+constexpr int kWaves = 8;
+constexpr int kSlabU4 = 16 * 64;  // uint4 of the largest slab (16 depth steps x 64 lanes)
+
+// activation epilogue of one 32-row block: bias + GELU, then re-pack as
+// the two depth steps (2 nt, 2 nt + 1) of the next layer's B operand
+__device__ __forceinline__ void hidden_epilogue(const f32x16& acc, const float* __restrict__ bias,
+                                                int nt, int half, uint4& s0, uint4& s1) {
+  float h[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int unit = 32 * nt + 8 * (i >> 2) + 4 * half + (i & 3);
+    h[i] = gelu(acc[i] + bias[unit]);
+  }
+  float lo[8], hi[8];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    // groups 0/1 -> depth step 2 nt, groups 2/3 -> depth step 2 nt + 1
+    const float a0 = h[e], a1 = h[4 + e], a2 = h[8 + e], a3 = h[12 + e];
+    const float r01 = __shfl_xor(half ? a0 : a1, 32);
+    const float r23 = __shfl_xor(half ? a2 : a3, 32);
+    lo[e] = half ? r01 : a0;
+    lo[4 + e] = half ? a1 : r01;
+    hi[e] = half ? r23 : a2;
+    hi[4 + e] = half ? a3 : r23;
+  }
+  s0 = make_uint4(pack2(lo[0], lo[1]), pack2(lo[2], lo[3]), pack2(lo[4], lo[5]),
+                  pack2(lo[6], lo[7]));
+  s1 = make_uint4(pack2(hi[0], hi[1]), pack2(hi[2], hi[3]), pack2(hi[4], hi[5]),
+                  pack2(hi[6], hi[7]));
+}
+
+}  // namespace
+
+// Wb: all slabs back to back, uint4 in MFMA A-operand order:
+//   layer 1: 8 slabs x 5 depth steps, layer 2: 8 x 16, layer 3: n3 x 16.
+// bias: b1 (256) b2 (256) b3 (32 n3, -inf beyond K).
+__global__ __launch_bounds__(512, 1) void propose_bf16_kernel(
+    const float* __restrict__ x, int H, int W, float logsb, const uint4* __restrict__ Wb,
+    const float* __restrict__ bias, int n3, int K, int m, uint16_t* __restrict__ cand) {
+  __shared__ uint4 slab[2][kSlabU4];  // 32 KB
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int half = lane >> 5;
+  const int col = lane & 31;
+  const int Hp = H - 7, Wp = W - 7;
+  const int r = blockIdx.y * kWaves + wave;
+  const int c = blockIdx.x * 32 + col;
+  const int rr = min(r, Hp - 1), cc = min(c, Wp - 1);
+
+  // ---- layer-1 input: DC-removed patch / 128 and log sigma_beta
+  uint4 xb[5];
+  {
+    float v[4][8];
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const float* row = x + (size_t)(rr + 2 * t + half) * W + cc;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        v[t][e] = row[e];
+        s += (double)v[t][e];
+      }
+    }
+    s += __shfl_xor(s, 32);
+    const double mean = s * (1.0 / 64.0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      float d[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) d[e] = (float)(((double)v[t][e] - mean) * (1.0 / kScaleIn));
+      xb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),
+                         pack2(d[6], d[7]));
+    }
+    xb[4] = make_uint4(half ? 0u : bf16_rne(logsb), 0u, 0u, 0u);
+  }
+
+  // slab schedule: q -> (layer, nt); offsets and sizes in uint4
+  const int nslab = 16 + n3;
+  auto slab_off = [&](int q) -> int {
+    if (q < 8) return q * 5 * 64;
+    if (q < 16) return 8 * 5 * 64 + (q - 8) * 16 * 64;
+    return 8 * 5 * 64 + 8 * 16 * 64 + (q - 16) * 16 * 64;
+  };
+  auto slab_len = [&](int q) -> int { return (q < 8 ? 5 : 16) * 64; };
+  uint4 pre[2];
+  auto fetch = [&](int q) {
+    const int off = slab_off(q), len = slab_len(q);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int i = threadIdx.x + j * 512;
+      if (i < len) pre[j] = Wb[off + i];
+    }
+  };
+  // make slab q resident in LDS buffer q & 1 and start fetching slab q + 1
+  auto stage = [&](int q) {
+    const int len = slab_len(q);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int i = threadIdx.x + j * 512;
+      if (i < len) slab[q & 1][i] = pre[j];
+    }
+    __syncthreads();
+    if (q + 1 < nslab) fetch(q + 1);
+  };
+  fetch(0);
+  uint4 h1[16], h2[16];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    stage(q);
+    const uint4* A = slab[q & 1] + lane;
+    f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 5; ++s) acc = mfma_bf16(A[s * 64], xb[s], acc);
+    hidden_epilogue(acc, bias, q, half, h1[2 * q], h1[2 * q + 1]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 8; q < 16; ++q) {
+    stage(q);
+    const uint4* A = slab[q & 1] + lane;
+    f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = mfma_bf16(A[s * 64], h1[s], acc);
+    hidden_epilogue(acc, bias + kHidden, q - 8, half, h2[2 * (q - 8)], h2[2 * (q - 8) + 1]);
+    __syncthreads();
+  }
+  Top8 top;
+  top.init();
+  const float* b3 = bias + 2 * kHidden;
+  for (int q = 16; q < nslab; ++q) {
+    stage(q);
+    const uint4* A = slab[q & 1] + lane;
+    f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) acc = mfma_bf16(A[s * 64], h2[s], acc);
+    const int nt = q - 16;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int cls = 32 * nt + 8 * (i >> 2) + 4 * half + (i & 3);
+      const float v = acc[i] + b3[cls];
+      top.insert(cls < K ? rank_key(v, cls) : 0u);
+    }
+    __syncthreads();
+  }
+  // merge the two halves' lists
+  // take the partner's whole list before inserting, so no key comes back twice
+  uint32_t other[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) other[i] = __shfl_xor(top.t[i], 32);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) top.insert(other[i]);
+  if (!half && r < Hp && c < Wp) {
+    const size_t idx = (size_t)r * Wp + c;
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t a = (2 * i < m) ? (uint32_t)key_class(top.t[2 * i]) : 0xffffu;
+      const uint32_t b = (2 * i + 1 < m) ? (uint32_t)key_class(top.t[2 * i + 1]) : 0xffffu;
+      w[i] = a | (b << 16);
+    }
+    reinterpret_cast<uint4*>(cand)[idx] = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+}
+
+hipError_t launch_propose_bf16(const float* x, int H, int W, double beta, const uint16_t* Wb,
+                               const float* bias, int K, int m, uint16_t* cand, hipStream_t st) {
+  const int Hp = H - 7, Wp = W - 7;
+  const int n3 = (K + 31) / 32;
+  dim3 grid((Wp + 31) / 32, (Hp + kWaves - 1) / kWaves);
+  hipLaunchKernelGGL(propose_bf16_kernel, grid, dim3(512), 0, st, x, H, W,
+                     (float)(-0.5 * log(beta)), reinterpret_cast<const uint4*>(Wb), bias, n3, K,
+                     m, cand);
+  return hipGetLastError();
+}
+
+}  // namespace fepll

@@ -1,0 +1,140 @@
+"""Training of the component-proposal network.
+
+The training pairs are produced by the method itself: the plain float32
+path (exact labels: certified float32 selection with float64 re-selection)
+runs the five HQS iterations on seeded synthetic images with sigma ~ U[5, 50]
+and records, for every patch and iteration, the network input
+[z~/128, log sigma_beta] and the selected component.  Training runs on the
+GPU through the library's own kernels (forward, softmax cross-entropy,
+backward, AdamW); PyTorch only holds the buffers and draws the minibatch
+order.
+
+    python -m paper_1710_08124_amd.proposal --out proposal.bin
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_BLOB = os.path.join(HERE, "data", "proposal_k200_gmm12.bin")
+SCHEDULE = (1.0, 4.0, 8.0, 16.0, 32.0)
+
+
+def training_pairs(gmm, images, log=print):
+    """(X, labels) on the GPU for every patch and HQS iteration of images
+    (dicts with 'y' and 'sigma'), labels from the exact float32 selection."""
+    import torch
+
+    from . import features, restore, select
+    Xs, ys = [], []
+    for n, im in enumerate(images):
+        y = torch.from_numpy(np.asarray(im["y"], np.float32)).cuda()
+        sigma = float(im["sigma"])
+        x = y.clone()
+        for b in SCHEDULE:
+            beta = b / sigma ** 2
+            Xs.append(features(x, beta))
+            lab, _, _, _ = select(gmm, x, beta)
+            ys.append(lab)
+            x = restore(gmm, y, sigma, betas=[beta], init=x)
+        log(f"pairs: image {n + 1}/{len(images)} sigma={sigma:.2f}")
+    torch.cuda.synchronize()
+    return torch.cat(Xs), torch.cat(ys)
+
+
+def train(K, X, y, epochs=8, batch=4096, lr=2e-3, weight_decay=1e-4, seed=0, init_seed=700,
+          log=print):
+    """AdamW with a cosine learning-rate decay; returns the MLP handle."""
+    import torch
+
+    import fepll_synth as fs
+
+    from . import MLP
+    net = MLP(K, fs.mlp_init(K, init_seed), max_batch=batch)
+    N = int(X.shape[0])
+    per_epoch = N // batch
+    total = epochs * per_epoch
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+    t0 = time.perf_counter()
+    step = 0
+    for ep in range(epochs):
+        perm = torch.randperm(N, generator=gen).to(torch.int32).to(X.device)
+        acc = 0.0
+        for i in range(per_epoch):
+            lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * step / total))
+            want = (i % 64 == 0)
+            net.train_step(X, y, rows=perm[i * batch:(i + 1) * batch], n=batch, lr=lr_t,
+                           weight_decay=weight_decay, loss=loss if want else None)
+            if want:
+                acc = float(loss.item())
+            step += 1
+        log(f"epoch {ep + 1}/{epochs} loss {acc:.4f} ({time.perf_counter() - t0:.1f} s)")
+    return net
+
+
+def evaluate(gmm, images, top_m=8, margin=0.5, log=print):
+    """Recall of the exact label in the top-m, fallback rate and label
+    agreement of the proposal path on held-out images (first iteration)."""
+    import torch
+
+    from . import propose, select
+    rec, fb, agree, n = 0.0, 0.0, 0.0, 0
+    for im in images:
+        y = torch.from_numpy(np.asarray(im["y"], np.float32)).cuda()
+        beta = 1.0 / float(im["sigma"]) ** 2
+        exact, _, _, _ = select(gmm, y, beta)
+        cand = propose(gmm, y, beta, top_m)
+        lab, _, _, flags = select(gmm, y, beta, precision="bf16", proposal=True, top_m=top_m,
+                                  margin=margin)
+        m = exact.shape[0]
+        rec += float((cand == exact[:, None].to(cand.dtype)).any(dim=1).float().sum())
+        fb += float(flags.float().sum())
+        agree += float((lab == exact).float().sum())
+        n += m
+    res = {"recall_top_m": rec / n, "fallback": fb / n, "agreement": agree / n}
+    log(f"held-out: {res}")
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=DEFAULT_BLOB)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--images", type=int, default=13)
+    ap.add_argument("--size", type=int, default=256)
+    args = ap.parse_args(argv)
+
+    import torch  # noqa: F401
+
+    import fepll_synth as fs
+
+    from . import GMM
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    U, lam, w = fs.gmm(200, 12)
+    g = GMM(U, lam, w)
+    imgs = fs.training_images(range(300, 300 + args.images), args.size)
+    X, y = training_pairs(g, imgs, log)
+    log(f"training pairs: {X.shape[0]}")
+    net = train(200, X, y, epochs=args.epochs, log=log)
+    blob = net.serialize()
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "wb") as f:
+        f.write(blob)
+    log(f"wrote {args.out} ({len(blob)} bytes)")
+    g.load_proposal(blob)
+    held = fs.training_images(range(400, 402), args.size, sigma_seed=601)
+    evaluate(g, held, log=log)
+
+
+if __name__ == "__main__":
+    main()

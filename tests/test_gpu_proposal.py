@@ -1,0 +1,276 @@
+"""The learned proposal on the GPU: network kernels against the FP64
+reference (features, forward, gradients, AdamW), serialization, the
+degenerate settings that must reproduce the full search bit for bit, the
+validity of the proposal decisions against exact costs, and what a trained
+network gains over an untrained one."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import fepll_synth as fs
+from oracle import epll64 as o
+from oracle import mlp64 as M
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_1710_08124_amd as F
+    F.lib()
+    return F
+
+
+def dev(a, dtype=np.float32):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).cuda()
+
+
+def f32(a):
+    return np.asarray(a, np.float32).astype(np.float64)
+
+
+def oracle_features(x, beta):
+    r, c = o.patch_corners(*x.shape)
+    Zt, _ = o.remove_dc(o.extract(x, r, c))
+    return M.features(Zt, beta)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_features_match_oracle(F):
+    x = f32(fs.test_image(40, 52, 9))
+    beta = 4.0 / 400.0
+    got = F.features(dev(x), beta).cpu().numpy().astype(np.float64)
+    want = oracle_features(x, beta)
+    np.testing.assert_allclose(got, want, rtol=0, atol=2e-6)
+
+
+def test_forward_matches_oracle(F):
+    K = 37
+    p = fs.mlp_init(K, 5)
+    X = fs.rng(6).normal(0, 1, (1000, 65))
+    net = F.MLP(K, p, max_batch=384)           # forward is chunked over 384 rows
+    got = net.forward(dev(X)).cpu().numpy().astype(np.float64)
+    pf = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in p.items()}
+    want, _ = M.forward(pf, f32(X))
+    assert rel_l2(got, want) < 1e-5
+
+
+def test_gradients_match_oracle(F):
+    """Float32 GPU gradients within 1e-3 per-tensor relative L2 of FP64."""
+    K = 200
+    p = fs.mlp_init(K, 8)
+    g = fs.rng(9)
+    X = g.normal(0, 0.5, (777, 65))
+    y = g.integers(0, K, 777)
+    net = F.MLP(K, p, max_batch=1024)
+    loss, grad = net.loss_grad(dev(X), dev(y, np.int32))
+    pf = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in p.items()}
+    wl, wg = M.loss_and_grad(pf, f32(X), y)
+    assert abs(float(loss.item()) - wl) < 1e-5 * max(1.0, wl)
+    gg = F.unflatten_params(grad.cpu().numpy().astype(np.float64), K)
+    for k in M.NAMES:
+        e = rel_l2(gg[k], wg[k])
+        print(k, e)
+        assert e < 1e-3, (k, e)
+
+
+def test_adamw_steps_match_oracle(F):
+    K = 16
+    p = fs.mlp_init(K, 11)
+    g = fs.rng(12)
+    X = g.normal(0, 1, (300, 65))
+    y = g.integers(0, K, 300)
+    net = F.MLP(K, p, max_batch=512)
+    pf = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in p.items()}
+    m = {k: np.zeros_like(v) for k, v in pf.items()}
+    v = {k: np.zeros_like(x) for k, x in pf.items()}
+    Xd, yd = dev(X), dev(y, np.int32)
+    for t in range(1, 4):
+        net.train_step(Xd, yd, lr=1e-2, weight_decay=0.01)
+        _, gr = M.loss_and_grad(pf, f32(X), y)
+        M.adamw_step(pf, gr, m, v, t, lr=1e-2, wd=0.01)
+    got = F.unflatten_params(net.params().astype(np.float64), K)
+    for k in M.NAMES:
+        assert rel_l2(got[k], pf[k]) < 1e-4, k
+
+
+def test_minibatch_rows_gather(F):
+    K = 10
+    p = fs.mlp_init(K, 13)
+    g = fs.rng(14)
+    X = g.normal(0, 1, (500, 65))
+    y = g.integers(0, K, 500)
+    rows = np.array([3, 499, 17, 17, 250], np.int32)
+    a = F.MLP(K, p, max_batch=64)
+    b = F.MLP(K, p, max_batch=64)
+    a.train_step(dev(X), dev(y, np.int32), rows=dev(rows, np.int32), lr=1e-2)
+    b.train_step(dev(X[rows]), dev(y[rows], np.int32), lr=1e-2)
+    np.testing.assert_array_equal(a.params(), b.params())
+
+
+def test_training_reduces_loss(F):
+    c = fs.config_c1()
+    x = f32(c["y"])
+    beta = 1.0 / 400.0
+    X = oracle_features(x, beta)
+    _, info = o.hqs_iteration(x, x, c["U"], c["lam"], c["w"], 20.0, beta)
+    y = info["labels"]
+    net = F.MLP(20, fs.mlp_init(20, 15), max_batch=512)
+    Xd, yd = dev(X), dev(y, np.int32)
+    l0, _ = net.loss_grad(Xd[:512], yd[:512])
+    gen = torch.Generator().manual_seed(0)
+    for ep in range(30):
+        perm = torch.randperm(X.shape[0], generator=gen).to(torch.int32).cuda()
+        for i in range(X.shape[0] // 512):
+            net.train_step(Xd, yd, rows=perm[i * 512:(i + 1) * 512], lr=3e-3)
+    l1, _ = net.loss_grad(Xd[:512], yd[:512])
+    print("loss", float(l0.item()), "->", float(l1.item()))
+    assert float(l1.item()) < 0.7 * float(l0.item())
+
+
+def test_serialization_and_checksum(F):
+    c = fs.config_c1()
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    net = F.MLP(20, fs.mlp_init(20, 16))
+    blob = net.serialize()
+    assert blob[:8] == b"FEPLLMLP" and len(blob) == 64 + 4 * F.lib().fepll_mlp_param_count(20)
+    g.load_proposal(blob)
+    bad = bytearray(blob)
+    bad[100] ^= 0x40
+    with pytest.raises(F.FepllError) as e:
+        g.load_proposal(bytes(bad))
+    assert e.value.status == -5
+    bad = bytearray(blob)
+    bad[0] = ord("X")
+    with pytest.raises(F.FepllError) as e:
+        g.load_proposal(bytes(bad))
+    assert e.value.status == -1
+    other = F.MLP(21, fs.mlp_init(21, 16)).serialize()
+    with pytest.raises(F.FepllError):
+        g.load_proposal(other)
+    with pytest.raises(F.FepllError):
+        g.load_proposal(blob[:-4])
+
+
+def test_propose_matches_oracle_ranking(F):
+    """bfloat16 inference against the FP64 forward: the top-8 sets agree
+    except where float rounding reorders near-equal logits."""
+    K = 200
+    p = fs.mlp_init(K, 17)
+    for k in ("W1", "W2", "W3"):
+        p[k] = p[k] * 3.0           # spread the logits of the untrained net
+    c = fs.config_c2(25.0)
+    x = f32(c["y"][:60, :90])
+    beta = 4.0 / 625.0
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    g.load_proposal(F.MLP(K, p).serialize())
+    cand = F.propose(g, dev(x), beta, 8).cpu().numpy()
+    pf = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in p.items()}
+    logits, _ = M.forward(pf, oracle_features(x, beta))
+    want = M.topm(logits, 8)
+    overlap = np.mean([len(set(a) & set(b)) / 8.0 for a, b in zip(cand, want)])
+    first = np.mean(cand[:, 0] == want[:, 0])
+    srt = np.sort(logits, axis=1)[:, ::-1]
+    spread = srt[:, 0] - srt[:, -1]
+    tol = 0.01 * spread + 1e-3           # bfloat16 inference error allowance
+    got_l = np.take_along_axis(logits, cand, axis=1)
+    print("top-8 overlap", overlap, "first equal", first)
+    # distinct candidates, each within rounding of the oracle's 8th logit,
+    # and every class clearly inside the oracle's top 8 is proposed
+    assert all(len(set(r)) == 8 for r in cand)
+    assert np.all(got_l >= srt[:, 7:8] - tol[:, None])
+    clear = logits >= (srt[:, 8] + tol)[:, None]
+    for i in range(len(cand)):
+        assert set(np.nonzero(clear[i])[0]) <= set(cand[i])
+    cand4 = F.propose(g, dev(x), beta, 4).cpu().numpy()
+    np.testing.assert_array_equal(cand4[:, :4], cand[:, :4])
+    assert np.all(cand4[:, 4:] == -1)
+
+
+def test_margin_inf_is_bitwise_the_full_search(F):
+    """Threshold +inf: every patch falls back, labels and image are the
+    bfloat16 full-K path's, bit for bit."""
+    c = fs.config_c2(25.0)
+    y = c["y"][:70, :150]
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    g.load_proposal(F.MLP(200, fs.mlp_init(200, 18)).serialize())
+    a, la = F.restore(g, dev(y), 25.0, precision="bf16", return_labels=True)
+    b, lb = F.restore(g, dev(y), 25.0, precision="bf16", proposal=True, margin=math.inf,
+                      return_labels=True)
+    np.testing.assert_array_equal(la.cpu().numpy(), lb.cpu().numpy())
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_top_m_equal_K_is_the_full_search(F):
+    U, lam, w = fs.gmm(8, 19)
+    y = fs.noisy(fs.test_image(48, 80, 20), 20.0, 21)
+    g = F.GMM(U, lam, w)
+    g.load_proposal(F.MLP(8, fs.mlp_init(8, 22)).serialize())
+    a, la = F.restore(g, dev(y), 20.0, precision="bf16", return_labels=True)
+    b, lb = F.restore(g, dev(y), 20.0, precision="bf16", proposal=True, top_m=8, margin=0.5,
+                      return_labels=True)
+    np.testing.assert_array_equal(la.cpu().numpy(), lb.cpu().numpy())
+    np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_proposal_decisions_are_valid(F):
+    """Against exact float64 costs: a patch that did not fall back took a
+    candidate within bfloat16 error of its candidates' exact minimum and had
+    an exact candidate margin above the threshold minus that error; a patch
+    whose exact candidate margin is clearly below the threshold fell back."""
+    c = fs.config_c2(25.0)
+    x = f32(c["y"][300:360, 100:190])
+    beta = 1.0 / 625.0
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    p = fs.mlp_init(200, 23)
+    g.load_proposal(F.MLP(200, p).serialize())
+    cand = F.propose(g, dev(x), beta, 8).cpu().numpy()
+    lab, best, second, fb = F.select(g, dev(x), beta, precision="bf16", proposal=True,
+                                     margin=0.5)
+    lab, fb = lab.cpu().numpy(), fb.cpu().numpy().astype(bool)
+    _, info = o.hqs_iteration(x, x, c["U"], c["lam"], c["w"], 25.0, beta, want_costs=True)
+    cost = info["costs"]
+    cc = np.take_along_axis(cost, cand, axis=1)
+    srt = np.sort(cc, axis=1)
+    exact_gap = 0.5 * (srt[:, 1] - srt[:, 0])
+    tol = 0.02 * np.abs(srt[:, 0]) + 0.5     # bfloat16 cost error allowance
+    keep = ~fb
+    assert np.all([lab[i] in cand[i] for i in np.nonzero(keep)[0]])
+    own = cost[np.arange(len(lab)), lab]
+    assert np.all(own[keep] <= srt[keep, 0] + tol[keep])
+    assert np.all(exact_gap[keep] >= 0.5 - tol[keep])
+    assert np.all(fb[exact_gap < 0.5 - tol])
+    print("fallback", fb.mean(), "kept agree with exact", np.mean(lab[keep] == info["labels"][keep]))
+
+
+def test_trained_network_gain(F):
+    """A network trained on labels of the method itself against the same
+    network untrained: fewer fallbacks, higher recall, same quality."""
+    from paper_1710_08124_amd import proposal as P
+    c = fs.config_c2(25.0, size=512)
+    U, lam, w = c["U"], c["lam"], c["w"]
+    g = F.GMM(U, lam, w)
+    imgs = fs.training_images(range(300, 303), 160)
+    X, y = P.training_pairs(g, imgs, log=print)
+    trained = P.train(200, X, y, epochs=6, batch=2048, lr=3e-3, log=print)
+    untrained = F.MLP(200, fs.mlp_init(200, 700))
+    held = [dict(y=c["y"][:144, :144], sigma=25.0)]
+    g.load_proposal(untrained.serialize())
+    r0 = P.evaluate(g, held, log=print)
+    g.load_proposal(trained.serialize())
+    r1 = P.evaluate(g, held, log=print)
+    assert r1["fallback"] < r0["fallback"]
+    assert r1["recall_top_m"] > r0["recall_top_m"]
+    yy = f32(held[0]["y"])
+    ref = o.restore(yy, U, lam, w, 25.0)
+    got = F.restore(g, dev(yy), 25.0, precision="bf16", proposal=True).cpu().numpy()
+    xs = c["x"][:144, :144]
+    d = o.psnr(xs, ref) - o.psnr(xs, got.astype(np.float64))
+    print("trained proposal dPSNR", d)
+    assert abs(d) <= 0.05
