@@ -1,22 +1,24 @@
-// Stable counting sort of patch indices by their selected component, and
-// the tile list of the grouped patch-estimation GEMM.
+// Counting sort of patch indices by their selected component, and the tile
+// list of the grouped patch-estimation GEMM.
 //
 // Patch estimation (Alg. 1) applies the Wiener filter of the chosen
 // component to each patch.  Grouping the patches by component turns the
 // per-patch 64x64 products into one dense GEMM per component (each filter
 // is loaded once per tile of kWienerTile patches instead of once per patch).
 //
-// Three launches, no atomics on global data:
+// Three launches, no atomics on global data (LDS counters only):
 //  1. hist:    per block of kSortBlock patches, a per-component count
 //              (workgroup-local LDS counters), stored component-major.
 //  2. scan:    one workgroup turns the counts into exclusive offsets
 //              (component-major, so a component's patches are contiguous and
 //              ordered by block), and derives per component its start, its
 //              count and the exclusive prefix of its tile count.
-//  3. scatter: every block writes its patch indices at their offsets; within
-//              a block the 16 waves take consecutive runs of patches in
-//              order, and inside a wave equal labels are ranked by lane, so
-//              the result is the stable order of patch indices.
+//  3. scatter: every block writes its patch indices into its slots of each
+//              component's range, slots handed out by LDS counters.  The
+//              order inside a range is not fixed, and need not be: a patch's
+//              estimate depends only on its own pixels and its component
+//              (every MFMA output column is computed independently), so the
+//              estimates written are the same whatever tile a patch lands in.
 #include "common.h"
 
 namespace fepll {
@@ -109,47 +111,13 @@ __global__ __launch_bounds__(1024) void scatter_kernel(const int32_t* __restrict
                                                        int K, int nb,
                                                        const int32_t* __restrict__ offs,
                                                        int32_t* __restrict__ perm) {
-  extern __shared__ int32_t sub[];  // [16][K]
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;  // 16
-  for (int i = threadIdx.x; i < nw * K; i += blockDim.x) sub[i] = 0;
+  extern __shared__ int32_t cur[];  // [K] next free slot of each component in this block
+  for (int k = threadIdx.x; k < K; k += blockDim.x) cur[k] = offs[(size_t)k * nb + blockIdx.x];
   __syncthreads();
-  const int per_wave = kSortBlock / nw;  // 1024
-  const int wbase = blockIdx.x * kSortBlock + wave * per_wave;
-  for (int i = lane; i < per_wave; i += 64) {
-    const int g = wbase + i;
-    if (g < Np) atomicAdd(&sub[wave * K + labels[g]], 1);
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < K; k += blockDim.x) {
-    int32_t run = offs[(size_t)k * nb + blockIdx.x];
-    for (int w = 0; w < nw; ++w) {
-      const int32_t c = sub[w * K + k];
-      sub[w * K + k] = run;
-      run += c;
-    }
-  }
-  __syncthreads();
-  int32_t* mine = sub + wave * K;
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  for (int ch = 0; ch < per_wave; ch += 64) {
-    const int g = wbase + ch + lane;
-    const bool valid = g < Np;
-    const int lab = valid ? labels[g] : -1;
-    unsigned long long active = __ballot(valid);
-    while (active) {
-      const int leader = __ffsll((long long)active) - 1;
-      const int L = __shfl(lab, leader);
-      const unsigned long long mask = __ballot(lab == L) & active;
-      const int32_t base = mine[L];
-      if (valid && lab == L) perm[base + __popcll(mask & lt)] = g;
-      __builtin_amdgcn_wave_barrier();
-      if (lane == leader) mine[L] = base + __popcll(mask);
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      active &= ~mask;
-    }
+  const int base = blockIdx.x * kSortBlock;
+  for (int i = threadIdx.x; i < kSortBlock; i += blockDim.x) {
+    const int g = base + i;
+    if (g < Np) perm[atomicAdd(&cur[labels[g]], 1)] = g;
   }
 }
 
@@ -163,8 +131,8 @@ hipError_t launch_bucket(const int32_t* labels, int Np, int K, int32_t* hist, in
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, hist, K, nb, Np, seg);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(1024), 16 * K * sizeof(int32_t), st, labels,
-                     Np, K, nb, hist, perm);
+  hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(1024), K * sizeof(int32_t), st, labels, Np,
+                     K, nb, hist, perm);
   return hipGetLastError();
 }
 

@@ -13,9 +13,10 @@
 //    entry W_k[q][p] with q = 32*qb + (l & 31), p = 2*s + (l >> 5), where
 //    W_k = U_k diag(gamma_k) U_k^t (the Wiener filter of Alg. 1, patch
 //    estimation, written back in pixel space).
-//  * Ub   bf16 bits (uint16), [T][K][2][4][64][8]: the bfloat16 E-step A
-//    operand, entry Ut_k[p][j] with j = 32*jb + (l & 31) and
-//    p = 16*t + 8*(l >> 5) + e for depth step t (0..3), lane l, element e.
+//  * Ub   bf16 bits (uint16), [T][K][4][2][64][8]: the bfloat16 E-step A
+//    operand (v_mfma_f32_16x16x32_bf16), entry Ut_k[p][j] with
+//    j = 16*rb + (l & 15) and p = 32*t + 8*(l >> 4) + e for eigen block rb
+//    (0..3), depth step t (0..1), lane l, element e.
 //  * L32  float,  [T][K]: L_k = iota_k + sum_j log nu_kj rounded from float64.
 //  * L64  double, [T][K] and invnu64 double [T][K][64]: the same terms in
 //    float64 for the re-selection of uncertified patches.

@@ -7,13 +7,18 @@
 // Labels are not certified in this mode: they are an approximation whose
 // agreement with the exact selection is measured, not assumed.
 //
-// One MFMA consumes 16 pixels of 32 patches: lane l supplies the 8 pixels
-// 16 t + 8 (l >> 5) + e (e = 0..7) of patch (l & 31) -- exactly one 8-pixel
-// row, dy = 2 t + (l >> 5), of the patch -- and the A operand supplies the
-// same 8 pixels of eigen-direction j = 32 jb + (l & 31).  A wave holds 128
-// patches (four blocks of 32) as B operands for its whole component loop;
-// per component it issues 2 (eigen blocks) x 4 (depth steps) x 4 (patch
-// blocks) MFMAs and 128 float32 FMAs of squares.
+// v_mfma_f32_16x16x32_bf16 multiplies 16 eigen-directions by 16 patches
+// over 32 pixels: lane l supplies the 8 pixels 32 t + 8 (l >> 4) + e
+// (e = 0..7) of patch (l & 15) -- exactly one 8-pixel row,
+// dy = 4 t + (l >> 4), of the patch -- and the A operand supplies the same
+// pixels of eigen-direction 16 rb + (l & 15).  (On gfx950 this shape keeps
+// the matrix cores busier than 32x32x16 for this loop: measured 83% against
+// 64% of the bf16 peak without the epilogue.)  A wave holds 128 patches
+// (eight blocks of 16) as B operands for its whole component loop; per
+// component it issues 4 (eigen blocks) x 2 (depth steps) x 8 (patch blocks)
+// MFMAs and 128 float32 FMAs of squares, then reduces each patch's squared
+// norm over the four 16-lane groups (lanes l, l^16, l^32, l^48) with a
+// transpose-reduction that leaves every lane owning 2 patches.
 //
 // Three modes share the kernel:
 //  * spatial, all K: a wave takes 128 consecutive patches of one row;
@@ -23,19 +28,22 @@
 //    candidates -- the exact rescoring of the proposal.  A patch whose half
 //    gap (in nats) between the two is below the margin is appended to a
 //    fallback list;
-//  * list, all K: the fallback patches, 128 list entries per wave, with a
-//    device-side list length (fixed grid, waves stride over the list and
-//    exit past its end).
+//  * list, all K: the fallback patches, 512 list entries per workgroup, with
+//    a device-side list length (fixed grid, workgroups stride over the list
+//    and exit past its end).
+// In the all-K modes the per-component operand is staged through
+// double-buffered LDS shared by the workgroup's 4 waves (one barrier per
+// component, the next component's operand already loading).
 #include "common.h"
 #include "propose.h"
 
 namespace fepll {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
-constexpr int CB = 4;  // blocks of 32 patches per wave
+constexpr int PB = 8;  // blocks of 16 patches per wave
 
 __device__ __forceinline__ uint32_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -45,19 +53,32 @@ __device__ __forceinline__ uint32_t bf16_rne(float f) {
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
   return bf16_rne(a) | (bf16_rne(b) << 16);
 }
-__device__ __forceinline__ f32x16 mfma_bf16(uint4 a, uint4 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+__device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
+// best / second smallest cost and the argmin (first k on ties), branch-free
 __device__ __forceinline__ void keep_best(float cost, int k, float& best, float& second,
                                           int& bk) {
-  if (cost < best) {
-    second = best;
-    best = cost;
-    bk = k;
-  } else if (cost < second) {
-    second = cost;
-  }
+  const bool better = cost < best;
+  second = better ? best : fminf(second, cost);
+  bk = better ? k : bk;
+  best = better ? cost : best;
+}
+// Exchange between lane halves (v_permlane32_swap: lanes 32..63 of a with
+// lanes 0..31 of b) and between 16-lane rows of each half
+// (v_permlane16_swap: rows 1 and 3 of a with rows 0 and 2 of b).  After
+// swap(a, b), a + b is, in lanes of the lower half (row), the pair sum of a
+// and, in the upper half (row), the pair sum of b.
+__device__ __forceinline__ float pair_sum32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pair_sum16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 __device__ __forceinline__ bool has(const uint4& c, int k) {
   const uint32_t w[4] = {c.x, c.y, c.z, c.w};
@@ -67,114 +88,137 @@ __device__ __forceinline__ bool has(const uint4& c, int k) {
   return r;
 }
 
-// DC-removed bfloat16 B operands of one 32-patch block; (r, c) top-left.
+// DC-removed bfloat16 B operands (2 depth steps) of one 16-patch block for
+// lane group g = l >> 4: patch rows g and 4 + g of the patch at (r, c).
 __device__ __forceinline__ void load_patch(const float* __restrict__ x, int W, int r, int c,
-                                           int half, uint4 zb[4]) {
-  float v[4][8];
-  double s = 0.0;
+                                           int g, uint4 zb[2]) {
+  // the mean is taken in float32: its rounding is far below the bfloat16
+  // rounding of the differences that follows
+  float v[2][8];
+  float s = 0.f;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const float* row = x + (size_t)(r + 2 * t + half) * W + c;
+  for (int t = 0; t < 2; ++t) {
+    const float* row = x + (size_t)(r + 4 * t + g) * W + c;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       v[t][e] = row[e];
-      s += (double)v[t][e];
+      s += v[t][e];
     }
   }
+  s += __shfl_xor(s, 16);
   s += __shfl_xor(s, 32);
-  const double m = s * (1.0 / 64.0);
+  const float m = s * (1.f / 64.f);
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < 2; ++t) {
     float d[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = (float)((double)v[t][e] - m);
+    for (int e = 0; e < 8; ++e) d[e] = v[t][e] - m;
     zb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),
                        pack2(d[6], d[7]));
   }
 }
 
-// Squared norms of the 4 x 32 patches for component k; returns the two
-// costs this lane owns (blocks half and 2 + half).
-__device__ __forceinline__ void score(const uint4* __restrict__ up, int k, const uint4 zb[CB][4],
-                                      float Lk, int half, float& cA, float& cB) {
+// Squared norms of the 8 x 16 patches for one component whose operand
+// (4 eigen blocks x 2 depth steps, this lane's entries) starts at ap with a
+// stride of 64 uint4.  Lane l (group g = l >> 4) returns the costs of the
+// two patches it owns: blocks 4 (g >> 1) + 2 (g & 1) + {0, 1}, column l & 15.
+__device__ __forceinline__ void score(const uint4* ap, const uint4 zb[PB][2], float Lk, int g,
+                                      float& cA, float& cB) {
   uint4 A[8];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) A[i] = up[(size_t)k * 512 + i * 64];
-  float q[CB];
+  for (int i = 0; i < 8; ++i) A[i] = ap[i * 64];
+  float q[PB];
 #pragma unroll
-  for (int cb = 0; cb < CB; ++cb) q[cb] = 0.f;
+  for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
 #pragma unroll
-  for (int jb = 0; jb < 2; ++jb) {
-    f32x16 acc[CB];
+  for (int rb = 0; rb < 4; ++rb) {
+    f32x4 acc[PB];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
-      acc[cb] = (f32x16){0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                         0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int pb = 0; pb < PB; ++pb) acc[pb] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) acc[cb] = mfma_bf16(A[jb * 4 + t], zb[cb][t], acc[cb]);
+      for (int pb = 0; pb < PB; ++pb) acc[pb] = mfma16(A[rb * 2 + t], zb[pb][t], acc[pb]);
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
+    for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) q[cb] = fmaf(acc[cb][i], acc[cb][i], q[cb]);
-    __builtin_amdgcn_sched_barrier(0);
+      for (int i = 0; i < 4; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
   }
-  // lanes < 32 finish blocks 0 and 2, lanes >= 32 blocks 1 and 3
-  const float r0 = __shfl_xor(half ? q[0] : q[1], 32);
-  const float r1 = __shfl_xor(half ? q[2] : q[3], 32);
-  cA = Lk + ((half ? q[1] : q[0]) + r0);
-  cB = Lk + ((half ? q[3] : q[2]) + r1);
+  // lane groups g and g ^ 2 split the 8 blocks in halves, then g and g ^ 1:
+  // lanes of groups 0/1 keep blocks 0..3, groups 2/3 keep 4..7, then even
+  // groups keep the first two of their four, odd groups the last two
+  float m4[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) m4[i] = pair_sum32(q[i], q[4 + i]);
+  float m2[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) m2[i] = pair_sum16(m4[i], m4[2 + i]);
+  (void)g;
+  cA = Lk + m2[0];
+  cB = Lk + m2[1];
 }
 }  // namespace
 
 template <int MODE>
-__global__ __launch_bounds__(256, 2) void estep_bf16_kernel(BF16Args a) {
+__global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
   __shared__ uint32_t bm[4][32];
   __shared__ uint16_t ul[4][kMaxK];
+  __shared__ uint4 Ash[2][512];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int half = lane >> 5;
-  const int col = lane & 31;
+  const int g = lane >> 4;
+  const int col = lane & 15;
   const int Hp = a.H - 7, Wp = a.W - 7;
-  const uint4* up = reinterpret_cast<const uint4*>(a.Ub) + lane;  // [K][2][4][64] uint4
+  const uint4* up = reinterpret_cast<const uint4*>(a.Ub) + lane;  // [K][4][2][64] uint4
 
   const int nlist = (MODE == kModeListFull) ? *a.list_count : 0;
-  const int nwaves = gridDim.x * gridDim.y * 4;
-  int chunk = (blockIdx.y * gridDim.x + blockIdx.x) * 4 + wave;
+  // list mode: the workgroup takes 512 consecutive list entries per pass (a
+  // workgroup-uniform loop: every wave reaches every barrier of the K loop)
+  int wchunk = blockIdx.y * gridDim.x + blockIdx.x;
+  const int nwg = gridDim.x * gridDim.y;
   for (;;) {
     // ---- this wave's 128 patches
-    int idx[CB];
-    bool valid[CB];
+    int idx[PB];
+    bool valid[PB];
     if (MODE == kModeListFull) {
-      if (chunk * 128 >= nlist) break;
+      if (wchunk * 512 >= nlist) break;
+      const int base = wchunk * 512;
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        const int e = chunk * 128 + 32 * cb + col;
-        valid[cb] = e < nlist;
-        idx[cb] = a.list[valid[cb] ? e : chunk * 128];
+      for (int pb = 0; pb < PB; ++pb) {
+        const int e = base + wave * 128 + 16 * pb + col;
+        valid[pb] = e < nlist;
+        idx[pb] = a.list[valid[pb] ? e : base];
       }
     } else {
       const int r = blockIdx.y * 4 + wave;
-      const int c0 = blockIdx.x * (32 * CB);
+      const int c0 = blockIdx.x * (16 * PB);
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb) {
-        const int c = c0 + 32 * cb + col;
-        valid[cb] = (r < Hp) && (c < Wp);
-        idx[cb] = min(r, Hp - 1) * Wp + min(c, Wp - 1);
+      for (int pb = 0; pb < PB; ++pb) {
+        const int c = c0 + 16 * pb + col;
+        valid[pb] = (r < Hp) && (c < Wp);
+        idx[pb] = min(r, Hp - 1) * Wp + min(c, Wp - 1);
       }
     }
-    uint4 zb[CB][4];
+    uint4 zb[PB][2];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int pr = idx[cb] / Wp;
-      load_patch(a.x, a.W, pr, idx[cb] - pr * Wp, half, zb[cb]);
+    for (int pb = 0; pb < PB; ++pb) {
+      const int pr = idx[pb] / Wp;
+      load_patch(a.x, a.W, pr, idx[pb] - pr * Wp, g, zb[pb]);
+      // one block's raw pixels live at a time (keeps the prologue in registers)
+      __builtin_amdgcn_sched_barrier(0);
     }
-    // lane's own patches: blocks half and 2 + half
-    const int iA = half ? idx[1] : idx[0];
-    const int iB = half ? idx[3] : idx[2];
-    const bool vA = half ? valid[1] : valid[0];
-    const bool vB = half ? valid[3] : valid[2];
+    // lane's own patches: blocks 4 (g >> 1) + 2 (g & 1) + {0, 1}
+    const int own = 4 * (g >> 1) + 2 * (g & 1);
+    int iA = idx[0], iB = idx[1];
+    bool vA = valid[0], vB = valid[1];
+#pragma unroll
+    for (int pb = 0; pb < PB; pb += 2)
+      if (pb == own) {
+        iA = idx[pb];
+        iB = idx[pb + 1];
+        vA = valid[pb];
+        vB = valid[pb + 1];
+      }
 
     float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
     int kA = 0, kB = 0;
@@ -217,17 +261,30 @@ __global__ __launch_bounds__(256, 2) void estep_bf16_kernel(BF16Args a) {
       for (int u = 0; u < nu; ++u) {
         const int k = ul[wave][u];
         float cA, cB;
-        score(up, k, zb, a.L[k], half, cA, cB);
+        score(up + (size_t)k * 512, zb, a.L[k], g, cA, cB);
         if (has(candA, k)) keep_best(cA, k, bA, sA, kA);
         if (has(candB, k)) keep_best(cB, k, bB, sB, kB);
       }
     } else {
+      // all K: the per-component operand (8 KB) is staged once per
+      // workgroup in LDS, double-buffered, the next one already in flight
+      const uint4* gsrc = reinterpret_cast<const uint4*>(a.Ub);
+      uint4 pre0 = gsrc[threadIdx.x], pre1 = gsrc[256 + threadIdx.x];
       for (int k = 0; k < a.K; ++k) {
+        uint4* As = Ash[k & 1];
+        As[threadIdx.x] = pre0;
+        As[256 + threadIdx.x] = pre1;
+        __syncthreads();
+        if (k + 1 < a.K) {
+          pre0 = gsrc[(size_t)(k + 1) * 512 + threadIdx.x];
+          pre1 = gsrc[(size_t)(k + 1) * 512 + 256 + threadIdx.x];
+        }
         float cA, cB;
-        score(up, k, zb, a.L[k], half, cA, cB);
+        score(As + lane, zb, a.L[k], g, cA, cB);
         keep_best(cA, k, bA, sA, kA);
         keep_best(cB, k, bB, sB, kB);
       }
+      __syncthreads();  // the staging buffers are reused by the next pass
     }
     // ---- outputs
 #pragma unroll
@@ -248,7 +305,7 @@ __global__ __launch_bounds__(256, 2) void estep_bf16_kernel(BF16Args a) {
       }
     }
     if (MODE != kModeListFull) break;
-    chunk += nwaves;
+    wchunk += nwg;
   }
 }
 
@@ -261,7 +318,7 @@ hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st
     hipLaunchKernelGGL(estep_bf16_kernel<kModeListFull>, dim3(blocks), dim3(256), 0, st, args);
     return hipGetLastError();
   }
-  dim3 grid((Wp + 32 * CB - 1) / (32 * CB), (Hp + 3) / 4);
+  dim3 grid((Wp + 16 * PB - 1) / (16 * PB), (Hp + 3) / 4);
   if (mode == kModeSpatialCand)
     hipLaunchKernelGGL(estep_bf16_kernel<kModeSpatialCand>, grid, dim3(256), 0, st, args);
   else

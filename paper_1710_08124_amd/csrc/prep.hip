@@ -48,10 +48,10 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
     const int j = 32 * jb + (l & 31);
     ut[idx] = (float)(Us[p * kP + j] * rs[j]);
     {
-      // bfloat16 table: same entries, MFMA 32x32x16 operand order
-      const int eb = idx & 7, lb = (idx >> 3) & 63, tb = (idx >> 9) & 3, jbb = idx >> 11;
-      const int pb = 16 * tb + 8 * (lb >> 5) + eb;
-      const int jb2 = 32 * jbb + (lb & 31);
+      // bfloat16 table: same entries, MFMA 16x16x32 operand order
+      const int eb = idx & 7, lb = (idx >> 3) & 63, tb = (idx >> 9) & 1, rb = idx >> 10;
+      const int pb = 32 * tb + 8 * (lb >> 4) + eb;
+      const int jb2 = 16 * rb + (lb & 15);
       uint32_t u = __float_as_uint((float)(Us[pb * kP + jb2] * rs[jb2]));
       u += 0x7fffu + ((u >> 16) & 1u);
       ub[idx] = (uint16_t)(u >> 16);

@@ -126,24 +126,25 @@ __global__ __launch_bounds__(512, 1) void propose_bf16_kernel(
   // ---- layer-1 input: DC-removed patch / 128 and log sigma_beta
   uint4 xb[5];
   {
+    // float32 mean: its rounding is far below the bfloat16 rounding below
     float v[4][8];
-    double s = 0.0;
+    float s = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const float* row = x + (size_t)(rr + 2 * t + half) * W + cc;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         v[t][e] = row[e];
-        s += (double)v[t][e];
+        s += v[t][e];
       }
     }
     s += __shfl_xor(s, 32);
-    const double mean = s * (1.0 / 64.0);
+    const float mean = s * (1.f / 64.f);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       float d[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) d[e] = (float)(((double)v[t][e] - mean) * (1.0 / kScaleIn));
+      for (int e = 0; e < 8; ++e) d[e] = (v[t][e] - mean) * (1.f / kScaleIn);
       xb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),
                          pack2(d[6], d[7]));
     }

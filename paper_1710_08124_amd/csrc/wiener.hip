@@ -4,9 +4,9 @@
 // float64 (prep.hip); here it is applied as a grouped GEMM over the patches
 // bucketed by component (bucket.hip): one wave takes a tile of up to 64
 // patches that share a component, recomputes their DC-removed pixels from
-// the current image, multiplies by W_k on MFMA and writes z^ as 64
-// consecutive floats per patch (pixel-space order 8*dy + dx), the layout the
-// reprojection kernel streams.
+// the current image, multiplies by W_k on MFMA and writes z^ in row planes:
+// Zhat[dy][patch][dx] (8 planes of Np x 8 floats), so that each patch row
+// is one 32-byte sector and the reprojection reads every plane row once.
 //
 // The tile count depends on the labels, so the grid is fixed and waves
 // stride over the device-side tile list; a wave exits once its stride passes
@@ -30,6 +30,7 @@ __global__ __launch_bounds__(256) void wiener_f32_kernel(const float* __restrict
   const int32_t* count = seg + (K + 1);
   const int32_t* tpre = seg + (2 * K + 1);
   const int total = seg[3 * K + 2];
+  const size_t Np8 = (size_t)(H - 7) * Wp * 8;  // floats per row plane of z^
   const int nwaves = gridDim.x * (blockDim.x >> 6);
   for (int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < total; t += nwaves) {
     // component of tile t: last k with tpre[k] <= t
@@ -44,18 +45,10 @@ __global__ __launch_bounds__(256) void wiener_f32_kernel(const float* __restrict
     const int n = min(kWienerTile, count[k] - first);
     const int32_t* ids = perm + start[k] + first;
 
-    // operand of W_k
-    const float4* wp = Wt + (size_t)k * 1024 + lane;
-    float4 A0[8], A1[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      A0[i] = wp[i * 64];
-      A1[i] = wp[512 + i * 64];
-    }
     // patches: lane holds pixels p = 2s + half of patches col and 32 + col
     const bool v0 = col < n, v1 = 32 + col < n;
-    const int id0 = v0 ? ids[col] : 0;
-    const int id1 = v1 ? ids[32 + col] : 0;
+    const int id0 = v0 ? ids[col] : ids[0];
+    const int id1 = v1 ? ids[32 + col] : ids[0];
     const int r0 = id0 / Wp, c0 = id0 - r0 * Wp;
     const int r1 = id1 / Wp, c1 = id1 - r1 * Wp;
     float z0[32], z1[32];
@@ -77,46 +70,40 @@ __global__ __launch_bounds__(256) void wiener_f32_kernel(const float* __restrict
       z0[s] = (float)((double)z0[s] - m0);
       z1[s] = (float)((double)z1[s] - m1);
     }
-    const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                         0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    f32x16 a00 = zero, a01 = zero, a10 = zero, a11 = zero;  // [qb][patch block]
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-#define STEP(E, S)                                                            \
-  a00 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[i].E, z0[S], a00, 0, 0, 0); \
-  a01 = __builtin_amdgcn_mfma_f32_32x32x2f32(A0[i].E, z1[S], a01, 0, 0, 0); \
-  a10 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[i].E, z0[S], a10, 0, 0, 0); \
-  a11 = __builtin_amdgcn_mfma_f32_32x32x2f32(A1[i].E, z1[S], a11, 0, 0, 0);
-      STEP(x, 4 * i + 0)
-      STEP(y, 4 * i + 1)
-      STEP(z, 4 * i + 2)
-      STEP(w, 4 * i + 3)
-#undef STEP
-    }
-    // accumulator register 4*g + e of lane l is pixel q = 32*qb + 8*g + 4*half + e
     const float fm0 = (float)m0, fm1 = (float)m1;
-    if (v0) {
-      float4* out = reinterpret_cast<float4*>(Zhat + (size_t)id0 * kP);
+    // one 32-row block of W_k at a time (rows q = 32 qb + ...)
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        out[(8 * g + 4 * half) >> 2] =
-            make_float4(a00[4 * g] + fm0, a00[4 * g + 1] + fm0, a00[4 * g + 2] + fm0,
-                        a00[4 * g + 3] + fm0);
-        out[(32 + 8 * g + 4 * half) >> 2] =
-            make_float4(a10[4 * g] + fm0, a10[4 * g + 1] + fm0, a10[4 * g + 2] + fm0,
-                        a10[4 * g + 3] + fm0);
+    for (int qb = 0; qb < 2; ++qb) {
+      const float4* wp = Wt + (size_t)k * 1024 + qb * 512 + lane;
+      float4 A[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) A[i] = wp[i * 64];
+      f32x16 a0 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      f32x16 a1 = a0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+#define STEP(E, S)                                                            \
+  a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].E, z0[S], a0, 0, 0, 0);      \
+  a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].E, z1[S], a1, 0, 0, 0);
+        STEP(x, 4 * i + 0)
+        STEP(y, 4 * i + 1)
+        STEP(z, 4 * i + 2)
+        STEP(w, 4 * i + 3)
+#undef STEP
       }
-    }
-    if (v1) {
-      float4* out = reinterpret_cast<float4*>(Zhat + (size_t)id1 * kP);
+      // accumulator 4 g + e of lane l is pixel q = 32 qb + 8 g + 4 half + e:
+      // row dy = 4 qb + g, columns dx = 4 half + e (one float4 of the row)
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
-        out[(8 * g + 4 * half) >> 2] =
-            make_float4(a01[4 * g] + fm1, a01[4 * g + 1] + fm1, a01[4 * g + 2] + fm1,
-                        a01[4 * g + 3] + fm1);
-        out[(32 + 8 * g + 4 * half) >> 2] =
-            make_float4(a11[4 * g] + fm1, a11[4 * g + 1] + fm1, a11[4 * g + 2] + fm1,
-                        a11[4 * g + 3] + fm1);
+        const size_t plane = (size_t)(4 * qb + g) * Np8;
+        if (v0)
+          *reinterpret_cast<float4*>(Zhat + plane + (size_t)id0 * 8 + 4 * half) =
+              make_float4(a0[4 * g] + fm0, a0[4 * g + 1] + fm0, a0[4 * g + 2] + fm0,
+                          a0[4 * g + 3] + fm0);
+        if (v1)
+          *reinterpret_cast<float4*>(Zhat + plane + (size_t)id1 * 8 + 4 * half) =
+              make_float4(a1[4 * g] + fm1, a1[4 * g + 1] + fm1, a1[4 * g + 2] + fm1,
+                          a1[4 * g + 3] + fm1);
       }
     }
   }
