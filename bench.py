@@ -57,6 +57,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (counter calibration)")
+    ap.add_argument("--paths", default="fp32,bf16,bf16+proposal",
+                    help="comma-separated paths to time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -69,6 +73,14 @@ def main():
     import fepll_synth as fs
     import paper_1710_08124_amd as F
 
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.copy_calibration_mib} MiB read + written")
+        del src, dst
     log("generating workload")
     c = fs.config_c3(args.size)
     H = W = args.size
@@ -130,7 +142,12 @@ def main():
     def psnr(ref, x):
         return float(10 * np.log10(255.0 ** 2 / np.mean((x.astype(np.float64) - ref) ** 2)))
 
-    names = ["fp32", "bf16"] + (["bf16+proposal"] if have_prop else [])
+    want = args.paths.split(",")
+    names = [p for p in ("fp32", "bf16", "bf16+proposal")
+             if p in want and (p != "bf16+proposal" or have_prop)]
+    for p in ("fp32", "bf16"):
+        if p not in names:
+            names.insert(0 if p == "fp32" else 1, p)
     paths = {p: run_path(p) for p in names}
     fp32, bf16 = paths["fp32"], paths["bf16"]
     # quality of the reduced-precision paths: PSNR against the clean image,
@@ -165,7 +182,7 @@ def main():
                         "dpsnr_vs_fp32_path_db": round(dpsnr_bf16, 4)},
         "speedup_vs_plain_fp32": round(hp["mpix_s"] / fp32["mpix_s"], 3),
     }
-    if have_prop:
+    if "bf16+proposal" in paths:
         pp = paths["bf16+proposal"]
         res["bf16_proposal"] = {"mpix_s": round(pp["mpix_s"], 4), "stages_ms": pp["stages_ms"],
                                 "psnr_db": round(pp["psnr"], 4),

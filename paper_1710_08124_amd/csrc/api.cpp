@@ -179,7 +179,7 @@ fepll_status ensure_ws(fepll_gmm* g, int H, int W) {
     HIPX(dalloc(&g->list, 4 * Np));  // int4 entries
     HIPX(dalloc(&g->count, 64));
     HIPX(dalloc(&g->hist, nb * g->K));
-    HIPX(dalloc(&g->seg, 3 * (size_t)g->K + 3));
+    HIPX(dalloc(&g->seg, seg_size(Np, g->K)));
     HIPX(dalloc(&g->perm, Np));
     HIPX(dalloc(&g->Zhat, Np * kP));
     HIPX(dalloc(&g->cand, Np * 8));

@@ -105,6 +105,21 @@ __global__ __launch_bounds__(1024) void scan_kernel(int32_t* __restrict__ hist, 
     tpre[K] = part[1023];
     seg[3 * K + 2] = part[1023];
   }
+  // tile table: tile -> (component, index of the tile within the component)
+  __shared__ int32_t tp[1025];
+  for (int k = t; k <= K; k += 1024) tp[k] = (k < K) ? part[k] - tiles[k] : part[1023];
+  __syncthreads();
+  const int total = tp[K];
+  int32_t* info = seg + (3 * K + 3);
+  for (int tile = t; tile < total; tile += 1024) {
+    int lo = 0, hi = K - 1;  // last k with tp[k] <= tile
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tp[mid] <= tile) lo = mid;
+      else hi = mid - 1;
+    }
+    info[tile] = lo | ((tile - tp[lo]) << 10);
+  }
 }
 
 __global__ __launch_bounds__(1024) void scatter_kernel(const int32_t* __restrict__ labels, int Np,

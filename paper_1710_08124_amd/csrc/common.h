@@ -10,7 +10,7 @@
 //    Scaling the eigenvectors by nu^-1/2 turns the Mahalanobis term
 //    sum_j c_j^2 / nu_kj of the selection cost into a plain sum of squares.
 //  * Wt   float,  [T][K][2][8][64][4]: the patch-estimation A operand,
-//    entry W_k[q][p] with q = 32*qb + (l & 31), p = 2*s + (l >> 5), where
+//    entry W_k[q][p] with q = 32*qb + (l & 31), p = 32*(l >> 5) + s, where
 //    W_k = U_k diag(gamma_k) U_k^t (the Wiener filter of Alg. 1, patch
 //    estimation, written back in pixel space).
 //  * Ub   bf16 bits (uint16), [T][K][4][2][64][8]: the bfloat16 E-step A
@@ -57,14 +57,18 @@ hipError_t launch_recheck_f64(const float* x, int H, int W, const double* U64,
                               const int32_t* list_count, const int32_t* list, int32_t* labels,
                               int max_list, hipStream_t st);
 
-// Counting sort of patch indices by label (stable) and the Wiener tile list.
-// hist: [K][nb] int32, nb = ceil(Np / kSortBlock); seg: [3*(K+1)+1] int32
-// laid out as start[K+1], count[K], tile_prefix[K+1], total_tiles.
+// Counting sort of patch indices by label and the Wiener tile list.
+// hist: [K][nb] int32, nb = ceil(Np / kSortBlock); seg: int32, laid out as
+// start[K+1], count[K], tile_prefix[K+1], total_tiles, then the tile table
+// (seg_size(Np, K) entries in all): entry t = k | (tile index in k) << 10.
 constexpr int kSortBlock = 16384;
-constexpr int kWienerTile = 64;
+constexpr int kWienerTile = 32;
+inline size_t seg_size(size_t Np, int K) { return 3 * (size_t)K + 3 + Np / kWienerTile + K + 1; }
 hipError_t launch_bucket(const int32_t* labels, int Np, int K, int32_t* hist, int32_t* seg,
                          int32_t* perm, hipStream_t st);
 
+// Patch estimates z^: float [Np][64], patch-major (pixel 8 dy + dx of patch i
+// at i * 64 + 8 dy + dx).
 hipError_t launch_wiener_f32(const float* x, int H, int W, const float* Wt_t, int K,
                              const int32_t* seg, const int32_t* perm, float* Zhat,
                              hipStream_t st);

@@ -3,18 +3,22 @@
 //   x  = (y + b x~) / (1 + b),  b = beta sigma^2     (A = identity)
 //
 // A gather, not a scatter: each output pixel sums the (up to 64) patch
-// entries that cover it in a fixed order -- dy ascending (patch rows
-// descending), dx ascending -- so the result is bitwise reproducible and
-// needs no atomics.
+// entries that cover it in a fixed order -- patch rows ascending (dy
+// descending), and within a patch row dx ascending -- so the result is
+// bitwise reproducible and needs no atomics.
 //
-// z^ is stored in row planes, Zhat[dy][patch][dx]: output row y takes row
-// dy of the patches of patch row y - dy, so every (plane, patch row)
-// segment is read by exactly one output row and only the 7-column halo of a
-// tile is read twice.  A workgroup owns 16 output rows x 64 columns and
-// walks 2 groups of 8 rows x 8 planes; each round stages the 8 segments of
-// a group (8 x 71 patches x 8 floats) in LDS with a 9-float pitch
-// (conflict-free reads), while the next round's segments are already in
-// flight in registers.
+// z^ is stored patch-major, Zhat[patch][dy][dx] (256 contiguous bytes per
+// patch), so one patch row of a tile (71 patches) is one contiguous 18 KB
+// run.  A workgroup owns 32 output rows x 64 columns and walks the 39 patch
+// rows that touch them, top to bottom: each patch row is staged in LDS (odd
+// pitch, conflict-free reads) while the next one is in flight in registers,
+// and every pixel row in flight keeps a running sum in a register of the
+// thread that owns it (thread row j owns pixel rows = j mod 4, two of them
+// in flight).  A pixel row is final once patch row y (dy = 0) is added.
+//
+// Tiles are numbered column-strip-major and dealt so that consecutive tiles
+// of a strip run on the same XCD at about the same time: the 7 patch rows a
+// tile shares with the tile below are then read from that XCD's L2.
 //
 // The per-pixel patch count of the valid patch set is the product of a row
 // and a column factor, cnt(y, x) = n(y, H) n(x, W) with
@@ -25,11 +29,11 @@ namespace fepll {
 
 namespace {
 constexpr int TX = 64;
-constexpr int TY = 16;
-constexpr int NP = TX + 7;      // patches per segment
-constexpr int PITCH = 9;        // floats per staged patch row
-constexpr int SEG = NP * PITCH;
-constexpr int F4 = 8 * NP * 2;  // float4 of one round (8 segments x NP patches x 2)
+constexpr int TY = 32;
+constexpr int NP = TX + 7;       // patches of one staged patch row
+constexpr int PITCH = 65;        // floats per staged patch
+constexpr int ROW = NP * PITCH;  // floats per staged patch row
+constexpr int F4 = NP * 16;      // float4 of one patch row
 constexpr int PER = (F4 + 255) / 256;
 }  // namespace
 
@@ -37,41 +41,35 @@ __global__ __launch_bounds__(256) void ola_update_kernel(const float* __restrict
                                                          const float* __restrict__ y, int H,
                                                          int W, float b,
                                                          float* __restrict__ xnew) {
-  __shared__ float buf[2][8 * SEG];
+  __shared__ float buf[2][ROW];
   const int Hp = H - 7, Wp = W - 7;
-  const size_t Np8 = (size_t)Hp * Wp * 8;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY;
+  const int G8 = gridDim.x;  // a multiple of 8
+  const int lin = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
+  if (lin >= ntx * nty) return;
+  const int x0 = (lin / nty) * TX, y0 = (lin % nty) * TY;
+  const int tx = threadIdx.x & 63, j = threadIdx.x >> 6;
   const int cfirst = x0 - 7;
 
-  // round q = (group, dy): segments j = 0..7 are (plane dy, patch row y0 + 8 group + j - dy)
   float4 pre[PER];
-  auto fetch = [&](int q) {
-    const int grp = q >> 3, dy = q & 7;
+  auto fetch = [&](int r) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + 256 * u;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (e < F4) {
-        const int j = e / (2 * NP), rem = e - j * 2 * NP;
-        const int p = rem >> 1, h = rem & 1;
-        const int r = y0 + 8 * grp + j - dy, c = cfirst + p;
-        if (r >= 0 && r < Hp && c >= 0 && c < Wp)
-          v = *reinterpret_cast<const float4*>(Zhat + dy * Np8 + ((size_t)r * Wp + c) * 8 +
-                                               4 * h);
-      }
+      const int p = e >> 4, f = e & 15;
+      const int c = cfirst + p;
+      if (e < F4 && r >= 0 && r < Hp && c >= 0 && c < Wp)
+        v = *reinterpret_cast<const float4*>(Zhat + ((size_t)r * Wp + c) * kP + 4 * f);
       pre[u] = v;
     }
   };
-  auto stash = [&](int q) {
-    float* B = buf[q & 1];
+  auto stash = [&](float* B) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + 256 * u;
       if (e < F4) {
-        const int j = e / (2 * NP), rem = e - j * 2 * NP;
-        const int p = rem >> 1, h = rem & 1;
-        float* d = B + j * SEG + p * PITCH + 4 * h;
+        float* d = B + (e >> 4) * PITCH + 4 * (e & 15);
         d[0] = pre[u].x;
         d[1] = pre[u].y;
         d[2] = pre[u].z;
@@ -80,52 +78,49 @@ __global__ __launch_bounds__(256) void ola_update_kernel(const float* __restrict
     }
   };
 
-  const int nq = 2 * 8;
-  fetch(0);
-  float acc[2][2] = {{0.f, 0.f}, {0.f, 0.f}};  // [group][row of the pair]
-  for (int q = 0; q < nq; ++q) {
-    stash(q);
-    __syncthreads();
-    if (q + 1 < nq) fetch(q + 1);
-    const float* B = buf[q & 1];
-    const int grp = q >> 3;
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const int j = 2 * ty + jj;
-      const float* S = B + j * SEG + (tx + 7) * PITCH;
-      const int dy = q & 7;
-      float s = 0.f;
-#pragma unroll
-      for (int dx = 0; dx < 8; ++dx) s += S[dx - dx * PITCH];
-      // the segment row is zero where the patch does not exist
-      (void)dy;
-      if (grp == 0) acc[0][jj] += s;
-      else acc[1][jj] += s;
-    }
-    __syncthreads();
-  }
   const int xx = x0 + tx;
-  if (xx >= W) return;
   const float ncol = (float)(min(xx, W - 8) - max(0, xx - 7) + 1);
   const float onepb = 1.f + b;
+  const int rb = y0 - 7, re = y0 + TY - 1;  // patch rows touching the tile
+  // pixel rows in flight of this thread: ya (closer to final) and ya + 4
+  int ya = rb + ((j - rb) & 3);
+  float acc_a = 0.f, acc_b = 0.f;
+  fetch(rb);
+  for (int r = rb; r <= re; ++r) {
+    float* B = buf[(r - rb) & 1];
+    stash(B);
+    __syncthreads();
+    if (r < re) fetch(r + 1);
+    const int da = ya - r;  // 0..3
+    const float* S = B + (tx + 7) * PITCH;
+    float sa = 0.f, sb = 0.f;
 #pragma unroll
-  for (int grp = 0; grp < 2; ++grp)
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj) {
-      const int yy = y0 + 8 * grp + 2 * ty + jj;
-      if (yy < H) {
-        const float nrow = (float)(min(yy, H - 8) - max(0, yy - 7) + 1);
-        const float xt = acc[grp][jj] / (nrow * ncol);
-        const size_t o = (size_t)yy * W + xx;
+    for (int dx = 0; dx < 8; ++dx) {
+      sa += S[8 * da + dx - dx * PITCH];
+      sb += S[8 * (da + 4) + dx - dx * PITCH];
+    }
+    acc_a += sa;
+    acc_b += sb;
+    if (da == 0) {  // row ya has all its patch rows
+      if (ya >= y0 && ya < H && xx < W) {
+        const float nrow = (float)(min(ya, H - 8) - max(0, ya - 7) + 1);
+        const float xt = acc_a / (nrow * ncol);
+        const size_t o = (size_t)ya * W + xx;
         xnew[o] = (y[o] + b * xt) / onepb;
       }
+      ya += 4;
+      acc_a = acc_b;
+      acc_b = 0.f;
     }
+  }
 }
 
 hipError_t launch_ola_update(const float* Zhat, const float* y, int H, int W, double b,
                              float* xnew, hipStream_t st) {
-  dim3 grid((W + TX - 1) / TX, (H + TY - 1) / TY);
-  hipLaunchKernelGGL(ola_update_kernel, grid, dim3(256), 0, st, Zhat, y, H, W, (float)b, xnew);
+  const int n = ((W + TX - 1) / TX) * ((H + TY - 1) / TY);
+  const int blocks = (n + 7) & ~7;  // whole rounds over the 8 XCDs
+  hipLaunchKernelGGL(ola_update_kernel, dim3(blocks), dim3(256), 0, st, Zhat, y, H, W, (float)b,
+                     xnew);
   return hipGetLastError();
 }
 

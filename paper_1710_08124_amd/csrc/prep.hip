@@ -56,10 +56,13 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
       u += 0x7fffu + ((u >> 16) & 1u);
       ub[idx] = (uint16_t)(u >> 16);
     }
-    // Wiener operand: row q of W_k = U_k diag(gamma) U_k^t, column p
+    // Wiener operand: row q of W_k = U_k diag(gamma) U_k^t, column pw;
+    // depth step s pairs pixel s (lanes 0..31) with pixel 32 + s (lanes
+    // 32..63), so each lane's patch operand is 32 consecutive pixels
     const int q = j;
+    const int pw = 32 * (l >> 5) + s;
     double acc = 0.0;
-    for (int jj = 0; jj < kP; ++jj) acc += Us[q * kP + jj] * gam[jj] * Us[p * kP + jj];
+    for (int jj = 0; jj < kP; ++jj) acc += Us[q * kP + jj] * gam[jj] * Us[pw * kP + jj];
     wt[idx] = (float)acc;
   }
 }

@@ -2,22 +2,25 @@
 // z^_i = U_k* diag(gamma_k*) U_k*^t z~_i + m_i = W_k* z~_i + m_i, with the
 // patch mean m_i added back unshrunk.  W_k is formed once per beta in
 // float64 (prep.hip); here it is applied as a grouped GEMM over the patches
-// bucketed by component (bucket.hip): one wave takes a tile of up to 64
+// bucketed by component (bucket.hip): one wave takes a tile of up to 32
 // patches that share a component, recomputes their DC-removed pixels from
-// the current image, multiplies by W_k on MFMA and writes z^ in row planes:
-// Zhat[dy][patch][dx] (8 planes of Np x 8 floats), so that each patch row
-// is one 32-byte sector and the reprojection reads every plane row once.
+// the current image, multiplies by W_k on MFMA and writes z^ patch-major,
+// Zhat[patch][dy][dx].  The patches of a tile lie anywhere in the image, so
+// every store goes to a different patch; patch-major, each patch's 256 bytes
+// are two whole cache lines written by one wave within a few cycles, where a
+// plane-per-row layout would leave 32-byte pieces of many lines for the
+// memory to merge.
 //
-// The tile count depends on the labels, so the grid is fixed and waves
-// stride over the device-side tile list; a wave exits once its stride passes
-// the total.
+// The tile count depends on the labels, so the grid is fixed (a multiple of
+// 8 workgroups) and each workgroup walks its share of the device-side tile
+// list; a wave exits at the end of its share.
 #include "common.h"
 
 namespace fepll {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__global__ __launch_bounds__(256) void wiener_f32_kernel(const float* __restrict__ x, int H,
+__global__ __launch_bounds__(256, 4) void wiener_f32_kernel(const float* __restrict__ x, int H,
                                                          int W, const float4* __restrict__ Wt,
                                                          int K, const int32_t* __restrict__ seg,
                                                          const int32_t* __restrict__ perm,
@@ -28,49 +31,53 @@ __global__ __launch_bounds__(256) void wiener_f32_kernel(const float* __restrict
   const int Wp = W - 7;
   const int32_t* start = seg;
   const int32_t* count = seg + (K + 1);
-  const int32_t* tpre = seg + (2 * K + 1);
+  const int32_t* tinfo = seg + (3 * K + 3);
   const int total = seg[3 * K + 2];
-  const size_t Np8 = (size_t)(H - 7) * Wp * 8;  // floats per row plane of z^
-  const int nwaves = gridDim.x * (blockDim.x >> 6);
-  for (int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); t < total; t += nwaves) {
-    // component of tile t: last k with tpre[k] <= t
-    int lo = 0, hi = K - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tpre[mid] <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    const int k = lo;
-    const int first = (t - tpre[k]) * kWienerTile;
+  // Each workgroup takes a contiguous range of tiles (tiles are ordered by
+  // component, so a range mostly shares one W_k, which then stays in the
+  // CU's L1), and consecutive ranges go to workgroups of the same XCD
+  // (workgroups are dealt round-robin over the 8 XCDs), so each XCD's L2
+  // holds only the filters of its part of the list.
+  const int G = gridDim.x;
+  const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int per = (total + G - 1) / G;
+  const int t_end = min(total, (lb + 1) * per);
+  for (int t = lb * per + (threadIdx.x >> 6); t < t_end; t += 4) {
+    // component of tile t and the tile's index within the component
+    const int info = tinfo[t];
+    const int k = info & 1023;
+    const int first = (info >> 10) * kWienerTile;
     const int n = min(kWienerTile, count[k] - first);
     const int32_t* ids = perm + start[k] + first;
 
-    // patches: lane holds pixels p = 2s + half of patches col and 32 + col
-    const bool v0 = col < n, v1 = 32 + col < n;
+    // patches: lane holds pixels 32 half + s (s = 0..31) -- patch rows
+    // 4 half .. 4 half + 3, read as float4 -- of patch col
+    const bool v0 = col < n;
     const int id0 = v0 ? ids[col] : ids[0];
-    const int id1 = v1 ? ids[32 + col] : ids[0];
     const int r0 = id0 / Wp, c0 = id0 - r0 * Wp;
-    const int r1 = id1 / Wp, c1 = id1 - r1 * Wp;
-    float z0[32], z1[32];
-    double s0 = 0.0, s1 = 0.0;
+    float z0[32];
 #pragma unroll
-    for (int s = 0; s < 32; ++s) {
-      const int dy = s >> 2;
-      const int dx = 2 * (s & 3) + half;
-      z0[s] = x[(size_t)(r0 + dy) * W + c0 + dx];
-      z1[s] = x[(size_t)(r1 + dy) * W + c1 + dx];
-      s0 += (double)z0[s];
-      s1 += (double)z1[s];
+    for (int rr = 0; rr < 4; ++rr) {
+      const float* p0 = x + (size_t)(r0 + 4 * half + rr) * W + c0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float4 a;
+        __builtin_memcpy(&a, p0 + 4 * h, 16);
+        const int o = 8 * rr + 4 * h;
+        z0[o] = a.x;
+        z0[o + 1] = a.y;
+        z0[o + 2] = a.z;
+        z0[o + 3] = a.w;
+      }
     }
+    double s0 = 0.0;
+#pragma unroll
+    for (int s = 0; s < 32; ++s) s0 += (double)z0[s];
     s0 += __shfl_xor(s0, 32);
-    s1 += __shfl_xor(s1, 32);
-    const double m0 = s0 * (1.0 / 64.0), m1 = s1 * (1.0 / 64.0);
+    const double m0 = s0 * (1.0 / 64.0);
 #pragma unroll
-    for (int s = 0; s < 32; ++s) {
-      z0[s] = (float)((double)z0[s] - m0);
-      z1[s] = (float)((double)z1[s] - m1);
-    }
-    const float fm0 = (float)m0, fm1 = (float)m1;
+    for (int s = 0; s < 32; ++s) z0[s] = (float)((double)z0[s] - m0);
+    const float fm0 = (float)m0;
     // one 32-row block of W_k at a time (rows q = 32 qb + ...)
 #pragma unroll
     for (int qb = 0; qb < 2; ++qb) {
@@ -79,31 +86,23 @@ __global__ __launch_bounds__(256) void wiener_f32_kernel(const float* __restrict
 #pragma unroll
       for (int i = 0; i < 8; ++i) A[i] = wp[i * 64];
       f32x16 a0 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      f32x16 a1 = a0;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-#define STEP(E, S)                                                            \
-  a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].E, z0[S], a0, 0, 0, 0);      \
-  a1 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].E, z1[S], a1, 0, 0, 0);
-        STEP(x, 4 * i + 0)
-        STEP(y, 4 * i + 1)
-        STEP(z, 4 * i + 2)
-        STEP(w, 4 * i + 3)
-#undef STEP
+        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].x, z0[4 * i + 0], a0, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].y, z0[4 * i + 1], a0, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].z, z0[4 * i + 2], a0, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].w, z0[4 * i + 3], a0, 0, 0, 0);
       }
-      // accumulator 4 g + e of lane l is pixel q = 32 qb + 8 g + 4 half + e:
-      // row dy = 4 qb + g, columns dx = 4 half + e (one float4 of the row)
+      // accumulator 4 g + e of lane l is pixel q = 32 qb + 8 g + 4 half + e of
+      // patch col; the two halves of the wave write the 128 contiguous bytes
+      // of pixels 32 qb .. 32 qb + 31 of each patch
+      if (v0) {
+        float* zp = Zhat + (size_t)id0 * kP + 32 * qb + 4 * half;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const size_t plane = (size_t)(4 * qb + g) * Np8;
-        if (v0)
-          *reinterpret_cast<float4*>(Zhat + plane + (size_t)id0 * 8 + 4 * half) =
+        for (int g = 0; g < 4; ++g)
+          *reinterpret_cast<float4*>(zp + 8 * g) =
               make_float4(a0[4 * g] + fm0, a0[4 * g + 1] + fm0, a0[4 * g + 2] + fm0,
                           a0[4 * g + 3] + fm0);
-        if (v1)
-          *reinterpret_cast<float4*>(Zhat + plane + (size_t)id1 * 8 + 4 * half) =
-              make_float4(a1[4 * g] + fm1, a1[4 * g + 1] + fm1, a1[4 * g + 2] + fm1,
-                          a1[4 * g + 3] + fm1);
       }
     }
   }
@@ -115,7 +114,8 @@ hipError_t launch_wiener_f32(const float* x, int H, int W, const float* Wt_t, in
   const int Np = (H - 7) * (W - 7);
   const int max_tiles = Np / kWienerTile + K;
   int blocks = (max_tiles + 3) / 4;
-  if (blocks > 2048) blocks = 2048;
+  if (blocks > 4096) blocks = 4096;
+  blocks = (blocks + 7) & ~7;  // whole rounds over the 8 XCDs
   hipLaunchKernelGGL(wiener_f32_kernel, dim3(blocks), dim3(256), 0, st, x, H, W,
                      reinterpret_cast<const float4*>(Wt_t), K, seg, perm, Zhat);
   return hipGetLastError();
