@@ -17,6 +17,14 @@ sys.path.insert(0, ROOT)
 METRIC = "restored Mpixels/s, plain FP32 vs BF16+learned proposal, at dPSNR<=0.05 dB"
 MFMA_F32_PEAK_TFLOPS = 157.3
 MFMA_BF16_PEAK_TFLOPS = 2500.0
+MFMA_FP8_PEAK_TFLOPS = 5000.0
+# per path: (dense MFMA peak of its selection operands, selection kernel, dtype)
+PATH_INFO = {
+    "fp32": (MFMA_F32_PEAK_TFLOPS, "estep_f32_kernel", "f32"),
+    "bf16": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
+    "fp8": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel", "fp8-e4m3"),
+    "bf16+proposal": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
+}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -59,7 +67,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--paths", default="fp32,bf16,bf16+proposal",
+    ap.add_argument("--paths", default="fp32,bf16,fp8,bf16+proposal",
                     help="comma-separated paths to time")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -143,7 +151,7 @@ def main():
         return float(10 * np.log10(255.0 ** 2 / np.mean((x.astype(np.float64) - ref) ** 2)))
 
     want = args.paths.split(",")
-    names = [p for p in ("fp32", "bf16", "bf16+proposal")
+    names = [p for p in ("fp32", "bf16", "fp8", "bf16+proposal")
              if p in want and (p != "bf16+proposal" or have_prop)]
     for p in ("fp32", "bf16"):
         if p not in names:
@@ -158,17 +166,19 @@ def main():
     head = max(ok, key=lambda p: paths[p]["mpix_s"])
     hp = paths[head]
     dpsnr_bf16 = bf16["dpsnr"]
-    peak = MFMA_BF16_PEAK_TFLOPS if head != "fp32" else MFMA_F32_PEAK_TFLOPS
+    peak, sel_kernel, head_dtype = PATH_INFO[head]
+    if hp["dominant"] == "propose":
+        peak = MFMA_BF16_PEAK_TFLOPS
     res = {
         "metric": METRIC, "value": round(hp["mpix_s"], 4), "unit": "Mpixels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(hp["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if head == "fp32" else "bf16", "data": "synthetic",
+        "dtype": head_dtype, "data": "synthetic",
         "config": {"workload": f"{H}x{W} dead leaves + 1/f texture (std 10), sigma 25, "
                                f"K={K} GMM, T=5 HQS iterations",
                    "path": head, "K": K, "image": [H, W], "T": 5},
         "roofline": {"bound": "mfma",
-                     "kernel": {"select": "estep_f32_kernel" if head == "fp32" else "estep_bf16_kernel",
+                     "kernel": {"select": sel_kernel,
                                 "propose": "propose_bf16_kernel"}.get(hp["dominant"], hp["dominant"]),
                      "achieved": round(hp["dominant_tflops"], 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(hp["dominant_tflops"] / peak, 4),
@@ -182,6 +192,13 @@ def main():
                         "dpsnr_vs_fp32_path_db": round(dpsnr_bf16, 4)},
         "speedup_vs_plain_fp32": round(hp["mpix_s"] / fp32["mpix_s"], 3),
     }
+    if "fp8" in paths:
+        p8 = paths["fp8"]
+        res["fp8_full_k"] = {"mpix_s": round(p8["mpix_s"], 4), "estep_tflops": round(p8["estep_tflops"], 2),
+                             "estep_frac_of_fp8_peak": round(p8["estep_tflops"] / MFMA_FP8_PEAK_TFLOPS, 4),
+                             "stages_ms": p8["stages_ms"], "psnr_db": round(p8["psnr"], 4),
+                             "dpsnr_vs_fp32_path_db": round(p8["dpsnr"], 4),
+                             "speedup_vs_plain_fp32": round(p8["mpix_s"] / fp32["mpix_s"], 3)}
     if "bf16+proposal" in paths:
         pp = paths["bf16+proposal"]
         res["bf16_proposal"] = {"mpix_s": round(pp["mpix_s"], 4), "stages_ms": pp["stages_ms"],

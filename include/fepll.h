@@ -66,9 +66,11 @@ typedef struct {
 
 typedef struct {
   /* Arithmetic of the projection c = U_k^t z~ in the selection step:
-   * FEPLL_FP32 (default), FEPLL_BF16 or FEPLL_FP8 (e4m3), always with float32
-   * accumulation; log-determinant terms, patch estimation, reprojection and
-   * image estimation stay float32.                                         */
+   * FEPLL_FP32 (default), FEPLL_BF16, or FEPLL_FP8 (OCP e4m3 operands with a
+   * power-of-two scale per component and per patch that brings the largest
+   * magnitude to at most 448), always with float32 accumulation;
+   * log-determinant terms, patch estimation, reprojection and image
+   * estimation stay float32.  The proposal path needs FEPLL_BF16.         */
   int32_t precision;
   /* FEPLL_FP32 only: every patch whose float32 selection is not certified
    * by the rounding-error bound of its costs is re-selected in float64, so

@@ -1,0 +1,169 @@
+"""Reduced-precision Gaussian selection -- the reference definitions.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+benchmark's CPU-baseline leg may import this module; the restoration library
+never does, and this module imports nothing from it.
+
+The paper evaluates the selection cost of Alg. 1 (Gaussian selection, in the
+eigenspace form of Sec. 2.1) in full precision.  The library also offers two
+reduced-precision selection modes -- a builder's choice, not the paper's --
+in which the projections c = Ut_k^t z~, Ut_k = U_k diag(nu_k)^-1/2, take
+rounded operands:
+
+* ``"bf16"``: z~ and Ut_k rounded to bfloat16 (8 significant bits, nearest,
+  ties to even);
+* ``"fp8"``:  z~ and Ut_k scaled by powers of two, 2^-e_z per patch and
+  2^-e_k per component, e the smallest integer that brings the largest
+  magnitude to at most 448, then rounded to e4m3 (OCP "E4M3FN": 4 exponent
+  bits with bias 7, 3 mantissa bits, subnormal step 2^-9, largest finite 448,
+  no infinities; nearest, ties to even); the scales are applied back
+  exactly.
+
+In both modes the cost is L_k + sum_j c_j^2 with L_k rounded from float64 to
+float32, and the products are exact: this module evaluates them in float64
+from the rounded operands.  What the GPU adds on top is float32 (or wider)
+accumulation, so its costs must agree with these to within that rounding.
+
+The DC-removed patch z~ = z - m is formed in float32, with the patch mean m
+accumulated in float32 in a fixed order (part of each mode's definition):
+
+* ``"bf16"``: s_g = sum, in order, of patch rows g and 4 + g (16 pixels,
+  row g first) for g = 0..3, then m = ((s_0 + s_1) + (s_2 + s_3)) / 64;
+* ``"fp8"``:  s_h = sum, in order, of pixels 32 h .. 32 h + 31 for h = 0, 1,
+  then m = (s_0 + s_1) / 64.
+
+Ut_k is formed in float64 and rounded to float32 before the format rounding
+(for fp8: Ut_k 2^-e_k rounded to float32, then to e4m3).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import epll64 as o
+
+E4M3_MAX = 448.0
+
+
+# ----------------------------------------------------------- rounding
+
+def round_bf16(x) -> np.ndarray:
+    """Nearest bfloat16 value (ties to even) of float32 x, as float32.
+
+    bfloat16 keeps float32's exponent range and 8 significant bits: on the
+    binade [2^(e-1), 2^e) the step is 2^(e-8), and below 2^-126 the step is
+    the smallest bfloat16 subnormal, 2^-133."""
+    x = np.asarray(x, np.float32).astype(np.float64)
+    _, e = np.frexp(x)
+    step = np.ldexp(1.0, np.maximum(e - 8, -133))
+    r = np.rint(x / step) * step  # rint: nearest, ties to even
+    return r.astype(np.float32)
+
+
+def round_e4m3(x) -> np.ndarray:
+    """Nearest e4m3 value (ties to even) of x, in float64; NaN where the
+    rounded magnitude exceeds 448 (the format has no infinity and the
+    conversion does not saturate).
+
+    Normal binades [2^(e-1), 2^e) for e - 1 >= -6 have the step 2^(e-4)
+    (3 mantissa bits); below 2^-6 the subnormal step is 2^-9."""
+    x = np.asarray(x, np.float64)
+    _, e = np.frexp(x)
+    step = np.ldexp(1.0, np.maximum(e - 4, -9))
+    r = np.rint(x / step) * step
+    return np.where(np.abs(r) > E4M3_MAX, np.nan, r)
+
+
+def pow2_exponent(mx) -> np.ndarray:
+    """Smallest integer e with mx * 2^-e <= 448 (0 for mx = 0), at least -127."""
+    mx = np.asarray(mx, np.float64)
+    out = np.zeros(mx.shape, np.int64)
+    pos = mx > 0
+    e = np.ceil(np.log2(np.where(pos, mx, 1.0) / E4M3_MAX)).astype(np.int64)
+    # settle the float log2 exactly: mx 2^-e <= 448 < mx 2^-(e-1)
+    for _ in range(2):
+        e = np.where(np.ldexp(mx, -e) > E4M3_MAX, e + 1, e)
+        e = np.where(np.ldexp(mx, -(e - 1)) <= E4M3_MAX, e - 1, e)
+    out[pos] = e[pos]
+    return np.maximum(out, -127)
+
+
+# ----------------------------------------------------------- operands
+
+def _seq_sum32(cols: np.ndarray) -> np.ndarray:
+    """float32 sum of the columns of cols, left to right."""
+    s = cols[:, 0].astype(np.float32)
+    for i in range(1, cols.shape[1]):
+        s = (s + cols[:, i]).astype(np.float32)
+    return s
+
+
+def dc_removed32(Z: np.ndarray, mode: str) -> np.ndarray:
+    """z~ = z - m in float32 for float32 patches Z (N x 64), m as in the
+    module docstring."""
+    Z = np.asarray(Z, np.float32)
+    if mode == "bf16":
+        s = []
+        for g in range(4):
+            cols = np.concatenate([Z[:, 8 * g:8 * g + 8], Z[:, 8 * (4 + g):8 * (4 + g) + 8]], 1)
+            s.append(_seq_sum32(cols))
+        tot = ((s[0] + s[1]).astype(np.float32) + (s[2] + s[3]).astype(np.float32)).astype(np.float32)
+    elif mode == "fp8":
+        tot = (_seq_sum32(Z[:, :32]) + _seq_sum32(Z[:, 32:])).astype(np.float32)
+    else:
+        raise ValueError(mode)
+    m = (tot * np.float32(1.0 / 64.0)).astype(np.float32)
+    return (Z - m[:, None]).astype(np.float32)
+
+
+def patch_operand(Zt32: np.ndarray, mode: str) -> np.ndarray:
+    """The rounded patch operand (N x 64, float64 values, scale applied)."""
+    if mode == "bf16":
+        return round_bf16(Zt32).astype(np.float64)
+    e = pow2_exponent(np.max(np.abs(Zt32.astype(np.float64)), axis=1))
+    q = round_e4m3(np.ldexp(Zt32.astype(np.float64), -e[:, None]))
+    return np.ldexp(q, e[:, None])
+
+
+def basis_operand(U: np.ndarray, nu: np.ndarray, mode: str) -> np.ndarray:
+    """The rounded Ut_k = U_k diag(nu_k)^-1/2 (K x 64 x 64, float64 values,
+    scale applied)."""
+    Ut = np.asarray(U, np.float64) / np.sqrt(nu)[:, None, :]
+    if mode == "bf16":
+        return round_bf16(Ut.astype(np.float32)).astype(np.float64)
+    e = pow2_exponent(np.max(np.abs(Ut), axis=(1, 2)))
+    q = round_e4m3(np.ldexp(Ut, -e[:, None, None]).astype(np.float32).astype(np.float64))
+    return np.ldexp(q, e[:, None, None])
+
+
+# ----------------------------------------------------------- selection
+
+def lowp_costs(x, U, lam, w, beta, mode: str, acc_eps: float | None = None):
+    """Selection costs (Np x K, float64) of every valid patch of the float32
+    image x in a reduced-precision mode: float32(L_k) + sum_j c_j^2 with c
+    the exact product of the rounded operands.
+
+    With ``acc_eps``, also return a bound (Np x K) on how far an evaluation
+    may land from these costs when it accumulates each projection c_j with a
+    relative error of at most acc_eps of sum_p |Ut[p,j] z[p]| and the 64
+    squares and L_k in float32."""
+    x = np.asarray(x, np.float32)
+    H, W = x.shape
+    r, c = o.patch_corners(H, W)
+    Z = o.extract(x.astype(np.float64), r, c).astype(np.float32)  # exact: x is float32
+    Zq = patch_operand(dc_removed32(Z, mode), mode)
+    _, nu, _, L = o.eigen_terms(np.asarray(lam, np.float64), np.asarray(w, np.float64), beta)
+    Uq = basis_operand(U, nu, mode)
+    L32 = L.astype(np.float32).astype(np.float64)
+    K = Uq.shape[0]
+    cost = np.empty((Zq.shape[0], K))
+    bound = np.empty_like(cost) if acc_eps is not None else None
+    u32 = 2.0 ** -24
+    for k in range(K):
+        C = Zq @ Uq[k]
+        sq = np.sum(C * C, axis=1)
+        cost[:, k] = L32[k] + sq
+        if bound is not None:
+            d = acc_eps * (np.abs(Zq) @ np.abs(Uq[k]))
+            bound[:, k] = (np.sum(2 * np.abs(C) * d + d * d, axis=1)
+                           + 65 * u32 * (sq + np.abs(L32[k])))
+    return (cost, bound) if bound is not None else cost

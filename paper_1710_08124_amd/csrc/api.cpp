@@ -54,6 +54,8 @@ struct fepll_gmm {
   float* L32 = nullptr;
   double* L64 = nullptr;
   double* invnu64 = nullptr;
+  uint8_t* Uf = nullptr;
+  int32_t* Ue = nullptr;
   // scratch
   size_t np_cap = 0, px_cap = 0;
   int32_t* labels = nullptr;
@@ -140,6 +142,8 @@ fepll_status ensure_consts(fepll_gmm* g, const Schedule& s, hipStream_t st) {
     dfree(g->L32);
     dfree(g->L64);
     dfree(g->invnu64);
+    dfree(g->Uf);
+    dfree(g->Ue);
     g->T_cap = 0;
     const size_t K = g->K;
     HIPX(dalloc(&g->Ut, (size_t)s.T * K * kTileStride));
@@ -148,12 +152,14 @@ fepll_status ensure_consts(fepll_gmm* g, const Schedule& s, hipStream_t st) {
     HIPX(dalloc(&g->L32, (size_t)s.T * K));
     HIPX(dalloc(&g->L64, (size_t)s.T * K));
     HIPX(dalloc(&g->invnu64, (size_t)s.T * K * kP));
+    HIPX(dalloc(&g->Uf, (size_t)s.T * K * kTileStride));
+    HIPX(dalloc(&g->Ue, (size_t)s.T * K));
     g->T_cap = s.T;
   }
   {
     StageTimer tm(g, 5, st);
     HIPX(launch_prep(g->U64, g->lam64, g->w64, g->K, s, g->Ut, g->Ub, g->Wt, g->L32, g->L64,
-                     g->invnu64, st));
+                     g->invnu64, g->Uf, g->Ue, st));
   }
   g->sched = s;
   g->have_sched = true;
@@ -237,8 +243,6 @@ hipError_t copy_out(fepll_image* im, const float* src, hipStream_t st) {
 fepll_status check_opt(const fepll_gmm* g, const fepll_options* o) {
   if (o->precision != FEPLL_FP32 && o->precision != FEPLL_BF16 && o->precision != FEPLL_FP8)
     return fail(FEPLL_EINVAL, "options.precision must be FEPLL_FP32, FEPLL_BF16 or FEPLL_FP8");
-  if (o->precision == FEPLL_FP8)
-    return fail(FEPLL_EUNSUPPORTED, "FEPLL_FP8 projections are not built in this library");
   if (o->use_proposal) {
     if (!g->has_proposal) return fail(FEPLL_EINVAL, "no proposal network is loaded");
     if (o->top_m < 1 || o->top_m > 8 || o->top_m > g->K)
@@ -261,6 +265,16 @@ fepll_status run_select(fepll_gmm* g, const float* x, int H, int W, int t, doubl
                         float* best, float* second, int32_t* flags, hipStream_t st) {
   const int Np = (H - 7) * (W - 7);
   const size_t K = g->K;
+  if (precision == FEPLL_FP8) {
+    if (flags) {
+      hipLaunchKernelGGL(zero_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, flags, Np);
+      HIPX(hipGetLastError());
+    }
+    StageTimer tm(g, 0, st);
+    HIPX(launch_estep_fp8(x, H, W, g->Uf + (size_t)t * K * kTileStride, g->Ue + (size_t)t * K,
+                          g->L32 + (size_t)t * K, g->K, labels, best, second, st));
+    return FEPLL_OK;
+  }
   if (precision == FEPLL_BF16) {
     if (flags) {
       hipLaunchKernelGGL(zero_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, flags, Np);
@@ -442,6 +456,8 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->L32);
   dfree(g->L64);
   dfree(g->invnu64);
+  dfree(g->Uf);
+  dfree(g->Ue);
   dfree(g->labels);
   dfree(g->list);
   dfree(g->count);

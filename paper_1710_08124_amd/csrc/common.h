@@ -17,6 +17,10 @@
 //    operand (v_mfma_f32_16x16x32_bf16), entry Ut_k[p][j] with
 //    j = 16*rb + (l & 15) and p = 32*t + 8*(l >> 4) + e for eigen block rb
 //    (0..3), depth step t (0..1), lane l, element e.
+//  * Uf   e4m3 bytes, [T][K][2][2][64][16]: the 8-bit E-step A operand
+//    (v_mfma_scale_f32_32x32x64_f8f6f4), byte b of [t][k][rb][part][l] is
+//    Ut_k[p][j] 2^-e_k with j = 32*rb + (l & 31), p = 32*(l >> 5) + 16*part + b;
+//    Ue int32 [T][K] holds the E8M0 code e_k + 127 of each component's scale.
 //  * L32  float,  [T][K]: L_k = iota_k + sum_j log nu_kj rounded from float64.
 //  * L64  double, [T][K] and invnu64 double [T][K][64]: the same terms in
 //    float64 for the re-selection of uncertified patches.
@@ -42,7 +46,7 @@ struct Schedule {
 
 hipError_t launch_prep(const double* U64, const double* lam64, const double* w64, int K,
                        const Schedule& sch, float* Ut, uint16_t* Ub, float* Wt, float* L32,
-                       double* L64, double* invnu64, hipStream_t st);
+                       double* L64, double* invnu64, uint8_t* Uf, int32_t* Ue, hipStream_t st);
 
 hipError_t launch_estep_f32(const float* x, int H, int W, const float* Ut_t, const float* L32_t,
                             int K, double beta, int32_t* labels, float* best, float* second,
@@ -51,6 +55,10 @@ hipError_t launch_estep_f32(const float* x, int H, int W, const float* Ut_t, con
 hipError_t launch_estep_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
                              const float* L32_t, int K, int32_t* labels, float* best,
                              float* second, hipStream_t st);
+
+hipError_t launch_estep_fp8(const float* x, int H, int W, const uint8_t* Uf_t,
+                            const int32_t* Ue_t, const float* L32_t, int K, int32_t* labels,
+                            float* best, float* second, hipStream_t st);
 
 hipError_t launch_recheck_f64(const float* x, int H, int W, const double* U64,
                               const double* invnu64_t, const double* L64_t, int K,

@@ -36,6 +36,7 @@
 // component, the next component's operand already loading).
 #include "common.h"
 #include "propose.h"
+#include "wave_ops.h"
 
 namespace fepll {
 
@@ -56,29 +57,6 @@ __device__ __forceinline__ uint32_t pack2(float a, float b) {
 __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
-}
-// best / second smallest cost and the argmin (first k on ties), branch-free
-__device__ __forceinline__ void keep_best(float cost, int k, float& best, float& second,
-                                          int& bk) {
-  const bool better = cost < best;
-  second = better ? best : fminf(second, cost);
-  bk = better ? k : bk;
-  best = better ? cost : best;
-}
-// Exchange between lane halves (v_permlane32_swap: lanes 32..63 of a with
-// lanes 0..31 of b) and between 16-lane rows of each half
-// (v_permlane16_swap: rows 1 and 3 of a with rows 0 and 2 of b).  After
-// swap(a, b), a + b is, in lanes of the lower half (row), the pair sum of a
-// and, in the upper half (row), the pair sum of b.
-__device__ __forceinline__ float pair_sum32(float a, float b) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false,
-                                                  false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-__device__ __forceinline__ float pair_sum16(float a, float b) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false,
-                                                  false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 __device__ __forceinline__ bool has(const uint4& c, int k) {
   const uint32_t w[4] = {c.x, c.y, c.z, c.w};

@@ -1,0 +1,167 @@
+// Gaussian selection with 8-bit float projections (Alg. 1 patch extraction
+// + Gaussian selection, eigenspace form of Sec. 2.1), the lowest-precision
+// mode: the DC-removed patches and the scaled eigenbases
+// Ut_k = U_k diag(nu_k)^-1/2 are rounded to e4m3 (OCP, largest finite 448)
+// after a power-of-two scale per component (Ut_k) and per patch (z~) that
+// brings their largest magnitude into (224, 448].  The matrix cores apply
+// both scales (v_mfma_scale_f32_32x32x64_f8f6f4 takes one 8-bit exponent per
+// operand row and column), so the accumulators hold c = Ut_k^t z~ in the
+// original units; squared norms, L_k and the argmin are float32, as in the
+// bfloat16 mode.  Labels are an approximation whose agreement with the
+// exact selection is measured.
+//
+// One 32x32x64 MFMA multiplies 32 eigen-directions by 32 patches over all 64
+// pixels: lane l supplies the 32 bytes of pixels 32 (l >> 5) + b (b = 0..31,
+// patch rows 4 (l >> 5) .. 4 (l >> 5) + 3) of patch l & 31, and the A operand
+// the same pixels of direction 32 rb + (l & 31).  A wave holds 128 patches
+// (four blocks of 32) for its whole component loop; per component it issues
+// 2 (eigen blocks) x 4 (patch blocks) MFMAs and 128 float32 FMAs of squares,
+// then one exchange between lane halves leaves every lane owning 2 patches.
+// The per-component operand (4 KB) is staged through double-buffered LDS
+// shared by the workgroup's 4 waves.
+#include "common.h"
+#include "wave_ops.h"
+
+namespace fepll {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+constexpr int PB = 4;  // blocks of 32 patches per wave
+
+// Power-of-two scale of a block whose largest magnitude is mx: the smallest
+// e with mx * 2^-e <= 448, returned with the block's E8M0 code e + 127.
+__device__ __forceinline__ int fp8_exponent(float mx) {
+  if (!(mx > 0.f)) return 0;
+  int ex;
+  const float f = frexpf(mx, &ex);  // mx = f 2^ex, f in [0.5, 1)
+  int e = (f <= 0.875f) ? ex - 9 : ex - 8;
+  return max(e, -127);
+}
+
+// e4m3 B operand (32 bytes) and E8M0 scale of the patch at (r, c) for lane
+// half h: rows 4 h .. 4 h + 3.  The mean is a float32 sum of the lane's 32
+// pixels in order, plus the other half's sum.
+__device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, int r, int c,
+                                            int h, i32x8& zq, int& code) {
+  float v[32];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const float* row = x + (size_t)(r + 4 * h + rr) * W + c;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[8 * rr + e] = row[e];
+  }
+  float s = v[0];
+#pragma unroll
+  for (int i = 1; i < 32; ++i) s += v[i];
+  s += __shfl_xor(s, 32);
+  const float m = s * (1.f / 64.f);
+  float mx = 0.f;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    v[i] -= m;
+    mx = fmaxf(mx, fabsf(v[i]));
+  }
+  mx = fmaxf(mx, __shfl_xor(mx, 32));
+  const int e = fp8_exponent(mx);
+  code = e + 127;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) {
+    int p = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(v[4 * w], -e), ldexpf(v[4 * w + 1], -e), 0,
+                                            false);
+    p = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(v[4 * w + 2], -e), ldexpf(v[4 * w + 3], -e), p,
+                                        true);
+    zq[w] = p;
+  }
+}
+}  // namespace
+
+__global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
+    const float* __restrict__ x, int H, int W, const uint4* __restrict__ Uf,
+    const int32_t* __restrict__ Ue, const float* __restrict__ L, int K,
+    int32_t* __restrict__ labels, float* __restrict__ best, float* __restrict__ second) {
+  __shared__ uint4 Ash[2][256];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const int col = lane & 31;
+  const int Hp = H - 7, Wp = W - 7;
+
+  const int r = blockIdx.y * 4 + wave;
+  const int c0 = blockIdx.x * (32 * PB);
+  i32x8 zq[PB];
+  int zc[PB];
+  int idx[PB];
+  bool valid[PB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb) {
+    const int c = c0 + 32 * pb + col;
+    valid[pb] = (r < Hp) && (c < Wp);
+    const int rr = min(r, Hp - 1), cc = min(c, Wp - 1);
+    idx[pb] = rr * Wp + cc;
+    load_patch8(x, W, rr, cc, h, zq[pb], zc[pb]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // lane's own patches after the half exchange: blocks h and 2 + h
+  const int iA = h ? idx[1] : idx[0], iB = h ? idx[3] : idx[2];
+  const bool vA = h ? valid[1] : valid[0], vB = h ? valid[3] : valid[2];
+
+  float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
+  int kA = 0, kB = 0;
+  uint4 pre = Uf[threadIdx.x];
+  for (int k = 0; k < K; ++k) {
+    uint4* As = Ash[k & 1];
+    As[threadIdx.x] = pre;
+    __syncthreads();
+    if (k + 1 < K) pre = Uf[(size_t)(k + 1) * 256 + threadIdx.x];
+    const int ek = Ue[k];
+    float q[PB];
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      const uint4 a0 = As[(2 * rb) * 64 + lane], a1 = As[(2 * rb + 1) * 64 + lane];
+      const i32x8 A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
+                       (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+      f32x16 acc[PB];
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) {
+        acc[pb] = (f32x16){0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                           0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, zq[pb], acc[pb], 0, 0, 0, ek,
+                                                                  0, zc[pb]);
+      }
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+    }
+    const float Lk = L[k];
+    const float cA = Lk + pair_sum32(q[0], q[1]);
+    const float cB = Lk + pair_sum32(q[2], q[3]);
+    keep_best(cA, k, bA, sA, kA);
+    keep_best(cB, k, bB, sB, kB);
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const bool v = p ? vB : vA;
+    if (!v) continue;
+    const int i = p ? iB : iA;
+    labels[i] = p ? kB : kA;
+    if (best) best[i] = p ? bB : bA;
+    if (second) second[i] = p ? sB : sA;
+  }
+}
+
+hipError_t launch_estep_fp8(const float* x, int H, int W, const uint8_t* Uf_t,
+                            const int32_t* Ue_t, const float* L32_t, int K, int32_t* labels,
+                            float* best, float* second, hipStream_t st) {
+  const int Hp = H - 7, Wp = W - 7;
+  dim3 grid((Wp + 32 * PB - 1) / (32 * PB), (Hp + 3) / 4);
+  hipLaunchKernelGGL(estep_fp8_kernel, grid, dim3(256), 0, st, x, H, W,
+                     reinterpret_cast<const uint4*>(Uf_t), Ue_t, L32_t, K, labels, best, second);
+  return hipGetLastError();
+}
+
+}  // namespace fepll

@@ -15,7 +15,9 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
                                                    float* __restrict__ Wt,
                                                    float* __restrict__ L32,
                                                    double* __restrict__ L64,
-                                                   double* __restrict__ invnu64) {
+                                                   double* __restrict__ invnu64,
+                                                   uint8_t* __restrict__ Uf,
+                                                   int32_t* __restrict__ Ue) {
   const int k = blockIdx.x;
   const int t = blockIdx.y;
   const double beta = sch.beta[t];
@@ -65,14 +67,48 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
     for (int jj = 0; jj < kP; ++jj) acc += Us[q * kP + jj] * gam[jj] * Us[pw * kP + jj];
     wt[idx] = (float)acc;
   }
+
+  // e4m3 table: Ut_k scaled by 2^-e, e the smallest exponent that brings
+  // max |Ut_k| to at most 448 (the largest finite e4m3), rounded float64 ->
+  // float32 -> e4m3 (nearest even); the scale's E8M0 code is e + 127
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < kP * kP; i += blockDim.x)
+    mx = fmax(mx, fabs(Us[i] * rs[i & (kP - 1)]));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  mx = red[0];
+  int e = 0;
+  if (mx > 0.0) {
+    int ex;
+    const double f = frexp(mx, &ex);
+    e = (f <= 0.875) ? ex - 9 : ex - 8;
+    e = max(-127, min(e, 127));
+  }
+  if (threadIdx.x == 0) Ue[t * K + k] = e + 127;
+  uint8_t* uf = Uf + ((size_t)t * K + k) * kTileStride;
+  for (int bi = threadIdx.x; bi < kTileStride; bi += blockDim.x) {
+    // byte bb of uint4 u = (2 rb + part) * 64 + l: row j = 32 rb + (l & 31),
+    // pixel p = 32 (l >> 5) + 16 part + bb
+    const int bb = bi & 15, u = bi >> 4;
+    const int l = u & 63, part = (u >> 6) & 1, rb = u >> 7;
+    const int j = 32 * rb + (l & 31);
+    const int p = 32 * (l >> 5) + 16 * part + bb;
+    const float q = (float)ldexp(Us[p * kP + j] * rs[j], -e);
+    uf[bi] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(q, 0.f, 0, false) & 0xff);
+  }
 }
 
 hipError_t launch_prep(const double* U64, const double* lam64, const double* w64, int K,
                        const Schedule& sch, float* Ut, uint16_t* Ub, float* Wt, float* L32,
-                       double* L64, double* invnu64, hipStream_t st) {
+                       double* L64, double* invnu64, uint8_t* Uf, int32_t* Ue, hipStream_t st) {
   dim3 grid(K, sch.T);
   hipLaunchKernelGGL(prep_kernel, grid, dim3(256), 0, st, U64, lam64, w64, K, sch, Ut, Ub, Wt,
-                     L32, L64, invnu64);
+                     L32, L64, invnu64, Uf, Ue);
   return hipGetLastError();
 }
 

@@ -1,13 +1,20 @@
-"""Reduced-precision projections (bfloat16) against the FP64 oracle.
+"""Reduced-precision projections (bfloat16, e4m3) against the oracles.
 
-In this mode the selection is an approximation: the tests state its label
-agreement with the exact selection and bound its PSNR loss, which is the
-quality criterion of the mode (within 0.05 dB of the FP64 oracle)."""
+Two kinds of check:
+* the selection kernels against the definition of their mode
+  (oracle/lowp.py: rounded operands, exact products): teacher-forced, the
+  GPU cost of the chosen label equals the definition's cost of that label to
+  float32 accumulation accuracy, and no component beats it by more;
+* the modes against the exact FP64 restoration: their selection is an
+  approximation, so the tests state its label agreement with the exact
+  selection and bound its PSNR loss, the quality criterion of the modes
+  (within 0.05 dB of the FP64 oracle)."""
 import numpy as np
 import pytest
 
 import fepll_synth as fs
 from oracle import epll64 as o
+from oracle import lowp
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -28,8 +35,13 @@ def f32(a):
     return np.asarray(a, np.float32).astype(np.float64)
 
 
+# minimum first-iteration label agreement with the exact selection, per mode
+MIN_AGREE = {"bf16": 0.9, "fp8": 0.6}
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
 @pytest.mark.parametrize("case", ["c1", "k200_10", "k200_25", "k200_50"])
-def test_bf16_quality(F, case):
+def test_lowp_quality(F, case, mode):
     if case == "c1":
         c = fs.config_c1()
         x, y = c["x"], c["y"]
@@ -41,18 +53,57 @@ def test_bf16_quality(F, case):
     y32 = f32(y)
     ref, hist = o.restore(y32, c["U"], c["lam"], c["w"], sigma, trace=True)
     g = F.GMM(c["U"], c["lam"], c["w"])
-    got, lab = F.restore(g, dev(y32), sigma, precision="bf16", return_labels=True)
+    got, lab = F.restore(g, dev(y32), sigma, precision=mode, return_labels=True)
     got = got.cpu().numpy().astype(np.float64)
     lab = lab.cpu().numpy()
     # teacher-forced first iteration: agreement of the selection alone
     agree0 = float(np.mean(lab[0] == hist[0]["labels"]))
     agree = [float(np.mean(lab[t] == hist[t]["labels"])) for t in range(5)]
     dpsnr = o.psnr(x, ref) - o.psnr(x, got)
-    print(f"{case}: label agreement first iteration {agree0:.4f}, per iteration "
+    print(f"{mode} {case}: label agreement first iteration {agree0:.4f}, per iteration "
           f"{np.round(agree, 4).tolist()}, dPSNR {dpsnr:+.4f} dB, "
           f"max|diff| {np.abs(got - ref).max():.3f}")
-    assert agree0 > 0.9
+    assert agree0 > MIN_AGREE[mode]
     assert abs(dpsnr) <= 0.05
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
+@pytest.mark.parametrize("sigma,t,shape", [(25, 0, (96, 130)), (25, 4, (96, 130)),
+                                           (10, 2, (40, 300)), (50, 1, (71, 8))])
+def test_lowp_select_matches_definition(F, mode, sigma, t, shape):
+    """Teacher-forced: GPU selection in a reduced-precision mode against the
+    mode's definition on the same float32 image (patch rows span several
+    128-patch tiles and a ragged tail; one case is a single patch column)."""
+    c = fs.config_c2(sigma)
+    H, W = shape
+    x = np.asarray(c["y"][150:150 + H, 90:90 + W], np.float32)
+    beta = float(o.default_betas(sigma)[t])
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    lab, best, second, _ = F.select(g, dev(x), beta, precision=mode)
+    lab, best, second = (v.cpu().numpy() for v in (lab, best, second))
+    # accumulation error of one 64-term projection, relative to the sum of
+    # the magnitudes of its products: float32 for bfloat16 operands; the
+    # e4m3 matrix-core instruction accumulates more coarsely (measured near
+    # 2^-17 on random e4m3 operands), bounded here by 2^-15
+    eps = {"bf16": 64 * 2.0 ** -24, "fp8": 2.0 ** -15}[mode]
+    cost, bnd = lowp.lowp_costs(x, c["U"], c["lam"], c["w"], beta, mode, acc_eps=eps)
+    n = cost.shape[0]
+    i = np.arange(n)
+    tol = bnd.max(1)
+    dev_best = np.abs(best - cost[i, lab])
+    lead = cost[i, lab] - cost.min(1)
+    srt = np.sort(cost, 1)
+    agree = float(np.mean(lab == cost.argmin(1)))
+    print(f"{mode} sigma {sigma} t {t} {shape}: max |best - def| / tol "
+          f"{np.max(dev_best / tol):.3f}, max lead / tol {np.max(lead / tol):.3f}, "
+          f"agreement {agree:.5f}")
+    assert np.all(dev_best <= tol)
+    assert np.all(lead <= 2 * tol)
+    # second: the definition's second-smallest cost within the same bound
+    assert np.all(np.abs(second - srt[:, 1]) <= 3 * tol)
+    # labels differ only where the definition has a near-tie
+    gap = srt[:, 1] - srt[:, 0]
+    assert np.all((lab == cost.argmin(1)) | (gap <= 2 * tol))
 
 
 def test_bf16_select_shape_and_range(F):

@@ -1,0 +1,123 @@
+"""Pins of the reduced-precision reference definitions (oracle/lowp.py).
+
+The rounding functions are written from the two formats' definitions; here
+they are held against PyTorch's own float32 -> bfloat16 and
+float32 -> float8_e4m3fn conversions (library routines, nearest-even), and
+the costs against the exact float64 costs where rounding is exact and
+against the rounding-error bound elsewhere."""
+import numpy as np
+import pytest
+
+import fepll_synth as fs
+from oracle import epll64 as o
+from oracle import lowp
+
+torch = pytest.importorskip("torch")
+
+
+def _probe_values(seed, n=200_000):
+    rng = np.random.default_rng(seed)
+    mag = np.ldexp(rng.uniform(1.0, 2.0, n), rng.integers(-14, 10, n))
+    x = (mag * rng.choice([-1.0, 1.0], n)).astype(np.float32)
+    return x
+
+
+def test_round_bf16_matches_torch():
+    x = _probe_values(1)
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    np.testing.assert_array_equal(lowp.round_bf16(x), want)
+
+
+def test_round_e4m3_matches_torch():
+    x = _probe_values(2)
+    x = x[np.abs(x) < 464.0]
+    # values at and between grid points, ties included
+    grid = np.unique(np.abs(lowp.round_e4m3(np.linspace(-448, 448, 20001))))
+    mids = ((grid[1:] + grid[:-1]) / 2).astype(np.float32)
+    x = np.concatenate([x, mids, -mids, grid.astype(np.float32)])
+    want = torch.from_numpy(x).to(torch.float8_e4m3fn).to(torch.float32).numpy()
+    got = lowp.round_e4m3(x)
+    np.testing.assert_array_equal(got, want.astype(np.float64))
+
+
+def test_e4m3_grid():
+    # 0, 7 subnormals and 15 binades x 8 mantissas less the NaN code: 127 magnitudes
+    x = np.concatenate([np.linspace(0.0, 0.03, 30001), np.linspace(-500, 500, 400001)])
+    grid = np.unique(np.abs(lowp.round_e4m3(x)))
+    grid = grid[np.isfinite(grid)]
+    assert grid[-1] == 448.0 and grid[1] == 2.0 ** -9
+    assert len(grid) == 127
+    assert np.isnan(lowp.round_e4m3(465.0)) and lowp.round_e4m3(464.0) == 448.0
+
+
+def test_pow2_exponent():
+    rng = np.random.default_rng(3)
+    mx = np.ldexp(rng.uniform(0.5, 1.0, 10000), rng.integers(-60, 60, 10000))
+    mx[:4] = [448.0, 448.0 * 2 ** 5, 449.0, 447.0]
+    e = lowp.pow2_exponent(mx)
+    assert np.all(np.ldexp(mx, -e) <= 448.0)
+    assert np.all(np.ldexp(mx, -(e - 1)) > 448.0)
+    assert list(e[:4]) == [0, 5, 1, 0]
+    assert lowp.pow2_exponent(0.0) == 0
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
+def test_dc_removed_orders(mode):
+    rng = np.random.default_rng(4)
+    Z = rng.uniform(0, 255, (500, 64)).astype(np.float32)
+    zt = lowp.dc_removed32(Z, mode)
+    # the float32 mean differs from the exact one by a few float32 ulps only
+    exact = Z.astype(np.float64) - Z.astype(np.float64).mean(1, keepdims=True)
+    assert np.max(np.abs(zt - exact)) < 64 * 2 ** -24 * 255 * 2
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
+def test_costs_exact_when_operands_are_representable(mode):
+    # U_k a signed permutation and nu_kj = 4^n (nu^-1/2 a power of two);
+    # the image 100 + 2 checker + stripes of period 4 (columns) and 2 (rows)
+    # has, in every 8x8 patch, the mean 100 exactly and z~ in
+    # {+-0.5, +-1.5, +-2.5, +-3.5}: every operand is exact in both formats,
+    # so the costs are the float64 ones up to the float32 rounding of L_k
+    rng = np.random.default_rng(5)
+    K = 3
+    U = np.zeros((K, 64, 64))
+    for k in range(K):
+        perm = rng.permutation(64)
+        U[k, perm, np.arange(64)] = rng.choice([-1.0, 1.0], 64)
+    beta = 1.0
+    nu = 4.0 ** rng.integers(0, 4, (K, 64))
+    nu[:, 0] = 1.0
+    lam = nu - 1.0 / beta
+    w = np.full(K, 1.0 / K)
+    rr, cc = np.meshgrid(np.arange(12), np.arange(13), indexing="ij")
+    x = (100.0 + 2.0 * (1 - 2 * ((rr + cc) % 2)) + 1.0 * (1 - 2 * ((cc // 2) % 2))
+         + 0.5 * (1 - 2 * (rr % 2)))
+    got = lowp.lowp_costs(x.astype(np.float32), U, lam, w, beta, mode)
+    r, c = o.patch_corners(12, 13)
+    Zt, m = o.remove_dc(o.extract(x, r, c))
+    assert np.all(m == 100.0)
+    _, nu2, _, L = o.eigen_terms(lam, w, beta)
+    want = o.selection_costs(Zt, U, nu2, L) - L + L.astype(np.float32)
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("mode,rel", [("bf16", 2.0 ** -8), ("fp8", 2.0 ** -4)])
+def test_costs_within_rounding_bound(mode, rel):
+    c = fs.config_c1()
+    x = np.asarray(c["y"][:24, :24], np.float32)
+    beta = 4.0 / c["sigma"] ** 2
+    got = lowp.lowp_costs(x, c["U"], c["lam"], c["w"], beta, mode)
+    r, cc = o.patch_corners(24, 24)
+    Zt, _ = o.remove_dc(o.extract(x.astype(np.float64), r, cc))
+    _, nu, _, L = o.eigen_terms(c["lam"], c["w"], beta)
+    want = o.selection_costs(Zt, c["U"], nu, L)
+    # |c~ - c| <= sum_p |u_p z_p| (2 rel + rel^2) per projection, rel the
+    # unit roundoff of the format (half its step): bound the squares with it
+    K = c["U"].shape[0]
+    for k in range(K):
+        Ut = c["U"][k] / np.sqrt(nu[k])[None, :]
+        C = Zt @ Ut
+        A = np.abs(Zt) @ np.abs(Ut)
+        d = A * (2 * rel + rel * rel) + 1e-6
+        bound = np.sum(2 * np.abs(C) * d + d * d, axis=1) + np.abs(L[k]) * 2 ** -23
+        assert np.all(np.abs(got[:, k] - want[:, k]) <= bound)
