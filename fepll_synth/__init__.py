@@ -194,9 +194,19 @@ def config_c3(size: int = 1024):
     return dict(x=x, y=y, sigma=25.0, U=U, lam=lam, w=w)
 
 
-def batch_c5(n: int = 48, seed: int = 500, texture_std: float = 10.0):
+def _c5_item(args):
+    H, W, img_seed, noise_seed, sig, texture_std = args
+    x = test_image(H, W, img_seed, texture_std)
+    return dict(x=x, y=noisy(x, sig, noise_seed), sigma=sig)
+
+
+def batch_c5(n: int = 48, seed: int = 500, texture_std: float = 10.0, workers: int = 1):
     """Uneven batch: image 0 is 256x256, image n-1 is 1024 rows x 1536 cols,
-    the rest H ~ U{256..1024}, W ~ U{256..1536}; sigma ~ U[5, 50]."""
+    the rest H ~ U{256..1024}, W ~ U{256..1536}; sigma ~ U[5, 50].
+
+    workers > 1 draws the images in that many forked processes (same
+    images: each has its own seeds); fork only from a process that has not
+    initialised a GPU."""
     g = rng(seed)
     shapes = [(256, 256)]
     for _ in range(n - 2):
@@ -205,12 +215,13 @@ def batch_c5(n: int = 48, seed: int = 500, texture_std: float = 10.0):
     sig = g.uniform(5.0, 50.0, n)
     img_seeds = g.integers(1, 2 ** 31 - 1, n)
     noise_seeds = g.integers(1, 2 ** 31 - 1, n)
-    out = []
-    for i, (H, W) in enumerate(shapes[:n]):
-        x = test_image(H, W, int(img_seeds[i]), texture_std)
-        out.append(dict(x=x, y=noisy(x, float(sig[i]), int(noise_seeds[i])),
-                        sigma=float(sig[i])))
-    return out
+    items = [(H, W, int(img_seeds[i]), int(noise_seeds[i]), float(sig[i]), texture_std)
+             for i, (H, W) in enumerate(shapes[:n])]
+    if workers <= 1:
+        return [_c5_item(a) for a in items]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_c5_item, items, chunksize=1)
 
 
 def training_images(seeds=range(300, 313), size: int = 256, sigma_seed: int = 600):

@@ -135,6 +135,55 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* H, do
                            const fepll_options* opt, int32_t* labels_out);
 
 /*
+ * Restore n independent images, each by the default schedule (T = 5,
+ * beta = {1, 4, 8, 16, 32} / sigma[i]^2, start x = y) of Alg. 1 with A =
+ * identity -- the same result per image as fepll_restore.
+ *   n:      1..65536 images, of any sizes (each >= 8 x 8).
+ *   y:      n noisy images (host or device, finite values).
+ *   sigma:  n noise levels (host), each > 0: every image has its own betas.
+ *   out:    n outputs, each of the shape of its y; out[i] may alias y[i].
+ *   opt:    NULL = defaults; options.init must be NULL.
+ * The images are packed one after the other in device memory and every
+ * stage of an iteration is one launch over all of them (the all-K
+ * bfloat16 / e4m3 selection as a persistent launch over the selection
+ * tiles of the batch; float32 and proposal selection image by image).
+ * Without options.profile the launch sequence of the 5 iterations is
+ * captured once as a HIP graph and replayed by later calls with the same
+ * sizes, noise levels and options.  Host images: the call returns after
+ * every result is in out.  Device images: the work is enqueued.
+ */
+fepll_status fepll_restore_batch(fepll_gmm* g, int32_t n, const fepll_image* y,
+                                 const double* sigma, fepll_image* out,
+                                 const fepll_options* opt);
+
+/* Launch shapes of the restoration kernels (per handle). */
+typedef struct {
+  int32_t est_blocks;    /* workgroups of the persistent selection launch;
+                            0 = one per tile (default 768: 3 per CU)       */
+  int32_t wiener_blocks; /* cap on the patch-estimation workgroups, a
+                            multiple of 8 (default 4096)                   */
+  int32_t ola_rows;      /* rows of a reprojection tile: 16, 32 (default)
+                            or 64                                          */
+  int32_t reserved;      /* 0                                              */
+} fepll_tuning;
+
+/* Set the launch shapes (NULL = defaults).  EINVAL when out of range. */
+fepll_status fepll_set_tuning(fepll_gmm* g, const fepll_tuning* t);
+fepll_status fepll_get_tuning(fepll_gmm* g, fepll_tuning* t);
+
+/*
+ * Autotuner: time every candidate launch shape of each stage (selection
+ * workgroups 0 / 512 / 768 / 1024, patch-estimation workgroups 1024 / 2048 /
+ * 4096 / 8192, reprojection rows 16 / 32 / 64) on a restoration of the given
+ * batch (arguments as fepll_restore_batch; the results are discarded), keep
+ * the fastest of each stage in the handle and return them in *best (may be
+ * NULL).  Synchronises.
+ */
+fepll_status fepll_autotune(fepll_gmm* g, int32_t n, const fepll_image* y,
+                            const double* sigma, const fepll_options* opt,
+                            fepll_tuning* best);
+
+/*
  * One Gaussian-selection step (Alg. 1, "Gaussian selection", eigenspace
  * form) on every patch of the device image x for one beta, without
  * estimation or reprojection.  Device buffers of Np entries each:

@@ -14,8 +14,8 @@ from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
 
 import numpy as np
 
-__all__ = ["FepllError", "GMM", "restore", "select", "profile", "library_path", "FP32", "BF16",
-           "FP8"]
+__all__ = ["FepllError", "GMM", "restore", "restore_batch", "autotune", "set_tuning",
+           "get_tuning", "select", "profile", "library_path", "FP32", "BF16", "FP8"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfepll.so")
@@ -41,6 +41,11 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("recheck", c_int32), ("use_proposal", c_int32),
                 ("top_m", c_int32), ("margin_nats", c_double), ("init", POINTER(Image)),
                 ("stream", c_void_p), ("profile", c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("est_blocks", c_int32), ("wiener_blocks", c_int32), ("ola_rows", c_int32),
+                ("reserved", c_int32)]
 
 
 class AdamW(ctypes.Structure):
@@ -75,6 +80,16 @@ def lib():
     L.fepll_restore.argtypes = [c_void_p, POINTER(Image), c_void_p, c_double, c_void_p, c_int32,
                                 POINTER(Image), POINTER(Options), c_void_p]
     L.fepll_restore.restype = c_int32
+    L.fepll_restore_batch.argtypes = [c_void_p, c_int32, POINTER(Image), c_void_p,
+                                      POINTER(Image), POINTER(Options)]
+    L.fepll_restore_batch.restype = c_int32
+    L.fepll_set_tuning.argtypes = [c_void_p, POINTER(Tuning)]
+    L.fepll_set_tuning.restype = c_int32
+    L.fepll_get_tuning.argtypes = [c_void_p, POINTER(Tuning)]
+    L.fepll_get_tuning.restype = c_int32
+    L.fepll_autotune.argtypes = [c_void_p, c_int32, POINTER(Image), c_void_p, POINTER(Options),
+                                 POINTER(Tuning)]
+    L.fepll_autotune.restype = c_int32
     L.fepll_select.argtypes = [c_void_p, POINTER(Image), c_double, c_void_p, c_void_p, c_void_p,
                                c_void_p, POINTER(Options)]
     L.fepll_select.restype = c_int32
@@ -240,6 +255,54 @@ def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
     _check(lib().fepll_restore(gmm.handle, ctypes.byref(yi), None, float(sigma), bptr, T,
                                ctypes.byref(oi), ctypes.byref(o), lptr))
     return (out, labels) if return_labels else out
+
+
+def _batch_args(ys, sigmas, outs):
+    import torch
+    n = len(ys)
+    if len(sigmas) != n:
+        raise ValueError("one sigma per image")
+    if outs is None:
+        outs = [torch.empty_like(y) if isinstance(y, torch.Tensor) else np.empty_like(y)
+                for y in ys]
+    yi = (Image * n)(*[_image(y) for y in ys])
+    oi = (Image * n)(*[_image(o) for o in outs])
+    sg = np.ascontiguousarray(sigmas, dtype=np.float64)
+    return n, yi, oi, sg, outs
+
+
+def restore_batch(gmm: GMM, ys, sigmas, precision="bf16", recheck=True, outs=None,
+                  profile=False, proposal=False, top_m=8, margin=0.5):
+    """Denoise a list of images (2-D float32 tensors or arrays, any sizes),
+    each with its own noise level, in one batched call (default schedule).
+    Returns the list of restored images."""
+    n, yi, oi, sg, outs = _batch_args(ys, sigmas, outs)
+    o = _options(precision, recheck, None, _stream_of(ys[0]), profile, proposal, top_m, margin)
+    _check(lib().fepll_restore_batch(gmm.handle, n, yi, sg.ctypes.data, oi, ctypes.byref(o)))
+    return outs
+
+
+def set_tuning(gmm: GMM, est_blocks=768, wiener_blocks=4096, ola_rows=32):
+    t = Tuning(int(est_blocks), int(wiener_blocks), int(ola_rows), 0)
+    _check(lib().fepll_set_tuning(gmm.handle, ctypes.byref(t)))
+
+
+def get_tuning(gmm: GMM) -> dict:
+    t = Tuning()
+    _check(lib().fepll_get_tuning(gmm.handle, ctypes.byref(t)))
+    return {"est_blocks": t.est_blocks, "wiener_blocks": t.wiener_blocks,
+            "ola_rows": t.ola_rows}
+
+
+def autotune(gmm: GMM, ys, sigmas, precision="bf16", proposal=False, top_m=8, margin=0.5):
+    """Time the candidate launch shapes on this batch, keep the fastest in
+    the handle and return them."""
+    n, yi, _, sg, _ = _batch_args(ys, sigmas, [ys[0]] * len(ys))
+    o = _options(precision, True, None, _stream_of(ys[0]), False, proposal, top_m, margin)
+    t = Tuning()
+    _check(lib().fepll_autotune(gmm.handle, n, yi, sg.ctypes.data, ctypes.byref(o),
+                                ctypes.byref(t)))
+    return get_tuning(gmm)
 
 
 def select(gmm: GMM, x, beta: float, recheck=True, precision="fp32", proposal=False, top_m=8,

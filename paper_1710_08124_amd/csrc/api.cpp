@@ -1,9 +1,12 @@
 // Host runtime behind include/fepll.h: argument validation, device copies of
-// the mixture, the per-beta constant cache, scratch memory, and the
-// per-iteration launch sequence of Alg. 1 (selection -> float64 recheck ->
-// bucketing -> patch estimation -> reprojection + image estimation).
+// the mixture, the per-beta constant cache, the packed layout of a batch of
+// images ("plan"), scratch memory, and the per-iteration launch sequence of
+// Alg. 1 (selection -> float64 recheck -> bucketing -> patch estimation ->
+// reprojection + image estimation), run eagerly or replayed from a captured
+// HIP graph.  A single restoration is a batch of one.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -44,20 +47,28 @@ struct fepll_gmm {
   double* U64 = nullptr;    // [K][64][64]
   double* lam64 = nullptr;  // [K][64]
   double* w64 = nullptr;    // [K]
-  // per-schedule constants
-  bool have_sched = false;
-  Schedule sched{};
-  int T_cap = 0;
-  float* Ut = nullptr;
-  uint16_t* Ub = nullptr;
-  float* Wt = nullptr;
-  float* L32 = nullptr;
-  double* L64 = nullptr;
-  double* invnu64 = nullptr;
-  uint8_t* Uf = nullptr;
-  int32_t* Ue = nullptr;
-  // scratch
-  size_t np_cap = 0, px_cap = 0;
+  // per-beta constants of the beta slots of the last call
+  std::vector<double> cbeta;
+  int cmask = 0;
+  size_t S_cap = 0;
+  double* dbeta = nullptr;
+  ConstTables tb{};
+  // plan of the last call: host copies (kept for the asynchronous uploads
+  // and to skip unchanged uploads) and device copies
+  std::vector<ImgDesc> hd;
+  std::vector<int32_t> h_est, h_sort, h_ola;
+  std::vector<float> hbvals;
+  Batch batch{};
+  bool plan_valid = false;
+  size_t n_cap = 0, wb_cap = 0, est_cap = 0, sort_cap = 0, ola_cap = 0, slot_cap = 0;
+  ImgDesc* d = nullptr;
+  int32_t* est_img = nullptr;
+  int32_t* sort_img = nullptr;
+  int32_t* ola_img = nullptr;
+  int32_t* wbase = nullptr;
+  float* bvals = nullptr;
+  // scratch, sized for the packed batch
+  size_t np_cap = 0, px_cap = 0, hist_cap = 0, seg_cap = 0;
   int32_t* labels = nullptr;
   int32_t* list = nullptr;
   int32_t* count = nullptr;
@@ -76,6 +87,12 @@ struct fepll_gmm {
   int32_t* fb_list = nullptr;  // Np
   hipStream_t last_stream = nullptr;
   bool used = false;
+  // launch shapes (fepll_set_tuning / fepll_autotune)
+  fepll_tuning tune{};
+  // the captured iteration loop of the last graph-eligible call
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint8_t> gkey;
+  hipStream_t cap_stream = nullptr;
   // profiling: events recorded around stages, resolved in fepll_profile
   struct Mark {
     int stage;
@@ -89,6 +106,15 @@ struct fepll_gmm {
 namespace {
 
 constexpr int kStages = 8;
+constexpr int kDefaultT = 5;
+const double kDefaultB[kDefaultT] = {1.0, 4.0, 8.0, 16.0, 32.0};
+
+void default_tuning(fepll_tuning* t) {
+  t->est_blocks = 768;  // 3 workgroups per compute unit
+  t->wiener_blocks = 4096;
+  t->ola_rows = 32;
+  t->reserved = 0;
+}
 
 hipEvent_t take_event(fepll_gmm* g) {
   if (!g->pool.empty()) {
@@ -131,77 +157,60 @@ fepll_status use_stream(fepll_gmm* g, hipStream_t st) {
   return FEPLL_OK;
 }
 
-fepll_status ensure_consts(fepll_gmm* g, const Schedule& s, hipStream_t st) {
-  if (g->have_sched && g->sched.T == s.T &&
-      std::memcmp(g->sched.beta, s.beta, sizeof(double) * s.T) == 0)
-    return FEPLL_OK;
-  if (s.T > g->T_cap) {
-    dfree(g->Ut);
-    dfree(g->Ub);
-    dfree(g->Wt);
-    dfree(g->L32);
-    dfree(g->L64);
-    dfree(g->invnu64);
-    dfree(g->Uf);
-    dfree(g->Ue);
-    g->T_cap = 0;
-    const size_t K = g->K;
-    HIPX(dalloc(&g->Ut, (size_t)s.T * K * kTileStride));
-    HIPX(dalloc(&g->Ub, (size_t)s.T * K * kTileStride));
-    HIPX(dalloc(&g->Wt, (size_t)s.T * K * kTileStride));
-    HIPX(dalloc(&g->L32, (size_t)s.T * K));
-    HIPX(dalloc(&g->L64, (size_t)s.T * K));
-    HIPX(dalloc(&g->invnu64, (size_t)s.T * K * kP));
-    HIPX(dalloc(&g->Uf, (size_t)s.T * K * kTileStride));
-    HIPX(dalloc(&g->Ue, (size_t)s.T * K));
-    g->T_cap = s.T;
-  }
-  {
-    StageTimer tm(g, 5, st);
-    HIPX(launch_prep(g->U64, g->lam64, g->w64, g->K, s, g->Ut, g->Ub, g->Wt, g->L32, g->L64,
-                     g->invnu64, g->Uf, g->Ue, st));
-  }
-  g->sched = s;
-  g->have_sched = true;
-  return FEPLL_OK;
+int table_mask(const fepll_options& o) {
+  if (o.precision == FEPLL_FP8) return kTabF8;
+  if (o.precision == FEPLL_BF16) return kTabBF16;
+  return kTabF32;
 }
 
-fepll_status ensure_ws(fepll_gmm* g, int H, int W) {
-  const size_t Np = (size_t)(H - 7) * (W - 7);
-  const size_t px = (size_t)H * W;
-  if (Np > g->np_cap) {
-    dfree(g->labels);
-    dfree(g->list);
-    dfree(g->count);
-    dfree(g->hist);
-    dfree(g->seg);
-    dfree(g->perm);
-    dfree(g->Zhat);
-    dfree(g->cand);
-    dfree(g->fb_list);
-    g->np_cap = 0;
-    const size_t nb = (Np + kSortBlock - 1) / kSortBlock;
-    HIPX(dalloc(&g->labels, Np));
-    HIPX(dalloc(&g->list, 4 * Np));  // int4 entries
-    HIPX(dalloc(&g->count, 64));
-    HIPX(dalloc(&g->hist, nb * g->K));
-    HIPX(dalloc(&g->seg, seg_size(Np, g->K)));
-    HIPX(dalloc(&g->perm, Np));
-    HIPX(dalloc(&g->Zhat, Np * kP));
-    HIPX(dalloc(&g->cand, Np * 8));
-    HIPX(dalloc(&g->fb_list, Np));
-    g->np_cap = Np;
+// Per-beta tables for the beta slots `betas` (at least the tables in mask).
+fepll_status ensure_consts(fepll_gmm* g, const std::vector<double>& betas, int mask,
+                           hipStream_t st) {
+  if (g->cbeta == betas && (g->cmask & mask) == mask) return FEPLL_OK;
+  const size_t S = betas.size();
+  const size_t K = g->K;
+  if (S > g->S_cap) {
+    HIPX(hipStreamSynchronize(st));
+    dfree(g->dbeta);
+    dfree(g->tb.Ut);
+    dfree(g->tb.Ub);
+    dfree(g->tb.Wt);
+    dfree(g->tb.L32);
+    dfree(g->tb.L64);
+    dfree(g->tb.invnu64);
+    dfree(g->tb.Uf);
+    dfree(g->tb.Ue);
+    g->S_cap = 0;
+    g->cbeta.clear();
+    g->cmask = 0;
+    HIPX(dalloc(&g->dbeta, S));
+    HIPX(dalloc(&g->tb.Wt, S * K * kTileStride));
+    HIPX(dalloc(&g->tb.L32, S * K));
+    g->S_cap = S;
   }
-  if (px > g->px_cap) {
-    dfree(g->ybuf);
-    dfree(g->xa);
-    dfree(g->xb);
-    g->px_cap = 0;
-    HIPX(dalloc(&g->ybuf, px));
-    HIPX(dalloc(&g->xa, px));
-    HIPX(dalloc(&g->xb, px));
-    g->px_cap = px;
+  // the tables of a precision are allocated the first time it is used
+  const size_t C = g->S_cap;
+  if ((mask & kTabF32) && !g->tb.Ut) {
+    HIPX(dalloc(&g->tb.Ut, C * K * kTileStride));
+    HIPX(dalloc(&g->tb.L64, C * K));
+    HIPX(dalloc(&g->tb.invnu64, C * K * kP));
   }
+  if ((mask & kTabBF16) && !g->tb.Ub) HIPX(dalloc(&g->tb.Ub, C * K * kTileStride));
+  if ((mask & kTabF8) && !g->tb.Uf) {
+    HIPX(dalloc(&g->tb.Uf, C * K * kTileStride));
+    HIPX(dalloc(&g->tb.Ue, C * K));
+  }
+  // same slots: add the missing tables; new slots: these tables only
+  const int build = (g->cbeta == betas) ? (mask | g->cmask) : mask;
+  HIPX(hipMemcpyAsync(g->dbeta, betas.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+  {
+    StageTimer tm(g, 5, st);
+    HIPX(launch_prep(g->U64, g->lam64, g->w64, g->K, g->dbeta, (int)S, build, g->tb, st));
+  }
+  // the host betas must outlive their asynchronous upload
+  HIPX(hipStreamSynchronize(st));
+  g->cbeta = betas;
+  g->cmask = build;
   return FEPLL_OK;
 }
 
@@ -254,41 +263,150 @@ fepll_status check_opt(const fepll_gmm* g, const fepll_options* o) {
   return FEPLL_OK;
 }
 
-// One Gaussian selection (E-step + optional float64 recheck) of image x.
+template <class T>
+fepll_status grow(T** p, size_t& cap, size_t n) {
+  if (n <= cap && *p) return FEPLL_OK;
+  dfree(*p);
+  cap = 0;
+  HIPX(dalloc(p, n));
+  cap = n;
+  return FEPLL_OK;
+}
+
+// Lay out n images of sizes H[i] x W[i] (T iterations, beta slots i*T + t,
+// bvals[slot] = beta sigma^2) in the packed buffers, size the scratch and
+// upload the plan (skipped when unchanged).
+fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
+                       const std::vector<float>& bvals, hipStream_t st) {
+  const int K = g->K;
+  const int ola_rows = g->tune.ola_rows;
+  std::vector<ImgDesc> hd(n);
+  std::vector<int32_t> est, sort, ola;
+  int64_t px = 0, np = 0, seg = 0;
+  for (int i = 0; i < n; ++i) {
+    const int Hp = H[i] - 7, Wp = W[i] - 7;
+    const int64_t Np = (int64_t)Hp * Wp;
+    ImgDesc& d = hd[i];
+    d.H = H[i];
+    d.W = W[i];
+    d.px = px;
+    d.np = np;
+    d.seg = seg;
+    d.sort0 = (int32_t)sort.size();
+    d.est0 = (int32_t)est.size();
+    d.ola0 = (int32_t)ola.size();
+    d.slot0 = i * T;
+    const int64_t nb = (Np + kSortBlock - 1) / kSortBlock;
+    const int64_t ne = (int64_t)((Wp + kEstCols - 1) / kEstCols) * ((Hp + 3) / 4);
+    const int64_t no =
+        (int64_t)((W[i] + kOlaX - 1) / kOlaX) * ((H[i] + ola_rows - 1) / ola_rows);
+    if ((int64_t)est.size() + ne > INT32_MAX / 2 || (int64_t)ola.size() + no > INT32_MAX / 2)
+      return fail(FEPLL_EUNSUPPORTED, "batch too large");
+    sort.insert(sort.end(), (size_t)nb, i);
+    est.insert(est.end(), (size_t)ne, i);
+    ola.insert(ola.end(), (size_t)no, i);
+    px += ((int64_t)H[i] * W[i] + 63) / 64 * 64;  // 256-byte aligned images
+    np += Np;
+    seg += (int64_t)seg_size(Np, K);
+  }
+  if (np > INT32_MAX) return fail(FEPLL_EUNSUPPORTED, "batch too large");
+  const bool same = g->plan_valid && g->hd.size() == hd.size() &&
+                    std::memcmp(g->hd.data(), hd.data(), sizeof(ImgDesc) * n) == 0 &&
+                    g->hbvals == bvals;
+  fepll_status s;
+  const size_t NP = (size_t)np, PX = (size_t)px;
+  // buffers in use by earlier work are only freed once it is done
+  if (NP > g->np_cap || PX > g->px_cap || (size_t)K * sort.size() > g->hist_cap ||
+      (size_t)seg > g->seg_cap || !same)
+    HIPX(hipStreamSynchronize(st));
+  if (NP > g->np_cap) {
+    dfree(g->labels);
+    dfree(g->list);
+    dfree(g->perm);
+    dfree(g->Zhat);
+    dfree(g->cand);
+    dfree(g->fb_list);
+    g->np_cap = 0;
+    HIPX(dalloc(&g->labels, NP));
+    HIPX(dalloc(&g->list, 4 * NP));  // int4 entries
+    HIPX(dalloc(&g->perm, NP));
+    HIPX(dalloc(&g->Zhat, NP * kP));
+    HIPX(dalloc(&g->cand, NP * 8));
+    HIPX(dalloc(&g->fb_list, NP));
+    g->np_cap = NP;
+  }
+  if (PX > g->px_cap) {
+    dfree(g->ybuf);
+    dfree(g->xa);
+    dfree(g->xb);
+    g->px_cap = 0;
+    HIPX(dalloc(&g->ybuf, PX));
+    HIPX(dalloc(&g->xa, PX));
+    HIPX(dalloc(&g->xb, PX));
+    g->px_cap = PX;
+  }
+  if (!g->count) HIPX(dalloc(&g->count, 64));
+  if ((s = grow(&g->hist, g->hist_cap, (size_t)K * sort.size())) != FEPLL_OK) return s;
+  if ((s = grow(&g->seg, g->seg_cap, (size_t)seg)) != FEPLL_OK) return s;
+  if (!same) {
+    if ((s = grow(&g->d, g->n_cap, (size_t)n)) != FEPLL_OK) return s;
+    if ((s = grow(&g->wbase, g->wb_cap, (size_t)n + 1)) != FEPLL_OK) return s;
+    if ((s = grow(&g->est_img, g->est_cap, est.size())) != FEPLL_OK) return s;
+    if ((s = grow(&g->sort_img, g->sort_cap, sort.size())) != FEPLL_OK) return s;
+    if ((s = grow(&g->ola_img, g->ola_cap, ola.size())) != FEPLL_OK) return s;
+    if ((s = grow(&g->bvals, g->slot_cap, bvals.size())) != FEPLL_OK) return s;
+    g->hd = std::move(hd);
+    g->h_est = std::move(est);
+    g->h_sort = std::move(sort);
+    g->h_ola = std::move(ola);
+    g->hbvals = bvals;
+    HIPX(hipMemcpyAsync(g->d, g->hd.data(), sizeof(ImgDesc) * n, hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(g->est_img, g->h_est.data(), sizeof(int32_t) * g->h_est.size(),
+                        hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(g->sort_img, g->h_sort.data(), sizeof(int32_t) * g->h_sort.size(),
+                        hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(g->ola_img, g->h_ola.data(), sizeof(int32_t) * g->h_ola.size(),
+                        hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(g->bvals, g->hbvals.data(), sizeof(float) * g->hbvals.size(),
+                        hipMemcpyHostToDevice, st));
+    g->plan_valid = true;
+  }
+  Batch& b = g->batch;
+  b.d = g->d;
+  b.est_img = g->est_img;
+  b.sort_img = g->sort_img;
+  b.ola_img = g->ola_img;
+  b.n = n;
+  b.n_est = (int)g->h_est.size();
+  b.n_sort = (int)g->h_sort.size();
+  b.n_ola = (int)g->h_ola.size();
+  b.n_patches = np;
+  b.ola_rows = ola_rows;
+  return FEPLL_OK;
+}
+
 __global__ void mark_kernel(const int32_t* count, const int32_t* list, int32_t* flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < *count) flags[list[i]] = 1;
 }
 
-fepll_status run_select(fepll_gmm* g, const float* x, int H, int W, int t, double beta,
-                        int precision, bool recheck, const fepll_options* prop, int32_t* labels,
-                        float* best, float* second, int32_t* flags, hipStream_t st) {
+// One Gaussian selection of one image x with the tables of beta slot
+// `slot`: float32 E-step + float64 recheck, or the proposal path.
+fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, double beta,
+                        const fepll_options& o, int32_t* labels, float* best, float* second,
+                        int32_t* flags, hipStream_t st) {
   const int Np = (H - 7) * (W - 7);
   const size_t K = g->K;
-  if (precision == FEPLL_FP8) {
+  if (o.precision == FEPLL_BF16) {
+    // the proposal path: network, exact rescoring of the candidates, full-K
+    // selection of the fallback list
     if (flags) {
       hipLaunchKernelGGL(zero_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, flags, Np);
       HIPX(hipGetLastError());
-    }
-    StageTimer tm(g, 0, st);
-    HIPX(launch_estep_fp8(x, H, W, g->Uf + (size_t)t * K * kTileStride, g->Ue + (size_t)t * K,
-                          g->L32 + (size_t)t * K, g->K, labels, best, second, st));
-    return FEPLL_OK;
-  }
-  if (precision == FEPLL_BF16) {
-    if (flags) {
-      hipLaunchKernelGGL(zero_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, flags, Np);
-      HIPX(hipGetLastError());
-    }
-    if (!prop) {
-      StageTimer tm(g, 0, st);
-      HIPX(launch_estep_bf16(x, H, W, g->Ub + (size_t)t * K * kTileStride,
-                             g->L32 + (size_t)t * K, g->K, labels, best, second, st));
-      return FEPLL_OK;
     }
     {
       StageTimer tm(g, 6, st);
-      HIPX(launch_propose_bf16(x, H, W, beta, g->pWb, g->pbias, g->K, prop->top_m, g->cand, st));
+      HIPX(launch_propose_bf16(x, H, W, beta, g->pWb, g->pbias, g->K, o.top_m, g->cand, st));
     }
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, g->count, 1);
     HIPX(hipGetLastError());
@@ -296,14 +414,14 @@ fepll_status run_select(fepll_gmm* g, const float* x, int H, int W, int t, doubl
     a.x = x;
     a.H = H;
     a.W = W;
-    a.Ub = g->Ub + (size_t)t * K * kTileStride;
-    a.L = g->L32 + (size_t)t * K;
+    a.Ub = g->tb.Ub + (size_t)slot * K * kTileStride;
+    a.L = g->tb.L32 + (size_t)slot * K;
     a.K = g->K;
     a.labels = labels;
     a.best = best;
     a.second = second;
     a.cand = reinterpret_cast<const uint4*>(g->cand);
-    a.margin = (float)prop->margin_nats;
+    a.margin = (float)o.margin_nats;
     a.fb_count = g->count;
     a.fb_list = g->fb_list;
     a.list_count = g->count;
@@ -327,15 +445,149 @@ fepll_status run_select(fepll_gmm* g, const float* x, int H, int W, int t, doubl
   HIPX(hipGetLastError());
   {
     StageTimer tm(g, 0, st);
-    HIPX(launch_estep_f32(x, H, W, g->Ut + (size_t)t * K * kTileStride,
-                          g->L32 + (size_t)t * K, g->K, beta, labels, best, second, flags,
-                          g->count, recheck ? g->list : nullptr, st));
+    HIPX(launch_estep_f32(x, H, W, g->tb.Ut + (size_t)slot * K * kTileStride,
+                          g->tb.L32 + (size_t)slot * K, g->K, beta, labels, best, second, flags,
+                          g->count, o.recheck ? g->list : nullptr, st));
   }
-  if (recheck) {
+  if (o.recheck) {
     StageTimer tm(g, 1, st);
-    HIPX(launch_recheck_f64(x, H, W, g->U64, g->invnu64 + (size_t)t * K * kP,
-                            g->L64 + (size_t)t * K, g->K, g->count, g->list, labels, Np, st));
+    HIPX(launch_recheck_f64(x, H, W, g->U64, g->tb.invnu64 + (size_t)slot * K * kP,
+                            g->tb.L64 + (size_t)slot * K, g->K, g->count, g->list, labels, Np,
+                            st));
   }
+  return FEPLL_OK;
+}
+
+// Selection of every image of the planned batch at iteration t.  The
+// all-K reduced-precision modes run as one persistent launch over the
+// batch; float32 (with its recheck) and the proposal path run image by
+// image.  best / second / flags: packed like labels, or NULL.
+fepll_status select_batch(fepll_gmm* g, int t, const fepll_options& o, const float* x,
+                          int32_t* labels, float* best, float* second, int32_t* flags,
+                          hipStream_t st) {
+  const Batch& b = g->batch;
+  const int blocks = g->tune.est_blocks;
+  if (o.precision == FEPLL_FP8 || (o.precision == FEPLL_BF16 && !o.use_proposal)) {
+    if (flags) {
+      const int n = (int)b.n_patches;
+      hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, n);
+      HIPX(hipGetLastError());
+    }
+    StageTimer tm(g, 0, st);
+    if (o.precision == FEPLL_FP8)
+      HIPX(launch_estep_fp8_batch(b, x, g->tb.Uf, g->tb.Ue, g->tb.L32, g->K, t, labels, best,
+                                  second, blocks, st));
+    else
+      HIPX(launch_estep_bf16_batch(b, x, g->tb.Ub, g->tb.L32, g->K, t, labels, best, second,
+                                   blocks, st));
+    return FEPLL_OK;
+  }
+  fepll_status s;
+  for (int i = 0; i < b.n; ++i) {
+    const ImgDesc& d = g->hd[i];
+    const int slot = d.slot0 + t;
+    if ((s = select_one(g, x + d.px, d.H, d.W, slot, g->cbeta[slot], o, labels + d.np,
+                        best ? best + d.np : nullptr, second ? second + d.np : nullptr,
+                        flags ? flags + d.np : nullptr, st)) != FEPLL_OK)
+      return s;
+  }
+  return FEPLL_OK;
+}
+
+// T iterations of Alg. 1 over the planned batch, from g->xa (y in g->ybuf);
+// *result receives the buffer holding the restored images.  labels_out
+// (single image only): per-iteration copies of the labels.
+fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* labels_out,
+                     hipMemcpyKind lkind, float** result, hipStream_t st) {
+  const Batch& b = g->batch;
+  float* xc = g->xa;
+  float* xn = g->xb;
+  fepll_status s;
+  for (int t = 0; t < T; ++t) {
+    if ((s = select_batch(g, t, o, xc, g->labels, nullptr, nullptr, nullptr, st)) != FEPLL_OK)
+      return s;
+    if (labels_out)
+      HIPX(hipMemcpyAsync(labels_out + (size_t)t * b.n_patches, g->labels,
+                          sizeof(int32_t) * b.n_patches, lkind, st));
+    {
+      StageTimer tm(g, 2, st);
+      HIPX(launch_bucket_batch(b, g->labels, g->K, g->hist, g->seg, g->perm, g->wbase, st));
+    }
+    {
+      StageTimer tm(g, 3, st);
+      HIPX(launch_wiener_batch(b, xc, g->tb.Wt, g->K, t, g->seg, g->perm, g->wbase, g->Zhat,
+                               g->tune.wiener_blocks, st));
+    }
+    {
+      StageTimer tm(g, 4, st);
+      HIPX(launch_ola_batch(b, g->Zhat, g->ybuf, g->bvals, t, xn, st));
+    }
+    std::swap(xc, xn);
+  }
+  *result = xc;
+  return FEPLL_OK;
+}
+
+template <class V>
+void put(std::vector<uint8_t>& k, const V& v) {
+  const uint8_t* p = reinterpret_cast<const uint8_t*>(&v);
+  k.insert(k.end(), p, p + sizeof(V));
+}
+
+// run_hqs through a captured graph: the launch sequence depends only on
+// the plan, the beta slots, the options, the launch shapes and the
+// buffers, so it is captured once and replayed while those stay the same.
+fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** result,
+                           hipStream_t st) {
+  std::vector<uint8_t> key;
+  put(key, T);
+  put(key, g->K);
+  put(key, o.precision);
+  put(key, o.recheck);
+  put(key, o.use_proposal);
+  put(key, o.top_m);
+  put(key, o.margin_nats);
+  put(key, g->tune);
+  for (const ImgDesc& d : g->hd) put(key, d);
+  for (double v : g->cbeta) put(key, v);
+  for (float v : g->hbvals) put(key, v);
+  const void* ptrs[] = {g->tb.Ut, g->tb.Ub, g->tb.Wt, g->tb.L32, g->tb.L64, g->tb.invnu64,
+                        g->tb.Uf, g->tb.Ue,   g->d,     g->est_img, g->sort_img, g->ola_img,
+                        g->wbase, g->bvals,   g->labels, g->list,  g->count,  g->hist,
+                        g->seg,   g->perm,    g->Zhat,  g->ybuf,   g->xa,     g->xb,
+                        g->pWb,   g->pbias,   g->cand,  g->fb_list};
+  for (const void* p : ptrs) put(key, p);
+  if (g->gexec && key == g->gkey) {
+    *result = (T % 2) ? g->xb : g->xa;
+    HIPX(hipGraphLaunch(g->gexec, st));
+    return FEPLL_OK;
+  }
+  if (g->gexec) {
+    HIPX(hipStreamSynchronize(st));
+    (void)hipGraphExecDestroy(g->gexec);
+    g->gexec = nullptr;
+    g->gkey.clear();
+  }
+  if (!g->cap_stream) HIPX(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+  HIPX(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+  float* res = nullptr;
+  const fepll_status s = run_hqs(g, T, o, nullptr, hipMemcpyDefault, &res, g->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(g->cap_stream, &graph);
+  if (s != FEPLL_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  HIPX(e);
+  const hipError_t ei = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) {
+    g->gexec = nullptr;
+    HIPX(ei);
+  }
+  g->gkey = std::move(key);
+  *result = res;
+  HIPX(hipGraphLaunch(g->gexec, st));
   return FEPLL_OK;
 }
 
@@ -358,7 +610,7 @@ void fepll_options_default(fepll_options* o) {
 
 const char* fepll_last_error(void) { return g_err.c_str(); }
 
-const char* fepll_version(void) { return "fepll-gfx950 0.1"; }
+const char* fepll_version(void) { return "fepll-gfx950 0.2"; }
 
 fepll_status fepll_gmm_create(const double* U, const double* lambda, const double* w, int32_t K,
                               int32_t d, fepll_gmm** out) {
@@ -392,6 +644,7 @@ fepll_status fepll_gmm_create(const double* U, const double* lambda, const doubl
   fepll_gmm* g = new (std::nothrow) fepll_gmm();
   if (!g) return fail(FEPLL_ENOMEM, "host allocation failed");
   g->K = K;
+  default_tuning(&g->tune);
   auto bad = [&](hipError_t e) {
     fepll_gmm_destroy(g);
     return fail(e == hipErrorOutOfMemory ? FEPLL_ENOMEM : FEPLL_EDEVICE,
@@ -447,17 +700,26 @@ void fepll_gmm_destroy(fepll_gmm* g) {
     (void)hipEventDestroy(m.b);
   }
   for (auto e : g->pool) (void)hipEventDestroy(e);
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   dfree(g->U64);
   dfree(g->lam64);
   dfree(g->w64);
-  dfree(g->Ut);
-  dfree(g->Ub);
-  dfree(g->Wt);
-  dfree(g->L32);
-  dfree(g->L64);
-  dfree(g->invnu64);
-  dfree(g->Uf);
-  dfree(g->Ue);
+  dfree(g->dbeta);
+  dfree(g->tb.Ut);
+  dfree(g->tb.Ub);
+  dfree(g->tb.Wt);
+  dfree(g->tb.L32);
+  dfree(g->tb.L64);
+  dfree(g->tb.invnu64);
+  dfree(g->tb.Uf);
+  dfree(g->tb.Ue);
+  dfree(g->d);
+  dfree(g->est_img);
+  dfree(g->sort_img);
+  dfree(g->ola_img);
+  dfree(g->wbase);
+  dfree(g->bvals);
   dfree(g->labels);
   dfree(g->list);
   dfree(g->count);
@@ -491,21 +753,19 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, 
   fepll_options_default(&o);
   if (opt) o = *opt;
   if ((s = check_opt(g, &o)) != FEPLL_OK) return s;
-  Schedule sch{};
+  std::vector<double> betas;
   if (!beta_schedule) {
-    if (T != 0 && T != 5) return fail(FEPLL_EINVAL, "default schedule has T = 5");
-    sch.T = 5;
-    const double m[5] = {1.0, 4.0, 8.0, 16.0, 32.0};
-    for (int t = 0; t < 5; ++t) sch.beta[t] = m[t] / (sigma * sigma);
+    if (T != 0 && T != kDefaultT) return fail(FEPLL_EINVAL, "default schedule has T = 5");
+    for (int t = 0; t < kDefaultT; ++t) betas.push_back(kDefaultB[t] / (sigma * sigma));
   } else {
     if (T < 1 || T > kMaxT) return fail(FEPLL_EINVAL, "T must be in 1..16");
-    sch.T = T;
     for (int t = 0; t < T; ++t) {
       if (!(beta_schedule[t] > 0.0) || !std::isfinite(beta_schedule[t]))
         return fail(FEPLL_EINVAL, "beta values must be finite and > 0");
-      sch.beta[t] = beta_schedule[t];
+      betas.push_back(beta_schedule[t]);
     }
   }
+  T = (int32_t)betas.size();
   if (o.init) {
     if ((s = check_image(o.init, "options.init")) != FEPLL_OK) return s;
     if (o.init->height != y->height || o.init->width != y->width)
@@ -515,46 +775,170 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, 
   if ((s = host_finite(y, "y")) != FEPLL_OK) return s;
 
   const int H = y->height, W = y->width;
-  const int Np = (H - 7) * (W - 7);
   hipStream_t st = (hipStream_t)o.stream;
   if ((s = use_stream(g, st)) != FEPLL_OK) return s;
   g->profiling = o.profile != 0;
-  if ((s = ensure_ws(g, H, W)) != FEPLL_OK) return s;
-  if ((s = ensure_consts(g, sch, st)) != FEPLL_OK) return s;
+  std::vector<float> bvals;
+  for (double b : betas) bvals.push_back((float)(b * sigma * sigma));
+  if ((s = make_plan(g, 1, &H, &W, T, bvals, st)) != FEPLL_OK) return s;
+  if ((s = ensure_consts(g, betas, table_mask(o), st)) != FEPLL_OK) return s;
 
   HIPX(copy_in(g->ybuf, y, st));
   if (o.init) HIPX(copy_in(g->xa, o.init, st));
   else HIPX(hipMemcpyAsync(g->xa, g->ybuf, sizeof(float) * H * W, hipMemcpyDeviceToDevice, st));
 
-  float* xc = g->xa;
-  float* xn = g->xb;
-  for (int t = 0; t < sch.T; ++t) {
-    const double beta = sch.beta[t];
-    if ((s = run_select(g, xc, H, W, t, beta, o.precision, o.recheck != 0,
-                        o.use_proposal ? &o : nullptr, g->labels, nullptr, nullptr, nullptr,
-                        st)) != FEPLL_OK)
-      return s;
-    if (labels_out)
-      HIPX(hipMemcpyAsync(labels_out + (size_t)t * Np, g->labels, sizeof(int32_t) * Np,
-                          y->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
-    {
-      StageTimer tm(g, 2, st);
-      HIPX(launch_bucket(g->labels, Np, g->K, g->hist, g->seg, g->perm, st));
-    }
-    {
-      StageTimer tm(g, 3, st);
-      HIPX(launch_wiener_f32(xc, H, W, g->Wt + (size_t)t * g->K * kTileStride, g->K, g->seg,
-                             g->perm, g->Zhat, st));
-    }
-    {
-      StageTimer tm(g, 4, st);
-      HIPX(launch_ola_update(g->Zhat, g->ybuf, H, W, beta * sigma * sigma, xn, st));
-    }
-    std::swap(xc, xn);
-  }
-  HIPX(copy_out(out, xc, st));
+  float* res = nullptr;
+  if (o.profile || labels_out)
+    s = run_hqs(g, T, o, labels_out,
+                y->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, &res, st);
+  else
+    s = run_hqs_graph(g, T, o, &res, st);
+  if (s != FEPLL_OK) return s;
+  HIPX(copy_out(out, res, st));
   if (!out->on_device || !y->on_device || (labels_out && !y->on_device))
     HIPX(hipStreamSynchronize(st));
+  return FEPLL_OK;
+}
+
+fepll_status fepll_restore_batch(fepll_gmm* g, int32_t n, const fepll_image* y,
+                                 const double* sigma, fepll_image* out,
+                                 const fepll_options* opt) {
+  g_err.clear();
+  if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
+  if (n < 1 || n > kMaxBatch) return fail(FEPLL_EINVAL, "n must be in 1..65536");
+  if (!y || !sigma || !out) return fail(FEPLL_EINVAL, "y, sigma and out must be non-NULL");
+  fepll_options o;
+  fepll_options_default(&o);
+  if (opt) o = *opt;
+  fepll_status s;
+  if ((s = check_opt(g, &o)) != FEPLL_OK) return s;
+  if (o.init) return fail(FEPLL_EINVAL, "options.init is not taken by fepll_restore_batch");
+  std::vector<int> Hs(n), Ws(n);
+  std::vector<double> betas;
+  std::vector<float> bvals;
+  bool host = false;
+  for (int i = 0; i < n; ++i) {
+    const std::string yi = "y[" + std::to_string(i) + "]";
+    const std::string oi = "out[" + std::to_string(i) + "]";
+    if ((s = check_image(&y[i], yi.c_str())) != FEPLL_OK) return s;
+    if ((s = check_image(&out[i], oi.c_str())) != FEPLL_OK) return s;
+    if (out[i].height != y[i].height || out[i].width != y[i].width)
+      return fail(FEPLL_EINVAL, oi + " must have the shape of " + yi);
+    if (!(sigma[i] > 0.0) || !std::isfinite(sigma[i]))
+      return fail(FEPLL_EINVAL, "sigma[" + std::to_string(i) + "] must be > 0");
+    if ((s = host_finite(&y[i], yi.c_str())) != FEPLL_OK) return s;
+    Hs[i] = y[i].height;
+    Ws[i] = y[i].width;
+    for (int t = 0; t < kDefaultT; ++t) {
+      betas.push_back(kDefaultB[t] / (sigma[i] * sigma[i]));
+      bvals.push_back((float)kDefaultB[t]);  // beta sigma^2
+    }
+    host = host || !y[i].on_device || !out[i].on_device;
+  }
+  hipStream_t st = (hipStream_t)o.stream;
+  if ((s = use_stream(g, st)) != FEPLL_OK) return s;
+  g->profiling = o.profile != 0;
+  if ((s = make_plan(g, n, Hs.data(), Ws.data(), kDefaultT, bvals, st)) != FEPLL_OK) return s;
+  if ((s = ensure_consts(g, betas, table_mask(o), st)) != FEPLL_OK) return s;
+  for (int i = 0; i < n; ++i) HIPX(copy_in(g->ybuf + g->hd[i].px, &y[i], st));
+  const int64_t px = g->hd[n - 1].px + (int64_t)Hs[n - 1] * Ws[n - 1];
+  HIPX(hipMemcpyAsync(g->xa, g->ybuf, sizeof(float) * px, hipMemcpyDeviceToDevice, st));
+  float* res = nullptr;
+  if (o.profile) s = run_hqs(g, kDefaultT, o, nullptr, hipMemcpyDefault, &res, st);
+  else s = run_hqs_graph(g, kDefaultT, o, &res, st);
+  if (s != FEPLL_OK) return s;
+  for (int i = 0; i < n; ++i) HIPX(copy_out(&out[i], res + g->hd[i].px, st));
+  if (host) HIPX(hipStreamSynchronize(st));
+  return FEPLL_OK;
+}
+
+fepll_status fepll_set_tuning(fepll_gmm* g, const fepll_tuning* t) {
+  g_err.clear();
+  if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
+  fepll_tuning v;
+  default_tuning(&v);
+  if (t) v = *t;
+  if (v.est_blocks < 0) return fail(FEPLL_EINVAL, "tuning.est_blocks must be >= 0");
+  if (v.wiener_blocks < 8 || v.wiener_blocks % 8)
+    return fail(FEPLL_EINVAL, "tuning.wiener_blocks must be a positive multiple of 8");
+  if (v.ola_rows != 16 && v.ola_rows != 32 && v.ola_rows != 64)
+    return fail(FEPLL_EINVAL, "tuning.ola_rows must be 16, 32 or 64");
+  v.reserved = 0;
+  g->tune = v;
+  g->plan_valid = false;  // the reprojection tiles depend on ola_rows
+  return FEPLL_OK;
+}
+
+fepll_status fepll_get_tuning(fepll_gmm* g, fepll_tuning* t) {
+  g_err.clear();
+  if (!g || !t) return fail(FEPLL_EINVAL, "NULL argument");
+  *t = g->tune;
+  return FEPLL_OK;
+}
+
+fepll_status fepll_autotune(fepll_gmm* g, int32_t n, const fepll_image* y, const double* sigma,
+                            const fepll_options* opt, fepll_tuning* best) {
+  g_err.clear();
+  if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
+  if (n < 1 || n > kMaxBatch || !y || !sigma)
+    return fail(FEPLL_EINVAL, "1..65536 images with their sigma are needed");
+  fepll_options o;
+  fepll_options_default(&o);
+  if (opt) o = *opt;
+  o.profile = 1;
+  fepll_status s;
+  int64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    if ((s = check_image(&y[i], "y")) != FEPLL_OK) return s;
+    total += (int64_t)y[i].height * y[i].width;
+  }
+  // every image is restored into a device scratch image
+  float* scratch = nullptr;
+  HIPX(dalloc(&scratch, (size_t)total));
+  std::vector<fepll_image> outs(y, y + n);
+  int64_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    outs[i].data = scratch + off;
+    outs[i].row_stride = y[i].width;
+    outs[i].on_device = 1;
+    off += (int64_t)y[i].height * y[i].width;
+  }
+  // Candidates per stage.  A stage's time does not depend on the other
+  // stages' shapes, so trial r takes candidate r mod (count) of every stage:
+  // 12 trials cover every candidate of every stage; each is kept at its
+  // fastest trial.
+  const int est_c[] = {0, 512, 768, 1024};
+  const int wie_c[] = {1024, 2048, 4096, 8192};
+  const int ola_c[] = {16, 32, 64};
+  const int ne = 4, nw = 4, no = 3, trials = 12;
+  std::vector<double> te(ne, 1e300), tw(nw, 1e300), to(no, 1e300);
+  const fepll_tuning saved = g->tune;
+  s = FEPLL_OK;
+  for (int r = -1; r < trials && s == FEPLL_OK; ++r) {
+    const int rr = r < 0 ? 0 : r;  // r = -1: warm-up (constants, scratch, code objects)
+    const fepll_tuning t{est_c[rr % ne], wie_c[rr % nw], ola_c[rr % no], 0};
+    if ((s = fepll_set_tuning(g, &t)) != FEPLL_OK) break;
+    double ms[kStages];
+    (void)fepll_profile(g, nullptr, nullptr, 0);
+    if ((s = fepll_restore_batch(g, n, y, sigma, outs.data(), &o)) != FEPLL_OK) break;
+    if ((s = fepll_profile(g, ms, nullptr, kStages)) != FEPLL_OK) break;
+    if (r < 0) continue;
+    te[rr % ne] = std::min(te[rr % ne], ms[0]);
+    tw[rr % nw] = std::min(tw[rr % nw], ms[3]);
+    to[rr % no] = std::min(to[rr % no], ms[4]);
+  }
+  (void)hipStreamSynchronize((hipStream_t)o.stream);
+  dfree(scratch);
+  if (s != FEPLL_OK) {
+    const std::string msg = g_err;
+    (void)fepll_set_tuning(g, &saved);
+    return fail(s, msg);
+  }
+  const fepll_tuning t{est_c[std::min_element(te.begin(), te.end()) - te.begin()],
+                       wie_c[std::min_element(tw.begin(), tw.end()) - tw.begin()],
+                       ola_c[std::min_element(to.begin(), to.end()) - to.begin()], 0};
+  if ((s = fepll_set_tuning(g, &t)) != FEPLL_OK) return s;
+  if (best) *best = t;
   return FEPLL_OK;
 }
 
@@ -593,7 +977,8 @@ fepll_status fepll_propose(fepll_gmm* g, const fepll_image* x, double beta, int3
   const int H = x->height, W = x->width;
   hipStream_t st = (hipStream_t)stream;
   if ((s = use_stream(g, st)) != FEPLL_OK) return s;
-  if ((s = ensure_ws(g, H, W)) != FEPLL_OK) return s;
+  const std::vector<float> bv(1, 1.f);
+  if ((s = make_plan(g, 1, &H, &W, 1, bv, st)) != FEPLL_OK) return s;
   HIPX(copy_in(g->xa, x, st));
   HIPX(launch_propose_bf16(g->xa, H, W, beta, g->pWb, g->pbias, g->K, top_m, cand, st));
   return FEPLL_OK;
@@ -616,14 +1001,12 @@ fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta, int32
   hipStream_t st = (hipStream_t)o.stream;
   if ((s = use_stream(g, st)) != FEPLL_OK) return s;
   g->profiling = o.profile != 0;
-  if ((s = ensure_ws(g, H, W)) != FEPLL_OK) return s;
-  Schedule sch{};
-  sch.T = 1;
-  sch.beta[0] = beta;
-  if ((s = ensure_consts(g, sch, st)) != FEPLL_OK) return s;
+  const std::vector<float> bv(1, 1.f);
+  if ((s = make_plan(g, 1, &H, &W, 1, bv, st)) != FEPLL_OK) return s;
+  if ((s = ensure_consts(g, std::vector<double>(1, beta), table_mask(o), st)) != FEPLL_OK)
+    return s;
   HIPX(copy_in(g->xa, x, st));
-  return run_select(g, g->xa, H, W, 0, beta, o.precision, o.recheck != 0,
-                    o.use_proposal ? &o : nullptr, labels, best, second, flags, st);
+  return select_batch(g, 0, o, g->xa, labels, best, second, flags, st);
 }
 
 }  // extern "C"

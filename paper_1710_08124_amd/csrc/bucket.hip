@@ -6,10 +6,11 @@
 // per-patch 64x64 products into one dense GEMM per component (each filter
 // is loaded once per tile of kWienerTile patches instead of once per patch).
 //
-// Three launches, no atomics on global data (LDS counters only):
+// Four launches over a batch of images, no atomics on global data (LDS
+// counters only); every image is sorted on its own:
 //  1. hist:    per block of kSortBlock patches, a per-component count
 //              (workgroup-local LDS counters), stored component-major.
-//  2. scan:    one workgroup turns the counts into exclusive offsets
+//  2. scan:    one workgroup per image turns the counts into exclusive offsets
 //              (component-major, so a component's patches are contiguous and
 //              ordered by block), and derives per component its start, its
 //              count and the exclusive prefix of its tile count.
@@ -19,22 +20,41 @@
 //              estimate depends only on its own pixels and its component
 //              (every MFMA output column is computed independently), so the
 //              estimates written are the same whatever tile a patch lands in.
+//  4. wbase:   the first Wiener tile of each image across the batch.
 #include "common.h"
 
 namespace fepll {
 
-__global__ __launch_bounds__(1024) void hist_kernel(const int32_t* __restrict__ labels, int Np,
-                                                    int K, int nb, int32_t* __restrict__ hist) {
+// Sort block blockIdx.x of the batch: its image, the image's patch count,
+// its number of sort blocks and the block's index within the image.
+struct SortBlock {
+  ImgDesc d;
+  int Np, nb, lb;
+};
+__device__ __forceinline__ SortBlock sort_block(const Batch& b) {
+  SortBlock s;
+  s.d = b.d[b.sort_img[blockIdx.x]];
+  s.Np = (s.d.H - 7) * (s.d.W - 7);
+  s.nb = (s.Np + kSortBlock - 1) / kSortBlock;
+  s.lb = blockIdx.x - s.d.sort0;
+  return s;
+}
+
+__global__ __launch_bounds__(1024) void hist_kernel(Batch b, const int32_t* __restrict__ labels_b,
+                                                    int K, int32_t* __restrict__ hist_b) {
   extern __shared__ int32_t h[];
+  const SortBlock sb = sort_block(b);
+  const int32_t* labels = labels_b + sb.d.np;
+  int32_t* hist = hist_b + (size_t)K * sb.d.sort0;
   for (int k = threadIdx.x; k < K; k += blockDim.x) h[k] = 0;
   __syncthreads();
-  const int base = blockIdx.x * kSortBlock;
+  const int base = sb.lb * kSortBlock;
   for (int i = threadIdx.x; i < kSortBlock; i += blockDim.x) {
     const int g = base + i;
-    if (g < Np) atomicAdd(&h[labels[g]], 1);
+    if (g < sb.Np) atomicAdd(&h[labels[g]], 1);
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < K; k += blockDim.x) hist[(size_t)k * nb + blockIdx.x] = h[k];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) hist[(size_t)k * sb.nb + sb.lb] = h[k];
 }
 
 // Exclusive scan of the inclusive per-thread totals held in s[0..n), n <= 1024.
@@ -54,9 +74,15 @@ __device__ void block_exclusive_scan(int32_t* s, int n) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(1024) void scan_kernel(int32_t* __restrict__ hist, int K, int nb,
-                                                    int Np, int32_t* __restrict__ seg) {
+// One workgroup per image of the batch.
+__global__ __launch_bounds__(1024) void scan_kernel(Batch b, int32_t* __restrict__ hist_b, int K,
+                                                    int32_t* __restrict__ seg_b) {
   __shared__ int32_t part[1024];
+  const ImgDesc d = b.d[blockIdx.x];
+  const int Np = (d.H - 7) * (d.W - 7);
+  const int nb = (Np + kSortBlock - 1) / kSortBlock;
+  int32_t* hist = hist_b + (size_t)K * d.sort0;
+  int32_t* seg = seg_b + d.seg;
   const int t = threadIdx.x;
   const int M = K * nb;
   const int chunk = (M + 1023) / 1024;
@@ -122,32 +148,63 @@ __global__ __launch_bounds__(1024) void scan_kernel(int32_t* __restrict__ hist, 
   }
 }
 
-__global__ __launch_bounds__(1024) void scatter_kernel(const int32_t* __restrict__ labels, int Np,
-                                                       int K, int nb,
-                                                       const int32_t* __restrict__ offs,
-                                                       int32_t* __restrict__ perm) {
+__global__ __launch_bounds__(1024) void scatter_kernel(Batch b, const int32_t* __restrict__ labels_b,
+                                                       int K, const int32_t* __restrict__ offs_b,
+                                                       int32_t* __restrict__ perm_b) {
   extern __shared__ int32_t cur[];  // [K] next free slot of each component in this block
-  for (int k = threadIdx.x; k < K; k += blockDim.x) cur[k] = offs[(size_t)k * nb + blockIdx.x];
+  const SortBlock sb = sort_block(b);
+  const int32_t* labels = labels_b + sb.d.np;
+  const int32_t* offs = offs_b + (size_t)K * sb.d.sort0;
+  int32_t* perm = perm_b + sb.d.np;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) cur[k] = offs[(size_t)k * sb.nb + sb.lb];
   __syncthreads();
-  const int base = blockIdx.x * kSortBlock;
+  const int base = sb.lb * kSortBlock;
   for (int i = threadIdx.x; i < kSortBlock; i += blockDim.x) {
     const int g = base + i;
-    if (g < Np) perm[atomicAdd(&cur[labels[g]], 1)] = g;
+    if (g < sb.Np) perm[atomicAdd(&cur[labels[g]], 1)] = g;
   }
 }
 
-hipError_t launch_bucket(const int32_t* labels, int Np, int K, int32_t* hist, int32_t* seg,
-                         int32_t* perm, hipStream_t st) {
-  const int nb = (Np + kSortBlock - 1) / kSortBlock;
-  hipLaunchKernelGGL(hist_kernel, dim3(nb), dim3(1024), K * sizeof(int32_t), st, labels, Np, K, nb,
-                     hist);
+// First Wiener tile of each image across the batch (exclusive prefix of the
+// per-image totals), one workgroup.
+__global__ __launch_bounds__(1024) void wbase_kernel(Batch b, int K,
+                                                     const int32_t* __restrict__ seg_b,
+                                                     int32_t* __restrict__ wbase) {
+  __shared__ int32_t part[1024];
+  int32_t carry = 0;
+  for (int i0 = 0; i0 < b.n; i0 += 1024) {
+    const int i = i0 + threadIdx.x;
+    const int32_t v = (i < b.n) ? seg_b[b.d[i].seg + 3 * K + 2] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int32_t u = (threadIdx.x >= off) ? part[threadIdx.x - off] : 0;
+      __syncthreads();
+      part[threadIdx.x] += u;
+      __syncthreads();
+    }
+    if (i < b.n) wbase[i] = carry + part[threadIdx.x] - v;
+    const int32_t tot = part[1023];
+    __syncthreads();
+    carry += tot;
+  }
+  if (threadIdx.x == 0) wbase[b.n] = carry;
+}
+
+hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int32_t* hist,
+                               int32_t* seg, int32_t* perm, int32_t* wbase, hipStream_t st) {
+  hipLaunchKernelGGL(hist_kernel, dim3(b.n_sort), dim3(1024), K * sizeof(int32_t), st, b, labels,
+                     K, hist);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, hist, K, nb, Np, seg);
+  hipLaunchKernelGGL(scan_kernel, dim3(b.n), dim3(1024), 0, st, b, hist, K, seg);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scatter_kernel, dim3(nb), dim3(1024), K * sizeof(int32_t), st, labels, Np,
-                     K, nb, hist, perm);
+  hipLaunchKernelGGL(scatter_kernel, dim3(b.n_sort), dim3(1024), K * sizeof(int32_t), st, b,
+                     labels, K, hist, perm);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(wbase_kernel, dim3(1), dim3(1024), 0, st, b, K, seg, wbase);
   return hipGetLastError();
 }
 

@@ -36,52 +36,119 @@ constexpr int kTileStride = 4096;  // floats per (t, k) operand table
 constexpr int kMaxT = 16;
 constexpr int kMaxK = 1024;
 
-struct Schedule {
-  int T;
-  double beta[kMaxT];
+// Which per-beta tables a prep launch fills (Wt and L32 always).
+enum { kTabF32 = 1, kTabBF16 = 2, kTabF8 = 4 };
+
+// Device pointers of the per-beta tables, [S][K][...] for S beta slots.
+struct ConstTables {
+  float* Ut;
+  uint16_t* Ub;
+  float* Wt;
+  float* L32;
+  double* L64;
+  double* invnu64;
+  uint8_t* Uf;
+  int32_t* Ue;
+};
+
+// One image of a batch (a single restoration is a batch of one): its size
+// and where it lives in the packed buffers.  Images are packed one after
+// the other: pixels (H x W, contiguous rows) from px, patches from np (the
+// labels, the sorted patch list and the patch estimates of the image),
+// the bucket segment table from seg.  Work is split into tiles numbered
+// across the batch: the image's first sort block, selection tile and
+// reprojection tile are sort0, est0 and ola0; its beta of iteration t is
+// slot slot0 + t of the per-beta tables.
+struct ImgDesc {
+  int32_t H, W;
+  int64_t px;
+  int64_t np;
+  int64_t seg;
+  int32_t sort0, est0, ola0, slot0;
+};
+
+// Selection tile: 4 patch rows x kEstCols patch columns (one workgroup).
+constexpr int kEstCols = 128;
+// Reprojection tile: kOlaX columns x Batch::ola_rows (16, 32 or 64) rows.
+constexpr int kOlaX = 64;
+constexpr int kMaxBatch = 65536;
+
+struct Batch {
+  const ImgDesc* d;         // device, n entries
+  const int32_t* est_img;   // device: image of each selection tile
+  const int32_t* sort_img;  // device: image of each sort block
+  const int32_t* ola_img;   // device: image of each reprojection tile
+  int n;
+  int n_est, n_sort, n_ola;  // tile totals
+  int64_t n_patches;         // patches of the whole batch
+  int ola_rows;              // rows of a reprojection tile
 };
 
 // ------------------------------------------------------------ launches
 // Every launcher returns hipSuccess or the launch error; none synchronises.
 
+// Tables of S beta slots (betas: device, S entries) for the tables in mask.
 hipError_t launch_prep(const double* U64, const double* lam64, const double* w64, int K,
-                       const Schedule& sch, float* Ut, uint16_t* Ub, float* Wt, float* L32,
-                       double* L64, double* invnu64, uint8_t* Uf, int32_t* Ue, hipStream_t st);
+                       const double* betas, int S, int mask, const ConstTables& tb,
+                       hipStream_t st);
 
+// Single-image selection kernels (tables of one beta).
 hipError_t launch_estep_f32(const float* x, int H, int W, const float* Ut_t, const float* L32_t,
                             int K, double beta, int32_t* labels, float* best, float* second,
                             int32_t* flags, int32_t* list_count, int32_t* list, hipStream_t st);
-
-hipError_t launch_estep_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
-                             const float* L32_t, int K, int32_t* labels, float* best,
-                             float* second, hipStream_t st);
-
-hipError_t launch_estep_fp8(const float* x, int H, int W, const uint8_t* Uf_t,
-                            const int32_t* Ue_t, const float* L32_t, int K, int32_t* labels,
-                            float* best, float* second, hipStream_t st);
 
 hipError_t launch_recheck_f64(const float* x, int H, int W, const double* U64,
                               const double* invnu64_t, const double* L64_t, int K,
                               const int32_t* list_count, const int32_t* list, int32_t* labels,
                               int max_list, hipStream_t st);
 
-// Counting sort of patch indices by label and the Wiener tile list.
-// hist: [K][nb] int32, nb = ceil(Np / kSortBlock); seg: int32, laid out as
-// start[K+1], count[K], tile_prefix[K+1], total_tiles, then the tile table
-// (seg_size(Np, K) entries in all): entry t = k | (tile index in k) << 10.
+// Batched selection, all K components, iteration t: x, labels, best, second
+// are packed buffers (best / second may be NULL); Ub / Uf / Ue / L32 the
+// tables of all slots.
+// blocks: workgroups of the persistent launch (0: one per tile).
+hipError_t launch_estep_bf16_batch(const Batch& b, const float* x, const uint16_t* Ub,
+                                   const float* L32, int K, int t, int32_t* labels, float* best,
+                                   float* second, int blocks, hipStream_t st);
+hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t* Uf,
+                                  const int32_t* Ue, const float* L32, int K, int t,
+                                  int32_t* labels, float* best, float* second, int blocks,
+                                  hipStream_t st);
+
+// Counting sort of each image's patch indices by label and the Wiener tile
+// lists.  hist: [K][sort blocks of the image] int32 per image, at
+// K * sort0; seg (per image, at d.seg, seg_size(Np, K) entries): start[K+1],
+// count[K], tile_prefix[K+1], total_tiles, then the tile table, entry
+// t = k | (tile index in k) << 10; perm: patch indices (local to the image)
+// sorted by label, at d.np; wbase (n + 1): first Wiener tile of each image
+// across the batch, wbase[n] the total.
 constexpr int kSortBlock = 16384;
 constexpr int kWienerTile = 32;
 inline size_t seg_size(size_t Np, int K) { return 3 * (size_t)K + 3 + Np / kWienerTile + K + 1; }
-hipError_t launch_bucket(const int32_t* labels, int Np, int K, int32_t* hist, int32_t* seg,
-                         int32_t* perm, hipStream_t st);
+hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int32_t* hist,
+                               int32_t* seg, int32_t* perm, int32_t* wbase, hipStream_t st);
 
-// Patch estimates z^: float [Np][64], patch-major (pixel 8 dy + dx of patch i
-// at i * 64 + 8 dy + dx).
-hipError_t launch_wiener_f32(const float* x, int H, int W, const float* Wt_t, int K,
-                             const int32_t* seg, const int32_t* perm, float* Zhat,
-                             hipStream_t st);
+// Patch estimates z^: float [patches][64], patch-major (pixel 8 dy + dx of
+// patch i at i * 64 + 8 dy + dx), at d.np * 64 per image.
+// blocks: workgroups of the launch, a multiple of 8 (a cap: never more than
+// the tiles need).
+hipError_t launch_wiener_batch(const Batch& b, const float* x, const float* Wt, int K, int t,
+                               const int32_t* seg, const int32_t* perm, const int32_t* wbase,
+                               float* Zhat, int blocks, hipStream_t st);
 
-hipError_t launch_ola_update(const float* Zhat, const float* y, int H, int W, double b,
-                             float* xnew, hipStream_t st);
+// Reprojection + image update of iteration t: bvals[slot] = beta sigma^2.
+hipError_t launch_ola_batch(const Batch& b, const float* Zhat, const float* y,
+                            const float* bvals, int t, float* xnew, hipStream_t st);
+
+// Image of tile `tile` given each image's first tile (first[0] = 0,
+// ascending): the last i with first[i] <= tile.
+__device__ __forceinline__ int image_of(const int32_t* __restrict__ first, int n, int tile) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 }  // namespace fepll

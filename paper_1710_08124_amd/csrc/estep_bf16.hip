@@ -146,21 +146,50 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;
   const int col = lane & 15;
-  const int Hp = a.H - 7, Wp = a.W - 7;
-  const uint4* up = reinterpret_cast<const uint4*>(a.Ub) + lane;  // [K][4][2][64] uint4
 
   const int nlist = (MODE == kModeListFull) ? *a.list_count : 0;
-  // list mode: the workgroup takes 512 consecutive list entries per pass (a
-  // workgroup-uniform loop: every wave reaches every barrier of the K loop)
-  int wchunk = blockIdx.y * gridDim.x + blockIdx.x;
+  // work items: list mode, 512 consecutive list entries; spatial all-K
+  // mode, one selection tile (4 patch rows x 128 columns) of any image of
+  // the batch.  The loop is workgroup-uniform: every wave reaches every
+  // barrier of the K loop.
+  int item = blockIdx.y * gridDim.x + blockIdx.x;
   const int nwg = gridDim.x * gridDim.y;
-  for (;;) {
+  for (;; item += nwg) {
+    // ---- this item's image and tables
+    const float* x = a.x;
+    int H = a.H, W = a.W;
+    const uint16_t* Ub = a.Ub;
+    const float* Lt = a.L;
+    int32_t* labels = a.labels;
+    float* bestp = a.best;
+    float* secondp = a.second;
+    int tr = blockIdx.y, tc = blockIdx.x;  // tile row / column (spatial modes)
+    if (MODE == kModeSpatialFull) {
+      if (item >= a.n_est) break;
+      const int im = a.est_img[item];
+      const ImgDesc d = a.d[im];
+      H = d.H;
+      W = d.W;
+      x += d.px;
+      const size_t slot = (size_t)(d.slot0 + a.t);
+      Ub += slot * a.K * kTileStride;
+      Lt += slot * a.K;
+      labels += d.np;
+      if (bestp) bestp += d.np;
+      if (secondp) secondp += d.np;
+      const int ntx = (W - 7 + kEstCols - 1) / kEstCols;
+      const int lt = item - d.est0;
+      tr = lt / ntx;
+      tc = lt - tr * ntx;
+    }
+    const int Hp = H - 7, Wp = W - 7;
+    const uint4* up = reinterpret_cast<const uint4*>(Ub) + lane;  // [K][4][2][64] uint4
     // ---- this wave's 128 patches
     int idx[PB];
     bool valid[PB];
     if (MODE == kModeListFull) {
-      if (wchunk * 512 >= nlist) break;
-      const int base = wchunk * 512;
+      if (item * 512 >= nlist) break;
+      const int base = item * 512;
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) {
         const int e = base + wave * 128 + 16 * pb + col;
@@ -168,8 +197,8 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
         idx[pb] = a.list[valid[pb] ? e : base];
       }
     } else {
-      const int r = blockIdx.y * 4 + wave;
-      const int c0 = blockIdx.x * (16 * PB);
+      const int r = tr * 4 + wave;
+      const int c0 = tc * (16 * PB);
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) {
         const int c = c0 + 16 * pb + col;
@@ -181,7 +210,7 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
       const int pr = idx[pb] / Wp;
-      load_patch(a.x, a.W, pr, idx[pb] - pr * Wp, g, zb[pb]);
+      load_patch(x, W, pr, idx[pb] - pr * Wp, g, zb[pb]);
       // one block's raw pixels live at a time (keeps the prologue in registers)
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -239,14 +268,14 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       for (int u = 0; u < nu; ++u) {
         const int k = ul[wave][u];
         float cA, cB;
-        score(up + (size_t)k * 512, zb, a.L[k], g, cA, cB);
+        score(up + (size_t)k * 512, zb, Lt[k], g, cA, cB);
         if (has(candA, k)) keep_best(cA, k, bA, sA, kA);
         if (has(candB, k)) keep_best(cB, k, bB, sB, kB);
       }
     } else {
       // all K: the per-component operand (8 KB) is staged once per
       // workgroup in LDS, double-buffered, the next one already in flight
-      const uint4* gsrc = reinterpret_cast<const uint4*>(a.Ub);
+      const uint4* gsrc = reinterpret_cast<const uint4*>(Ub);
       uint4 pre0 = gsrc[threadIdx.x], pre1 = gsrc[256 + threadIdx.x];
       for (int k = 0; k < a.K; ++k) {
         uint4* As = Ash[k & 1];
@@ -258,7 +287,7 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
           pre1 = gsrc[(size_t)(k + 1) * 512 + 256 + threadIdx.x];
         }
         float cA, cB;
-        score(As + lane, zb, a.L[k], g, cA, cB);
+        score(As + lane, zb, Lt[k], g, cA, cB);
         keep_best(cA, k, bA, sA, kA);
         keep_best(cB, k, bB, sB, kB);
       }
@@ -271,9 +300,9 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       if (!v) continue;
       const int i = p ? iB : iA;
       const float b = p ? bB : bA, s = p ? sB : sA;
-      a.labels[i] = p ? kB : kA;
-      if (a.best) a.best[i] = b;
-      if (a.second) a.second[i] = s;
+      labels[i] = p ? kB : kA;
+      if (bestp) bestp[i] = b;
+      if (secondp) secondp[i] = s;
       if (MODE == kModeSpatialCand) {
         const float gap = (s < INFINITY) ? 0.5f * (s - b) : -INFINITY;
         if (!(gap >= a.margin)) {
@@ -282,41 +311,48 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
         }
       }
     }
-    if (MODE != kModeListFull) break;
-    wchunk += nwg;
+    if (MODE == kModeSpatialCand) break;
   }
 }
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st) {
-  const int Hp = args.H - 7, Wp = args.W - 7;
   if (mode == kModeListFull) {
-    const int Np = Hp * Wp;
+    const int Np = (args.H - 7) * (args.W - 7);
     int blocks = (Np + 511) / 512;
     if (blocks > 512) blocks = 512;
     hipLaunchKernelGGL(estep_bf16_kernel<kModeListFull>, dim3(blocks), dim3(256), 0, st, args);
     return hipGetLastError();
   }
+  if (mode == kModeSpatialFull) {
+    // persistent: a fixed number of workgroups looping over the tiles
+    int blocks = args.n_est;
+    if (args.blocks > 0 && args.blocks < blocks) blocks = args.blocks;
+    if (blocks < 1) return hipSuccess;
+    hipLaunchKernelGGL(estep_bf16_kernel<kModeSpatialFull>, dim3(blocks), dim3(256), 0, st, args);
+    return hipGetLastError();
+  }
+  const int Hp = args.H - 7, Wp = args.W - 7;
   dim3 grid((Wp + 16 * PB - 1) / (16 * PB), (Hp + 3) / 4);
-  if (mode == kModeSpatialCand)
-    hipLaunchKernelGGL(estep_bf16_kernel<kModeSpatialCand>, grid, dim3(256), 0, st, args);
-  else
-    hipLaunchKernelGGL(estep_bf16_kernel<kModeSpatialFull>, grid, dim3(256), 0, st, args);
+  hipLaunchKernelGGL(estep_bf16_kernel<kModeSpatialCand>, grid, dim3(256), 0, st, args);
   return hipGetLastError();
 }
 
-hipError_t launch_estep_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
-                             const float* L32_t, int K, int32_t* labels, float* best,
-                             float* second, hipStream_t st) {
+hipError_t launch_estep_bf16_batch(const Batch& b, const float* x, const uint16_t* Ub,
+                                   const float* L32, int K, int t, int32_t* labels, float* best,
+                                   float* second, int blocks, hipStream_t st) {
   BF16Args a{};
+  a.blocks = blocks;
   a.x = x;
-  a.H = H;
-  a.W = W;
-  a.Ub = Ub_t;
-  a.L = L32_t;
+  a.Ub = Ub;
+  a.L = L32;
   a.K = K;
   a.labels = labels;
   a.best = best;
   a.second = second;
+  a.d = b.d;
+  a.est_img = b.est_img;
+  a.n_est = b.n_est;
+  a.t = t;
   return launch_estep_bf16_mode(kModeSpatialFull, a, st);
 }
 

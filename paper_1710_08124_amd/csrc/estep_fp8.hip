@@ -18,7 +18,8 @@
 // 2 (eigen blocks) x 4 (patch blocks) MFMAs and 128 float32 FMAs of squares,
 // then one exchange between lane halves leaves every lane owning 2 patches.
 // The per-component operand (4 KB) is staged through double-buffered LDS
-// shared by the workgroup's 4 waves.
+// shared by the workgroup's 4 waves.  The launch is persistent over the
+// selection tiles of a batch of images, each with its own beta.
 #include "common.h"
 #include "wave_ops.h"
 
@@ -78,89 +79,108 @@ __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, 
 }  // namespace
 
 __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
-    const float* __restrict__ x, int H, int W, const uint4* __restrict__ Uf,
-    const int32_t* __restrict__ Ue, const float* __restrict__ L, int K,
-    int32_t* __restrict__ labels, float* __restrict__ best, float* __restrict__ second) {
+    const ImgDesc* __restrict__ dsc, const int32_t* __restrict__ est_img, int n_est, int t,
+    const float* __restrict__ xb, const uint4* __restrict__ Uf_all,
+    const int32_t* __restrict__ Ue_all, const float* __restrict__ L_all, int K,
+    int32_t* __restrict__ labels_b, float* __restrict__ best_b, float* __restrict__ second_b) {
   __shared__ uint4 Ash[2][256];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int h = lane >> 5;
   const int col = lane & 31;
-  const int Hp = H - 7, Wp = W - 7;
 
-  const int r = blockIdx.y * 4 + wave;
-  const int c0 = blockIdx.x * (32 * PB);
-  i32x8 zq[PB];
-  int zc[PB];
-  int idx[PB];
-  bool valid[PB];
-#pragma unroll
-  for (int pb = 0; pb < PB; ++pb) {
-    const int c = c0 + 32 * pb + col;
-    valid[pb] = (r < Hp) && (c < Wp);
-    const int rr = min(r, Hp - 1), cc = min(c, Wp - 1);
-    idx[pb] = rr * Wp + cc;
-    load_patch8(x, W, rr, cc, h, zq[pb], zc[pb]);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-  // lane's own patches after the half exchange: blocks h and 2 + h
-  const int iA = h ? idx[1] : idx[0], iB = h ? idx[3] : idx[2];
-  const bool vA = h ? valid[1] : valid[0], vB = h ? valid[3] : valid[2];
+  // persistent: each workgroup loops over selection tiles (4 patch rows x
+  // 128 columns) of the batch; the loop is workgroup-uniform
+  for (int item = blockIdx.x; item < n_est; item += gridDim.x) {
+    const ImgDesc d = dsc[est_img[item]];
+    const int W = d.W, Hp = d.H - 7, Wp = d.W - 7;
+    const float* x = xb + d.px;
+    const size_t slot = (size_t)(d.slot0 + t);
+    const uint4* Uf = Uf_all + slot * K * (kTileStride / 16);
+    const int32_t* Ue = Ue_all + slot * K;
+    const float* L = L_all + slot * K;
+    const int ntx = (Wp + kEstCols - 1) / kEstCols;
+    const int lt = item - d.est0;
+    const int tr = lt / ntx, tc = lt - tr * ntx;
 
-  float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
-  int kA = 0, kB = 0;
-  uint4 pre = Uf[threadIdx.x];
-  for (int k = 0; k < K; ++k) {
-    uint4* As = Ash[k & 1];
-    As[threadIdx.x] = pre;
-    __syncthreads();
-    if (k + 1 < K) pre = Uf[(size_t)(k + 1) * 256 + threadIdx.x];
-    const int ek = Ue[k];
-    float q[PB];
+    const int r = tr * 4 + wave;
+    const int c0 = tc * (32 * PB);
+    i32x8 zq[PB];
+    int zc[PB];
+    int idx[PB];
+    bool valid[PB];
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb) {
-      const uint4 a0 = As[(2 * rb) * 64 + lane], a1 = As[(2 * rb + 1) * 64 + lane];
-      const i32x8 A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
-                       (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
-      f32x16 acc[PB];
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) {
-        acc[pb] = (f32x16){0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                           0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, zq[pb], acc[pb], 0, 0, 0, ek,
-                                                                  0, zc[pb]);
-      }
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+    for (int pb = 0; pb < PB; ++pb) {
+      const int c = c0 + 32 * pb + col;
+      valid[pb] = (r < Hp) && (c < Wp);
+      const int rr = min(r, Hp - 1), cc = min(c, Wp - 1);
+      idx[pb] = rr * Wp + cc;
+      load_patch8(x, W, rr, cc, h, zq[pb], zc[pb]);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    const float Lk = L[k];
-    const float cA = Lk + pair_sum32(q[0], q[1]);
-    const float cB = Lk + pair_sum32(q[2], q[3]);
-    keep_best(cA, k, bA, sA, kA);
-    keep_best(cB, k, bB, sB, kB);
-  }
+    // lane's own patches after the half exchange: blocks h and 2 + h
+    const int iA = h ? idx[1] : idx[0], iB = h ? idx[3] : idx[2];
+    const bool vA = h ? valid[1] : valid[0], vB = h ? valid[3] : valid[2];
+
+    float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
+    int kA = 0, kB = 0;
+    uint4 pre = Uf[threadIdx.x];
+    for (int k = 0; k < K; ++k) {
+      uint4* As = Ash[k & 1];
+      As[threadIdx.x] = pre;
+      __syncthreads();
+      if (k + 1 < K) pre = Uf[(size_t)(k + 1) * 256 + threadIdx.x];
+      const int ek = Ue[k];
+      float q[PB];
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const bool v = p ? vB : vA;
-    if (!v) continue;
-    const int i = p ? iB : iA;
-    labels[i] = p ? kB : kA;
-    if (best) best[i] = p ? bB : bA;
-    if (second) second[i] = p ? sB : sA;
+      for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const uint4 a0 = As[(2 * rb) * 64 + lane], a1 = As[(2 * rb + 1) * 64 + lane];
+        const i32x8 A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
+                         (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+        f32x16 acc[PB];
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) {
+          acc[pb] = (f32x16){0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                             0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+          acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, zq[pb], acc[pb], 0, 0, 0,
+                                                                    ek, 0, zc[pb]);
+        }
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+      }
+      const float Lk = L[k];
+      const float cA = Lk + pair_sum32(q[0], q[1]);
+      const float cB = Lk + pair_sum32(q[2], q[3]);
+      keep_best(cA, k, bA, sA, kA);
+      keep_best(cB, k, bB, sB, kB);
+    }
+    __syncthreads();  // the staging buffers are reused by the next tile
+    int32_t* labels = labels_b + d.np;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const bool v = p ? vB : vA;
+      if (!v) continue;
+      const int i = p ? iB : iA;
+      labels[i] = p ? kB : kA;
+      if (best_b) best_b[d.np + i] = p ? bB : bA;
+      if (second_b) second_b[d.np + i] = p ? sB : sA;
+    }
   }
 }
 
-hipError_t launch_estep_fp8(const float* x, int H, int W, const uint8_t* Uf_t,
-                            const int32_t* Ue_t, const float* L32_t, int K, int32_t* labels,
-                            float* best, float* second, hipStream_t st) {
-  const int Hp = H - 7, Wp = W - 7;
-  dim3 grid((Wp + 32 * PB - 1) / (32 * PB), (Hp + 3) / 4);
-  hipLaunchKernelGGL(estep_fp8_kernel, grid, dim3(256), 0, st, x, H, W,
-                     reinterpret_cast<const uint4*>(Uf_t), Ue_t, L32_t, K, labels, best, second);
+hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t* Uf,
+                                  const int32_t* Ue, const float* L32, int K, int t,
+                                  int32_t* labels, float* best, float* second, int blocks,
+                                  hipStream_t st) {
+  // persistent: a fixed number of workgroups looping over the tiles
+  if (blocks <= 0 || blocks > b.n_est) blocks = b.n_est;
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(estep_fp8_kernel, dim3(blocks), dim3(256), 0, st, b.d, b.est_img, b.n_est,
+                     t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, K, labels, best, second);
   return hipGetLastError();
 }
 

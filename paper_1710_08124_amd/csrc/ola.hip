@@ -9,16 +9,18 @@
 //
 // z^ is stored patch-major, Zhat[patch][dy][dx] (256 contiguous bytes per
 // patch), so one patch row of a tile (71 patches) is one contiguous 18 KB
-// run.  A workgroup owns 32 output rows x 64 columns and walks the 39 patch
-// rows that touch them, top to bottom: each patch row is staged in LDS (odd
+// run.  A workgroup owns TY output rows x 64 columns (TY = 16, 32 or 64, a
+// tuning choice) and walks the TY + 7 patch rows that touch them, top to
+// bottom: each patch row is staged in LDS (odd
 // pitch, conflict-free reads) while the next one is in flight in registers,
 // and every pixel row in flight keeps a running sum in a register of the
 // thread that owns it (thread row j owns pixel rows = j mod 4, two of them
 // in flight).  A pixel row is final once patch row y (dy = 0) is added.
 //
-// Tiles are numbered column-strip-major and dealt so that consecutive tiles
-// of a strip run on the same XCD at about the same time: the 7 patch rows a
-// tile shares with the tile below are then read from that XCD's L2.
+// Tiles are numbered across the batch, image after image and column-strip-
+// major within an image, and dealt so that consecutive tiles of a strip run
+// on the same XCD at about the same time: the 7 patch rows a tile shares
+// with the tile below are then read from that XCD's L2.
 //
 // The per-pixel patch count of the valid patch set is the product of a row
 // and a column factor, cnt(y, x) = n(y, H) n(x, W) with
@@ -28,8 +30,7 @@
 namespace fepll {
 
 namespace {
-constexpr int TX = 64;
-constexpr int TY = 32;
+constexpr int TX = kOlaX;
 constexpr int NP = TX + 7;       // patches of one staged patch row
 constexpr int PITCH = 65;        // floats per staged patch
 constexpr int ROW = NP * PITCH;  // floats per staged patch row
@@ -37,17 +38,26 @@ constexpr int F4 = NP * 16;      // float4 of one patch row
 constexpr int PER = (F4 + 255) / 256;
 }  // namespace
 
-__global__ __launch_bounds__(256) void ola_update_kernel(const float* __restrict__ Zhat,
-                                                         const float* __restrict__ y, int H,
-                                                         int W, float b,
-                                                         float* __restrict__ xnew) {
+template <int TY>
+__global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
+                                                         const float* __restrict__ Zhat_b,
+                                                         const float* __restrict__ y_b,
+                                                         const float* __restrict__ bvals, int it,
+                                                         float* __restrict__ xnew_b) {
   __shared__ float buf[2][ROW];
-  const int Hp = H - 7, Wp = W - 7;
-  const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY;
   const int G8 = gridDim.x;  // a multiple of 8
   const int lin = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
-  if (lin >= ntx * nty) return;
-  const int x0 = (lin / nty) * TX, y0 = (lin % nty) * TY;
+  if (lin >= bt.n_ola) return;
+  const ImgDesc d = bt.d[bt.ola_img[lin]];
+  const int H = d.H, W = d.W;
+  const int Hp = H - 7, Wp = W - 7;
+  const float b = bvals[d.slot0 + it];
+  const float* Zhat = Zhat_b + (size_t)d.np * kP;
+  const float* y = y_b + d.px;
+  float* xnew = xnew_b + d.px;
+  const int nty = (H + TY - 1) / TY;
+  const int lt = lin - d.ola0;
+  const int x0 = (lt / nty) * TX, y0 = (lt % nty) * TY;
   const int tx = threadIdx.x & 63, j = threadIdx.x >> 6;
   const int cfirst = x0 - 7;
 
@@ -69,11 +79,11 @@ __global__ __launch_bounds__(256) void ola_update_kernel(const float* __restrict
     for (int u = 0; u < PER; ++u) {
       const int e = threadIdx.x + 256 * u;
       if (e < F4) {
-        float* d = B + (e >> 4) * PITCH + 4 * (e & 15);
-        d[0] = pre[u].x;
-        d[1] = pre[u].y;
-        d[2] = pre[u].z;
-        d[3] = pre[u].w;
+        float* q = B + (e >> 4) * PITCH + 4 * (e & 15);
+        q[0] = pre[u].x;
+        q[1] = pre[u].y;
+        q[2] = pre[u].z;
+        q[3] = pre[u].w;
       }
     }
   };
@@ -115,12 +125,18 @@ __global__ __launch_bounds__(256) void ola_update_kernel(const float* __restrict
   }
 }
 
-hipError_t launch_ola_update(const float* Zhat, const float* y, int H, int W, double b,
-                             float* xnew, hipStream_t st) {
-  const int n = ((W + TX - 1) / TX) * ((H + TY - 1) / TY);
-  const int blocks = (n + 7) & ~7;  // whole rounds over the 8 XCDs
-  hipLaunchKernelGGL(ola_update_kernel, dim3(blocks), dim3(256), 0, st, Zhat, y, H, W, (float)b,
-                     xnew);
+hipError_t launch_ola_batch(const Batch& b, const float* Zhat, const float* y,
+                            const float* bvals, int t, float* xnew, hipStream_t st) {
+  const int blocks = (b.n_ola + 7) & ~7;  // whole rounds over the 8 XCDs
+  if (b.ola_rows == 16)
+    hipLaunchKernelGGL(ola_update_kernel<16>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
+                       t, xnew);
+  else if (b.ola_rows == 64)
+    hipLaunchKernelGGL(ola_update_kernel<64>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
+                       t, xnew);
+  else
+    hipLaunchKernelGGL(ola_update_kernel<32>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
+                       t, xnew);
   return hipGetLastError();
 }
 

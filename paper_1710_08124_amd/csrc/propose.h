@@ -12,6 +12,9 @@ namespace fepll {
 enum { kModeSpatialFull = 0, kModeSpatialCand = 1, kModeListFull = 2 };
 
 struct BF16Args {
+  // spatial all-K mode: x, Ub, L, labels, best, second are the packed
+  // buffers / all-slot tables of a batch (see ImgDesc); other modes: one
+  // image and the tables of one beta
   const float* x;         // current image, H x W contiguous
   int H, W;
   const uint16_t* Ub;     // bfloat16 operand table of this beta
@@ -26,6 +29,11 @@ struct BF16Args {
   int32_t* fb_list;       // candidates mode: fallback list (Np)
   const int32_t* list_count;  // list mode: list length (device)
   const int32_t* list;        // list mode: patch indices
+  const ImgDesc* d;           // spatial all-K mode: the batch
+  const int32_t* est_img;     // spatial all-K mode: image of each tile
+  int n_est;                  // spatial all-K mode: tiles of the batch
+  int t;                      // spatial all-K mode: iteration (slot0 + t)
+  int blocks;                 // spatial all-K mode: workgroups (0 = one per tile)
 };
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st);

@@ -13,42 +13,54 @@
 //
 // The tile count depends on the labels, so the grid is fixed (a multiple of
 // 8 workgroups) and each workgroup walks its share of the device-side tile
-// list; a wave exits at the end of its share.
+// list of the whole batch (images one after the other, each image's tiles
+// ordered by component); a wave exits at the end of its share.
 #include "common.h"
 
 namespace fepll {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__global__ __launch_bounds__(256, 4) void wiener_f32_kernel(const float* __restrict__ x, int H,
-                                                         int W, const float4* __restrict__ Wt,
-                                                         int K, const int32_t* __restrict__ seg,
-                                                         const int32_t* __restrict__ perm,
-                                                         float* __restrict__ Zhat) {
+__global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const float* __restrict__ xb,
+                                                         const float4* __restrict__ Wt_all,
+                                                         int K, int it,
+                                                         const int32_t* __restrict__ seg_b,
+                                                         const int32_t* __restrict__ perm_b,
+                                                         const int32_t* __restrict__ wbase,
+                                                         float* __restrict__ Zhat_b) {
   const int lane = threadIdx.x & 63;
   const int half = lane >> 5;
   const int col = lane & 31;
-  const int Wp = W - 7;
-  const int32_t* start = seg;
-  const int32_t* count = seg + (K + 1);
-  const int32_t* tinfo = seg + (3 * K + 3);
-  const int total = seg[3 * K + 2];
+  const int total = wbase[bt.n];
   // Each workgroup takes a contiguous range of tiles (tiles are ordered by
-  // component, so a range mostly shares one W_k, which then stays in the
-  // CU's L1), and consecutive ranges go to workgroups of the same XCD
-  // (workgroups are dealt round-robin over the 8 XCDs), so each XCD's L2
-  // holds only the filters of its part of the list.
+  // image, then component, so a range mostly shares one W_k, which then
+  // stays in the CU's L1), and consecutive ranges go to workgroups of the
+  // same XCD (workgroups are dealt round-robin over the 8 XCDs), so each
+  // XCD's L2 holds only the filters of its part of the list.
   const int G = gridDim.x;
   const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   const int per = (total + G - 1) / G;
   const int t_end = min(total, (lb + 1) * per);
-  for (int t = lb * per + (threadIdx.x >> 6); t < t_end; t += 4) {
+  int t = lb * per + (threadIdx.x >> 6);
+  if (t >= t_end) return;
+  int im = image_of(wbase, bt.n, t);
+  for (; t < t_end; t += 4) {
+    while (t >= wbase[im + 1]) ++im;
+    const ImgDesc d = bt.d[im];
+    const int W = d.W, Wp = d.W - 7;
+    const float* x = xb + d.px;
+    const int32_t* seg = seg_b + d.seg;
+    const int32_t* start = seg;
+    const int32_t* count = seg + (K + 1);
+    const int32_t* tinfo = seg + (3 * K + 3);
+    const float4* Wt = Wt_all + (size_t)(d.slot0 + it) * K * 1024;
+    float* Zhat = Zhat_b + (size_t)d.np * kP;
     // component of tile t and the tile's index within the component
-    const int info = tinfo[t];
+    const int info = tinfo[t - wbase[im]];
     const int k = info & 1023;
     const int first = (info >> 10) * kWienerTile;
     const int n = min(kWienerTile, count[k] - first);
-    const int32_t* ids = perm + start[k] + first;
+    const int32_t* ids = perm_b + d.np + start[k] + first;
 
     // patches: lane holds pixels 32 half + s (s = 0..31) -- patch rows
     // 4 half .. 4 half + 3, read as float4 -- of patch col
@@ -108,16 +120,16 @@ __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(const float* __restr
   }
 }
 
-hipError_t launch_wiener_f32(const float* x, int H, int W, const float* Wt_t, int K,
-                             const int32_t* seg, const int32_t* perm, float* Zhat,
-                             hipStream_t st) {
-  const int Np = (H - 7) * (W - 7);
-  const int max_tiles = Np / kWienerTile + K;
-  int blocks = (max_tiles + 3) / 4;
-  if (blocks > 4096) blocks = 4096;
+hipError_t launch_wiener_batch(const Batch& b, const float* x, const float* Wt, int K, int t,
+                               const int32_t* seg, const int32_t* perm, const int32_t* wbase,
+                               float* Zhat, int max_blocks, hipStream_t st) {
+  // tile total <= patches / tile + K per image
+  const int64_t max_tiles = b.n_patches / kWienerTile + (int64_t)K * b.n;
+  int64_t blocks = (max_tiles + 3) / 4;
+  if (blocks > max_blocks) blocks = max_blocks;
   blocks = (blocks + 7) & ~7;  // whole rounds over the 8 XCDs
-  hipLaunchKernelGGL(wiener_f32_kernel, dim3(blocks), dim3(256), 0, st, x, H, W,
-                     reinterpret_cast<const float4*>(Wt_t), K, seg, perm, Zhat);
+  hipLaunchKernelGGL(wiener_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, b, x,
+                     reinterpret_cast<const float4*>(Wt), K, t, seg, perm, wbase, Zhat);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(F.Image) == 32
     assert ctypes.sizeof(F.Options) == 48
+    assert ctypes.sizeof(F.Tuning) == 16
 
 
 def test_options_defaults_and_version():
@@ -112,3 +113,16 @@ def test_restore_rejects_null_handle():
     st = F.lib().fepll_restore(None, ctypes.byref(yi), None, 10.0, None, 0, ctypes.byref(oi),
                                None, None)
     assert st == -1
+
+
+def test_batch_and_tuning_reject_bad_arguments():
+    y = np.zeros((16, 16), np.float32)
+    yi = (F.Image * 1)(F._image(y))
+    oi = (F.Image * 1)(F._image(np.zeros_like(y)))
+    sg = np.array([10.0])
+    L = F.lib()
+    assert L.fepll_restore_batch(None, 1, yi, sg.ctypes.data, oi, None) == -1
+    t = F.Tuning(768, 4096, 32, 0)
+    assert L.fepll_set_tuning(None, ctypes.byref(t)) == -1
+    assert L.fepll_get_tuning(None, ctypes.byref(t)) == -1
+    assert L.fepll_autotune(None, 1, yi, sg.ctypes.data, None, None) == -1
