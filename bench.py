@@ -40,6 +40,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes (read + written) per launch of `kernel` from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when none was taken
+    or the kernel's source has changed since (sha256 of its file)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "restore_1024x1024_k200_traffic.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = line.split()
+        if len(f) == 6 and f[0] == "traffic" and f[1] == kernel:
+            src = os.path.join(ROOT, "paper_1710_08124_amd", "csrc", f[2])
+            if not os.path.exists(src):
+                return None
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() != f[3]:
+                return None
+            return int(f[4]) + int(f[5])
+    return None
+
+
 def psnr(ref, x):
     import numpy as np
     return float(10 * np.log10(255.0 ** 2 / np.mean((x.astype(np.float64) - ref) ** 2)))
@@ -215,7 +235,8 @@ def main():
                                 "propose": "propose_bf16_kernel"}.get(hp["dominant"], hp["dominant"]),
                      "achieved": round(hp["dominant_tflops"], 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(hp["dominant_tflops"] / peak, 4),
-                     "traffic": None},
+                     "traffic": (measured_traffic(sel_kernel) if hp["dominant"] == "select"
+                                 and args.size == 1024 else None)},
         "speedup_vs_plain_fp32": round(hp["mpix_s"] / fp32["mpix_s"], 3),
         "graph_replay_mpix_s": round(hp["graph_mpix_s"], 4),
     }
@@ -230,6 +251,15 @@ def main():
             "stages_ms": pr["stages_ms"], "psnr_db": round(pr["psnr"], 4),
             "dpsnr_vs_fp32_path_db": round(pr["dpsnr"], 4),
             "speedup_vs_plain_fp32": round(pr["mpix_s"] / fp32["mpix_s"], 3)}
+    # the headline path with host buffers: PCIe copies of y and the result
+    # included (context only, never the headline value)
+    yh = np.asarray(c["y"], np.float32)
+    oh = np.empty_like(yh)
+    F.restore(g, yh, sigma, out=oh, **PATH_KW[head])
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        F.restore(g, yh, sigma, out=oh, **PATH_KW[head])
+    res["host_buffers_mpix_s"] = round(H * W * args.steps / (time.perf_counter() - t0) / 1e6, 4)
     # share of patches whose float32 selection needed the float64 recheck
     fl = []
     for beta in (1.0 / sigma ** 2, 32.0 / sigma ** 2):

@@ -17,6 +17,8 @@
 // (four blocks of 32) for its whole component loop; per component it issues
 // 2 (eigen blocks) x 4 (patch blocks) MFMAs and 128 float32 FMAs of squares,
 // then one exchange between lane halves leaves every lane owning 2 patches.
+// Three workgroups per compute unit (3 waves per SIMD): the squares of one
+// wave are summed while the matrix core runs another wave's MFMAs.
 // The per-component operand (4 KB) is staged through double-buffered LDS
 // shared by the workgroup's 4 waves.  The launch is persistent over the
 // selection tiles of a batch of images, each with its own beta.
@@ -84,6 +86,8 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const int32_t* __restrict__ Ue_all, const float* __restrict__ L_all, int K,
     int32_t* __restrict__ labels_b, float* __restrict__ best_b, float* __restrict__ second_b) {
   __shared__ uint4 Ash[2][256];
+  __shared__ int Esh[kMaxK];
+  __shared__ float Lsh[kMaxK];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int h = lane >> 5;
@@ -107,30 +111,29 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const int c0 = tc * (32 * PB);
     i32x8 zq[PB];
     int zc[PB];
-    int idx[PB];
-    bool valid[PB];
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
       const int c = c0 + 32 * pb + col;
-      valid[pb] = (r < Hp) && (c < Wp);
-      const int rr = min(r, Hp - 1), cc = min(c, Wp - 1);
-      idx[pb] = rr * Wp + cc;
-      load_patch8(x, W, rr, cc, h, zq[pb], zc[pb]);
+      load_patch8(x, W, min(r, Hp - 1), min(c, Wp - 1), h, zq[pb], zc[pb]);
       __builtin_amdgcn_sched_barrier(0);
     }
-    // lane's own patches after the half exchange: blocks h and 2 + h
-    const int iA = h ? idx[1] : idx[0], iB = h ? idx[3] : idx[2];
-    const bool vA = h ? valid[1] : valid[0], vB = h ? valid[3] : valid[2];
-
+    // the component scales and L_k of the tile's beta sit in LDS, read with
+    // the operand (no scalar-memory wait in the component loop)
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+      Esh[k] = Ue[k];
+      Lsh[k] = L[k];
+    }
     float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
     int kA = 0, kB = 0;
+    const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                         0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     uint4 pre = Uf[threadIdx.x];
     for (int k = 0; k < K; ++k) {
       uint4* As = Ash[k & 1];
       As[threadIdx.x] = pre;
       __syncthreads();
       if (k + 1 < K) pre = Uf[(size_t)(k + 1) * 256 + threadIdx.x];
-      const int ek = Ue[k];
+      const int ek = Esh[k];
       float q[PB];
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
@@ -141,33 +144,28 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
                          (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
         f32x16 acc[PB];
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb) {
-          acc[pb] = (f32x16){0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
-                             0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-          acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, zq[pb], acc[pb], 0, 0, 0,
-                                                                    ek, 0, zc[pb]);
-        }
+        for (int pb = 0; pb < PB; ++pb)
+          acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, zq[pb], zero, 0, 0, 0, ek,
+                                                                    0, zc[pb]);
 #pragma unroll
         for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
           for (int i = 0; i < 16; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
       }
-      const float Lk = L[k];
-      const float cA = Lk + pair_sum32(q[0], q[1]);
-      const float cB = Lk + pair_sum32(q[2], q[3]);
-      keep_best(cA, k, bA, sA, kA);
-      keep_best(cB, k, bB, sB, kB);
+      const float Lk = Lsh[k];
+      keep_best(Lk + pair_sum32(q[0], q[1]), k, bA, sA, kA);
+      keep_best(Lk + pair_sum32(q[2], q[3]), k, bB, sB, kB);
     }
     __syncthreads();  // the staging buffers are reused by the next tile
-    int32_t* labels = labels_b + d.np;
+    // lane's own patches after the half exchange: blocks h and 2 + h
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const bool v = p ? vB : vA;
-      if (!v) continue;
-      const int i = p ? iB : iA;
-      labels[i] = p ? kB : kA;
-      if (best_b) best_b[d.np + i] = p ? bB : bA;
-      if (second_b) second_b[d.np + i] = p ? sB : sA;
+      const int c = c0 + 32 * (2 * p + h) + col;
+      if (r >= Hp || c >= Wp) continue;
+      const int64_t i = d.np + (int64_t)r * Wp + c;
+      labels_b[i] = p ? kB : kA;
+      if (best_b) best_b[i] = p ? bB : bA;
+      if (second_b) second_b[i] = p ? sB : sA;
     }
   }
 }
