@@ -85,6 +85,12 @@ struct fepll_gmm {
   bool has_proposal = false;
   uint16_t* cand = nullptr;   // Np x 8
   int32_t* fb_list = nullptr;  // Np
+  // exact rescoring: (patch, candidate) pairs sorted by component
+  size_t pair_cap = 0, pcost_cap = 0, phist_cap = 0, pseg_cap = 0;
+  int32_t* psorted = nullptr;  // 8 Np
+  float* pcost = nullptr;      // 8 Np
+  int32_t* phist = nullptr;
+  int32_t* pseg = nullptr;
   hipStream_t last_stream = nullptr;
   bool used = false;
   // launch shapes (fepll_set_tuning / fepll_autotune)
@@ -335,6 +341,21 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     HIPX(dalloc(&g->fb_list, NP));
     g->np_cap = NP;
   }
+  {
+    // pair scratch of the proposal path, sized for the largest image
+    size_t npmax = 0;
+    for (int i = 0; i < n; ++i) npmax = std::max(npmax, (size_t)(H[i] - 7) * (W[i] - 7));
+    if ((s = grow(&g->psorted, g->pair_cap, 8 * npmax)) != FEPLL_OK) return s;
+    if (!g->pcost || 8 * npmax > g->pcost_cap) {
+      dfree(g->pcost);
+      g->pcost_cap = 0;
+      HIPX(dalloc(&g->pcost, 8 * npmax));
+      g->pcost_cap = 8 * npmax;
+    }
+    const size_t nb2 = (npmax + kPairBlock - 1) / kPairBlock;
+    if ((s = grow(&g->phist, g->phist_cap, (size_t)K * nb2)) != FEPLL_OK) return s;
+    if ((s = grow(&g->pseg, g->pseg_cap, pair_seg_size(npmax, K))) != FEPLL_OK) return s;
+  }
   if (PX > g->px_cap) {
     dfree(g->ybuf);
     dfree(g->xa);
@@ -410,26 +431,29 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
     }
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, g->count, 1);
     HIPX(hipGetLastError());
+    const uint16_t* Ub = g->tb.Ub + (size_t)slot * K * kTileStride;
+    const float* L = g->tb.L32 + (size_t)slot * K;
+    {
+      // exact rescoring of the candidates: pairs bucketed by component
+      StageTimer tm(g, 0, st);
+      HIPX(launch_pair_bucket(g->cand, Np, o.top_m, g->K, g->phist, g->pseg, g->psorted, st));
+      HIPX(launch_pair_scores_bf16(x, H, W, Ub, L, g->K, o.top_m, g->pseg, g->psorted, g->pcost,
+                                   st));
+      HIPX(launch_pair_reduce(g->cand, g->pcost, Np, o.top_m, g->K, (float)o.margin_nats, labels,
+                              best, second, g->count, g->fb_list, st));
+    }
     BF16Args a{};
     a.x = x;
     a.H = H;
     a.W = W;
-    a.Ub = g->tb.Ub + (size_t)slot * K * kTileStride;
-    a.L = g->tb.L32 + (size_t)slot * K;
+    a.Ub = Ub;
+    a.L = L;
     a.K = g->K;
     a.labels = labels;
     a.best = best;
     a.second = second;
-    a.cand = reinterpret_cast<const uint4*>(g->cand);
-    a.margin = (float)o.margin_nats;
-    a.fb_count = g->count;
-    a.fb_list = g->fb_list;
     a.list_count = g->count;
     a.list = g->fb_list;
-    {
-      StageTimer tm(g, 0, st);
-      HIPX(launch_estep_bf16_mode(kModeSpatialCand, a, st));
-    }
     {
       StageTimer tm(g, 7, st);
       HIPX(launch_estep_bf16_mode(kModeListFull, a, st));
@@ -555,7 +579,8 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
                         g->tb.Uf, g->tb.Ue,   g->d,     g->est_img, g->sort_img, g->ola_img,
                         g->wbase, g->bvals,   g->labels, g->list,  g->count,  g->hist,
                         g->seg,   g->perm,    g->Zhat,  g->ybuf,   g->xa,     g->xb,
-                        g->pWb,   g->pbias,   g->cand,  g->fb_list};
+                        g->pWb,   g->pbias,   g->cand,  g->fb_list,
+                        g->psorted, g->pcost, g->phist, g->pseg};
   for (const void* p : ptrs) put(key, p);
   if (g->gexec && key == g->gkey) {
     *result = (T % 2) ? g->xb : g->xa;
@@ -729,6 +754,10 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->Zhat);
   dfree(g->cand);
   dfree(g->fb_list);
+  dfree(g->psorted);
+  dfree(g->pcost);
+  dfree(g->phist);
+  dfree(g->pseg);
   dfree(g->pWb);
   dfree(g->pbias);
   dfree(g->ybuf);

@@ -74,25 +74,25 @@ __device__ void block_exclusive_scan(int32_t* s, int n) {
   __syncthreads();
 }
 
-// One workgroup per image of the batch.
-__global__ __launch_bounds__(1024) void scan_kernel(Batch b, int32_t* __restrict__ hist_b, int K,
-                                                    int32_t* __restrict__ seg_b) {
+// Exclusive offsets of K x nb block counts (component-major, in place),
+// then per component its start, count and tile prefix (tiles of `tile`
+// entries), the total and the tile table (entry t = k | (tile index in k) << 10)
+// in seg; N entries in all.  Called by one whole workgroup of 1024 threads.
+__device__ void scan_segments(int32_t* __restrict__ hist, int K, int nb, int N, int tile,
+                              int32_t* __restrict__ seg) {
   __shared__ int32_t part[1024];
-  const ImgDesc d = b.d[blockIdx.x];
-  const int Np = (d.H - 7) * (d.W - 7);
-  const int nb = (Np + kSortBlock - 1) / kSortBlock;
-  int32_t* hist = hist_b + (size_t)K * d.sort0;
-  int32_t* seg = seg_b + d.seg;
   const int t = threadIdx.x;
   const int M = K * nb;
   const int chunk = (M + 1023) / 1024;
   const int lo = min(M, t * chunk), hi = min(M, lo + chunk);
   int32_t sum = 0;
+#pragma unroll 8
   for (int i = lo; i < hi; ++i) sum += hist[i];
   part[t] = sum;
   __syncthreads();
   block_exclusive_scan(part, 1024);
   int32_t run = part[t];
+#pragma unroll 8
   for (int i = lo; i < hi; ++i) {
     const int32_t v = hist[i];
     hist[i] = run;
@@ -107,12 +107,12 @@ __global__ __launch_bounds__(1024) void scan_kernel(Batch b, int32_t* __restrict
   __shared__ int32_t tiles[1024];
   for (int k = t; k < K; k += 1024) {
     const int32_t s = hist[(size_t)k * nb];
-    const int32_t e = (k + 1 < K) ? hist[(size_t)(k + 1) * nb] : Np;
+    const int32_t e = (k + 1 < K) ? hist[(size_t)(k + 1) * nb] : N;
     start[k] = s;
     count[k] = e - s;
-    tiles[k] = (e - s + kWienerTile - 1) / kWienerTile;
+    tiles[k] = (e - s + tile - 1) / tile;
   }
-  if (t == 0) start[K] = Np;
+  if (t == 0) start[K] = N;
   __syncthreads();
   // K <= 1024: one scan of the tile counts
   int32_t mine = (t < K) ? tiles[t] : 0;
@@ -137,15 +137,24 @@ __global__ __launch_bounds__(1024) void scan_kernel(Batch b, int32_t* __restrict
   __syncthreads();
   const int total = tp[K];
   int32_t* info = seg + (3 * K + 3);
-  for (int tile = t; tile < total; tile += 1024) {
-    int lo = 0, hi = K - 1;  // last k with tp[k] <= tile
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tp[mid] <= tile) lo = mid;
-      else hi = mid - 1;
+  for (int tl = t; tl < total; tl += 1024) {
+    int lo2 = 0, hi2 = K - 1;  // last k with tp[k] <= tl
+    while (lo2 < hi2) {
+      const int mid = (lo2 + hi2 + 1) >> 1;
+      if (tp[mid] <= tl) lo2 = mid;
+      else hi2 = mid - 1;
     }
-    info[tile] = lo | ((tile - tp[lo]) << 10);
+    info[tl] = lo2 | ((tl - tp[lo2]) << 10);
   }
+}
+
+// One workgroup per image of the batch.
+__global__ __launch_bounds__(1024) void scan_kernel(Batch b, int32_t* __restrict__ hist_b, int K,
+                                                    int32_t* __restrict__ seg_b) {
+  const ImgDesc d = b.d[blockIdx.x];
+  const int Np = (d.H - 7) * (d.W - 7);
+  const int nb = (Np + kSortBlock - 1) / kSortBlock;
+  scan_segments(hist_b + (size_t)K * d.sort0, K, nb, Np, kWienerTile, seg_b + d.seg);
 }
 
 __global__ __launch_bounds__(1024) void scatter_kernel(Batch b, const int32_t* __restrict__ labels_b,
@@ -189,6 +198,62 @@ __global__ __launch_bounds__(1024) void wbase_kernel(Batch b, int K,
     carry += tot;
   }
   if (threadIdx.x == 0) wbase[b.n] = carry;
+}
+
+// ---- (patch, candidate) pairs of the proposal, sorted by component for
+// the exact rescoring: pair p = 8 i + j is candidate j < m of patch i.
+
+__global__ __launch_bounds__(1024) void pair_hist_kernel(const uint16_t* __restrict__ cand, int Np,
+                                                         int m, int K, int nb,
+                                                         int32_t* __restrict__ hist) {
+  extern __shared__ int32_t h[];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) h[k] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kPairBlock;
+  for (int e = threadIdx.x; e < kPairBlock * m; e += blockDim.x) {
+    const int i = base + e / m, j = e - (e / m) * m;
+    if (i >= Np) continue;
+    const int k = cand[(size_t)i * 8 + j];
+    if (k < K) atomicAdd(&h[k], 1);  // (an index >= K is skipped everywhere)
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += blockDim.x) hist[(size_t)k * nb + blockIdx.x] = h[k];
+}
+
+__global__ __launch_bounds__(1024) void pair_scan_kernel(int32_t* __restrict__ hist, int K, int nb,
+                                                         int N, int32_t* __restrict__ seg) {
+  scan_segments(hist, K, nb, N, kPairTile, seg);
+}
+
+__global__ __launch_bounds__(1024) void pair_scatter_kernel(const uint16_t* __restrict__ cand,
+                                                            int Np, int m, int K, int nb,
+                                                            const int32_t* __restrict__ offs,
+                                                            int32_t* __restrict__ sorted) {
+  extern __shared__ int32_t cur[];
+  for (int k = threadIdx.x; k < K; k += blockDim.x) cur[k] = offs[(size_t)k * nb + blockIdx.x];
+  __syncthreads();
+  const int base = blockIdx.x * kPairBlock;
+  for (int e = threadIdx.x; e < kPairBlock * m; e += blockDim.x) {
+    const int i = base + e / m, j = e - (e / m) * m;
+    if (i >= Np) continue;
+    const int k = cand[(size_t)i * 8 + j];
+    if (k < K) sorted[atomicAdd(&cur[k], 1)] = 8 * i + j;
+  }
+}
+
+hipError_t launch_pair_bucket(const uint16_t* cand, int Np, int m, int K, int32_t* hist,
+                              int32_t* seg, int32_t* sorted, hipStream_t st) {
+  const int nb = (Np + kPairBlock - 1) / kPairBlock;
+  hipLaunchKernelGGL(pair_hist_kernel, dim3(nb), dim3(1024), K * sizeof(int32_t), st, cand, Np,
+                     m, K, nb, hist);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, hist, K, nb, Np * m, seg);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pair_scatter_kernel, dim3(nb), dim3(1024), K * sizeof(int32_t), st, cand,
+                     Np, m, K, nb, hist, sorted);
+  return hipGetLastError();
 }
 
 hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int32_t* hist,

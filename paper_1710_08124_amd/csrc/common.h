@@ -127,6 +127,17 @@ inline size_t seg_size(size_t Np, int K) { return 3 * (size_t)K + 3 + Np / kWien
 hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int32_t* hist,
                                int32_t* seg, int32_t* perm, int32_t* wbase, hipStream_t st);
 
+// Pairs (patch i, candidate j < m) of the proposal, sorted by component:
+// hist [K][nb] with nb = ceil(Np / kPairBlock); seg as above with tiles of
+// kPairTile pairs (pair_seg_size entries); sorted: pair ids 8 i + j.
+constexpr int kPairBlock = 4096;
+constexpr int kPairTile = 128;
+inline size_t pair_seg_size(size_t Np, int K) {
+  return 3 * (size_t)K + 3 + 8 * Np / kPairTile + K + 1;
+}
+hipError_t launch_pair_bucket(const uint16_t* cand, int Np, int m, int K, int32_t* hist,
+                              int32_t* seg, int32_t* sorted, hipStream_t st);
+
 // Patch estimates z^: float [patches][64], patch-major (pixel 8 dy + dx of
 // patch i at i * 64 + 8 dy + dx), at d.np * 64 per image.
 // blocks: workgroups of the launch, a multiple of 8 (a cap: never more than

@@ -20,17 +20,14 @@
 // norm over the four 16-lane groups (lanes l, l^16, l^32, l^48) with a
 // transpose-reduction that leaves every lane owning 2 patches.
 //
-// Three modes share the kernel:
+// Two modes share the kernel:
 //  * spatial, all K: a wave takes 128 consecutive patches of one row;
-//  * spatial, candidates: each patch carries the components proposed for it;
-//    the wave scores the union of its patches' candidates (sorted, built in
-//    LDS) and each patch keeps the best and second best of its own
-//    candidates -- the exact rescoring of the proposal.  A patch whose half
-//    gap (in nats) between the two is below the margin is appended to a
-//    fallback list;
-//  * list, all K: the fallback patches, 512 list entries per workgroup, with
-//    a device-side list length (fixed grid, workgroups stride over the list
-//    and exit past its end).
+//  * list, all K: the proposal's fallback patches, 512 list entries per
+//    workgroup, with a device-side list length (fixed grid, workgroups
+//    stride over the list and exit past its end).
+// The exact rescoring of the proposal's candidates runs over (patch,
+// candidate) pairs bucketed by component (pairs_bf16_kernel), each tile of
+// 128 pairs sharing one operand, with the same scoring arithmetic.
 // In the all-K modes the per-component operand is staged through
 // double-buffered LDS shared by the workgroup's 4 waves (one barrier per
 // component, the next component's operand already loading).
@@ -58,14 +55,6 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
-__device__ __forceinline__ bool has(const uint4& c, int k) {
-  const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-  bool r = false;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) r |= ((int)(w[i] & 0xffffu) == k) | ((int)(w[i] >> 16) == k);
-  return r;
-}
-
 // DC-removed bfloat16 B operands (2 depth steps) of one 16-patch block for
 // lane group g = l >> 4: patch rows g and 4 + g of the patch at (r, c).
 __device__ __forceinline__ void load_patch(const float* __restrict__ x, int W, int r, int c,
@@ -82,6 +71,42 @@ __device__ __forceinline__ void load_patch(const float* __restrict__ x, int W, i
       v[t][e] = row[e];
       s += v[t][e];
     }
+  }
+  s += __shfl_xor(s, 16);
+  s += __shfl_xor(s, 32);
+  const float m = s * (1.f / 64.f);
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    float d[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = v[t][e] - m;
+    zb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),
+                       pack2(d[6], d[7]));
+  }
+}
+
+// The same operands for a patch anywhere in the image (the pair rescoring):
+// each 8-pixel row as two 16-byte loads, the sum in the same order.
+__device__ __forceinline__ void load_patch_gather(const float* __restrict__ x, int W, int r,
+                                                  int c, int g, uint4 zb[2]) {
+  float v[2][8];
+  float s = 0.f;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const float* row = x + (size_t)(r + 4 * t + g) * W + c;
+    float4 a, b;
+    __builtin_memcpy(&a, row, 16);
+    __builtin_memcpy(&b, row + 4, 16);
+    v[t][0] = a.x;
+    v[t][1] = a.y;
+    v[t][2] = a.z;
+    v[t][3] = a.w;
+    v[t][4] = b.x;
+    v[t][5] = b.y;
+    v[t][6] = b.z;
+    v[t][7] = b.w;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s += v[t][e];
   }
   s += __shfl_xor(s, 16);
   s += __shfl_xor(s, 32);
@@ -139,8 +164,6 @@ __device__ __forceinline__ void score(const uint4* ap, const uint4 zb[PB][2], fl
 
 template <int MODE>
 __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
-  __shared__ uint32_t bm[4][32];
-  __shared__ uint16_t ul[4][kMaxK];
   __shared__ uint4 Ash[2][512];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -183,7 +206,6 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       tc = lt - tr * ntx;
     }
     const int Hp = H - 7, Wp = W - 7;
-    const uint4* up = reinterpret_cast<const uint4*>(Ub) + lane;  // [K][4][2][64] uint4
     // ---- this wave's 128 patches
     int idx[PB];
     bool valid[PB];
@@ -229,50 +251,7 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
 
     float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
     int kA = 0, kB = 0;
-    if (MODE == kModeSpatialCand) {
-      const uint4 candA = a.cand[iA];
-      const uint4 candB = a.cand[iB];
-      // union of the candidates of the wave's valid patches, ascending
-      if (lane < 32) bm[wave][lane] = 0u;
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      const uint32_t cw[8] = {candA.x, candA.y, candA.z, candA.w,
-                              candB.x, candB.y, candB.z, candB.w};
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const bool own = (i < 4) ? vA : vB;
-        const int k0 = (int)(cw[i] & 0xffffu), k1 = (int)(cw[i] >> 16);
-        if (own && k0 < a.K) atomicOr(&bm[wave][k0 >> 5], 1u << (k0 & 31));
-        if (own && k1 < a.K) atomicOr(&bm[wave][k1 >> 5], 1u << (k1 & 31));
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      const uint32_t word = (lane < 32) ? bm[wave][lane] : 0u;
-      const int cnt = __popc(word);
-      int incl = cnt;
-#pragma unroll
-      for (int d = 1; d < 32; d <<= 1) {
-        const int o = __shfl_up(incl, d);
-        if (lane >= d) incl += o;
-      }
-      const int nu = __shfl(incl, 31);
-      int pos = incl - cnt;
-      uint32_t wv = word;
-      while (wv) {
-        const int b = __ffs(wv) - 1;
-        ul[wave][pos++] = (uint16_t)(32 * lane + b);
-        wv &= wv - 1u;
-      }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      for (int u = 0; u < nu; ++u) {
-        const int k = ul[wave][u];
-        float cA, cB;
-        score(up + (size_t)k * 512, zb, Lt[k], g, cA, cB);
-        if (has(candA, k)) keep_best(cA, k, bA, sA, kA);
-        if (has(candB, k)) keep_best(cB, k, bB, sB, kB);
-      }
-    } else {
+    {
       // all K: the per-component operand (8 KB) is staged once per
       // workgroup in LDS, double-buffered, the next one already in flight
       const uint4* gsrc = reinterpret_cast<const uint4*>(Ub);
@@ -303,16 +282,117 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       labels[i] = p ? kB : kA;
       if (bestp) bestp[i] = b;
       if (secondp) secondp[i] = s;
-      if (MODE == kModeSpatialCand) {
-        const float gap = (s < INFINITY) ? 0.5f * (s - b) : -INFINITY;
-        if (!(gap >= a.margin)) {
-          const int slot = atomicAdd(a.fb_count, 1);
-          a.fb_list[slot] = i;
-        }
-      }
     }
-    if (MODE == kModeSpatialCand) break;
   }
+}
+
+// Exact rescoring of the proposal: one wave scores the up to 128 pairs of
+// one tile of the pair list (all of one component k) with the same
+// arithmetic as the all-K selection (score(): the cost of a (patch, k) pair
+// is bit for bit the one the full search computes), gathering each pair's
+// patch from the image, and writes the costs at the pairs' ids.
+__global__ __launch_bounds__(256, 3) void pairs_bf16_kernel(
+    const float* __restrict__ x, int H, int W, const uint16_t* __restrict__ Ub,
+    const float* __restrict__ L, int K, const int32_t* __restrict__ seg,
+    const int32_t* __restrict__ sorted, float* __restrict__ pair_cost) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int col = lane & 15;
+  const int Wp = W - 7;
+  (void)H;
+  const int32_t* start = seg;
+  const int32_t* count = seg + (K + 1);
+  const int32_t* tinfo = seg + (3 * K + 3);
+  const int total = seg[3 * K + 2];
+  const uint4* up = reinterpret_cast<const uint4*>(Ub) + lane;
+  for (int t = blockIdx.x * 4 + wave; t < total; t += gridDim.x * 4) {
+    const int info = tinfo[t];
+    const int k = info & 1023;
+    const int first = (info >> 10) * kPairTile;
+    const int n = min(kPairTile, count[k] - first);
+    const int32_t* ids = sorted + start[k] + first;
+    int idx[PB];
+    bool valid[PB];
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int e = 16 * pb + col;
+      valid[pb] = e < n;
+      idx[pb] = ids[valid[pb] ? e : 0];
+    }
+    uint4 zb[PB][2];
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int i = idx[pb] >> 3;
+      const int pr = i / Wp;
+      load_patch_gather(x, W, pr, i - pr * Wp, g, zb[pb]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    float cA, cB;
+    score(up + (size_t)k * 512, zb, L[k], g, cA, cB);
+    const int own = 4 * (g >> 1) + 2 * (g & 1);
+#pragma unroll
+    for (int pb = 0; pb < PB; pb += 2)
+      if (pb == own) {
+        if (valid[pb]) pair_cost[idx[pb]] = cA;
+        if (valid[pb + 1]) pair_cost[idx[pb + 1]] = cB;
+      }
+  }
+}
+
+// Per patch: the best and second best of its m rescored candidates (ties to
+// the lower component), its label, and the fallback decision: the patch
+// goes to the full-K list when half the exact gap (in nats) is below the
+// margin, or when it has a single candidate.
+__global__ __launch_bounds__(1024) void pair_reduce_kernel(
+    const uint16_t* __restrict__ cand, const float* __restrict__ pair_cost, int Np, int m, int K,
+    float margin, int32_t* __restrict__ labels, float* __restrict__ best,
+    float* __restrict__ second, int32_t* __restrict__ fb_count, int32_t* __restrict__ fb_list) {
+  __shared__ int wcnt[16];
+  __shared__ int wbase[16];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  bool fb = false;
+  if (i < Np) {
+    // the patch's 8 candidate slots and costs in three 16-byte loads
+    const uint4 cw = reinterpret_cast<const uint4*>(cand)[i];
+    const float4 c0 = reinterpret_cast<const float4*>(pair_cost)[2 * (size_t)i];
+    const float4 c1 = reinterpret_cast<const float4*>(pair_cost)[2 * (size_t)i + 1];
+    const uint32_t kw[4] = {cw.x, cw.y, cw.z, cw.w};
+    const float cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+    float b = INFINITY, s = INFINITY;
+    int bk = 0x7fffffff;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = (int)((kw[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+      const bool use = (j < m) && (k < K);  // an index >= K is never scored
+      const float c = use ? cv[j] : INFINITY;
+      const bool better = use && (c < b || (c == b && k < bk));
+      s = better ? b : fminf(s, c);
+      bk = better ? k : bk;
+      b = better ? c : b;
+    }
+    labels[i] = bk;
+    if (best) best[i] = b;
+    if (second) second[i] = s;
+    const float gap = (s < INFINITY) ? 0.5f * (s - b) : -INFINITY;
+    fb = !(gap >= margin);
+  }
+  // the fallback list: one global atomic per workgroup (ballots, LDS prefix)
+  const uint64_t mask = __ballot(fb);
+  if (lane == 0) wcnt[wave] = __popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      wbase[w] = run;
+      run += wcnt[w];
+    }
+    const int base = run ? atomicAdd(fb_count, run) : 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) wbase[w] += base;
+  }
+  __syncthreads();
+  if (fb) fb_list[wbase[wave] + __popcll(mask & ((1ull << lane) - 1ull))] = i;
 }
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st) {
@@ -323,17 +403,32 @@ hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st
     hipLaunchKernelGGL(estep_bf16_kernel<kModeListFull>, dim3(blocks), dim3(256), 0, st, args);
     return hipGetLastError();
   }
-  if (mode == kModeSpatialFull) {
-    // persistent: a fixed number of workgroups looping over the tiles
-    int blocks = args.n_est;
-    if (args.blocks > 0 && args.blocks < blocks) blocks = args.blocks;
-    if (blocks < 1) return hipSuccess;
-    hipLaunchKernelGGL(estep_bf16_kernel<kModeSpatialFull>, dim3(blocks), dim3(256), 0, st, args);
-    return hipGetLastError();
-  }
-  const int Hp = args.H - 7, Wp = args.W - 7;
-  dim3 grid((Wp + 16 * PB - 1) / (16 * PB), (Hp + 3) / 4);
-  hipLaunchKernelGGL(estep_bf16_kernel<kModeSpatialCand>, grid, dim3(256), 0, st, args);
+  // persistent: a fixed number of workgroups looping over the tiles
+  int blocks = args.n_est;
+  if (args.blocks > 0 && args.blocks < blocks) blocks = args.blocks;
+  if (blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(estep_bf16_kernel<kModeSpatialFull>, dim3(blocks), dim3(256), 0, st, args);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_scores_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
+                                   const float* L32_t, int K, int m, const int32_t* seg,
+                                   const int32_t* sorted, float* pair_cost, hipStream_t st) {
+  // the tile total depends on the labels: a fixed grid walks the device list
+  const int64_t Np = (int64_t)(H - 7) * (W - 7);
+  int64_t blocks = (Np * m / kPairTile + K + 3) / 4;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(pairs_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, H, W, Ub_t,
+                     L32_t, K, seg, sorted, pair_cost);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_reduce(const uint16_t* cand, const float* pair_cost, int Np, int m, int K,
+                              float margin, int32_t* labels, float* best, float* second,
+                              int32_t* fb_count, int32_t* fb_list, hipStream_t st) {
+  hipLaunchKernelGGL(pair_reduce_kernel, dim3((Np + 1023) / 1024), dim3(1024), 0, st, cand,
+                     pair_cost, Np, m, K, margin, labels, best, second, fb_count, fb_list);
   return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@
 
 namespace fepll {
 
-enum { kModeSpatialFull = 0, kModeSpatialCand = 1, kModeListFull = 2 };
+enum { kModeSpatialFull = 0, kModeListFull = 2 };
 
 struct BF16Args {
   // spatial all-K mode: x, Ub, L, labels, best, second are the packed
@@ -23,10 +23,6 @@ struct BF16Args {
   int32_t* labels;        // Np
   float* best;            // Np or NULL
   float* second;          // Np or NULL
-  const uint4* cand;      // candidates mode: Np x 8 uint16 (0xffff = none)
-  float margin;           // candidates mode: fallback when half the gap < margin
-  int32_t* fb_count;      // candidates mode: fallback list length (device)
-  int32_t* fb_list;       // candidates mode: fallback list (Np)
   const int32_t* list_count;  // list mode: list length (device)
   const int32_t* list;        // list mode: patch indices
   const ImgDesc* d;           // spatial all-K mode: the batch
@@ -37,6 +33,18 @@ struct BF16Args {
 };
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st);
+
+// Exact rescoring of the proposal (one image, tables of one beta): the cost
+// of every (patch, candidate) pair of the component-sorted pair list
+// (launch_pair_bucket) at pair_cost[8 i + j], then per patch the best /
+// second of its m candidates, its label and the fallback list (patches
+// whose half exact gap is below margin; count at *fb_count, zeroed before).
+hipError_t launch_pair_scores_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
+                                   const float* L32_t, int K, int m, const int32_t* seg,
+                                   const int32_t* sorted, float* pair_cost, hipStream_t st);
+hipError_t launch_pair_reduce(const uint16_t* cand, const float* pair_cost, int Np, int m, int K,
+                              float margin, int32_t* labels, float* best, float* second,
+                              int32_t* fb_count, int32_t* fb_list, hipStream_t st);
 
 // Network inference + top-m: cand[i] gets the m best classes of patch i in
 // decreasing logit order (ties to the lower class), 0xffff after the m-th.

@@ -5,9 +5,9 @@
 // classes) on the MFMA rows, 32 patches on the columns.  The 32x32 output of
 // v_mfma_f32_32x32x16_bf16 leaves lane l with patch (l & 31) and units
 // 8 g + 4 (l >> 5) + e (g, e = 0..3); the next layer's B operand needs units
-// 16 s + 8 (l >> 5) + 0..7, so one exchange between lanes l and l ^ 32 per
-// group pair re-packs every activation in registers: no activation ever
-// leaves the wave.  The layer-1 B operand is the patch itself (one 8-pixel
+// 16 s + 8 (l >> 5) + 0..7, so one v_permlane32_swap between lanes l and
+// l ^ 32 per group pair re-packs every activation in registers: no
+// activation ever leaves the wave.  The layer-1 B operand is the patch itself (one 8-pixel
 // patch row per depth step, as in the selection kernels) plus the
 // log sigma_beta feature.
 //
@@ -42,8 +42,14 @@ __device__ __forceinline__ f32x16 mfma_bf16(uint4 a, uint4 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
+// GELU in the tanh form of Hendrycks & Gimpel (2016),
+// x * sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3)): within 5e-4 of the exact
+// x Phi(x) the network is trained with, far below the bfloat16 rounding of
+// the activations that follows, and branch-free (one exp2, one reciprocal).
 __device__ __forceinline__ float gelu(float a) {
-  return 0.5f * a * (1.f + erff(a * 0.70710678118654752f));
+  const float t = a * fmaf(0.0713548162726f, a * a, 1.59576912161f);  // 2 sqrt(2/pi) (a + 0.044715 a^3)
+  const float e = __builtin_amdgcn_exp2f(-t * 1.44269504089f);
+  return a * __builtin_amdgcn_rcpf(1.f + e);
 }
 
 // Ranking key of a logit: an order-preserving map of the float to uint32,
@@ -90,14 +96,18 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16& acc, const float* 
   float lo[8], hi[8];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    // groups 0/1 -> depth step 2 nt, groups 2/3 -> depth step 2 nt + 1
-    const float a0 = h[e], a1 = h[4 + e], a2 = h[8 + e], a3 = h[12 + e];
-    const float r01 = __shfl_xor(half ? a0 : a1, 32);
-    const float r23 = __shfl_xor(half ? a2 : a3, 32);
-    lo[e] = half ? r01 : a0;
-    lo[4 + e] = half ? a1 : r01;
-    hi[e] = half ? r23 : a2;
-    hi[4 + e] = half ? a3 : r23;
+    // groups 0/1 -> depth step 2 nt, groups 2/3 -> depth step 2 nt + 1.
+    // v_permlane32_swap(a0, a1) leaves the lower half with (own a0,
+    // partner's a0) and the upper half with (partner's a1, own a1): units
+    // 8 g + 0..3 and 8 g + 4..7 of the lane's column, in order.
+    const auto p01 = __builtin_amdgcn_permlane32_swap(__float_as_uint(h[e]),
+                                                      __float_as_uint(h[4 + e]), false, false);
+    const auto p23 = __builtin_amdgcn_permlane32_swap(__float_as_uint(h[8 + e]),
+                                                      __float_as_uint(h[12 + e]), false, false);
+    lo[e] = __uint_as_float(p01[0]);
+    lo[4 + e] = __uint_as_float(p01[1]);
+    hi[e] = __uint_as_float(p23[0]);
+    hi[4 + e] = __uint_as_float(p23[1]);
   }
   s0 = make_uint4(pack2(lo[0], lo[1]), pack2(lo[2], lo[3]), pack2(lo[4], lo[5]),
                   pack2(lo[6], lo[7]));
@@ -114,6 +124,7 @@ __global__ __launch_bounds__(512, 1) void propose_bf16_kernel(
     const float* __restrict__ x, int H, int W, float logsb, const uint4* __restrict__ Wb,
     const float* __restrict__ bias, int n3, int K, int m, uint16_t* __restrict__ cand) {
   __shared__ uint4 slab[2][kSlabU4];  // 32 KB
+  __shared__ float bsh[2 * kHidden + 32 * 32];  // b1, b2, b3 (n3 <= 32 blocks of 32)
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int half = lane >> 5;
@@ -122,6 +133,9 @@ __global__ __launch_bounds__(512, 1) void propose_bf16_kernel(
   const int r = blockIdx.y * kWaves + wave;
   const int c = blockIdx.x * 32 + col;
   const int rr = min(r, Hp - 1), cc = min(c, Wp - 1);
+
+  for (int i = threadIdx.x; i < 2 * kHidden + 32 * n3; i += blockDim.x) bsh[i] = bias[i];
+  // (made visible by the first slab's barrier)
 
   // ---- layer-1 input: DC-removed patch / 128 and log sigma_beta
   uint4 xb[5];
@@ -188,28 +202,41 @@ __global__ __launch_bounds__(512, 1) void propose_bf16_kernel(
     f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 5; ++s) acc = mfma_bf16(A[s * 64], xb[s], acc);
-    hidden_epilogue(acc, bias, q, half, h1[2 * q], h1[2 * q + 1]);
+    hidden_epilogue(acc, bsh, q, half, h1[2 * q], h1[2 * q + 1]);
     __syncthreads();
   }
 #pragma unroll
   for (int q = 8; q < 16; ++q) {
     stage(q);
     const uint4* A = slab[q & 1] + lane;
+    // two independent accumulation chains (even / odd depth steps)
     f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    f32x16 acc2 = acc;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) acc = mfma_bf16(A[s * 64], h1[s], acc);
-    hidden_epilogue(acc, bias + kHidden, q - 8, half, h2[2 * (q - 8)], h2[2 * (q - 8) + 1]);
+    for (int s = 0; s < 16; s += 2) {
+      acc = mfma_bf16(A[s * 64], h1[s], acc);
+      acc2 = mfma_bf16(A[(s + 1) * 64], h1[s + 1], acc2);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] += acc2[i];
+    hidden_epilogue(acc, bsh + kHidden, q - 8, half, h2[2 * (q - 8)], h2[2 * (q - 8) + 1]);
     __syncthreads();
   }
   Top8 top;
   top.init();
-  const float* b3 = bias + 2 * kHidden;
+  const float* b3 = bsh + 2 * kHidden;
   for (int q = 16; q < nslab; ++q) {
     stage(q);
     const uint4* A = slab[q & 1] + lane;
     f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    f32x16 acc2 = acc;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) acc = mfma_bf16(A[s * 64], h2[s], acc);
+    for (int s = 0; s < 16; s += 2) {
+      acc = mfma_bf16(A[s * 64], h2[s], acc);
+      acc2 = mfma_bf16(A[(s + 1) * 64], h2[s + 1], acc2);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] += acc2[i];
     const int nt = q - 16;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
