@@ -109,6 +109,27 @@ void fepll_options_default(fepll_options* opt);
 fepll_status fepll_gmm_create(const double* U, const double* lambda, const double* w,
                               int32_t K, int32_t d, fepll_gmm** out);
 
+/*
+ * Create a GMM handle from the covariances (the eigendecomposition of
+ * Sec. 2.1 is done here, in float64, by the cyclic Jacobi method).
+ *   Sigma: K x d x d float64, host, row-major, each symmetric (1e-9 of its
+ *          largest entry) and positive semidefinite (eigenvalues below
+ *          -1e-10 of the largest rejected; smaller negative ones set to 0).
+ *   w, K, d: as fepll_gmm_create.
+ * EINVAL on a violated condition, otherwise as fepll_gmm_create.
+ */
+fepll_status fepll_gmm_create_from_cov(const double* Sigma, const double* w, int32_t K,
+                                       int32_t d, fepll_gmm** out);
+
+/*
+ * The float64 eigendecomposition used by fepll_gmm_create_from_cov, on the
+ * host only (no device is touched): U (K x d x d, column j of U_k the j-th
+ * eigenvector) and lambda (K x d, decreasing) receive Sigma_k = U_k
+ * diag(lambda_k) U_k^t.  d in 1..1024.  Same conditions as above.
+ */
+fepll_status fepll_cov_eig(const double* Sigma, int32_t K, int32_t d, double* U,
+                           double* lambda);
+
 /* Release a handle (NULL is a no-op).  Synchronises the device first. */
 void fepll_gmm_destroy(fepll_gmm* g);
 

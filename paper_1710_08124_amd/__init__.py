@@ -14,7 +14,7 @@ from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_void_p
 
 import numpy as np
 
-__all__ = ["FepllError", "GMM", "restore", "restore_batch", "autotune", "set_tuning",
+__all__ = ["FepllError", "GMM", "cov_eig", "restore", "restore_batch", "autotune", "set_tuning",
            "get_tuning", "select", "profile", "library_path", "FP32", "BF16", "FP8"]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -75,6 +75,11 @@ def lib():
     L.fepll_gmm_create.argtypes = [c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                    POINTER(c_void_p)]
     L.fepll_gmm_create.restype = c_int32
+    L.fepll_gmm_create_from_cov.argtypes = [c_void_p, c_void_p, c_int32, c_int32,
+                                            POINTER(c_void_p)]
+    L.fepll_gmm_create_from_cov.restype = c_int32
+    L.fepll_cov_eig.argtypes = [c_void_p, c_int32, c_int32, c_void_p, c_void_p]
+    L.fepll_cov_eig.restype = c_int32
     L.fepll_gmm_destroy.argtypes = [c_void_p]
     L.fepll_gmm_destroy.restype = None
     L.fepll_restore.argtypes = [c_void_p, POINTER(Image), c_void_p, c_double, c_void_p, c_int32,
@@ -192,6 +197,23 @@ class GMM:
         self._h = h
         self.K = K
 
+    @classmethod
+    def from_cov(cls, Sigma, w):
+        """Mixture from its covariances Sigma (K,64,64) and weights w (K,),
+        float64; the eigendecomposition runs in the library."""
+        Sigma = np.ascontiguousarray(Sigma, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        K = w.shape[0]
+        if Sigma.shape != (K, 64, 64):
+            raise ValueError("Sigma must be (K,64,64), w (K,)")
+        self = cls.__new__(cls)
+        h = c_void_p()
+        _check(lib().fepll_gmm_create_from_cov(Sigma.ctypes.data, w.ctypes.data, K, 64,
+                                               ctypes.byref(h)))
+        self._h = h
+        self.K = K
+        return self
+
     @property
     def handle(self):
         return self._h
@@ -211,6 +233,17 @@ class GMM:
             self.close()
         except Exception:
             pass
+
+
+def cov_eig(Sigma):
+    """(U, lam) with Sigma[k] = U[k] diag(lam[k]) U[k]^t, lam decreasing:
+    the library's float64 eigendecomposition (host only)."""
+    Sigma = np.ascontiguousarray(Sigma, dtype=np.float64)
+    K, d, _ = Sigma.shape
+    U = np.empty((K, d, d))
+    lam = np.empty((K, d))
+    _check(lib().fepll_cov_eig(Sigma.ctypes.data, K, d, U.ctypes.data, lam.ctypes.data))
+    return U, lam
 
 
 def profile(gmm: GMM):

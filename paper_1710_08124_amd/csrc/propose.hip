@@ -14,7 +14,8 @@
 // A workgroup of 8 waves owns 256 patches (8 patch rows x 32 columns) and
 // streams the 23 weight slabs (one slab = one 32-row block of a layer, all
 // depth steps, already in MFMA operand order) through double-buffered LDS,
-// so each weight byte read from L2 serves 256 patches.
+// so each weight byte read from L2 serves 256 patches; each slab is fetched
+// from L2 two slabs ahead.
 //
 // Top-m: each lane keeps the 8 largest ranking keys (logit, then lower
 // class) of its 112 classes in sorted registers, then merges with lane
@@ -81,7 +82,9 @@ struct Top8 {
 };
 
 constexpr int kWaves = 8;
+constexpr int kThreads = 64 * kWaves;
 constexpr int kSlabU4 = 16 * 64;  // uint4 of the largest slab (16 depth steps x 64 lanes)
+constexpr int kPer = kSlabU4 / kThreads;  // uint4 of a slab per thread
 
 // activation epilogue of one 32-row block: bias + GELU, then re-pack as
 // the two depth steps (2 nt, 2 nt + 1) of the next layer's B operand
@@ -120,7 +123,7 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16& acc, const float* 
 // Wb: all slabs back to back, uint4 in MFMA A-operand order:
 //   layer 1: 8 slabs x 5 depth steps, layer 2: 8 x 16, layer 3: n3 x 16.
 // bias: b1 (256) b2 (256) b3 (32 n3, -inf beyond K).
-__global__ __launch_bounds__(512, 1) void propose_bf16_kernel(
+__global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
     const float* __restrict__ x, int H, int W, float logsb, const uint4* __restrict__ Wb,
     const float* __restrict__ bias, int n3, int K, int m, uint16_t* __restrict__ cand) {
   __shared__ uint4 slab[2][kSlabU4];  // 32 KB
@@ -173,27 +176,31 @@ __global__ __launch_bounds__(512, 1) void propose_bf16_kernel(
     return 8 * 5 * 64 + 8 * 16 * 64 + (q - 16) * 16 * 64;
   };
   auto slab_len = [&](int q) -> int { return (q < 8 ? 5 : 16) * 64; };
-  uint4 pre[2];
-  auto fetch = [&](int q) {
+  // slabs q + 1 and q + 2 in flight in registers (preA holds the even
+  // slabs, preB the odd ones)
+  uint4 preA[kPer], preB[kPer];
+  auto fetch = [&](int q, uint4 (&pre)[kPer]) {
     const int off = slab_off(q), len = slab_len(q);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int i = threadIdx.x + j * 512;
+    for (int j = 0; j < kPer; ++j) {
+      const int i = threadIdx.x + j * kThreads;
       if (i < len) pre[j] = Wb[off + i];
     }
   };
-  // make slab q resident in LDS buffer q & 1 and start fetching slab q + 1
+  // make slab q resident in LDS buffer q & 1 and start fetching slab q + 2
   auto stage = [&](int q) {
     const int len = slab_len(q);
+    uint4 (&pre)[kPer] = (q & 1) ? preB : preA;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int i = threadIdx.x + j * 512;
+    for (int j = 0; j < kPer; ++j) {
+      const int i = threadIdx.x + j * kThreads;
       if (i < len) slab[q & 1][i] = pre[j];
     }
     __syncthreads();
-    if (q + 1 < nslab) fetch(q + 1);
+    if (q + 2 < nslab) fetch(q + 2, pre);
   };
-  fetch(0);
+  fetch(0, preA);
+  fetch(1, preB);
   uint4 h1[16], h2[16];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
@@ -271,7 +278,7 @@ hipError_t launch_propose_bf16(const float* x, int H, int W, double beta, const 
   const int Hp = H - 7, Wp = W - 7;
   const int n3 = (K + 31) / 32;
   dim3 grid((Wp + 31) / 32, (Hp + kWaves - 1) / kWaves);
-  hipLaunchKernelGGL(propose_bf16_kernel, grid, dim3(512), 0, st, x, H, W,
+  hipLaunchKernelGGL(propose_bf16_kernel, grid, dim3(kThreads), 0, st, x, H, W,
                      (float)(-0.5 * log(beta)), reinterpret_cast<const uint4*>(Wb), bias, n3, K,
                      m, cand);
   return hipGetLastError();

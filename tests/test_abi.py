@@ -126,3 +126,47 @@ def test_batch_and_tuning_reject_bad_arguments():
     assert L.fepll_set_tuning(None, ctypes.byref(t)) == -1
     assert L.fepll_get_tuning(None, ctypes.byref(t)) == -1
     assert L.fepll_autotune(None, 1, yi, sg.ctypes.data, None, None) == -1
+
+
+def test_cov_eig_matches_numpy():
+    """The library's float64 Jacobi eigendecomposition (host only) against
+    numpy.linalg.eigh: same spectrum, orthonormal U, U diag(lam) U^t = Sigma,
+    decreasing order."""
+    rng = np.random.default_rng(9)
+    K, d = 3, 64
+    A = rng.standard_normal((K, d, d))
+    Sigma = A @ A.transpose(0, 2, 1) * 10.0
+    Sigma[2] = Sigma[2] / 1e6 + np.eye(d)  # a near-isotropic one
+    U, lam = F.cov_eig(Sigma)
+    for k in range(K):
+        want = np.sort(np.linalg.eigvalsh(Sigma[k]))[::-1]
+        np.testing.assert_allclose(lam[k], want, rtol=1e-10, atol=1e-10 * want[0])
+        assert np.all(np.diff(lam[k]) <= 0)
+        np.testing.assert_allclose(U[k].T @ U[k], np.eye(d), atol=1e-12)
+        np.testing.assert_allclose(U[k] @ np.diag(lam[k]) @ U[k].T, Sigma[k],
+                                   atol=1e-11 * np.abs(Sigma[k]).max())
+
+
+def test_cov_eig_recovers_the_synthetic_mixture():
+    U0, lam0, _ = fs.gmm(4, 3)
+    Sigma = U0 @ (lam0[:, :, None] * U0.transpose(0, 2, 1))
+    U, lam = F.cov_eig(Sigma)
+    np.testing.assert_allclose(lam, lam0, rtol=1e-11, atol=1e-9)
+    # eigenvectors up to sign (the spectra have distinct eigenvalues)
+    sgn = np.sign(np.sum(U * U0, axis=1))
+    np.testing.assert_allclose(U * sgn[:, None, :], U0, atol=1e-9)
+
+
+def test_cov_eig_rejects_bad_input():
+    d = 64
+    S = np.eye(d)[None].copy()
+    S[0, 1, 2] = 0.5  # not symmetric
+    with pytest.raises(F.FepllError, match="EINVAL"):
+        F.cov_eig(S)
+    S = -np.eye(d)[None]  # negative definite
+    with pytest.raises(F.FepllError, match="EINVAL"):
+        F.cov_eig(S)
+    S = np.eye(d)[None].copy()
+    S[0, 3, 3] = np.nan
+    with pytest.raises(F.FepllError, match="EINVAL"):
+        F.cov_eig(S)

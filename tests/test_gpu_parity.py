@@ -216,3 +216,22 @@ def test_full_size_first_iteration_sampled(F, seed):
         vals = Zh[np.arange(rr.size), 8 * (py - rr) + (px - c2)]
         want_px = o.image_update(y32[py, px], vals.mean(), beta, sigma)
         assert abs(got[py, px] - want_px) <= TOL, (py, px, got[py, px], want_px)
+
+
+def test_mixture_from_covariances(F):
+    """fepll_gmm_create_from_cov (float64 Jacobi eigendecomposition in the
+    library) restores like the mixture given by its eigendecomposition: the
+    eigenvectors differ at most in sign, which the costs (squares) and the
+    Wiener filters U diag(gamma) U^t do not see."""
+    c = fs.config_c1()
+    U, lam, w = c["U"], c["lam"], c["w"]
+    Sigma = U @ (lam[:, :, None] * U.transpose(0, 2, 1))
+    g0 = F.GMM(U, lam, w)
+    g1 = F.GMM.from_cov(Sigma, w)
+    y = dev(f32(c["y"]))
+    a, la = F.restore(g0, y, c["sigma"], return_labels=True)
+    b, lb = F.restore(g1, y, c["sigma"], return_labels=True)
+    agree = float((la == lb).float().mean().item())
+    err = float((a - b).abs().max().item())
+    print("labels agree", agree, "max |diff|", err)
+    assert agree >= 0.999 and err <= 1e-3
