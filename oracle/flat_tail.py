@@ -36,8 +36,10 @@ def flat_tail(lam, rho: float):
     out = lam.copy()
     r = np.empty(K, dtype=np.int64)
     for k in range(K):
-        total = lam[k].sum()
+        # Sec. 3.1 does not fix a summation order: the trace, the partial
+        # sums and the tail sum are taken in index order
         cum = np.cumsum(lam[k])
+        total = cum[-1]
         rk = P
         for j in range(P):  # the smallest rank holding rho of the trace
             if cum[j] >= rho * total:
@@ -45,7 +47,7 @@ def flat_tail(lam, rho: float):
                 break
         r[k] = rk
         if rk < P:
-            out[k, rk:] = lam[k, rk:].sum() / (P - rk)
+            out[k, rk:] = np.cumsum(lam[k, rk:])[-1] / (P - rk)
     return out, r
 
 

@@ -34,6 +34,17 @@ accumulated in float32 in a fixed order (part of each mode's definition):
 
 Ut_k is formed in float64 and rounded to float32 before the format rounding
 (for fp8: Ut_k 2^-e_k rounded to float32, then to e4m3).
+
+Flat-tail form (Sec. 3.1, ``rank`` given, lam the flat-tailed spectra):
+for a component with r_k < 64 kept eigenvalues, Sec. 3.1's rewritten cost
+
+  L_k + |z~|^2 / nu_P - sum_{j < r_k} c_j^2 (1/nu_P - 1/nu_j)
+
+is evaluated with the operand Ut_k = U_k diag(s), s_j = sqrt(1/nu_P - 1/nu_j)
+for j < r_k and 0 beyond (nu_P the tail's nu), rounded as above; 1/nu_P is
+rounded from float64 to float32, and |z~|^2 is the exact squared norm of the
+float32 DC-removed patch (before the format rounding).  Components with
+r_k = 64 keep the plain form.
 """
 from __future__ import annotations
 
@@ -124,10 +135,29 @@ def patch_operand(Zt32: np.ndarray, mode: str) -> np.ndarray:
     return np.ldexp(q, e[:, None])
 
 
-def basis_operand(U: np.ndarray, nu: np.ndarray, mode: str) -> np.ndarray:
+def flat_scales(nu: np.ndarray, rank) -> np.ndarray:
+    """Column scales of the flat-tail operand (K x 64): sqrt(1/nu_P - 1/nu_j)
+    for the kept directions, 0 for the tail; 1/sqrt(nu_j) for components
+    without a tail."""
+    nu = np.asarray(nu, np.float64)
+    K, P = nu.shape
+    s = np.zeros((K, P))
+    for k in range(K):
+        rk = int(rank[k])
+        if rk >= P:
+            s[k] = 1.0 / np.sqrt(nu[k])
+        else:
+            s[k, :rk] = np.sqrt(np.maximum(1.0 / nu[k, rk] - 1.0 / nu[k, :rk], 0.0))
+    return s
+
+
+def basis_operand(U: np.ndarray, nu: np.ndarray, mode: str, rank=None) -> np.ndarray:
     """The rounded Ut_k = U_k diag(nu_k)^-1/2 (K x 64 x 64, float64 values,
-    scale applied)."""
-    Ut = np.asarray(U, np.float64) / np.sqrt(nu)[:, None, :]
+    scale applied); with ``rank``, the flat-tail operand U_k diag(s)."""
+    if rank is None:
+        Ut = np.asarray(U, np.float64) / np.sqrt(nu)[:, None, :]
+    else:
+        Ut = np.asarray(U, np.float64) * flat_scales(nu, rank)[:, None, :]
     if mode == "bf16":
         return round_bf16(Ut.astype(np.float32)).astype(np.float64)
     e = pow2_exponent(np.max(np.abs(Ut), axis=(1, 2)))
@@ -137,33 +167,46 @@ def basis_operand(U: np.ndarray, nu: np.ndarray, mode: str) -> np.ndarray:
 
 # ----------------------------------------------------------- selection
 
-def lowp_costs(x, U, lam, w, beta, mode: str, acc_eps: float | None = None):
+def lowp_costs(x, U, lam, w, beta, mode: str, acc_eps: float | None = None, rank=None):
     """Selection costs (Np x K, float64) of every valid patch of the float32
     image x in a reduced-precision mode: float32(L_k) + sum_j c_j^2 with c
-    the exact product of the rounded operands.
+    the exact product of the rounded operands.  With ``rank`` (lam then the
+    flat-tailed spectra), the flat-tail form of the module docstring.
 
     With ``acc_eps``, also return a bound (Np x K) on how far an evaluation
     may land from these costs when it accumulates each projection c_j with a
     relative error of at most acc_eps of sum_p |Ut[p,j] z[p]| and the 64
-    squares and L_k in float32."""
+    squares, |z~|^2, and the terms of the cost in float32."""
     x = np.asarray(x, np.float32)
     H, W = x.shape
     r, c = o.patch_corners(H, W)
     Z = o.extract(x.astype(np.float64), r, c).astype(np.float32)  # exact: x is float32
-    Zq = patch_operand(dc_removed32(Z, mode), mode)
+    Zt32 = dc_removed32(Z, mode)
+    Zq = patch_operand(Zt32, mode)
     _, nu, _, L = o.eigen_terms(np.asarray(lam, np.float64), np.asarray(w, np.float64), beta)
-    Uq = basis_operand(U, nu, mode)
+    Uq = basis_operand(U, nu, mode, rank)
     L32 = L.astype(np.float32).astype(np.float64)
-    K = Uq.shape[0]
+    K, P = Uq.shape[0], Uq.shape[1]
+    if rank is not None:
+        z64 = Zt32.astype(np.float64)
+        nz2 = np.sum(z64 * z64, axis=1)
     cost = np.empty((Zq.shape[0], K))
     bound = np.empty_like(cost) if acc_eps is not None else None
     u32 = 2.0 ** -24
     for k in range(K):
         C = Zq @ Uq[k]
         sq = np.sum(C * C, axis=1)
-        cost[:, k] = L32[k] + sq
+        flat = rank is not None and int(rank[k]) < P
+        if flat:
+            pinv = float(np.float32(1.0 / nu[k, int(rank[k])]))
+            cost[:, k] = L32[k] + pinv * nz2 - sq
+        else:
+            cost[:, k] = L32[k] + sq
         if bound is not None:
             d = acc_eps * (np.abs(Zq) @ np.abs(Uq[k]))
+            # flat tail: |z~|^2 summed in float32 (64 roundings), then
+            # two more roundings of the cost's terms
             bound[:, k] = (np.sum(2 * np.abs(C) * d + d * d, axis=1)
-                           + 65 * u32 * (sq + np.abs(L32[k])))
+                           + 65 * u32 * (sq + np.abs(L32[k]))
+                           + (130 * u32 * pinv * nz2 if flat else 0.0))
     return (cost, bound) if bound is not None else cost

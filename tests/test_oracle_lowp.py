@@ -121,3 +121,95 @@ def test_costs_within_rounding_bound(mode, rel):
         d = A * (2 * rel + rel * rel) + 1e-6
         bound = np.sum(2 * np.abs(C) * d + d * d, axis=1) + np.abs(L[k]) * 2 ** -23
         assert np.all(np.abs(got[:, k] - want[:, k]) <= bound)
+
+
+# ---------------------------------------------------------------- flat tail
+
+def _flat_exact_mixture():
+    """Signed-permutation bases; beta = 1.  Components 0 and 1 have flat
+    tails of 3 (nu_P = 4) after r_k kept eigenvalues 13/3 and 49/15, whose
+    flat-tail scales sqrt(1/nu_P - 1/nu_j) are 1/4 and 1/8; component 2 has
+    no tail (r = 64) and nu_kj = 4^n."""
+    rng = np.random.default_rng(7)
+    K = 3
+    U = np.zeros((K, 64, 64))
+    for k in range(K):
+        perm = rng.permutation(64)
+        U[k, perm, np.arange(64)] = rng.choice([-1.0, 1.0], 64)
+    lam = np.empty((K, 64))
+    rank = np.array([5, 12, 64])
+    for k in range(2):
+        r = rank[k]
+        n1 = r // 2
+        lam[k, :n1] = 13.0 / 3.0
+        lam[k, n1:r] = 49.0 / 15.0
+        lam[k, r:] = 3.0
+    nu = np.sort(4.0 ** rng.integers(0, 4, 64))[::-1]
+    nu[-1] = 1.0
+    lam[2] = nu - 1.0
+    w = np.array([0.5, 0.25, 0.25])
+    return U, lam, w, rank
+
+
+def _checker_stripes(h, w):
+    rr, cc = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    return (100.0 + 2.0 * (1 - 2 * ((rr + cc) % 2)) + 1.0 * (1 - 2 * ((cc // 2) % 2))
+            + 0.5 * (1 - 2 * (rr % 2)))
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
+def test_flat_costs_exact_when_operands_are_representable(mode):
+    """Sec. 3.1's rewritten cost from exactly representable operands equals
+    the float64 flat-tail cost (oracle/flat_tail.py), up to the float32
+    rounding of L_k: pins the sign and the 1/nu_P |z~|^2 term."""
+    from oracle import flat_tail as ft
+    U, lam, w, rank = _flat_exact_mixture()
+    s = lowp.flat_scales(lam + 1.0, rank)
+    assert np.all(np.isin(s[0, :5], [0.25, 0.125])) and np.all(s[0, 5:] == 0)
+    x = _checker_stripes(12, 13)
+    got = lowp.lowp_costs(x.astype(np.float32), U, lam, w, 1.0, mode, rank=rank)
+    r, c = o.patch_corners(12, 13)
+    Zt, m = o.remove_dc(o.extract(x, r, c))
+    assert np.all(m == 100.0)
+    _, _, _, L = o.eigen_terms(lam, w, 1.0)
+    want = ft.flat_tail_costs(Zt, U, lam, rank, w, 1.0) - L + L.astype(np.float32)
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-11)
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
+def test_flat_costs_without_tail_are_the_plain_costs(mode):
+    c = fs.config_c1()
+    x = np.asarray(c["y"][:20, :20], np.float32)
+    beta = 8.0 / c["sigma"] ** 2
+    K = c["U"].shape[0]
+    plain = lowp.lowp_costs(x, c["U"], c["lam"], c["w"], beta, mode)
+    flat = lowp.lowp_costs(x, c["U"], c["lam"], c["w"], beta, mode, rank=np.full(K, 64))
+    np.testing.assert_array_equal(flat, plain)
+
+
+@pytest.mark.parametrize("mode,rel", [("bf16", 2.0 ** -8), ("fp8", 2.0 ** -4)])
+def test_flat_costs_within_rounding_bound(mode, rel):
+    """Rounded flat-tail costs stay within the operand-rounding bound of the
+    exact flat-tail costs of the same spectra."""
+    from oracle import flat_tail as ft
+    c = fs.config_c1()
+    lft, rank = ft.flat_tail(c["lam"], 0.95)
+    assert rank.max() < 64
+    x = np.asarray(c["y"][:24, :24], np.float32)
+    beta = 4.0 / c["sigma"] ** 2
+    got = lowp.lowp_costs(x, c["U"], lft, c["w"], beta, mode, rank=rank)
+    r, cc = o.patch_corners(24, 24)
+    Zt, _ = o.remove_dc(o.extract(x.astype(np.float64), r, cc))
+    _, nu, _, L = o.eigen_terms(lft, c["w"], beta)
+    want = ft.flat_tail_costs(Zt, c["U"], lft, rank, c["w"], beta)
+    S = lowp.flat_scales(nu, rank)
+    nz2 = np.sum(Zt * Zt, axis=1)
+    for k in range(c["U"].shape[0]):
+        Ut = c["U"][k] * S[k][None, :]
+        C = Zt @ Ut
+        A = np.abs(Zt) @ np.abs(Ut)
+        d = A * (2 * rel + rel * rel) + 1e-6
+        pinv = 1.0 / nu[k, rank[k]]
+        bound = (np.sum(2 * np.abs(C) * d + d * d, axis=1) + np.abs(L[k]) * 2 ** -23
+                 + pinv * nz2 * 2 ** -20)
+        assert np.all(np.abs(got[:, k] - want[:, k]) <= bound)
