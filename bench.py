@@ -27,13 +27,22 @@ PATH_INFO = {
     "bf16": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
     "fp8": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel", "fp8-e4m3"),
     "bf16+proposal": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
+    "bf16+flat": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
+    "fp8+flat": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel", "fp8-e4m3"),
+    "bf16+proposal+flat": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
 }
+ALL_PATHS = ("fp32", "bf16", "fp8", "bf16+proposal", "bf16+flat", "fp8+flat",
+             "bf16+proposal+flat")
 PATH_KW = {
     "fp32": dict(precision="fp32"),
     "bf16": dict(precision="bf16"),
     "fp8": dict(precision="fp8"),
     "bf16+proposal": dict(precision="bf16", proposal=True, top_m=8, margin=0.5),
 }
+# "+flat": the same options on the flat-tailed mixture (Sec. 3.1)
+for _p in ALL_PATHS:
+    if _p.endswith("+flat"):
+        PATH_KW[_p] = PATH_KW[_p[:-len("+flat")]]
 
 
 def log(*a):
@@ -100,8 +109,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (counter calibration)")
-    ap.add_argument("--paths", default="fp32,bf16,fp8,bf16+proposal",
+    ap.add_argument("--paths", default=",".join(ALL_PATHS),
                     help="comma-separated paths to time")
+    ap.add_argument("--rho", type=float, default=0.95,
+                    help="flat-tail share of the trace kept per component (Sec. 3.1)")
     ap.add_argument("--batch", type=int, default=48,
                     help="images of the uneven batch workload (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -141,18 +152,29 @@ def main():
         del src, dst
     H = W = args.size
     g = F.GMM(c["U"], c["lam"], c["w"])
+    # the same mixture with flat-tailed spectra (Sec. 3.1), for the "+flat" paths
+    gf = F.GMM(c["U"], c["lam"], c["w"])
+    ranks = gf.flat_tail(args.rho)
+    g0 = g
     y = torch.from_numpy(np.asarray(c["y"], np.float32)).cuda()
     out = torch.empty_like(y)
     sigma = c["sigma"]
     Np = (H - 7) * (W - 7)
     K = g.K
     flops_launch = 2.0 * 64 * 64 * K * Np  # algorithmic flops of one selection launch
+    # flat tail: 64 x r_k projections per component plus the squared norm
+    flops_flat = (2.0 * 64 * float(ranks.sum()) + 2.0 * 64) * Np
     # algorithmic flops per launch of each timed stage (None: data-dependent)
     mlp_flops = 2.0 * (65 * 256 + 256 * 256 + 256 * K)
 
+    def select_flops(name):
+        if "proposal" in name:
+            return 8 * 2.0 * 64 * 64 * Np
+        return flops_flat if name.endswith("+flat") else flops_launch
+
     def stage_flops(name, stage):
         if stage == "select":
-            return 8 * 2.0 * 64 * 64 * Np if name == "bf16+proposal" else flops_launch
+            return select_flops(name)
         if stage == "propose":
             return mlp_flops * Np
         if stage == "wiener":
@@ -162,12 +184,14 @@ def main():
     blob_path = os.path.join(os.path.dirname(F.__file__), "data", "proposal_k200_gmm12.bin")
     if K == 200 and os.path.exists(blob_path):
         g.load_proposal(open(blob_path, "rb").read())
+        gf.load_proposal(open(blob_path, "rb").read())
         have_prop = True
     else:
         have_prop = False
 
     def run_path(name):
         kw = PATH_KW[name]
+        g = gf if name.endswith("+flat") else g0
         for i in range(args.warmup):
             F.restore(g, y, sigma, out=out, **kw)
             log(f"{name} warmup {i + 1}/{args.warmup}")
@@ -198,15 +222,15 @@ def main():
         return {"mpix_s": H * W * args.steps / dt / 1e6, "ms_per_step": dt / args.steps * 1e3,
                 "graph_mpix_s": H * W * args.steps / dtg / 1e6,
                 "estep_ms": est_ms / est_n,
-                "estep_tflops": flops_launch / (est_ms / est_n / 1e3) / 1e12,
+                "estep_tflops": select_flops(name) / (est_ms / est_n / 1e3) / 1e12,
                 "dominant": dom, "dominant_ms": dom_s * 1e3,
                 "dominant_tflops": (fl / dom_s / 1e12) if fl else None,
                 "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]},
                 "psnr": psnr(c["x"], out.cpu().numpy())}
 
     want = args.paths.split(",")
-    names = [p for p in ("fp32", "bf16", "fp8", "bf16+proposal")
-             if p in want and (p != "bf16+proposal" or have_prop)]
+    names = [p for p in ALL_PATHS
+             if p in want and ("proposal" not in p or have_prop)]
     for p in ("fp32", "bf16"):
         if p not in names:
             names.insert(0 if p == "fp32" else 1, p)
@@ -247,7 +271,7 @@ def main():
             "mpix_s": round(pr["mpix_s"], 4), "graph_mpix_s": round(pr["graph_mpix_s"], 4),
             "estep_ms": round(pr["estep_ms"], 4),
             "estep_frac_of_peak": (round(pr["estep_tflops"] / pk, 4)
-                                   if p != "bf16+proposal" else None),
+                                   if "proposal" not in p else None),
             "stages_ms": pr["stages_ms"], "psnr_db": round(pr["psnr"], 4),
             "dpsnr_vs_fp32_path_db": round(pr["dpsnr"], 4),
             "speedup_vs_plain_fp32": round(pr["mpix_s"] / fp32["mpix_s"], 3)}
@@ -255,10 +279,11 @@ def main():
     # included (context only, never the headline value)
     yh = np.asarray(c["y"], np.float32)
     oh = np.empty_like(yh)
-    F.restore(g, yh, sigma, out=oh, **PATH_KW[head])
+    gh = gf if head.endswith("+flat") else g
+    F.restore(gh, yh, sigma, out=oh, **PATH_KW[head])
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        F.restore(g, yh, sigma, out=oh, **PATH_KW[head])
+        F.restore(gh, yh, sigma, out=oh, **PATH_KW[head])
     res["host_buffers_mpix_s"] = round(H * W * args.steps / (time.perf_counter() - t0) / 1e6, 4)
     # share of patches whose float32 selection needed the float64 recheck
     fl = []
@@ -267,15 +292,17 @@ def main():
         fl.append(round(float(f.float().mean().item()), 5))
     res["fp32"]["uncertified_fraction_beta1_beta32"] = fl
 
+    res["flat_tail"] = {"rho": args.rho, "rank_mean": round(float(ranks.mean()), 3),
+                        "rank_max": int(ranks.max()), "rank_min": int(ranks.min())}
     if batch:
-        res["batch"] = run_batch(F, torch, np, g, batch, names, args.batch_steps)
+        res["batch"] = run_batch(F, torch, np, g, gf, batch, names, args.batch_steps)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(res), flush=True)
 
 
-def run_batch(F, torch, np, g, batch, names, steps):
+def run_batch(F, torch, np, g0, gf, batch, names, steps):
     """The uneven batch (48 images, 256^2 .. 1024 x 1536, sigma ~ U[5, 50]) in
     one fepll_restore_batch call per step, replayed from its captured graph;
     launch shapes from the autotuner."""
@@ -284,11 +311,13 @@ def run_batch(F, torch, np, g, batch, names, steps):
     outs = [torch.empty_like(t) for t in ys]
     mpix = sum(t.numel() for t in ys) / 1e6
     t0 = time.perf_counter()
-    tuned = F.autotune(g, ys, sig, precision="bf16")
+    tuned = F.autotune(g0, ys, sig, precision="bf16")
+    F.set_tuning(gf, **{k: tuned[k] for k in ("est_blocks", "wiener_blocks", "ola_rows")})
     log(f"batch autotune {tuned} in {time.perf_counter() - t0:.1f} s")
     rows = {}
     for p in names:
         kw = PATH_KW[p]
+        g = gf if p.endswith("+flat") else g0
         F.restore_batch(g, ys, sig, outs=outs, **kw)  # constants, plan, graph capture
         torch.cuda.synchronize()
         t0 = time.perf_counter()

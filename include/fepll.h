@@ -130,6 +130,26 @@ fepll_status fepll_gmm_create_from_cov(const double* Sigma, const double* w, int
 fepll_status fepll_cov_eig(const double* Sigma, int32_t K, int32_t d, double* U,
                            double* lambda);
 
+/*
+ * Flat-tail spectrum approximation (Sec. 3.1) of the mixture, for every
+ * later call on the handle.  In each component, r_k is the smallest rank
+ * whose r_k largest eigenvalues hold at least rho of the trace (sums taken
+ * in index order), and the 64 - r_k smaller eigenvalues are replaced by
+ * their average.  Restoration is then EPLL with these spectra: the FEPLL_FP32
+ * selection stays exact (certified) for them; the FEPLL_BF16 / FEPLL_FP8
+ * selections and the proposal's rescoring take Sec. 3.1's rewritten cost,
+ * projecting each patch on only the r_k leading eigenvectors plus one
+ * squared norm of the DC-removed patch, |z~|^2 / nu_P.  rho = 1 restores the
+ * spectra as created (no approximation).  Each call starts from the
+ * spectra as created (calls do not compound).
+ *   rho:   in (0, 1]; anything else (NaN included) returns EINVAL.
+ *   ranks: NULL or K int32 (host) receiving r_k (64 for every component
+ *          when rho = 1).
+ * Synchronises the device (tables and captured work of earlier calls read
+ * the spectra).  EDEVICE / ENOMEM on a device failure.
+ */
+fepll_status fepll_gmm_flat_tail(fepll_gmm* g, double rho, int32_t* ranks);
+
 /* Release a handle (NULL is a no-op).  Synchronises the device first. */
 void fepll_gmm_destroy(fepll_gmm* g);
 

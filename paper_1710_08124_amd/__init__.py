@@ -82,6 +82,8 @@ def lib():
     L.fepll_cov_eig.restype = c_int32
     L.fepll_gmm_destroy.argtypes = [c_void_p]
     L.fepll_gmm_destroy.restype = None
+    L.fepll_gmm_flat_tail.argtypes = [c_void_p, c_double, c_void_p]
+    L.fepll_gmm_flat_tail.restype = c_int32
     L.fepll_restore.argtypes = [c_void_p, POINTER(Image), c_void_p, c_double, c_void_p, c_int32,
                                 POINTER(Image), POINTER(Options), c_void_p]
     L.fepll_restore.restype = c_int32
@@ -217,6 +219,13 @@ class GMM:
     @property
     def handle(self):
         return self._h
+
+    def flat_tail(self, rho: float) -> np.ndarray:
+        """Flat-tail spectrum approximation (Sec. 3.1) for later calls:
+        returns the kept ranks r_k (K,) int32; rho = 1 turns it off."""
+        r = np.empty(self.K, dtype=np.int32)
+        _check(lib().fepll_gmm_flat_tail(self._h, float(rho), r.ctypes.data))
+        return r
 
     def load_proposal(self, blob: bytes):
         """Attach a serialized proposal network (see MLP.serialize)."""

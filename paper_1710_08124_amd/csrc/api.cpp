@@ -45,8 +45,14 @@ struct fepll_gmm {
   int K = 0;
   int device = 0;
   double* U64 = nullptr;    // [K][64][64]
-  double* lam64 = nullptr;  // [K][64]
+  double* lam64 = nullptr;  // [K][64]: the spectra in use (flat-tailed or not)
   double* w64 = nullptr;    // [K]
+  // the spectra as created, and the flat-tail approximation in use (Sec.
+  // 3.1; rho = 1: none)
+  std::vector<double> lam_h;
+  double rho = 1.0;
+  std::vector<int32_t> h_rk;
+  int32_t* rk = nullptr;  // [K] kept ranks, device
   // per-beta constants of the beta slots of the last call
   std::vector<double> cbeta;
   int cmask = 0;
@@ -182,6 +188,7 @@ fepll_status ensure_consts(fepll_gmm* g, const std::vector<double>& betas, int m
     dfree(g->tb.Ub);
     dfree(g->tb.Wt);
     dfree(g->tb.L32);
+    dfree(g->tb.Pinv);
     dfree(g->tb.L64);
     dfree(g->tb.invnu64);
     dfree(g->tb.Uf);
@@ -192,6 +199,7 @@ fepll_status ensure_consts(fepll_gmm* g, const std::vector<double>& betas, int m
     HIPX(dalloc(&g->dbeta, S));
     HIPX(dalloc(&g->tb.Wt, S * K * kTileStride));
     HIPX(dalloc(&g->tb.L32, S * K));
+    HIPX(dalloc(&g->tb.Pinv, S * K));
     g->S_cap = S;
   }
   // the tables of a precision are allocated the first time it is used
@@ -437,8 +445,8 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
       // exact rescoring of the candidates: pairs bucketed by component
       StageTimer tm(g, 0, st);
       HIPX(launch_pair_bucket(g->cand, Np, o.top_m, g->K, g->phist, g->pseg, g->psorted, st));
-      HIPX(launch_pair_scores_bf16(x, H, W, Ub, L, g->K, o.top_m, g->pseg, g->psorted, g->pcost,
-                                   st));
+      HIPX(launch_pair_scores_bf16(x, H, W, Ub, L, g->tb.rk, g->tb.Pinv + (size_t)slot * K, g->K,
+                                   o.top_m, g->pseg, g->psorted, g->pcost, st));
       HIPX(launch_pair_reduce(g->cand, g->pcost, Np, o.top_m, g->K, (float)o.margin_nats, labels,
                               best, second, g->count, g->fb_list, st));
     }
@@ -454,6 +462,8 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
     a.second = second;
     a.list_count = g->count;
     a.list = g->fb_list;
+    a.rk = g->tb.rk;
+    a.Pinv = g->tb.Pinv + (size_t)slot * K;
     {
       StageTimer tm(g, 7, st);
       HIPX(launch_estep_bf16_mode(kModeListFull, a, st));
@@ -499,11 +509,11 @@ fepll_status select_batch(fepll_gmm* g, int t, const fepll_options& o, const flo
     }
     StageTimer tm(g, 0, st);
     if (o.precision == FEPLL_FP8)
-      HIPX(launch_estep_fp8_batch(b, x, g->tb.Uf, g->tb.Ue, g->tb.L32, g->K, t, labels, best,
-                                  second, blocks, st));
+      HIPX(launch_estep_fp8_batch(b, x, g->tb.Uf, g->tb.Ue, g->tb.L32, g->tb.rk, g->tb.Pinv,
+                                  g->K, t, labels, best, second, blocks, st));
     else
-      HIPX(launch_estep_bf16_batch(b, x, g->tb.Ub, g->tb.L32, g->K, t, labels, best, second,
-                                   blocks, st));
+      HIPX(launch_estep_bf16_batch(b, x, g->tb.Ub, g->tb.L32, g->tb.rk, g->tb.Pinv, g->K, t,
+                                   labels, best, second, blocks, st));
     return FEPLL_OK;
   }
   fepll_status s;
@@ -572,6 +582,7 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
   put(key, o.top_m);
   put(key, o.margin_nats);
   put(key, g->tune);
+  put(key, g->rho);
   for (const ImgDesc& d : g->hd) put(key, d);
   for (double v : g->cbeta) put(key, v);
   for (float v : g->hbvals) put(key, v);
@@ -580,7 +591,8 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
                         g->wbase, g->bvals,   g->labels, g->list,  g->count,  g->hist,
                         g->seg,   g->perm,    g->Zhat,  g->ybuf,   g->xa,     g->xb,
                         g->pWb,   g->pbias,   g->cand,  g->fb_list,
-                        g->psorted, g->pcost, g->phist, g->pseg};
+                        g->psorted, g->pcost, g->phist, g->pseg,
+                        g->tb.rk,   g->tb.Pinv};
   for (const void* p : ptrs) put(key, p);
   if (g->gexec && key == g->gkey) {
     *result = (T % 2) ? g->xb : g->xa;
@@ -687,6 +699,7 @@ fepll_status fepll_gmm_create(const double* U, const double* lambda, const doubl
     return bad(e);
   if ((e = hipMemcpy(g->w64, w, sizeof(double) * K, hipMemcpyHostToDevice)) != hipSuccess)
     return bad(e);
+  g->lam_h.assign(lambda, lambda + (size_t)K * d);
   *out = g;
   return FEPLL_OK;
 }
@@ -730,6 +743,8 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->U64);
   dfree(g->lam64);
   dfree(g->w64);
+  dfree(g->rk);
+  dfree(g->tb.Pinv);
   dfree(g->dbeta);
   dfree(g->tb.Ut);
   dfree(g->tb.Ub);
@@ -968,6 +983,52 @@ fepll_status fepll_autotune(fepll_gmm* g, int32_t n, const fepll_image* y, const
                        ola_c[std::min_element(to.begin(), to.end()) - to.begin()], 0};
   if ((s = fepll_set_tuning(g, &t)) != FEPLL_OK) return s;
   if (best) *best = t;
+  return FEPLL_OK;
+}
+
+fepll_status fepll_gmm_flat_tail(fepll_gmm* g, double rho, int32_t* ranks) {
+  g_err.clear();
+  if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
+  if (!(rho > 0.0 && rho <= 1.0)) return fail(FEPLL_EINVAL, "rho must be in (0, 1]");
+  const int K = g->K;
+  // Sec. 3.1: r_k is the smallest rank whose leading eigenvalues hold rho of
+  // the trace; the eigenvalues after it are replaced by their average.  The
+  // trace, the partial sums and the tail sum are taken in index order.
+  std::vector<double> lam = g->lam_h;
+  std::vector<int32_t> rk(K, kP);
+  if (rho < 1.0) {
+    for (int k = 0; k < K; ++k) {
+      double* l = lam.data() + (size_t)k * kP;
+      double cum[kP];
+      double c = 0.0;
+      for (int j = 0; j < kP; ++j) cum[j] = (c += l[j]);
+      const double goal = rho * cum[kP - 1];
+      int r = kP;
+      for (int j = 0; j < kP; ++j)
+        if (cum[j] >= goal) {
+          r = j + 1;
+          break;
+        }
+      rk[k] = r;
+      if (r < kP) {
+        double tail = 0.0;
+        for (int j = r; j < kP; ++j) tail += l[j];
+        const double avg = tail / (kP - r);
+        for (int j = r; j < kP; ++j) l[j] = avg;
+      }
+    }
+  }
+  // tables and captured work of earlier calls read the spectra: let them end
+  HIPX(hipDeviceSynchronize());
+  if (!g->rk) HIPX(dalloc(&g->rk, (size_t)K));
+  HIPX(hipMemcpy(g->lam64, lam.data(), sizeof(double) * lam.size(), hipMemcpyHostToDevice));
+  HIPX(hipMemcpy(g->rk, rk.data(), sizeof(int32_t) * K, hipMemcpyHostToDevice));
+  g->tb.rk = (rho < 1.0) ? g->rk : nullptr;
+  g->rho = rho;
+  g->h_rk = rk;
+  g->cbeta.clear();  // every per-beta table is rebuilt on next use
+  g->cmask = 0;
+  if (ranks) std::memcpy(ranks, rk.data(), sizeof(int32_t) * K);
   return FEPLL_OK;
 }
 

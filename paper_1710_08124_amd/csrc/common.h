@@ -49,6 +49,13 @@ struct ConstTables {
   double* invnu64;
   uint8_t* Uf;
   int32_t* Ue;
+  // flat-tail spectrum approximation (Sec. 3.1): rk[k] eigenvalues kept per
+  // component (64: none replaced; NULL: all 64); with a tail, the bf16 / e4m3
+  // operands hold only the first rk columns, scaled by
+  // sqrt(1/nu_j - 1/nu_P), and Pinv [S][K] = 1/nu_P multiplies |z~|^2 (0
+  // without a tail)
+  const int32_t* rk;
+  float* Pinv;
 };
 
 // One image of a batch (a single restoration is a batch of one): its size
@@ -106,13 +113,15 @@ hipError_t launch_recheck_f64(const float* x, int H, int W, const double* U64,
 // are packed buffers (best / second may be NULL); Ub / Uf / Ue / L32 the
 // tables of all slots.
 // blocks: workgroups of the persistent launch (0: one per tile).
+// (rk / Pinv: the flat-tail tables of ConstTables, or NULL for the plain form)
 hipError_t launch_estep_bf16_batch(const Batch& b, const float* x, const uint16_t* Ub,
-                                   const float* L32, int K, int t, int32_t* labels, float* best,
-                                   float* second, int blocks, hipStream_t st);
+                                   const float* L32, const int32_t* rk, const float* Pinv, int K,
+                                   int t, int32_t* labels, float* best, float* second, int blocks,
+                                   hipStream_t st);
 hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t* Uf,
-                                  const int32_t* Ue, const float* L32, int K, int t,
-                                  int32_t* labels, float* best, float* second, int blocks,
-                                  hipStream_t st);
+                                  const int32_t* Ue, const float* L32, const int32_t* rk,
+                                  const float* Pinv, int K, int t, int32_t* labels, float* best,
+                                  float* second, int blocks, hipStream_t st);
 
 // Counting sort of each image's patch indices by label and the Wiener tile
 // lists.  hist: [K][sort blocks of the image] int32 per image, at

@@ -57,8 +57,11 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
 }
 // DC-removed bfloat16 B operands (2 depth steps) of one 16-patch block for
 // lane group g = l >> 4: patch rows g and 4 + g of the patch at (r, c).
+// With NZ, nz receives the float32 squared norm of the (unrounded)
+// DC-removed patch, the same in the 4 lanes of its column.
+template <bool NZ>
 __device__ __forceinline__ void load_patch(const float* __restrict__ x, int W, int r, int c,
-                                           int g, uint4 zb[2]) {
+                                           int g, uint4 zb[2], float& nz) {
   // the mean is taken in float32: its rounding is far below the bfloat16
   // rounding of the differences that follows
   float v[2][8];
@@ -75,20 +78,29 @@ __device__ __forceinline__ void load_patch(const float* __restrict__ x, int W, i
   s += __shfl_xor(s, 16);
   s += __shfl_xor(s, 32);
   const float m = s * (1.f / 64.f);
+  float q2 = 0.f;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     float d[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = v[t][e] - m;
+    for (int e = 0; e < 8; ++e) {
+      d[e] = v[t][e] - m;
+      if (NZ) q2 = fmaf(d[e], d[e], q2);
+    }
     zb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),
                        pack2(d[6], d[7]));
+  }
+  if (NZ) {
+    q2 += __shfl_xor(q2, 16);
+    nz = q2 + __shfl_xor(q2, 32);
   }
 }
 
 // The same operands for a patch anywhere in the image (the pair rescoring):
 // each 8-pixel row as two 16-byte loads, the sum in the same order.
+template <bool NZ>
 __device__ __forceinline__ void load_patch_gather(const float* __restrict__ x, int W, int r,
-                                                  int c, int g, uint4 zb[2]) {
+                                                  int c, int g, uint4 zb[2], float& nz) {
   float v[2][8];
   float s = 0.f;
 #pragma unroll
@@ -111,41 +123,70 @@ __device__ __forceinline__ void load_patch_gather(const float* __restrict__ x, i
   s += __shfl_xor(s, 16);
   s += __shfl_xor(s, 32);
   const float m = s * (1.f / 64.f);
+  float q2 = 0.f;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     float d[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = v[t][e] - m;
+    for (int e = 0; e < 8; ++e) {
+      d[e] = v[t][e] - m;
+      if (NZ) q2 = fmaf(d[e], d[e], q2);
+    }
     zb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),
                        pack2(d[6], d[7]));
   }
+  if (NZ) {
+    q2 += __shfl_xor(q2, 16);
+    nz = q2 + __shfl_xor(q2, 32);
+  }
 }
 
-// Squared norms of the 8 x 16 patches for one component whose operand
-// (4 eigen blocks x 2 depth steps, this lane's entries) starts at ap with a
-// stride of 64 uint4.  Lane l (group g = l >> 4) returns the costs of the
-// two patches it owns: blocks 4 (g >> 1) + 2 (g & 1) + {0, 1}, column l & 15.
-__device__ __forceinline__ void score(const uint4* ap, const uint4 zb[PB][2], float Lk, int g,
-                                      float& cA, float& cB) {
-  uint4 A[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) A[i] = ap[i * 64];
+// Squared norms of the 8 x 16 patches' projections on the first 16 NB
+// directions of one component whose operand (4 eigen blocks x 2 depth steps,
+// this lane's entries) starts at ap with a stride of 64 uint4.  Lane l
+// (group g = l >> 4) returns the sums of the two patches it owns: blocks
+// 4 (g >> 1) + 2 (g & 1) + {0, 1}, column l & 15.
+// NB < 0: the block count nb (1..4) is known at run time only, and each
+// block's operand is loaded in turn (the flat-tail form).
+template <int NB>
+__device__ __forceinline__ void project(const uint4* ap, const uint4 zb[PB][2], float& mA,
+                                        float& mB, int nb = NB) {
   float q[PB];
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
+  if (NB > 0) {
+    uint4 A[2 * (NB > 0 ? NB : 1)];
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb) {
-    f32x4 acc[PB];
+    for (int i = 0; i < 2 * NB; ++i) A[i] = ap[i * 64];
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb) acc[pb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int rb = 0; rb < NB; ++rb) {
+      f32x4 acc[PB];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+      for (int pb = 0; pb < PB; ++pb) acc[pb] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb) acc[pb] = mfma16(A[rb * 2 + t], zb[pb][t], acc[pb]);
+      for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb)
+        for (int pb = 0; pb < PB; ++pb) acc[pb] = mfma16(A[rb * 2 + t], zb[pb][t], acc[pb]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+      for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+    }
+  } else {
+    for (int rb = 0; rb < nb; ++rb) {
+      const uint4 A0 = ap[(2 * rb) * 64], A1 = ap[(2 * rb + 1) * 64];
+      f32x4 acc[PB];
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) acc[pb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) acc[pb] = mfma16(A0, zb[pb][0], acc[pb]);
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) acc[pb] = mfma16(A1, zb[pb][1], acc[pb]);
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+    }
   }
   // lane groups g and g ^ 2 split the 8 blocks in halves, then g and g ^ 1:
   // lanes of groups 0/1 keep blocks 0..3, groups 2/3 keep 4..7, then even
@@ -156,13 +197,34 @@ __device__ __forceinline__ void score(const uint4* ap, const uint4 zb[PB][2], fl
   float m2[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) m2[i] = pair_sum16(m4[i], m4[2 + i]);
-  (void)g;
-  cA = Lk + m2[0];
-  cB = Lk + m2[1];
+  mA = m2[0];
+  mB = m2[1];
+}
+
+// Costs of the lane's two patches for component k.  Plain form: L_k plus
+// the 64 squared projections.  Flat-tail form (Sec. 3.1, rk < 64 kept
+// directions): L_k + Pk |z~|^2 minus the squared projections on the
+// ceil(rk / 16) blocks that hold the kept directions (the operand's
+// columns carry sqrt(1/nu_P - 1/nu_j), Pk = 1/nu_P); a component without a
+// tail (rk = 64, Pk = 0) takes the plain form, rounded identically.
+template <bool FLAT>
+__device__ __forceinline__ void score(const uint4* ap, const uint4 zb[PB][2], float Lk, int rk,
+                                      float Pk, float nzA, float nzB, float& cA, float& cB) {
+  float mA, mB;
+  if (!FLAT) {
+    project<4>(ap, zb, mA, mB);
+    cA = Lk + mA;
+    cB = Lk + mB;
+    return;
+  }
+  project<-1>(ap, zb, mA, mB, (rk + 15) >> 4);
+  const float sg = (rk < kP) ? -1.f : 1.f;
+  cA = fmaf(sg, mA, fmaf(Pk, nzA, Lk));
+  cB = fmaf(sg, mB, fmaf(Pk, nzB, Lk));
 }
 }  // namespace
 
-template <int MODE>
+template <int MODE, bool FLAT>
 __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
   __shared__ uint4 Ash[2][512];
   const int lane = threadIdx.x & 63;
@@ -183,6 +245,7 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
     int H = a.H, W = a.W;
     const uint16_t* Ub = a.Ub;
     const float* Lt = a.L;
+    const float* Pt = a.Pinv;
     int32_t* labels = a.labels;
     float* bestp = a.best;
     float* secondp = a.second;
@@ -197,6 +260,7 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       const size_t slot = (size_t)(d.slot0 + a.t);
       Ub += slot * a.K * kTileStride;
       Lt += slot * a.K;
+      if (FLAT) Pt += slot * a.K;
       labels += d.np;
       if (bestp) bestp += d.np;
       if (secondp) secondp += d.np;
@@ -229,10 +293,17 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       }
     }
     uint4 zb[PB][2];
+    float nzA = 0.f, nzB = 0.f;  // flat tail: |z~|^2 of the lane's own patches
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
       const int pr = idx[pb] / Wp;
-      load_patch(x, W, pr, idx[pb] - pr * Wp, g, zb[pb]);
+      float nz = 0.f;
+      load_patch<FLAT>(x, W, pr, idx[pb] - pr * Wp, g, zb[pb], nz);
+      if (FLAT) {
+        const int ow = 4 * (g >> 1) + 2 * (g & 1);
+        nzA = (pb == ow) ? nz : nzA;
+        nzB = (pb == ow + 1) ? nz : nzB;
+      }
       // one block's raw pixels live at a time (keeps the prologue in registers)
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -254,19 +325,46 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
     {
       // all K: the per-component operand (8 KB) is staged once per
       // workgroup in LDS, double-buffered, the next one already in flight
+      // (flat tail: only the 128 uint4 of each block that holds kept
+      // directions)
       const uint4* gsrc = reinterpret_cast<const uint4*>(Ub);
-      uint4 pre0 = gsrc[threadIdx.x], pre1 = gsrc[256 + threadIdx.x];
+      const int tid = threadIdx.x;
+      int rn = kP, nu4 = 512;
+      uint4 pre0, pre1;
+      if (FLAT) {
+        rn = a.rk[0];
+        nu4 = 128 * ((rn + 15) >> 4);
+        pre0 = pre1 = make_uint4(0, 0, 0, 0);
+        if (tid < nu4) pre0 = gsrc[tid];
+        if (256 + tid < nu4) pre1 = gsrc[256 + tid];
+      } else {
+        pre0 = gsrc[tid];
+        pre1 = gsrc[256 + tid];
+      }
       for (int k = 0; k < a.K; ++k) {
         uint4* As = Ash[k & 1];
-        As[threadIdx.x] = pre0;
-        As[256 + threadIdx.x] = pre1;
+        const int rk = rn;
+        if (FLAT) {
+          if (tid < nu4) As[tid] = pre0;
+          if (256 + tid < nu4) As[256 + tid] = pre1;
+        } else {
+          As[tid] = pre0;
+          As[256 + tid] = pre1;
+        }
         __syncthreads();
         if (k + 1 < a.K) {
-          pre0 = gsrc[(size_t)(k + 1) * 512 + threadIdx.x];
-          pre1 = gsrc[(size_t)(k + 1) * 512 + 256 + threadIdx.x];
+          if (FLAT) {
+            rn = a.rk[k + 1];
+            nu4 = 128 * ((rn + 15) >> 4);
+            if (tid < nu4) pre0 = gsrc[(size_t)(k + 1) * 512 + tid];
+            if (256 + tid < nu4) pre1 = gsrc[(size_t)(k + 1) * 512 + 256 + tid];
+          } else {
+            pre0 = gsrc[(size_t)(k + 1) * 512 + tid];
+            pre1 = gsrc[(size_t)(k + 1) * 512 + 256 + tid];
+          }
         }
         float cA, cB;
-        score(As + lane, zb, Lt[k], g, cA, cB);
+        score<FLAT>(As + lane, zb, Lt[k], rk, FLAT ? Pt[k] : 0.f, nzA, nzB, cA, cB);
         keep_best(cA, k, bA, sA, kA);
         keep_best(cB, k, bB, sB, kB);
       }
@@ -291,10 +389,12 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
 // arithmetic as the all-K selection (score(): the cost of a (patch, k) pair
 // is bit for bit the one the full search computes), gathering each pair's
 // patch from the image, and writes the costs at the pairs' ids.
+template <bool FLAT>
 __global__ __launch_bounds__(256, 3) void pairs_bf16_kernel(
     const float* __restrict__ x, int H, int W, const uint16_t* __restrict__ Ub,
-    const float* __restrict__ L, int K, const int32_t* __restrict__ seg,
-    const int32_t* __restrict__ sorted, float* __restrict__ pair_cost) {
+    const float* __restrict__ L, const int32_t* __restrict__ rkt, const float* __restrict__ Pinv,
+    int K, const int32_t* __restrict__ seg, const int32_t* __restrict__ sorted,
+    float* __restrict__ pair_cost) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;
@@ -320,17 +420,24 @@ __global__ __launch_bounds__(256, 3) void pairs_bf16_kernel(
       valid[pb] = e < n;
       idx[pb] = ids[valid[pb] ? e : 0];
     }
+    const int own = 4 * (g >> 1) + 2 * (g & 1);
     uint4 zb[PB][2];
+    float nzA = 0.f, nzB = 0.f;
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
       const int i = idx[pb] >> 3;
       const int pr = i / Wp;
-      load_patch_gather(x, W, pr, i - pr * Wp, g, zb[pb]);
+      float nz = 0.f;
+      load_patch_gather<FLAT>(x, W, pr, i - pr * Wp, g, zb[pb], nz);
+      if (FLAT) {
+        nzA = (pb == own) ? nz : nzA;
+        nzB = (pb == own + 1) ? nz : nzB;
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
     float cA, cB;
-    score(up + (size_t)k * 512, zb, L[k], g, cA, cB);
-    const int own = 4 * (g >> 1) + 2 * (g & 1);
+    score<FLAT>(up + (size_t)k * 512, zb, L[k], FLAT ? rkt[k] : kP, FLAT ? Pinv[k] : 0.f, nzA,
+                nzB, cA, cB);
 #pragma unroll
     for (int pb = 0; pb < PB; pb += 2)
       if (pb == own) {
@@ -400,27 +507,42 @@ hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st
     const int Np = (args.H - 7) * (args.W - 7);
     int blocks = (Np + 511) / 512;
     if (blocks > 512) blocks = 512;
-    hipLaunchKernelGGL(estep_bf16_kernel<kModeListFull>, dim3(blocks), dim3(256), 0, st, args);
+    if (args.rk)
+      hipLaunchKernelGGL((estep_bf16_kernel<kModeListFull, true>), dim3(blocks), dim3(256), 0, st,
+                         args);
+    else
+      hipLaunchKernelGGL((estep_bf16_kernel<kModeListFull, false>), dim3(blocks), dim3(256), 0,
+                         st, args);
     return hipGetLastError();
   }
   // persistent: a fixed number of workgroups looping over the tiles
   int blocks = args.n_est;
   if (args.blocks > 0 && args.blocks < blocks) blocks = args.blocks;
   if (blocks < 1) return hipSuccess;
-  hipLaunchKernelGGL(estep_bf16_kernel<kModeSpatialFull>, dim3(blocks), dim3(256), 0, st, args);
+  if (args.rk)
+    hipLaunchKernelGGL((estep_bf16_kernel<kModeSpatialFull, true>), dim3(blocks), dim3(256), 0,
+                       st, args);
+  else
+    hipLaunchKernelGGL((estep_bf16_kernel<kModeSpatialFull, false>), dim3(blocks), dim3(256), 0,
+                       st, args);
   return hipGetLastError();
 }
 
 hipError_t launch_pair_scores_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
-                                   const float* L32_t, int K, int m, const int32_t* seg,
-                                   const int32_t* sorted, float* pair_cost, hipStream_t st) {
+                                   const float* L32_t, const int32_t* rk, const float* Pinv_t,
+                                   int K, int m, const int32_t* seg, const int32_t* sorted,
+                                   float* pair_cost, hipStream_t st) {
   // the tile total depends on the labels: a fixed grid walks the device list
   const int64_t Np = (int64_t)(H - 7) * (W - 7);
   int64_t blocks = (Np * m / kPairTile + K + 3) / 4;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(pairs_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, x, H, W, Ub_t,
-                     L32_t, K, seg, sorted, pair_cost);
+  if (rk)
+    hipLaunchKernelGGL(pairs_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, x, H, W,
+                       Ub_t, L32_t, rk, Pinv_t, K, seg, sorted, pair_cost);
+  else
+    hipLaunchKernelGGL(pairs_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, x, H,
+                       W, Ub_t, L32_t, rk, Pinv_t, K, seg, sorted, pair_cost);
   return hipGetLastError();
 }
 
@@ -433,9 +555,12 @@ hipError_t launch_pair_reduce(const uint16_t* cand, const float* pair_cost, int 
 }
 
 hipError_t launch_estep_bf16_batch(const Batch& b, const float* x, const uint16_t* Ub,
-                                   const float* L32, int K, int t, int32_t* labels, float* best,
-                                   float* second, int blocks, hipStream_t st) {
+                                   const float* L32, const int32_t* rk, const float* Pinv, int K,
+                                   int t, int32_t* labels, float* best, float* second, int blocks,
+                                   hipStream_t st) {
   BF16Args a{};
+  a.rk = rk;
+  a.Pinv = Pinv;
   a.blocks = blocks;
   a.x = x;
   a.Ub = Ub;

@@ -46,8 +46,11 @@ __device__ __forceinline__ int fp8_exponent(float mx) {
 // e4m3 B operand (32 bytes) and E8M0 scale of the patch at (r, c) for lane
 // half h: rows 4 h .. 4 h + 3.  The mean is a float32 sum of the lane's 32
 // pixels in order, plus the other half's sum.
+// With NZ, nz receives the float32 squared norm of the (unrounded)
+// DC-removed patch, the same in both lanes of its column.
+template <bool NZ>
 __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, int r, int c,
-                                            int h, i32x8& zq, int& code) {
+                                            int h, i32x8& zq, int& code, float& nz) {
   float v[32];
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
@@ -60,13 +63,15 @@ __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, 
   for (int i = 1; i < 32; ++i) s += v[i];
   s += __shfl_xor(s, 32);
   const float m = s * (1.f / 64.f);
-  float mx = 0.f;
+  float mx = 0.f, q2 = 0.f;
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
     v[i] -= m;
     mx = fmaxf(mx, fabsf(v[i]));
+    if (NZ) q2 = fmaf(v[i], v[i], q2);
   }
   mx = fmaxf(mx, __shfl_xor(mx, 32));
+  if (NZ) nz = q2 + __shfl_xor(q2, 32);
   const int e = fp8_exponent(mx);
   code = e + 127;
 #pragma unroll
@@ -80,14 +85,23 @@ __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, 
 }
 }  // namespace
 
+// FLAT: the flat-tail form (Sec. 3.1) -- only the eigen blocks of 32 that
+// hold a component's kept directions are staged and projected on, and the
+// cost is L_k + Pk |z~|^2 minus their squared projections (the operand's
+// columns carry sqrt(1/nu_P - 1/nu_j), Pk = 1/nu_P); a component without a
+// tail (rk = 64) takes the plain form.
+template <bool FLAT>
 __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const ImgDesc* __restrict__ dsc, const int32_t* __restrict__ est_img, int n_est, int t,
     const float* __restrict__ xb, const uint4* __restrict__ Uf_all,
-    const int32_t* __restrict__ Ue_all, const float* __restrict__ L_all, int K,
+    const int32_t* __restrict__ Ue_all, const float* __restrict__ L_all,
+    const int32_t* __restrict__ rkt, const float* __restrict__ P_all, int K,
     int32_t* __restrict__ labels_b, float* __restrict__ best_b, float* __restrict__ second_b) {
   __shared__ uint4 Ash[2][256];
   __shared__ int Esh[kMaxK];
   __shared__ float Lsh[kMaxK];
+  __shared__ float Psh[FLAT ? kMaxK : 1];
+  __shared__ int Rsh[FLAT ? kMaxK : 1];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int h = lane >> 5;
@@ -103,6 +117,7 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const uint4* Uf = Uf_all + slot * K * (kTileStride / 16);
     const int32_t* Ue = Ue_all + slot * K;
     const float* L = L_all + slot * K;
+    const float* Pk_t = FLAT ? P_all + slot * K : nullptr;
     const int ntx = (Wp + kEstCols - 1) / kEstCols;
     const int lt = item - d.est0;
     const int tr = lt / ntx, tc = lt - tr * ntx;
@@ -111,10 +126,16 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const int c0 = tc * (32 * PB);
     i32x8 zq[PB];
     int zc[PB];
+    float nzA = 0.f, nzB = 0.f;  // own patches: blocks h and 2 + h
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
       const int c = c0 + 32 * pb + col;
-      load_patch8(x, W, min(r, Hp - 1), min(c, Wp - 1), h, zq[pb], zc[pb]);
+      float nz = 0.f;
+      load_patch8<FLAT>(x, W, min(r, Hp - 1), min(c, Wp - 1), h, zq[pb], zc[pb], nz);
+      if (FLAT) {
+        nzA = (pb == h) ? nz : nzA;
+        nzB = (pb == 2 + h) ? nz : nzB;
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
     // the component scales and L_k of the tile's beta sit in LDS, read with
@@ -122,23 +143,37 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     for (int k = threadIdx.x; k < K; k += blockDim.x) {
       Esh[k] = Ue[k];
       Lsh[k] = L[k];
+      if (FLAT) {
+        Psh[k] = Pk_t[k];
+        Rsh[k] = rkt[k];
+      }
     }
     float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
     int kA = 0, kB = 0;
     const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                          0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    uint4 pre = Uf[threadIdx.x];
+    // (flat tail: the eigen blocks of 32 beyond the kept rank are zero and
+    // neither staged nor multiplied)
+    const int tid = threadIdx.x;
+    int rn = FLAT ? rkt[0] : kP;
+    uint4 pre = make_uint4(0, 0, 0, 0);
+    if (tid < 128 * ((rn + 31) >> 5)) pre = Uf[tid];
     for (int k = 0; k < K; ++k) {
       uint4* As = Ash[k & 1];
-      As[threadIdx.x] = pre;
+      const int nb = (rn + 31) >> 5;
+      if (tid < 128 * nb) As[tid] = pre;
       __syncthreads();
-      if (k + 1 < K) pre = Uf[(size_t)(k + 1) * 256 + threadIdx.x];
+      if (k + 1 < K) {
+        rn = FLAT ? rkt[k + 1] : kP;
+        if (tid < 128 * ((rn + 31) >> 5)) pre = Uf[(size_t)(k + 1) * 256 + tid];
+      }
       const int ek = Esh[k];
       float q[PB];
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
+        if (FLAT && rb >= nb) break;
         const uint4 a0 = As[(2 * rb) * 64 + lane], a1 = As[(2 * rb + 1) * 64 + lane];
         const i32x8 A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
                          (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
@@ -153,8 +188,15 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
           for (int i = 0; i < 16; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
       }
       const float Lk = Lsh[k];
-      keep_best(Lk + pair_sum32(q[0], q[1]), k, bA, sA, kA);
-      keep_best(Lk + pair_sum32(q[2], q[3]), k, bB, sB, kB);
+      const float mA = pair_sum32(q[0], q[1]), mB = pair_sum32(q[2], q[3]);
+      if (FLAT) {
+        const float Pk = Psh[k], sg = (Rsh[k] < kP) ? -1.f : 1.f;
+        keep_best(fmaf(sg, mA, fmaf(Pk, nzA, Lk)), k, bA, sA, kA);
+        keep_best(fmaf(sg, mB, fmaf(Pk, nzB, Lk)), k, bB, sB, kB);
+      } else {
+        keep_best(Lk + mA, k, bA, sA, kA);
+        keep_best(Lk + mB, k, bB, sB, kB);
+      }
     }
     __syncthreads();  // the staging buffers are reused by the next tile
     // lane's own patches after the half exchange: blocks h and 2 + h
@@ -171,14 +213,20 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
 }
 
 hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t* Uf,
-                                  const int32_t* Ue, const float* L32, int K, int t,
-                                  int32_t* labels, float* best, float* second, int blocks,
-                                  hipStream_t st) {
+                                  const int32_t* Ue, const float* L32, const int32_t* rk,
+                                  const float* Pinv, int K, int t, int32_t* labels, float* best,
+                                  float* second, int blocks, hipStream_t st) {
   // persistent: a fixed number of workgroups looping over the tiles
   if (blocks <= 0 || blocks > b.n_est) blocks = b.n_est;
   if (blocks < 1) return hipSuccess;
-  hipLaunchKernelGGL(estep_fp8_kernel, dim3(blocks), dim3(256), 0, st, b.d, b.est_img, b.n_est,
-                     t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, K, labels, best, second);
+  if (rk)
+    hipLaunchKernelGGL(estep_fp8_kernel<true>, dim3(blocks), dim3(256), 0, st, b.d, b.est_img,
+                       b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K,
+                       labels, best, second);
+  else
+    hipLaunchKernelGGL(estep_fp8_kernel<false>, dim3(blocks), dim3(256), 0, st, b.d, b.est_img,
+                       b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K,
+                       labels, best, second);
   return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
   const double beta = betas[t];
   __shared__ double Us[kP * UP];  // U_k[p][j] at p * UP + j
   __shared__ double Ws[kP * UP];  // W_k[q][p]
-  __shared__ double nu[kP], gam[kP], rs[kP];
+  __shared__ double nu[kP], gam[kP], rs[kP], rsf[kP];
   __shared__ double red[256];
   for (int i = threadIdx.x; i < kP * kP; i += blockDim.x)
     Us[(i >> 6) * UP + (i & 63)] = U64[(size_t)k * kP * kP + i];
@@ -36,6 +36,20 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
     rs[j] = 1.0 / sqrt(n);
     if (mask & kTabF32) tb.invnu64[((size_t)t * K + k) * kP + j] = 1.0 / n;
   }
+  __syncthreads();
+  // flat-tail form of the reduced-precision operands (Sec. 3.1): with a
+  // tail (r_k < 64), cost = L_k + |z~|^2 / nu_P - sum_{j < r_k} c_j^2
+  // (1/nu_P - 1/nu_j), so the kept columns carry sqrt(1/nu_P - 1/nu_j) (>= 0:
+  // the tail average is at most every kept eigenvalue) and the others
+  // vanish; without a tail, the plain nu^-1/2
+  const int rk = tb.rk ? tb.rk[k] : kP;
+  if (threadIdx.x < kP) {
+    const int j = threadIdx.x;
+    if (rk >= kP) rsf[j] = rs[j];
+    else rsf[j] = (j < rk) ? sqrt(fmax(1.0 / nu[rk] - 1.0 / nu[j], 0.0)) : 0.0;
+  }
+  if (threadIdx.x == 0 && (mask & (kTabBF16 | kTabF8)))
+    tb.Pinv[t * K + k] = (rk >= kP) ? 0.f : (float)(1.0 / nu[rk]);
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = -2.0 * log(w[k]);
@@ -69,7 +83,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
   double mx = 0.0;
   if (mask & kTabF8)
     for (int i = threadIdx.x; i < kP * kP; i += blockDim.x)
-      mx = fmax(mx, fabs(Us[(i >> 6) * UP + (i & 63)] * rs[i & 63]));
+      mx = fmax(mx, fabs(Us[(i >> 6) * UP + (i & 63)] * rsf[i & 63]));
   red[threadIdx.x] = mx;
   __syncthreads();
   const size_t tk = (size_t)t * K + k;
@@ -89,7 +103,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
       const int eb = idx & 7, lb = (idx >> 3) & 63, tbk = (idx >> 9) & 1, rb = idx >> 10;
       const int pb = 32 * tbk + 8 * (lb >> 4) + eb;
       const int jb2 = 16 * rb + (lb & 15);
-      uint32_t u = __float_as_uint((float)(Us[pb * UP + jb2] * rs[jb2]));
+      uint32_t u = __float_as_uint((float)(Us[pb * UP + jb2] * rsf[jb2]));
       u += 0x7fffu + ((u >> 16) & 1u);
       ub[idx] = (uint16_t)(u >> 16);
     }
@@ -124,7 +138,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
     const int l = u & 63, part = (u >> 6) & 1, rb = u >> 7;
     const int j = 32 * rb + (l & 31);
     const int p = 32 * (l >> 5) + 16 * part + bb;
-    const float q = (float)ldexp(Us[p * UP + j] * rs[j], -ee);
+    const float q = (float)ldexp(Us[p * UP + j] * rsf[j], -ee);
     uf[bi] = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(q, 0.f, 0, false) & 0xff);
   }
 }

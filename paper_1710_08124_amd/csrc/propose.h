@@ -30,6 +30,11 @@ struct BF16Args {
   int n_est;                  // spatial all-K mode: tiles of the batch
   int t;                      // spatial all-K mode: iteration (slot0 + t)
   int blocks;                 // spatial all-K mode: workgroups (0 = one per tile)
+  // flat-tail form (Sec. 3.1), or NULL: kept ranks per component, and 1/nu_P
+  // per component (all-slot table in the spatial all-K mode, this beta's
+  // otherwise)
+  const int32_t* rk;
+  const float* Pinv;
 };
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st);
@@ -40,8 +45,9 @@ hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st
 // second of its m candidates, its label and the fallback list (patches
 // whose half exact gap is below margin; count at *fb_count, zeroed before).
 hipError_t launch_pair_scores_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
-                                   const float* L32_t, int K, int m, const int32_t* seg,
-                                   const int32_t* sorted, float* pair_cost, hipStream_t st);
+                                   const float* L32_t, const int32_t* rk, const float* Pinv_t,
+                                   int K, int m, const int32_t* seg, const int32_t* sorted,
+                                   float* pair_cost, hipStream_t st);
 hipError_t launch_pair_reduce(const uint16_t* cand, const float* pair_cost, int Np, int m, int K,
                               float margin, int32_t* labels, float* best, float* second,
                               int32_t* fb_count, int32_t* fb_list, hipStream_t st);

@@ -126,6 +126,7 @@ def test_batch_and_tuning_reject_bad_arguments():
     assert L.fepll_set_tuning(None, ctypes.byref(t)) == -1
     assert L.fepll_get_tuning(None, ctypes.byref(t)) == -1
     assert L.fepll_autotune(None, 1, yi, sg.ctypes.data, None, None) == -1
+    assert L.fepll_gmm_flat_tail(None, 0.9, None) == -1
 
 
 def test_cov_eig_matches_numpy():

@@ -83,9 +83,10 @@ def test_lowp_select_matches_definition(F, mode, sigma, t, shape):
     lab, best, second = (v.cpu().numpy() for v in (lab, best, second))
     # accumulation error of one 64-term projection, relative to the sum of
     # the magnitudes of its products: float32 for bfloat16 operands; the
-    # e4m3 matrix-core instruction accumulates more coarsely (measured near
-    # 2^-17 on random e4m3 operands), bounded here by 2^-15
-    eps = {"bf16": 64 * 2.0 ** -24, "fp8": 2.0 ** -15}[mode]
+    # e4m3 matrix-core instruction accumulates more coarsely (typically near
+    # 2^-17, at most 1.2e-4 ~ 2^-13 measured on random full-range e4m3
+    # operands), bounded here by 2^-12
+    eps = {"bf16": 64 * 2.0 ** -24, "fp8": 2.0 ** -12}[mode]
     cost, bnd = lowp.lowp_costs(x, c["U"], c["lam"], c["w"], beta, mode, acc_eps=eps)
     n = cost.shape[0]
     i = np.arange(n)
