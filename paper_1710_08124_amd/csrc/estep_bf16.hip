@@ -48,8 +48,13 @@ __device__ __forceinline__ uint32_t bf16_rne(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return u >> 16;
 }
+// two floats to bfloat16 (nearest, ties to even), a in the low half: one
+// v_cvt_pk_bf16_f32, the same rounding as bf16_rne for finite values
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
-  return bf16_rne(a) | (bf16_rne(b) << 16);
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
@@ -217,7 +222,11 @@ __device__ __forceinline__ void score(const uint4* ap, const uint4 zb[PB][2], fl
     cB = Lk + mB;
     return;
   }
-  project<-1>(ap, zb, mA, mB, (rk + 15) >> 4);
+  const int nb = (rk + 15) >> 4;
+  if (nb == 1)  // the common case (r_k <= 16)
+    project<1>(ap, zb, mA, mB);
+  else
+    project<-1>(ap, zb, mA, mB, nb);
   const float sg = (rk < kP) ? -1.f : 1.f;
   cA = fmaf(sg, mA, fmaf(Pk, nzA, Lk));
   cB = fmaf(sg, mB, fmaf(Pk, nzB, Lk));

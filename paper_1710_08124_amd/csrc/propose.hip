@@ -36,8 +36,13 @@ __device__ __forceinline__ uint32_t bf16_rne(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return u >> 16;
 }
+// two floats to bfloat16 (nearest, ties to even), a in the low half: one
+// v_cvt_pk_bf16_f32, the same rounding as bf16_rne for finite values
 __device__ __forceinline__ uint32_t pack2(float a, float b) {
-  return bf16_rne(a) | (bf16_rne(b) << 16);
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  const f32x2_t v = {a, b};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 __device__ __forceinline__ f32x16 mfma_bf16(uint4 a, uint4 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
@@ -84,7 +89,7 @@ struct Top8 {
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
 constexpr int kSlabU4 = 16 * 64;  // uint4 of the largest slab (16 depth steps x 64 lanes)
-constexpr int kPer = kSlabU4 / kThreads;  // uint4 of a slab per thread
+static_assert(kSlabU4 == 2 * kThreads, "two uint4 of a slab per thread");
 
 // activation epilogue of one 32-row block: bias + GELU, then re-pack as
 // the two depth steps (2 nt, 2 nt + 1) of the next layer's B operand
@@ -116,6 +121,40 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16& acc, const float* 
                   pack2(lo[6], lo[7]));
   s1 = make_uint4(pack2(hi[0], hi[1]), pack2(hi[2], hi[3]), pack2(hi[4], hi[5]),
                   pack2(hi[6], hi[7]));
+}
+
+// Weight-slab pipeline.  Slab q's offset (uint4) in Wb: 8 layer-1 slabs of
+// 5 x 64, then 8 layer-2 and n3 layer-3 slabs of 16 x 64.  Every slab moves
+// as kSlabU4 uint4 (two per thread), so the number of loads in flight is
+// fixed and each wait is for the older slab only; a layer-1 slab carries
+// the head of the next slab along, unused and in bounds (larger slabs
+// follow the last one).
+// (native vectors: copies of HIP's uint4 struct lower to memcpy, which keeps
+// the pair in private memory)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+struct SlabRegs {
+  u32x4 a, b;
+};
+__device__ __forceinline__ int slab_offset(int q) {
+  if (q < 8) return q * 5 * 64;
+  if (q < 16) return 8 * 5 * 64 + (q - 8) * 16 * 64;
+  return 8 * 5 * 64 + 8 * 16 * 64 + (q - 16) * 16 * 64;
+}
+__device__ __forceinline__ void fetch_slab(const uint4* __restrict__ Wb, int q, SlabRegs& p) {
+  const u32x4* w = reinterpret_cast<const u32x4*>(Wb) + slab_offset(q) + threadIdx.x;
+  p.a = w[0];
+  p.b = w[kThreads];
+}
+// make slab q resident in the LDS buffer buf and start fetching slab q + 2
+// into the same registers (past the last slab, the last one again: no
+// branch, so every wait stays exact)
+__device__ __forceinline__ void stage_slab(uint4* buf, SlabRegs& p, const uint4* __restrict__ Wb,
+                                           int q, int nslab) {
+  u32x4* d = reinterpret_cast<u32x4*>(buf) + threadIdx.x;
+  d[0] = p.a;
+  d[kThreads] = p.b;
+  __syncthreads();
+  fetch_slab(Wb, min(q + 2, nslab - 1), p);
 }
 
 }  // namespace
@@ -168,43 +207,20 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
     xb[4] = make_uint4(half ? 0u : bf16_rne(logsb), 0u, 0u, 0u);
   }
 
-  // slab schedule: q -> (layer, nt); offsets and sizes in uint4
-  const int nslab = 16 + n3;
-  auto slab_off = [&](int q) -> int {
-    if (q < 8) return q * 5 * 64;
-    if (q < 16) return 8 * 5 * 64 + (q - 8) * 16 * 64;
-    return 8 * 5 * 64 + 8 * 16 * 64 + (q - 16) * 16 * 64;
-  };
-  auto slab_len = [&](int q) -> int { return (q < 8 ? 5 : 16) * 64; };
   // slabs q + 1 and q + 2 in flight in registers (preA holds the even
-  // slabs, preB the odd ones)
-  uint4 preA[kPer], preB[kPer];
-  auto fetch = [&](int q, uint4 (&pre)[kPer]) {
-    const int off = slab_off(q), len = slab_len(q);
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int i = threadIdx.x + j * kThreads;
-      if (i < len) pre[j] = Wb[off + i];
-    }
-  };
-  // make slab q resident in LDS buffer q & 1 and start fetching slab q + 2
-  auto stage = [&](int q) {
-    const int len = slab_len(q);
-    uint4 (&pre)[kPer] = (q & 1) ? preB : preA;
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int i = threadIdx.x + j * kThreads;
-      if (i < len) slab[q & 1][i] = pre[j];
-    }
-    __syncthreads();
-    if (q + 2 < nslab) fetch(q + 2, pre);
-  };
-  fetch(0, preA);
-  fetch(1, preB);
+  // slabs, preB the odd ones; each call below names its pair at compile
+  // time, so both stay in registers)
+  const int nslab = 16 + n3;
+  SlabRegs preA, preB;
+  fetch_slab(Wb, 0, preA);
+  fetch_slab(Wb, 1, preB);
   uint4 h1[16], h2[16];
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
-    stage(q);
+    if (q & 1)
+      stage_slab(slab[1], preB, Wb, q, nslab);
+    else
+      stage_slab(slab[0], preA, Wb, q, nslab);
     const uint4* A = slab[q & 1] + lane;
     f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -214,7 +230,10 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
   }
 #pragma unroll
   for (int q = 8; q < 16; ++q) {
-    stage(q);
+    if (q & 1)
+      stage_slab(slab[1], preB, Wb, q, nslab);
+    else
+      stage_slab(slab[0], preA, Wb, q, nslab);
     const uint4* A = slab[q & 1] + lane;
     // two independent accumulation chains (even / odd depth steps)
     f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -232,8 +251,8 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
   Top8 top;
   top.init();
   const float* b3 = bsh + 2 * kHidden;
-  for (int q = 16; q < nslab; ++q) {
-    stage(q);
+  auto layer3 = [&](int q, SlabRegs& pre) __attribute__((always_inline)) {
+    stage_slab(slab[q & 1], pre, Wb, q, nslab);
     const uint4* A = slab[q & 1] + lane;
     f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     f32x16 acc2 = acc;
@@ -252,6 +271,11 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
       top.insert(cls < K ? rank_key(v, cls) : 0u);
     }
     __syncthreads();
+  };
+  // layer-3 slabs in pairs: even ones in preA, odd ones in preB
+  for (int q = 16; q < nslab; q += 2) {
+    layer3(q, preA);
+    if (q + 1 < nslab) layer3(q + 1, preB);
   }
   // merge the two halves' lists
   // take the partner's whole list before inserting, so no key comes back twice
