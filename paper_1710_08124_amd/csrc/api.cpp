@@ -95,6 +95,11 @@ struct fepll_gmm {
   size_t pair_cap = 0, pcost_cap = 0, phist_cap = 0, pseg_cap = 0;
   int32_t* psorted = nullptr;  // 8 Np
   float* pcost = nullptr;      // 8 Np
+  // the patches' bfloat16 selection operands and squared norms, written by
+  // the network for the rescoring and the fallback
+  size_t zop_cap = 0, znz_cap = 0;
+  uint16_t* zop = nullptr;  // 64 Np
+  float* znz = nullptr;     // Np
   int32_t* phist = nullptr;
   int32_t* pseg = nullptr;
   hipStream_t last_stream = nullptr;
@@ -363,6 +368,10 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     const size_t nb2 = (npmax + kPairBlock - 1) / kPairBlock;
     if ((s = grow(&g->phist, g->phist_cap, (size_t)K * nb2)) != FEPLL_OK) return s;
     if ((s = grow(&g->pseg, g->pseg_cap, pair_seg_size(npmax, K))) != FEPLL_OK) return s;
+    if (g->has_proposal) {
+      if ((s = grow(&g->zop, g->zop_cap, 64 * npmax)) != FEPLL_OK) return s;
+      if ((s = grow(&g->znz, g->znz_cap, npmax)) != FEPLL_OK) return s;
+    }
   }
   if (PX > g->px_cap) {
     dfree(g->ybuf);
@@ -410,6 +419,9 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
   b.n_sort = (int)g->h_sort.size();
   b.n_ola = (int)g->h_ola.size();
   b.n_patches = np;
+  b.max_np = 0;
+  for (const ImgDesc& dd : g->hd)
+    b.max_np = std::max<int64_t>(b.max_np, (int64_t)(dd.H - 7) * (dd.W - 7));
   b.ola_rows = ola_rows;
   return FEPLL_OK;
 }
@@ -435,7 +447,8 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
     }
     {
       StageTimer tm(g, 6, st);
-      HIPX(launch_propose_bf16(x, H, W, beta, g->pWb, g->pbias, g->K, o.top_m, g->cand, st));
+      HIPX(launch_propose_bf16(x, H, W, beta, g->pWb, g->pbias, g->K, o.top_m, g->cand, g->zop,
+                               g->znz, st));
     }
     hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, g->count, 1);
     HIPX(hipGetLastError());
@@ -445,8 +458,9 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
       // exact rescoring of the candidates: pairs bucketed by component
       StageTimer tm(g, 0, st);
       HIPX(launch_pair_bucket(g->cand, Np, o.top_m, g->K, g->phist, g->pseg, g->psorted, st));
-      HIPX(launch_pair_scores_bf16(x, H, W, Ub, L, g->tb.rk, g->tb.Pinv + (size_t)slot * K, g->K,
-                                   o.top_m, g->pseg, g->psorted, g->pcost, st));
+      HIPX(launch_pair_scores_bf16(g->zop, g->znz, Np, Ub, L, g->tb.rk,
+                                   g->tb.Pinv + (size_t)slot * K, g->K, o.top_m, g->pseg,
+                                   g->psorted, g->pcost, st));
       HIPX(launch_pair_reduce(g->cand, g->pcost, Np, o.top_m, g->K, (float)o.margin_nats, labels,
                               best, second, g->count, g->fb_list, st));
     }
@@ -464,6 +478,8 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
     a.list = g->fb_list;
     a.rk = g->tb.rk;
     a.Pinv = g->tb.Pinv + (size_t)slot * K;
+    a.zop = reinterpret_cast<const uint4*>(g->zop);
+    a.znz = g->znz;
     {
       StageTimer tm(g, 7, st);
       HIPX(launch_estep_bf16_mode(kModeListFull, a, st));
@@ -592,7 +608,7 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
                         g->seg,   g->perm,    g->Zhat,  g->ybuf,   g->xa,     g->xb,
                         g->pWb,   g->pbias,   g->cand,  g->fb_list,
                         g->psorted, g->pcost, g->phist, g->pseg,
-                        g->tb.rk,   g->tb.Pinv};
+                        g->tb.rk,   g->tb.Pinv, g->zop,  g->znz};
   for (const void* p : ptrs) put(key, p);
   if (g->gexec && key == g->gkey) {
     *result = (T % 2) ? g->xb : g->xa;
@@ -771,6 +787,8 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->fb_list);
   dfree(g->psorted);
   dfree(g->pcost);
+  dfree(g->zop);
+  dfree(g->znz);
   dfree(g->phist);
   dfree(g->pseg);
   dfree(g->pWb);
@@ -1070,7 +1088,8 @@ fepll_status fepll_propose(fepll_gmm* g, const fepll_image* x, double beta, int3
   const std::vector<float> bv(1, 1.f);
   if ((s = make_plan(g, 1, &H, &W, 1, bv, st)) != FEPLL_OK) return s;
   HIPX(copy_in(g->xa, x, st));
-  HIPX(launch_propose_bf16(g->xa, H, W, beta, g->pWb, g->pbias, g->K, top_m, cand, st));
+  HIPX(launch_propose_bf16(g->xa, H, W, beta, g->pWb, g->pbias, g->K, top_m, cand, nullptr,
+                           nullptr, st));
   return FEPLL_OK;
 }
 

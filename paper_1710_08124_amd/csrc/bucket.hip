@@ -6,14 +6,15 @@
 // per-patch 64x64 products into one dense GEMM per component (each filter
 // is loaded once per tile of kWienerTile patches instead of once per patch).
 //
-// Four launches over a batch of images, no atomics on global data (LDS
-// counters only); every image is sorted on its own:
+// Launches over a batch of images, no atomics on global data (LDS counters
+// only); every image is sorted on its own:
 //  1. hist:    per block of kSortBlock patches, a per-component count
 //              (workgroup-local LDS counters), stored component-major.
-//  2. scan:    one workgroup per image turns the counts into exclusive offsets
+//  2. tables:  the counts become exclusive offsets within each component
 //              (component-major, so a component's patches are contiguous and
-//              ordered by block), and derives per component its start, its
-//              count and the exclusive prefix of its tile count.
+//              ordered by block), and per component its start, its count and
+//              the exclusive prefix of its tile count, plus the tile table
+//              (three launches, parallel over components and tiles).
 //  3. scatter: every block writes its patch indices into its slots of each
 //              component's range, slots handed out by LDS counters.  The
 //              order inside a range is not fixed, and need not be: a patch's
@@ -57,115 +58,168 @@ __global__ __launch_bounds__(1024) void hist_kernel(Batch b, const int32_t* __re
   for (int k = threadIdx.x; k < K; k += blockDim.x) hist[(size_t)k * sb.nb + sb.lb] = h[k];
 }
 
-// Exclusive scan of the inclusive per-thread totals held in s[0..n), n <= 1024.
-__device__ void block_exclusive_scan(int32_t* s, int n) {
-  const int t = threadIdx.x;
-  for (int off = 1; off < 1024; off <<= 1) {
-    int32_t v = 0;
-    if (t < n && t >= off) v = s[t - off];
-    __syncthreads();
-    if (t < n) s[t] += v;
-    __syncthreads();
-  }
-  int32_t ex = 0;
-  if (t < n) ex = (t == 0) ? 0 : s[t - 1];
-  __syncthreads();
-  if (t < n) s[t] = ex;
-  __syncthreads();
+// ---- segment tables, in three parallel launches (shared by the Wiener
+// sort and the pair rescoring).  A problem is K x nb block counts at hist
+// (component-major) and its table seg (start[K+1], count[K],
+// tile_prefix[K+1], total tiles, tile table); `tile` entries per tile.
+//  A. one workgroup per (component, problem): exclusive scan of the
+//     component's nb block counts in place -> offsets within the component,
+//     and count[k];
+//  B. one workgroup per problem: start[k] and the tile prefix (K <= 1024);
+//  C. one thread per tile: the tile table, entry t = k | (tile in k) << 10.
+// The scatter adds start[k] to the offsets of A.
+
+struct SegProblem {
+  int32_t* hist;
+  int32_t* seg;
+  int nb;
+};
+// problem blockIdx.y: an image of the batch (BATCH: blocks of kSortBlock
+// patches), or the one problem given by (hist, seg, nb)
+template <bool BATCH>
+__device__ __forceinline__ SegProblem seg_problem(const Batch& b, int32_t* hist, int32_t* seg,
+                                                  int nb, int K) {
+  if (!BATCH) return {hist, seg, nb};
+  const ImgDesc d = b.d[blockIdx.y];
+  const int Np = (d.H - 7) * (d.W - 7);
+  return {hist + (size_t)K * d.sort0, seg + d.seg, (Np + kSortBlock - 1) / kSortBlock};
 }
 
-// Exclusive offsets of K x nb block counts (component-major, in place),
-// then per component its start, count and tile prefix (tiles of `tile`
-// entries), the total and the tile table (entry t = k | (tile index in k) << 10)
-// in seg; N entries in all.  Called by one whole workgroup of 1024 threads.
-__device__ void scan_segments(int32_t* __restrict__ hist, int K, int nb, int N, int tile,
-                              int32_t* __restrict__ seg) {
+// inclusive scan of v over a workgroup of 256 threads (wave prefix by
+// shuffles, then the 4 wave totals); returns the inclusive value, *total
+// the workgroup's sum
+__device__ __forceinline__ int32_t wg256_inclusive_scan(int32_t v, int32_t* wsum, int32_t* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t u = __shfl_up(v, off);
+    if (lane >= off) v += u;
+  }
+  if (lane == 63) wsum[wave] = v;
+  __syncthreads();
+  int32_t before = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) before += (w < wave) ? wsum[w] : 0;
+  *total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  __syncthreads();  // wsum is reused by the next call
+  return v + before;
+}
+
+template <bool BATCH>
+__global__ __launch_bounds__(256) void seg_comp_kernel(Batch b, int32_t* __restrict__ hist_a,
+                                                       int32_t* __restrict__ seg_a, int nb_a,
+                                                       int K) {
+  __shared__ int32_t wsum[4];
+  const SegProblem p = seg_problem<BATCH>(b, hist_a, seg_a, nb_a, K);
+  const int k = blockIdx.x;
+  int32_t* h = p.hist + (size_t)k * p.nb;
+  int32_t carry = 0;
+  for (int i0 = 0; i0 < p.nb; i0 += 256) {
+    const int i = i0 + threadIdx.x;
+    const int32_t v = (i < p.nb) ? h[i] : 0;
+    int32_t tot;
+    const int32_t inc = wg256_inclusive_scan(v, wsum, &tot);
+    if (i < p.nb) h[i] = carry + inc - v;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) p.seg[(K + 1) + k] = carry;  // count[k]
+}
+
+template <bool BATCH>
+__global__ __launch_bounds__(1024) void seg_total_kernel(Batch b, int32_t* __restrict__ hist_a,
+                                                         int32_t* __restrict__ seg_a, int nb_a,
+                                                         int K, int tile) {
   __shared__ int32_t part[1024];
+  const SegProblem p = seg_problem<BATCH>(b, hist_a, seg_a, nb_a, K);
+  int32_t* start = p.seg;
+  const int32_t* count = p.seg + (K + 1);
+  int32_t* tpre = p.seg + (2 * K + 1);
   const int t = threadIdx.x;
-  const int M = K * nb;
-  const int chunk = (M + 1023) / 1024;
-  const int lo = min(M, t * chunk), hi = min(M, lo + chunk);
-  int32_t sum = 0;
-#pragma unroll 8
-  for (int i = lo; i < hi; ++i) sum += hist[i];
-  part[t] = sum;
+  const int32_t c = (t < K) ? count[t] : 0;
+  const int32_t nt = (c + tile - 1) / tile;
+  // the starts (exclusive prefix of the counts), then the tile prefix
+  part[t] = c;
   __syncthreads();
-  block_exclusive_scan(part, 1024);
-  int32_t run = part[t];
-#pragma unroll 8
-  for (int i = lo; i < hi; ++i) {
-    const int32_t v = hist[i];
-    hist[i] = run;
-    run += v;
-  }
-  __syncthreads();
-  __threadfence_block();
-  // per-component start / count / tile prefix
-  int32_t* start = seg;
-  int32_t* count = seg + (K + 1);
-  int32_t* tpre = seg + (2 * K + 1);
-  __shared__ int32_t tiles[1024];
-  for (int k = t; k < K; k += 1024) {
-    const int32_t s = hist[(size_t)k * nb];
-    const int32_t e = (k + 1 < K) ? hist[(size_t)(k + 1) * nb] : N;
-    start[k] = s;
-    count[k] = e - s;
-    tiles[k] = (e - s + tile - 1) / tile;
-  }
-  if (t == 0) start[K] = N;
-  __syncthreads();
-  // K <= 1024: one scan of the tile counts
-  int32_t mine = (t < K) ? tiles[t] : 0;
-  __syncthreads();
-  part[t] = mine;
-  __syncthreads();
-  // inclusive scan
   for (int off = 1; off < 1024; off <<= 1) {
-    int32_t v = (t >= off) ? part[t - off] : 0;
+    const int32_t u = (t >= off) ? part[t - off] : 0;
     __syncthreads();
-    part[t] += v;
+    part[t] += u;
     __syncthreads();
   }
-  if (t < K) tpre[t] = part[t] - mine;
+  if (t < K) start[t] = part[t] - c;
+  if (t == 1023) start[K] = part[1023];
+  __syncthreads();
+  part[t] = nt;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int32_t u = (t >= off) ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += u;
+    __syncthreads();
+  }
+  if (t < K) tpre[t] = part[t] - nt;
   if (t == 1023) {
     tpre[K] = part[1023];
-    seg[3 * K + 2] = part[1023];
-  }
-  // tile table: tile -> (component, index of the tile within the component)
-  __shared__ int32_t tp[1025];
-  for (int k = t; k <= K; k += 1024) tp[k] = (k < K) ? part[k] - tiles[k] : part[1023];
-  __syncthreads();
-  const int total = tp[K];
-  int32_t* info = seg + (3 * K + 3);
-  for (int tl = t; tl < total; tl += 1024) {
-    int lo2 = 0, hi2 = K - 1;  // last k with tp[k] <= tl
-    while (lo2 < hi2) {
-      const int mid = (lo2 + hi2 + 1) >> 1;
-      if (tp[mid] <= tl) lo2 = mid;
-      else hi2 = mid - 1;
-    }
-    info[tl] = lo2 | ((tl - tp[lo2]) << 10);
+    p.seg[3 * K + 2] = part[1023];
   }
 }
 
-// One workgroup per image of the batch.
-__global__ __launch_bounds__(1024) void scan_kernel(Batch b, int32_t* __restrict__ hist_b, int K,
-                                                    int32_t* __restrict__ seg_b) {
-  const ImgDesc d = b.d[blockIdx.x];
-  const int Np = (d.H - 7) * (d.W - 7);
-  const int nb = (Np + kSortBlock - 1) / kSortBlock;
-  scan_segments(hist_b + (size_t)K * d.sort0, K, nb, Np, kWienerTile, seg_b + d.seg);
+template <bool BATCH>
+__global__ __launch_bounds__(256) void seg_info_kernel(Batch b, int32_t* __restrict__ hist_a,
+                                                       int32_t* __restrict__ seg_a, int nb_a,
+                                                       int K) {
+  __shared__ int32_t tp[kMaxK + 1];
+  const SegProblem p = seg_problem<BATCH>(b, hist_a, seg_a, nb_a, K);
+  const int32_t* tpre = p.seg + (2 * K + 1);
+  const int32_t total = p.seg[3 * K + 2];
+  const int tl = blockIdx.x * 256 + threadIdx.x;
+  if ((int)(blockIdx.x * 256) >= total) return;  // (workgroup-uniform)
+  for (int k = threadIdx.x; k <= K; k += 256) tp[k] = tpre[k];
+  __syncthreads();
+  if (tl >= total) return;
+  int lo = 0, hi = K - 1;  // the last k with tp[k] <= tl
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tp[mid] <= tl)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  p.seg[(3 * K + 3) + tl] = lo | ((tl - tp[lo]) << 10);
+}
+
+// A, B and C for `nprob` problems (BATCH: the images of b); max_tiles bounds
+// the tile count of every problem
+template <bool BATCH>
+hipError_t launch_seg_tables(const Batch& b, int32_t* hist, int32_t* seg, int nb, int K,
+                             int tile, int nprob, int64_t max_tiles, hipStream_t st) {
+  hipLaunchKernelGGL(seg_comp_kernel<BATCH>, dim3(K, nprob), dim3(256), 0, st, b, hist, seg, nb,
+                     K);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(seg_total_kernel<BATCH>, dim3(1, nprob), dim3(1024), 0, st, b, hist, seg, nb,
+                     K, tile);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t gx = (max_tiles + 255) / 256;
+  if (gx < 1) return hipSuccess;
+  hipLaunchKernelGGL(seg_info_kernel<BATCH>, dim3((unsigned)gx, nprob), dim3(256), 0, st, b, hist,
+                     seg, nb, K);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(1024) void scatter_kernel(Batch b, const int32_t* __restrict__ labels_b,
                                                        int K, const int32_t* __restrict__ offs_b,
+                                                       const int32_t* __restrict__ seg_b,
                                                        int32_t* __restrict__ perm_b) {
   extern __shared__ int32_t cur[];  // [K] next free slot of each component in this block
   const SortBlock sb = sort_block(b);
   const int32_t* labels = labels_b + sb.d.np;
   const int32_t* offs = offs_b + (size_t)K * sb.d.sort0;
   int32_t* perm = perm_b + sb.d.np;
-  for (int k = threadIdx.x; k < K; k += blockDim.x) cur[k] = offs[(size_t)k * sb.nb + sb.lb];
+  const int32_t* start = seg_b + sb.d.seg;
+  for (int k = threadIdx.x; k < K; k += blockDim.x)
+    cur[k] = start[k] + offs[(size_t)k * sb.nb + sb.lb];
   __syncthreads();
   const int base = sb.lb * kSortBlock;
   for (int i = threadIdx.x; i < kSortBlock; i += blockDim.x) {
@@ -220,17 +274,14 @@ __global__ __launch_bounds__(1024) void pair_hist_kernel(const uint16_t* __restr
   for (int k = threadIdx.x; k < K; k += blockDim.x) hist[(size_t)k * nb + blockIdx.x] = h[k];
 }
 
-__global__ __launch_bounds__(1024) void pair_scan_kernel(int32_t* __restrict__ hist, int K, int nb,
-                                                         int N, int32_t* __restrict__ seg) {
-  scan_segments(hist, K, nb, N, kPairTile, seg);
-}
-
 __global__ __launch_bounds__(1024) void pair_scatter_kernel(const uint16_t* __restrict__ cand,
                                                             int Np, int m, int K, int nb,
                                                             const int32_t* __restrict__ offs,
+                                                            const int32_t* __restrict__ start,
                                                             int32_t* __restrict__ sorted) {
   extern __shared__ int32_t cur[];
-  for (int k = threadIdx.x; k < K; k += blockDim.x) cur[k] = offs[(size_t)k * nb + blockIdx.x];
+  for (int k = threadIdx.x; k < K; k += blockDim.x)
+    cur[k] = start[k] + offs[(size_t)k * nb + blockIdx.x];
   __syncthreads();
   const int base = blockIdx.x * kPairBlock;
   for (int e = threadIdx.x; e < kPairBlock * m; e += blockDim.x) {
@@ -248,11 +299,11 @@ hipError_t launch_pair_bucket(const uint16_t* cand, int Np, int m, int K, int32_
                      m, K, nb, hist);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pair_scan_kernel, dim3(1), dim3(1024), 0, st, hist, K, nb, Np * m, seg);
-  e = hipGetLastError();
+  e = launch_seg_tables<false>(Batch{}, hist, seg, nb, K, kPairTile, 1,
+                               (int64_t)Np * m / kPairTile + K, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(pair_scatter_kernel, dim3(nb), dim3(1024), K * sizeof(int32_t), st, cand,
-                     Np, m, K, nb, hist, sorted);
+                     Np, m, K, nb, hist, seg, sorted);
   return hipGetLastError();
 }
 
@@ -262,11 +313,11 @@ hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int
                      K, hist);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scan_kernel, dim3(b.n), dim3(1024), 0, st, b, hist, K, seg);
-  e = hipGetLastError();
+  e = launch_seg_tables<true>(b, hist, seg, 0, K, kWienerTile, b.n,
+                              b.max_np / kWienerTile + K, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(scatter_kernel, dim3(b.n_sort), dim3(1024), K * sizeof(int32_t), st, b,
-                     labels, K, hist, perm);
+                     labels, K, hist, seg, perm);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(wbase_kernel, dim3(1), dim3(1024), 0, st, b, K, seg, wbase);

@@ -88,6 +88,7 @@ struct Batch {
   int n;
   int n_est, n_sort, n_ola;  // tile totals
   int64_t n_patches;         // patches of the whole batch
+  int64_t max_np;            // patches of the largest image
   int ola_rows;              // rows of a reprojection tile
 };
 

@@ -24,7 +24,8 @@
 //  * spatial, all K: a wave takes 128 consecutive patches of one row;
 //  * list, all K: the proposal's fallback patches, 512 list entries per
 //    workgroup, with a device-side list length (fixed grid, workgroups
-//    stride over the list and exit past its end).
+//    stride over the list and exit past its end); the patches' operands
+//    come from the records the proposal network writes.
 // The exact rescoring of the proposal's candidates runs over (patch,
 // candidate) pairs bucketed by component (pairs_bf16_kernel), each tile of
 // 128 pairs sharing one operand, with the same scoring arithmetic.
@@ -101,49 +102,17 @@ __device__ __forceinline__ void load_patch(const float* __restrict__ x, int W, i
   }
 }
 
-// The same operands for a patch anywhere in the image (the pair rescoring):
-// each 8-pixel row as two 16-byte loads, the sum in the same order.
+// The same operands for a patch anywhere in the image, from the patch-major
+// records the proposal network writes (rows dy at uint4 dy, the squared norm
+// beside): lane group g takes rows g and 4 + g.  Bit for bit what
+// load_patch computes (same mean and norm order).
 template <bool NZ>
-__device__ __forceinline__ void load_patch_gather(const float* __restrict__ x, int W, int r,
-                                                  int c, int g, uint4 zb[2], float& nz) {
-  float v[2][8];
-  float s = 0.f;
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const float* row = x + (size_t)(r + 4 * t + g) * W + c;
-    float4 a, b;
-    __builtin_memcpy(&a, row, 16);
-    __builtin_memcpy(&b, row + 4, 16);
-    v[t][0] = a.x;
-    v[t][1] = a.y;
-    v[t][2] = a.z;
-    v[t][3] = a.w;
-    v[t][4] = b.x;
-    v[t][5] = b.y;
-    v[t][6] = b.z;
-    v[t][7] = b.w;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) s += v[t][e];
-  }
-  s += __shfl_xor(s, 16);
-  s += __shfl_xor(s, 32);
-  const float m = s * (1.f / 64.f);
-  float q2 = 0.f;
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    float d[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      d[e] = v[t][e] - m;
-      if (NZ) q2 = fmaf(d[e], d[e], q2);
-    }
-    zb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),
-                       pack2(d[6], d[7]));
-  }
-  if (NZ) {
-    q2 += __shfl_xor(q2, 16);
-    nz = q2 + __shfl_xor(q2, 32);
-  }
+__device__ __forceinline__ void load_operand(const uint4* __restrict__ zop,
+                                             const float* __restrict__ znz, int i, int g,
+                                             uint4 zb[2], float& nz) {
+  zb[0] = zop[(size_t)i * 8 + g];
+  zb[1] = zop[(size_t)i * 8 + 4 + g];
+  if (NZ) nz = znz[i];
 }
 
 // Squared norms of the 8 x 16 patches' projections on the first 16 NB
@@ -305,9 +274,13 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
     float nzA = 0.f, nzB = 0.f;  // flat tail: |z~|^2 of the lane's own patches
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
-      const int pr = idx[pb] / Wp;
       float nz = 0.f;
-      load_patch<FLAT>(x, W, pr, idx[pb] - pr * Wp, g, zb[pb], nz);
+      if (MODE == kModeListFull) {
+        load_operand<FLAT>(a.zop, a.znz, idx[pb], g, zb[pb], nz);
+      } else {
+        const int pr = idx[pb] / Wp;
+        load_patch<FLAT>(x, W, pr, idx[pb] - pr * Wp, g, zb[pb], nz);
+      }
       if (FLAT) {
         const int ow = 4 * (g >> 1) + 2 * (g & 1);
         nzA = (pb == ow) ? nz : nzA;
@@ -396,20 +369,19 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
 // Exact rescoring of the proposal: one wave scores the up to 128 pairs of
 // one tile of the pair list (all of one component k) with the same
 // arithmetic as the all-K selection (score(): the cost of a (patch, k) pair
-// is bit for bit the one the full search computes), gathering each pair's
-// patch from the image, and writes the costs at the pairs' ids.
+// is bit for bit the one the full search computes), reading each pair's
+// patch operand from the network's records (one 128-byte line per patch),
+// and writes the costs at the pairs' ids.
 template <bool FLAT>
 __global__ __launch_bounds__(256, 3) void pairs_bf16_kernel(
-    const float* __restrict__ x, int H, int W, const uint16_t* __restrict__ Ub,
-    const float* __restrict__ L, const int32_t* __restrict__ rkt, const float* __restrict__ Pinv,
-    int K, const int32_t* __restrict__ seg, const int32_t* __restrict__ sorted,
-    float* __restrict__ pair_cost) {
+    const uint4* __restrict__ zop, const float* __restrict__ znz,
+    const uint16_t* __restrict__ Ub, const float* __restrict__ L, const int32_t* __restrict__ rkt,
+    const float* __restrict__ Pinv, int K, const int32_t* __restrict__ seg,
+    const int32_t* __restrict__ sorted, float* __restrict__ pair_cost) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int g = lane >> 4;
   const int col = lane & 15;
-  const int Wp = W - 7;
-  (void)H;
   const int32_t* start = seg;
   const int32_t* count = seg + (K + 1);
   const int32_t* tinfo = seg + (3 * K + 3);
@@ -434,10 +406,8 @@ __global__ __launch_bounds__(256, 3) void pairs_bf16_kernel(
     float nzA = 0.f, nzB = 0.f;
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
-      const int i = idx[pb] >> 3;
-      const int pr = i / Wp;
       float nz = 0.f;
-      load_patch_gather<FLAT>(x, W, pr, i - pr * Wp, g, zb[pb], nz);
+      load_operand<FLAT>(zop, znz, idx[pb] >> 3, g, zb[pb], nz);
       if (FLAT) {
         nzA = (pb == own) ? nz : nzA;
         nzB = (pb == own + 1) ? nz : nzB;
@@ -537,21 +507,22 @@ hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_pair_scores_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
-                                   const float* L32_t, const int32_t* rk, const float* Pinv_t,
-                                   int K, int m, const int32_t* seg, const int32_t* sorted,
-                                   float* pair_cost, hipStream_t st) {
+hipError_t launch_pair_scores_bf16(const uint16_t* zop, const float* znz, int Np_,
+                                   const uint16_t* Ub_t, const float* L32_t, const int32_t* rk,
+                                   const float* Pinv_t, int K, int m, const int32_t* seg,
+                                   const int32_t* sorted, float* pair_cost, hipStream_t st) {
   // the tile total depends on the labels: a fixed grid walks the device list
-  const int64_t Np = (int64_t)(H - 7) * (W - 7);
+  const int64_t Np = Np_;
+  const uint4* z4 = reinterpret_cast<const uint4*>(zop);
   int64_t blocks = (Np * m / kPairTile + K + 3) / 4;
   if (blocks > 1024) blocks = 1024;
   if (blocks < 1) blocks = 1;
   if (rk)
-    hipLaunchKernelGGL(pairs_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, x, H, W,
+    hipLaunchKernelGGL(pairs_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, z4, znz,
                        Ub_t, L32_t, rk, Pinv_t, K, seg, sorted, pair_cost);
   else
-    hipLaunchKernelGGL(pairs_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, x, H,
-                       W, Ub_t, L32_t, rk, Pinv_t, K, seg, sorted, pair_cost);
+    hipLaunchKernelGGL(pairs_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, z4,
+                       znz, Ub_t, L32_t, rk, Pinv_t, K, seg, sorted, pair_cost);
   return hipGetLastError();
 }
 

@@ -35,6 +35,10 @@ struct BF16Args {
   // otherwise)
   const int32_t* rk;
   const float* Pinv;
+  // list mode: the patches' bfloat16 operands (8 uint4 per patch) and
+  // squared norms, as written by the proposal network
+  const uint4* zop;
+  const float* znz;
 };
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st);
@@ -44,19 +48,23 @@ hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st
 // (launch_pair_bucket) at pair_cost[8 i + j], then per patch the best /
 // second of its m candidates, its label and the fallback list (patches
 // whose half exact gap is below margin; count at *fb_count, zeroed before).
-hipError_t launch_pair_scores_bf16(const float* x, int H, int W, const uint16_t* Ub_t,
-                                   const float* L32_t, const int32_t* rk, const float* Pinv_t,
-                                   int K, int m, const int32_t* seg, const int32_t* sorted,
-                                   float* pair_cost, hipStream_t st);
+hipError_t launch_pair_scores_bf16(const uint16_t* zop, const float* znz, int Np,
+                                   const uint16_t* Ub_t, const float* L32_t, const int32_t* rk,
+                                   const float* Pinv_t, int K, int m, const int32_t* seg,
+                                   const int32_t* sorted, float* pair_cost, hipStream_t st);
 hipError_t launch_pair_reduce(const uint16_t* cand, const float* pair_cost, int Np, int m, int K,
                               float margin, int32_t* labels, float* best, float* second,
                               int32_t* fb_count, int32_t* fb_list, hipStream_t st);
 
 // Network inference + top-m: cand[i] gets the m best classes of patch i in
 // decreasing logit order (ties to the lower class), 0xffff after the m-th.
-// Wb / bias: see propose.hip.
+// Wb / bias: see propose.hip.  zop (Np x 64 bfloat16) / znz (Np floats):
+// NULL, or they receive every patch's bfloat16 selection operand (row dy at
+// entries 8 dy .. 8 dy + 7) and the float32 squared norm of its DC-removed
+// pixels, bit for bit as the bfloat16 selection computes them.
 hipError_t launch_propose_bf16(const float* x, int H, int W, double beta, const uint16_t* Wb,
-                               const float* bias, int K, int m, uint16_t* cand, hipStream_t st);
+                               const float* bias, int K, int m, uint16_t* cand, uint16_t* zop,
+                               float* znz, hipStream_t st);
 
 // Host-side packing of float32 parameters into the inference layouts.
 // Returns the number of uint16 entries of Wb and fills wb / bias.

@@ -15,7 +15,8 @@
 // streams the 23 weight slabs (one slab = one 32-row block of a layer, all
 // depth steps, already in MFMA operand order) through double-buffered LDS,
 // so each weight byte read from L2 serves 256 patches; each slab is fetched
-// from L2 two slabs ahead.
+// from L2 two slabs ahead, and one barrier per slab (after its LDS store)
+// orders the buffers.
 //
 // Top-m: each lane keeps the 8 largest ranking keys (logit, then lower
 // class) of its 112 classes in sorted registers, then merges with lane
@@ -117,10 +118,19 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16& acc, const float* 
     hi[e] = __uint_as_float(p23[0]);
     hi[4 + e] = __uint_as_float(p23[1]);
   }
-  s0 = make_uint4(pack2(lo[0], lo[1]), pack2(lo[2], lo[3]), pack2(lo[4], lo[5]),
-                  pack2(lo[6], lo[7]));
-  s1 = make_uint4(pack2(hi[0], hi[1]), pack2(hi[2], hi[3]), pack2(hi[4], hi[5]),
-                  pack2(hi[6], hi[7]));
+  uint32_t w[8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    w[i] = pack2(lo[2 * i], lo[2 * i + 1]);
+    w[4 + i] = pack2(hi[2 * i], hi[2 * i + 1]);
+    // keep the packed words: left alone, the compiler holds the floats and
+    // converts them again at every use (twice the registers, 64 more
+    // conversions per slab)
+    asm volatile("" : "+v"(w[i]));
+    asm volatile("" : "+v"(w[4 + i]));
+  }
+  s0 = make_uint4(w[0], w[1], w[2], w[3]);
+  s1 = make_uint4(w[4], w[5], w[6], w[7]);
 }
 
 // Weight-slab pipeline.  Slab q's offset (uint4) in Wb: 8 layer-1 slabs of
@@ -162,9 +172,12 @@ __device__ __forceinline__ void stage_slab(uint4* buf, SlabRegs& p, const uint4*
 // Wb: all slabs back to back, uint4 in MFMA A-operand order:
 //   layer 1: 8 slabs x 5 depth steps, layer 2: 8 x 16, layer 3: n3 x 16.
 // bias: b1 (256) b2 (256) b3 (32 n3, -inf beyond K).
+// zop / znz: NULL, or Np x 8 uint4 and Np floats receiving the selection
+// operand of every patch and its squared norm (see the input stage).
 __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
     const float* __restrict__ x, int H, int W, float logsb, const uint4* __restrict__ Wb,
-    const float* __restrict__ bias, int n3, int K, int m, uint16_t* __restrict__ cand) {
+    const float* __restrict__ bias, int n3, int K, int m, uint16_t* __restrict__ cand,
+    uint4* __restrict__ zop, float* __restrict__ znz) {
   __shared__ uint4 slab[2][kSlabU4];  // 32 KB
   __shared__ float bsh[2 * kHidden + 32 * 32];  // b1, b2, b3 (n3 <= 32 blocks of 32)
   const int lane = threadIdx.x & 63;
@@ -179,32 +192,69 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
   for (int i = threadIdx.x; i < 2 * kHidden + 32 * n3; i += blockDim.x) bsh[i] = bias[i];
   // (made visible by the first slab's barrier)
 
-  // ---- layer-1 input: DC-removed patch / 128 and log sigma_beta
+  // ---- layer-1 input: DC-removed patch / 128 and log sigma_beta.  The
+  // mean is summed in the order of the bfloat16 selection's operand (rows g
+  // and 4 + g in order into s_g, then (s_0 + s_1) + (s_2 + s_3)); lane half
+  // h holds rows 2 t + h, so s_h (rows h, 4 + h) and s_{2+h} (rows 2 + h,
+  // 6 + h).  With zop, the patch is also written as that operand
+  // (bfloat16, row dy at uint4 dy of the patch's 128 bytes) with its float32
+  // squared norm in the same order: what the rescoring of the candidates
+  // reads, bit for bit the full search's operands.
   uint4 xb[5];
   {
-    // float32 mean: its rounding is far below the bfloat16 rounding below
     float v[4][8];
-    float s = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const float* row = x + (size_t)(rr + 2 * t + half) * W + cc;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        v[t][e] = row[e];
-        s += v[t][e];
-      }
+      for (int e = 0; e < 8; ++e) v[t][e] = row[e];
     }
-    s += __shfl_xor(s, 32);
-    const float mean = s * (1.f / 64.f);
+    float sa = 0.f, sb = 0.f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sa += v[0][e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sa += v[2][e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sb += v[1][e];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sb += v[3][e];
+    const float pa = __shfl_xor(sa, 32), pb = __shfl_xor(sb, 32);
+    const float mean = ((sa + pa) + (sb + pb)) * (1.f / 64.f);
+    float d[4][8];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) d[t][e] = v[t][e] - mean;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      float d[8];
+      float q[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) d[e] = (v[t][e] - mean) * (1.f / kScaleIn);
-      xb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),
-                         pack2(d[6], d[7]));
+      for (int e = 0; e < 8; ++e) q[e] = d[t][e] * (1.f / kScaleIn);
+      xb[t] = make_uint4(pack2(q[0], q[1]), pack2(q[2], q[3]), pack2(q[4], q[5]),
+                         pack2(q[6], q[7]));
     }
     xb[4] = make_uint4(half ? 0u : bf16_rne(logsb), 0u, 0u, 0u);
+    if (zop) {  // (uniform: the shuffles see every lane)
+      const bool ok = r < Hp && c < Wp;
+      const size_t idx = (size_t)rr * Wp + cc;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (ok)
+          zop[idx * 8 + 2 * t + half] =
+              make_uint4(pack2(d[t][0], d[t][1]), pack2(d[t][2], d[t][3]),
+                         pack2(d[t][4], d[t][5]), pack2(d[t][6], d[t][7]));
+      float qa = 0.f, qb = 0.f;  // rows h then 4 + h; rows 2 + h then 6 + h
+#pragma unroll
+      for (int e = 0; e < 8; ++e) qa = fmaf(d[0][e], d[0][e], qa);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) qa = fmaf(d[2][e], d[2][e], qa);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) qb = fmaf(d[1][e], d[1][e], qb);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) qb = fmaf(d[3][e], d[3][e], qb);
+      const float oa = __shfl_xor(qa, 32), ob = __shfl_xor(qb, 32);
+      if (ok && !half) znz[idx] = (qa + oa) + (qb + ob);
+    }
   }
 
   // slabs q + 1 and q + 2 in flight in registers (preA holds the even
@@ -226,7 +276,11 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
 #pragma unroll
     for (int s = 0; s < 5; ++s) acc = mfma_bf16(A[s * 64], xb[s], acc);
     hidden_epilogue(acc, bsh, q, half, h1[2 * q], h1[2 * q + 1]);
-    __syncthreads();
+    // (no barrier here: slab q + 1 goes to the other buffer, and slab q + 2
+    // overwrites this one only after the next stage's barrier, which every
+    // wave reaches after its last read of this slab -- the waves of a SIMD
+    // may drift by up to one slab and overlap one's epilogue with the
+    // other's matrix products)
   }
 #pragma unroll
   for (int q = 8; q < 16; ++q) {
@@ -246,7 +300,6 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] += acc2[i];
     hidden_epilogue(acc, bsh + kHidden, q - 8, half, h2[2 * (q - 8)], h2[2 * (q - 8) + 1]);
-    __syncthreads();
   }
   Top8 top;
   top.init();
@@ -268,9 +321,9 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
     for (int i = 0; i < 16; ++i) {
       const int cls = 32 * nt + 8 * (i >> 2) + 4 * half + (i & 3);
       const float v = acc[i] + b3[cls];
-      top.insert(cls < K ? rank_key(v, cls) : 0u);
+      const uint32_t key = rank_key(v, cls);
+      top.insert(cls < K ? key : 0u);  // (a select: classes past K rank last)
     }
-    __syncthreads();
   };
   // layer-3 slabs in pairs: even ones in preA, odd ones in preB
   for (int q = 16; q < nslab; q += 2) {
@@ -298,13 +351,14 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
 }
 
 hipError_t launch_propose_bf16(const float* x, int H, int W, double beta, const uint16_t* Wb,
-                               const float* bias, int K, int m, uint16_t* cand, hipStream_t st) {
+                               const float* bias, int K, int m, uint16_t* cand, uint16_t* zop,
+                               float* znz, hipStream_t st) {
   const int Hp = H - 7, Wp = W - 7;
   const int n3 = (K + 31) / 32;
   dim3 grid((Wp + 31) / 32, (Hp + kWaves - 1) / kWaves);
   hipLaunchKernelGGL(propose_bf16_kernel, grid, dim3(kThreads), 0, st, x, H, W,
                      (float)(-0.5 * log(beta)), reinterpret_cast<const uint4*>(Wb), bias, n3, K,
-                     m, cand);
+                     m, cand, reinterpret_cast<uint4*>(zop), znz);
   return hipGetLastError();
 }
 
