@@ -88,6 +88,20 @@ typedef struct {
   /* Nonzero: bracket every kernel stage with HIP events on `stream` and
    * accumulate the stage times in the handle (read with fepll_profile).    */
   int32_t profile;
+  /* Jittered stochastic patch subsampling (Sec. 3.3): 0 (default) = every
+   * patch; s in 1..8 = each iteration runs on the patches of a grid of
+   * spacing s, shifted as a whole at random and each point moved uniformly
+   * by at most floor((8 - s) / 2) pixels per direction, clamped so that
+   * every pixel stays covered, drawn again at every iteration; the
+   * reprojection averages the chosen patches only.  Random numbers:
+   * Philox4x32-10 keyed by `seed` (low word, high word), counter
+   * (t, grid row, grid column, 0) for a point's offsets (word 0 rows, word 1
+   * columns) and (t, 0xffffffff, 0xffffffff, 0) for the shift; uniform
+   * integers as a word modulo their range.  Every image of a batch uses the
+   * same seed.  Not with use_proposal (EUNSUPPORTED), nor in fepll_select.
+   * labels_out gives K for the patches not chosen.                        */
+  int32_t jitter;
+  uint64_t seed;
 } fepll_options;
 
 /* Fill *opt with the defaults above. */

@@ -40,7 +40,8 @@ class Image(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("recheck", c_int32), ("use_proposal", c_int32),
                 ("top_m", c_int32), ("margin_nats", c_double), ("init", POINTER(Image)),
-                ("stream", c_void_p), ("profile", c_int32)]
+                ("stream", c_void_p), ("profile", c_int32), ("jitter", c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 class Tuning(ctypes.Structure):
@@ -159,7 +160,7 @@ STAGES = ("select", "recheck", "bucket", "wiener", "ola_update", "prep", "propos
 
 
 def _options(precision="fp32", recheck=True, init=None, stream=None, profile=False,
-             proposal=False, top_m=8, margin=0.5) -> Options:
+             proposal=False, top_m=8, margin=0.5, jitter=0, seed=0) -> Options:
     o = Options()
     lib().fepll_options_default(ctypes.byref(o))
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
@@ -172,6 +173,8 @@ def _options(precision="fp32", recheck=True, init=None, stream=None, profile=Fal
     o.use_proposal = 1 if proposal else 0
     o.top_m = int(top_m)
     o.margin_nats = float(margin)
+    o.jitter = int(jitter)
+    o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     return o
 
 
@@ -265,19 +268,23 @@ def profile(gmm: GMM):
 
 def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
             recheck=True, return_labels=False, out=None, profile=False, proposal=False,
-            top_m=8, margin=0.5):
+            top_m=8, margin=0.5, jitter=0, seed=0):
     """Denoise y (2-D float32 torch tensor, CUDA or CPU, or numpy array).
 
     betas: absolute beta values (default {1,4,8,16,32}/sigma^2).
+    jitter: 0, or the grid spacing s of the jittered patch subsampling
+    (Sec. 3.3) with its Philox seed.
     Returns the restored image (same kind and device as y) and, with
-    return_labels, the (T, Np) int32 labels of every iteration.
+    return_labels, the (T, Np) int32 labels of every iteration (K for the
+    patches an iteration did not choose).
     """
     import torch
     yi = _image(y)
     if out is None:
         out = torch.empty_like(y) if isinstance(y, torch.Tensor) else np.empty_like(y)
     oi = _image(out)
-    o = _options(precision, recheck, init, _stream_of(y), profile, proposal, top_m, margin)
+    o = _options(precision, recheck, init, _stream_of(y), profile, proposal, top_m, margin,
+                 jitter, seed)
     if betas is None:
         bptr, T = None, 0
         Tn = 5
@@ -314,12 +321,13 @@ def _batch_args(ys, sigmas, outs):
 
 
 def restore_batch(gmm: GMM, ys, sigmas, precision="bf16", recheck=True, outs=None,
-                  profile=False, proposal=False, top_m=8, margin=0.5):
+                  profile=False, proposal=False, top_m=8, margin=0.5, jitter=0, seed=0):
     """Denoise a list of images (2-D float32 tensors or arrays, any sizes),
     each with its own noise level, in one batched call (default schedule).
     Returns the list of restored images."""
     n, yi, oi, sg, outs = _batch_args(ys, sigmas, outs)
-    o = _options(precision, recheck, None, _stream_of(ys[0]), profile, proposal, top_m, margin)
+    o = _options(precision, recheck, None, _stream_of(ys[0]), profile, proposal, top_m, margin,
+                 jitter, seed)
     _check(lib().fepll_restore_batch(gmm.handle, n, yi, sg.ctypes.data, oi, ctypes.byref(o)))
     return outs
 

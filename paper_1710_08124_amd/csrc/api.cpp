@@ -82,6 +82,12 @@ struct fepll_gmm {
   int32_t* seg = nullptr;
   int32_t* perm = nullptr;
   float* Zhat = nullptr;
+  // jittered subsampling: chosen-patch flags and list (packed like labels),
+  // list length per image
+  int32_t* jflags = nullptr;
+  int32_t* jlist = nullptr;
+  size_t jcount_cap = 0;
+  int32_t* jcount = nullptr;
   float* ybuf = nullptr;
   float* xa = nullptr;
   float* xb = nullptr;
@@ -279,6 +285,9 @@ fepll_status check_opt(const fepll_gmm* g, const fepll_options* o) {
       return fail(FEPLL_EUNSUPPORTED, "the proposal path runs with FEPLL_BF16 projections");
   }
   if (std::isnan(o->margin_nats)) return fail(FEPLL_EINVAL, "options.margin_nats is NaN");
+  if (o->jitter < 0 || o->jitter > 8) return fail(FEPLL_EINVAL, "options.jitter must be in 0..8");
+  if (o->jitter && o->use_proposal)
+    return fail(FEPLL_EUNSUPPORTED, "jittered subsampling does not run with the proposal");
   return FEPLL_OK;
 }
 
@@ -345,6 +354,8 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     dfree(g->Zhat);
     dfree(g->cand);
     dfree(g->fb_list);
+    dfree(g->jflags);
+    dfree(g->jlist);
     g->np_cap = 0;
     HIPX(dalloc(&g->labels, NP));
     HIPX(dalloc(&g->list, 4 * NP));  // int4 entries
@@ -352,6 +363,8 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     HIPX(dalloc(&g->Zhat, NP * kP));
     HIPX(dalloc(&g->cand, NP * 8));
     HIPX(dalloc(&g->fb_list, NP));
+    HIPX(dalloc(&g->jflags, NP));
+    HIPX(dalloc(&g->jlist, NP));
     g->np_cap = NP;
   }
   {
@@ -384,6 +397,7 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     g->px_cap = PX;
   }
   if (!g->count) HIPX(dalloc(&g->count, 64));
+  if ((s = grow(&g->jcount, g->jcount_cap, (size_t)n)) != FEPLL_OK) return s;
   if ((s = grow(&g->hist, g->hist_cap, (size_t)K * sort.size())) != FEPLL_OK) return s;
   if ((s = grow(&g->seg, g->seg_cap, (size_t)seg)) != FEPLL_OK) return s;
   if (!same) {
@@ -512,11 +526,67 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
 // all-K reduced-precision modes run as one persistent launch over the
 // batch; float32 (with its recheck) and the proposal path run image by
 // image.  best / second / flags: packed like labels, or NULL.
+// Jittered subsampling (Sec. 3.3) at iteration t: the chosen patches of every
+// image (flags, then the list and the label K for the others), and their
+// selection; float32 selects every patch first (its certification and
+// recheck are per patch) and marks the others after.
+fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const float* x,
+                           int32_t* labels, hipStream_t st) {
+  const Batch& b = g->batch;
+  const int n = (int)b.n_patches;
+  const size_t K = g->K;
+  fepll_status s;
+  if (o.precision == FEPLL_FP32) {
+    for (int i = 0; i < b.n; ++i) {
+      const ImgDesc& d = g->hd[i];
+      const int slot = d.slot0 + t;
+      if ((s = select_one(g, x + d.px, d.H, d.W, slot, g->cbeta[slot], o, labels + d.np, nullptr,
+                          nullptr, nullptr, st)) != FEPLL_OK)
+        return s;
+    }
+  }
+  StageTimer tm(g, 0, st);  // (float32: the positions only; its selection timed above)
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n);
+  HIPX(hipGetLastError());
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((b.n + 255) / 256), dim3(256), 0, st, g->jcount, b.n);
+  HIPX(hipGetLastError());
+  for (int i = 0; i < b.n; ++i) {
+    const ImgDesc& d = g->hd[i];
+    const int Np = (d.H - 7) * (d.W - 7);
+    HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, st));
+    HIPX(launch_jitter_compact(Np, g->K, g->jflags + d.np, labels + d.np, g->jcount + i,
+                               g->jlist + d.np, st));
+    if (o.precision == FEPLL_FP32) continue;
+    const int slot = d.slot0 + t;
+    if (o.precision == FEPLL_FP8) {
+      HIPX(launch_estep_fp8_list(g->d + i, Np, t, x, g->tb.Uf, g->tb.Ue, g->tb.L32, g->tb.rk,
+                                 g->tb.Pinv, g->K, g->jcount + i, g->jlist + d.np, labels,
+                                 nullptr, nullptr, st));
+    } else {
+      BF16Args a{};
+      a.x = x + d.px;
+      a.H = d.H;
+      a.W = d.W;
+      a.Ub = g->tb.Ub + (size_t)slot * K * kTileStride;
+      a.L = g->tb.L32 + (size_t)slot * K;
+      a.K = g->K;
+      a.labels = labels + d.np;
+      a.list_count = g->jcount + i;
+      a.list = g->jlist + d.np;
+      a.rk = g->tb.rk;
+      a.Pinv = g->tb.Pinv + (size_t)slot * K;
+      HIPX(launch_estep_bf16_mode(kModeListFull, a, st));
+    }
+  }
+  return FEPLL_OK;
+}
+
 fepll_status select_batch(fepll_gmm* g, int t, const fepll_options& o, const float* x,
                           int32_t* labels, float* best, float* second, int32_t* flags,
                           hipStream_t st) {
   const Batch& b = g->batch;
   const int blocks = g->tune.est_blocks;
+  if (o.jitter) return select_jitter(g, t, o, x, labels, st);
   if (o.precision == FEPLL_FP8 || (o.precision == FEPLL_BF16 && !o.use_proposal)) {
     if (flags) {
       const int n = (int)b.n_patches;
@@ -570,7 +640,8 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     }
     {
       StageTimer tm(g, 4, st);
-      HIPX(launch_ola_batch(b, g->Zhat, g->ybuf, g->bvals, t, xn, st));
+      HIPX(launch_ola_batch(b, g->Zhat, g->ybuf, g->bvals, t, xn,
+                            o.jitter ? g->labels : nullptr, g->K, st));
     }
     std::swap(xc, xn);
   }
@@ -597,6 +668,8 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
   put(key, o.use_proposal);
   put(key, o.top_m);
   put(key, o.margin_nats);
+  put(key, o.jitter);
+  put(key, o.seed);
   put(key, g->tune);
   put(key, g->rho);
   for (const ImgDesc& d : g->hd) put(key, d);
@@ -608,7 +681,8 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
                         g->seg,   g->perm,    g->Zhat,  g->ybuf,   g->xa,     g->xb,
                         g->pWb,   g->pbias,   g->cand,  g->fb_list,
                         g->psorted, g->pcost, g->phist, g->pseg,
-                        g->tb.rk,   g->tb.Pinv, g->zop,  g->znz};
+                        g->tb.rk,   g->tb.Pinv, g->zop,  g->znz,
+                        g->jflags,  g->jlist,   g->jcount};
   for (const void* p : ptrs) put(key, p);
   if (g->gexec && key == g->gkey) {
     *result = (T % 2) ? g->xb : g->xa;
@@ -789,6 +863,9 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->pcost);
   dfree(g->zop);
   dfree(g->znz);
+  dfree(g->jflags);
+  dfree(g->jlist);
+  dfree(g->jcount);
   dfree(g->phist);
   dfree(g->pseg);
   dfree(g->pWb);
@@ -1106,6 +1183,7 @@ fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta, int32
   fepll_options_default(&o);
   if (opt) o = *opt;
   if ((s = check_opt(g, &o)) != FEPLL_OK) return s;
+  if (o.jitter) return fail(FEPLL_EUNSUPPORTED, "fepll_select runs on every patch (jitter = 0)");
   const int H = x->height, W = x->width;
   hipStream_t st = (hipStream_t)o.stream;
   if ((s = use_stream(g, st)) != FEPLL_OK) return s;

@@ -52,7 +52,10 @@ __global__ __launch_bounds__(1024) void hist_kernel(Batch b, const int32_t* __re
   const int base = sb.lb * kSortBlock;
   for (int i = threadIdx.x; i < kSortBlock; i += blockDim.x) {
     const int g = base + i;
-    if (g < sb.Np) atomicAdd(&h[labels[g]], 1);
+    if (g < sb.Np) {
+      const int k = labels[g];
+      if (k < K) atomicAdd(&h[k], 1);  // (label K: not in the patch subset)
+    }
   }
   __syncthreads();
   for (int k = threadIdx.x; k < K; k += blockDim.x) hist[(size_t)k * sb.nb + sb.lb] = h[k];
@@ -224,7 +227,10 @@ __global__ __launch_bounds__(1024) void scatter_kernel(Batch b, const int32_t* _
   const int base = sb.lb * kSortBlock;
   for (int i = threadIdx.x; i < kSortBlock; i += blockDim.x) {
     const int g = base + i;
-    if (g < sb.Np) perm[atomicAdd(&cur[labels[g]], 1)] = g;
+    if (g < sb.Np) {
+      const int k = labels[g];
+      if (k < K) perm[atomicAdd(&cur[k], 1)] = g;
+    }
   }
 }
 

@@ -157,8 +157,30 @@ hipError_t launch_wiener_batch(const Batch& b, const float* x, const float* Wt, 
                                float* Zhat, int blocks, hipStream_t st);
 
 // Reprojection + image update of iteration t: bvals[slot] = beta sigma^2.
+// subset_labels: NULL (every patch), or the packed labels, a patch being in
+// the subset when its label is below K (the average then runs over the
+// subset's patches only).
 hipError_t launch_ola_batch(const Batch& b, const float* Zhat, const float* y,
-                            const float* bvals, int t, float* xnew, hipStream_t st);
+                            const float* bvals, int t, float* xnew, const int32_t* subset_labels,
+                            int K, hipStream_t st);
+
+// Jittered subsampling (Sec. 3.3) of one image, iteration t: flags (Np,
+// zeroed before) of the chosen patches set to 1; then every flagged patch
+// appended to list (*count zeroed before; any order) and every other
+// patch's label set to K.
+hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
+                              hipStream_t st);
+hipError_t launch_jitter_compact(int Np, int K, const int32_t* flags, int32_t* labels,
+                                 int32_t* count, int32_t* list, hipStream_t st);
+// e4m3 selection of the patches in list (*count entries, indices within the
+// image) of the one image d[0] of a batch at iteration t; x, the tables,
+// labels / best / second: packed batch buffers and all-slot tables, as for
+// launch_estep_fp8_batch; Np: the image's patch count (grid size)
+hipError_t launch_estep_fp8_list(const ImgDesc* d, int Np, int t, const float* x,
+                                 const uint8_t* Uf, const int32_t* Ue, const float* L32,
+                                 const int32_t* rk, const float* Pinv, int K,
+                                 const int32_t* count, const int32_t* list, int32_t* labels,
+                                 float* best, float* second, hipStream_t st);
 
 // Image of tile `tile` given each image's first tile (first[0] = 0,
 // ascending): the last i with first[i] <= tile.

@@ -25,7 +25,8 @@
 //  * list, all K: the proposal's fallback patches, 512 list entries per
 //    workgroup, with a device-side list length (fixed grid, workgroups
 //    stride over the list and exit past its end); the patches' operands
-//    come from the records the proposal network writes.
+//    come from the records the proposal network writes, or, without them
+//    (the jittered patch subset), from the image.
 // The exact rescoring of the proposal's candidates runs over (patch,
 // candidate) pairs bucketed by component (pairs_bf16_kernel), each tile of
 // 128 pairs sharing one operand, with the same scoring arithmetic.
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
       float nz = 0.f;
-      if (MODE == kModeListFull) {
+      if (MODE == kModeListFull && a.zop) {  // (uniform)
         load_operand<FLAT>(a.zop, a.znz, idx[pb], g, zb[pb], nz);
       } else {
         const int pr = idx[pb] / Wp;

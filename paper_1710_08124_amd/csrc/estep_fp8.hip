@@ -90,13 +90,19 @@ __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, 
 // cost is L_k + Pk |z~|^2 minus their squared projections (the operand's
 // columns carry sqrt(1/nu_P - 1/nu_j), Pk = 1/nu_P); a component without a
 // tail (rk = 64) takes the plain form.
-template <bool FLAT>
+//
+// LIST: the patches of a list (a jittered subset, Sec. 3.3) of the one image
+// dsc[0] instead of the batch's tiles: 512 list entries per work item (128
+// per wave, as 4 blocks of 32), the list length read on the device, a fixed
+// grid striding over the items.
+template <bool FLAT, bool LIST>
 __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const ImgDesc* __restrict__ dsc, const int32_t* __restrict__ est_img, int n_est, int t,
     const float* __restrict__ xb, const uint4* __restrict__ Uf_all,
     const int32_t* __restrict__ Ue_all, const float* __restrict__ L_all,
     const int32_t* __restrict__ rkt, const float* __restrict__ P_all, int K,
-    int32_t* __restrict__ labels_b, float* __restrict__ best_b, float* __restrict__ second_b) {
+    int32_t* __restrict__ labels_b, float* __restrict__ best_b, float* __restrict__ second_b,
+    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count) {
   __shared__ uint4 Ash[2][256];
   __shared__ int Esh[kMaxK];
   __shared__ float Lsh[kMaxK];
@@ -108,9 +114,12 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
   const int col = lane & 31;
 
   // persistent: each workgroup loops over selection tiles (4 patch rows x
-  // 128 columns) of the batch; the loop is workgroup-uniform
-  for (int item = blockIdx.x; item < n_est; item += gridDim.x) {
-    const ImgDesc d = dsc[est_img[item]];
+  // 128 columns) of the batch, or over 512-entry chunks of the list; the
+  // loop is workgroup-uniform
+  const int nlist = LIST ? *list_count : 0;
+  const int nitems = LIST ? (nlist + 511) / 512 : n_est;
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const ImgDesc d = dsc[LIST ? 0 : est_img[item]];
     const int W = d.W, Hp = d.H - 7, Wp = d.W - 7;
     const float* x = xb + d.px;
     const size_t slot = (size_t)(d.slot0 + t);
@@ -118,20 +127,39 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const int32_t* Ue = Ue_all + slot * K;
     const float* L = L_all + slot * K;
     const float* Pk_t = FLAT ? P_all + slot * K : nullptr;
-    const int ntx = (Wp + kEstCols - 1) / kEstCols;
-    const int lt = item - d.est0;
-    const int tr = lt / ntx, tc = lt - tr * ntx;
-
-    const int r = tr * 4 + wave;
-    const int c0 = tc * (32 * PB);
+    // this lane's patch of block pb: index (r Wp + c) of the image and
+    // whether it is a real patch (tile edge / list end otherwise)
+    int pidx[PB];
+    bool pval[PB];
+    if (LIST) {
+      const int base = item * 512 + wave * 128;
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) {
+        const int e = base + 32 * pb + col;
+        pval[pb] = e < nlist;
+        pidx[pb] = list[pval[pb] ? e : item * 512];
+      }
+    } else {
+      const int ntx = (Wp + kEstCols - 1) / kEstCols;
+      const int lt = item - d.est0;
+      const int tr = lt / ntx, tc = lt - tr * ntx;
+      const int r = tr * 4 + wave;
+      const int c0 = tc * (32 * PB);
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) {
+        const int c = c0 + 32 * pb + col;
+        pval[pb] = r < Hp && c < Wp;
+        pidx[pb] = min(r, Hp - 1) * Wp + min(c, Wp - 1);
+      }
+    }
     i32x8 zq[PB];
     int zc[PB];
     float nzA = 0.f, nzB = 0.f;  // own patches: blocks h and 2 + h
 #pragma unroll
     for (int pb = 0; pb < PB; ++pb) {
-      const int c = c0 + 32 * pb + col;
       float nz = 0.f;
-      load_patch8<FLAT>(x, W, min(r, Hp - 1), min(c, Wp - 1), h, zq[pb], zc[pb], nz);
+      const int pr = pidx[pb] / Wp;
+      load_patch8<FLAT>(x, W, pr, pidx[pb] - pr * Wp, h, zq[pb], zc[pb], nz);
       if (FLAT) {
         nzA = (pb == h) ? nz : nzA;
         nzB = (pb == 2 + h) ? nz : nzB;
@@ -202,9 +230,17 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     // lane's own patches after the half exchange: blocks h and 2 + h
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
-      const int c = c0 + 32 * (2 * p + h) + col;
-      if (r >= Hp || c >= Wp) continue;
-      const int64_t i = d.np + (int64_t)r * Wp + c;
+      const int pb = 2 * p + h;
+      bool v = pval[0];
+      int pi = pidx[0];
+#pragma unroll
+      for (int q = 1; q < PB; ++q)
+        if (q == pb) {
+          v = pval[q];
+          pi = pidx[q];
+        }
+      if (!v) continue;
+      const int64_t i = d.np + (int64_t)pi;
       labels_b[i] = p ? kB : kA;
       if (best_b) best_b[i] = p ? bB : bA;
       if (second_b) second_b[i] = p ? sB : sA;
@@ -220,13 +256,32 @@ hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t*
   if (blocks <= 0 || blocks > b.n_est) blocks = b.n_est;
   if (blocks < 1) return hipSuccess;
   if (rk)
-    hipLaunchKernelGGL(estep_fp8_kernel<true>, dim3(blocks), dim3(256), 0, st, b.d, b.est_img,
-                       b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K,
-                       labels, best, second);
+    hipLaunchKernelGGL((estep_fp8_kernel<true, false>), dim3(blocks), dim3(256), 0, st, b.d,
+                       b.est_img, b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk,
+                       Pinv, K, labels, best, second, nullptr, nullptr);
   else
-    hipLaunchKernelGGL(estep_fp8_kernel<false>, dim3(blocks), dim3(256), 0, st, b.d, b.est_img,
-                       b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K,
-                       labels, best, second);
+    hipLaunchKernelGGL((estep_fp8_kernel<false, false>), dim3(blocks), dim3(256), 0, st, b.d,
+                       b.est_img, b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk,
+                       Pinv, K, labels, best, second, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_estep_fp8_list(const ImgDesc* d, int Np, int t, const float* x,
+                                 const uint8_t* Uf, const int32_t* Ue, const float* L32,
+                                 const int32_t* rk, const float* Pinv, int K,
+                                 const int32_t* count, const int32_t* list, int32_t* labels,
+                                 float* best, float* second, hipStream_t st) {
+  // the list length is on the device: a fixed grid strides over its chunks
+  int blocks = (Np + 511) / 512;
+  if (blocks > 768) blocks = 768;
+  if (rk)
+    hipLaunchKernelGGL((estep_fp8_kernel<true, true>), dim3(blocks), dim3(256), 0, st, d, nullptr,
+                       0, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels,
+                       best, second, list, count);
+  else
+    hipLaunchKernelGGL((estep_fp8_kernel<false, true>), dim3(blocks), dim3(256), 0, st, d,
+                       nullptr, 0, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K,
+                       labels, best, second, list, count);
   return hipGetLastError();
 }
 

@@ -1,0 +1,125 @@
+// Jittered stochastic patch subsampling (Sec. 3.3): the patches of one
+// iteration are the points of a grid of spacing s, shifted as a whole by a
+// random offset, each point moved independently and uniformly by at most
+// b = floor((8 - s) / 2) pixels per direction and clamped to the image, so
+// that every pixel stays covered; positions are drawn again at every
+// iteration.
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011),
+// key = the 64-bit seed, counter (t, a, c, 0) for grid point (a, c) of
+// iteration t (word 0 moves the row, word 1 the column) and
+// (t, 0xffffffff, 0xffffffff, 0) for the shift; uniform integers in
+// {0..n-1} as the word modulo n.  Grid rows: i0 = g - s n0 + s a, n0 the
+// smallest n with g - s n <= -b, up to the first a with i0 - b >= Hp - 1
+// (likewise for columns): consecutive starts differ by at most s + 2 b <= 8
+// and the first and last clamp to the image's edges.
+//
+// Two launches per iteration: mark (one thread per grid point, flags of the
+// chosen patches set to 1 -- several points may land on one patch) and
+// compact (the flagged patches appended to a list in any order, the others'
+// labels set to K, the "not in the subset" mark every later stage reads).
+#include "common.h"
+
+namespace fepll {
+
+namespace {
+
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+    const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += W0;  // (the bump after the last round is unused)
+    k1 += W1;
+  }
+  return c;
+}
+
+// first grid coordinate along an axis with shift g: g - s n0, n0 the
+// smallest n with g - s n <= -b
+__device__ __forceinline__ int grid_first(int g, int s, int b) {
+  const int n0 = (g + b + s - 1) / s;
+  return g - s * n0;
+}
+
+__global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, uint32_t k0,
+                                                          uint32_t k1, int t, int amax, int cmax,
+                                                          int32_t* __restrict__ flags) {
+  const int Hp = H - 7, Wp = W - 7;
+  const int b = (8 - s) / 2;
+  const U4 sh = philox4x32_10(U4{(uint32_t)t, 0xffffffffu, 0xffffffffu, 0u}, k0, k1);
+  const int fy = grid_first((int)(sh.x % (uint32_t)s), s, b);
+  const int fx = grid_first((int)(sh.y % (uint32_t)s), s, b);
+  // grid extent: points up to the first one whose lowest start reaches the
+  // last patch row / column
+  const int na = (Hp - 1 + b - fy + s - 1) / s + 1;
+  const int nc = (Wp - 1 + b - fx + s - 1) / s + 1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= amax * cmax) return;
+  const int a = i / cmax, c = i - a * cmax;
+  if (a >= na || c >= nc) return;
+  const U4 u = philox4x32_10(U4{(uint32_t)t, (uint32_t)a, (uint32_t)c, 0u}, k0, k1);
+  const uint32_t n = (uint32_t)(2 * b + 1);
+  const int r = min(max(fy + s * a + (int)(u.x % n) - b, 0), Hp - 1);
+  const int q = min(max(fx + s * c + (int)(u.y % n) - b, 0), Wp - 1);
+  flags[(size_t)r * Wp + q] = 1;
+}
+
+__global__ __launch_bounds__(1024) void jitter_compact_kernel(int Np, int K,
+                                                              const int32_t* __restrict__ flags,
+                                                              int32_t* __restrict__ labels,
+                                                              int32_t* __restrict__ count,
+                                                              int32_t* __restrict__ list) {
+  __shared__ int wcnt[16];
+  __shared__ int wbase[16];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const bool in = i < Np && flags[i] != 0;
+  if (i < Np && !in) labels[i] = K;
+  // one global atomic per workgroup (ballots, LDS prefix)
+  const uint64_t mask = __ballot(in);
+  if (lane == 0) wcnt[wave] = __popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      wbase[w] = run;
+      run += wcnt[w];
+    }
+    const int base = run ? atomicAdd(count, run) : 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) wbase[w] += base;
+  }
+  __syncthreads();
+  if (in && list) list[wbase[wave] + __popcll(mask & ((1ull << lane) - 1ull))] = i;
+}
+
+}  // namespace
+
+// Upper bound of the grid points per axis for n patch starts.
+static int grid_points_max(int n, int s) { return (n - 1 + 2 * 3 + 2 * s) / s + 2; }
+
+hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
+                              hipStream_t st) {
+  const int amax = grid_points_max(H - 7, s), cmax = grid_points_max(W - 7, s);
+  const int n = amax * cmax;
+  hipLaunchKernelGGL(jitter_mark_kernel, dim3((n + 255) / 256), dim3(256), 0, st, H, W, s,
+                     (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), t, amax, cmax,
+                     flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_jitter_compact(int Np, int K, const int32_t* flags, int32_t* labels,
+                                 int32_t* count, int32_t* list, hipStream_t st) {
+  hipLaunchKernelGGL(jitter_compact_kernel, dim3((Np + 1023) / 1024), dim3(1024), 0, st, Np, K,
+                     flags, labels, count, list);
+  return hipGetLastError();
+}
+
+}  // namespace fepll

@@ -36,7 +36,8 @@ struct BF16Args {
   const int32_t* rk;
   const float* Pinv;
   // list mode: the patches' bfloat16 operands (8 uint4 per patch) and
-  // squared norms, as written by the proposal network
+  // squared norms, as written by the proposal network, or NULL (read the
+  // patches from the image)
   const uint4* zop;
   const float* znz;
 };

@@ -35,10 +35,32 @@ def test_library_exports_every_declared_symbol():
         getattr(L, n)
 
 
-def test_struct_layouts_match_header():
-    assert ctypes.sizeof(F.Image) == 32
-    assert ctypes.sizeof(F.Options) == 48
-    assert ctypes.sizeof(F.Tuning) == 16
+def test_struct_layouts_match_header(tmp_path):
+    """The binding's structs against the C compiler's layout of the header
+    (sizes and every field offset)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    fields = {"fepll_image": F.Image, "fepll_options": F.Options, "fepll_tuning": F.Tuning}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fepll.h"', "int main(void) {"]
+    for cname, py in fields.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for cname, py in fields.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_options_defaults_and_version():
