@@ -24,25 +24,37 @@ HBM_PEAK_GBS = 8000.0
 # per path: (dense MFMA peak of its selection operands, selection kernel, dtype)
 PATH_INFO = {
     "fp32": (MFMA_F32_PEAK_TFLOPS, "estep_f32_kernel", "f32"),
-    "bf16": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
-    "fp8": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel", "fp8-e4m3"),
-    "bf16+proposal": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
-    "bf16+flat": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
-    "fp8+flat": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel", "fp8-e4m3"),
-    "bf16+proposal+flat": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel", "bf16"),
+    "bf16": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel<0, false>", "bf16"),
+    "fp8": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<false, false>", "fp8-e4m3"),
+    "bf16+proposal": (MFMA_BF16_PEAK_TFLOPS, "pairs_bf16_kernel<false>", "bf16"),
+    "bf16+flat": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel<0, true>", "bf16"),
+    "fp8+flat": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<true, false>", "fp8-e4m3"),
+    "bf16+proposal+flat": (MFMA_BF16_PEAK_TFLOPS, "pairs_bf16_kernel<true>", "bf16"),
+    "bf16+jitter": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel<2, false>", "bf16"),
+    "fp8+jitter": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<false, true>", "fp8-e4m3"),
+    "fp8+flat+jitter": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<true, true>", "fp8-e4m3"),
 }
 ALL_PATHS = ("fp32", "bf16", "fp8", "bf16+proposal", "bf16+flat", "fp8+flat",
-             "bf16+proposal+flat")
+             "bf16+proposal+flat", "bf16+jitter", "fp8+jitter", "fp8+flat+jitter")
+JITTER_SEED = 20171023
 PATH_KW = {
     "fp32": dict(precision="fp32"),
     "bf16": dict(precision="bf16"),
     "fp8": dict(precision="fp8"),
     "bf16+proposal": dict(precision="bf16", proposal=True, top_m=8, margin=0.5),
 }
-# "+flat": the same options on the flat-tailed mixture (Sec. 3.1)
+# "+flat": the same options on the flat-tailed mixture (Sec. 3.1);
+# "+jitter": jittered patch subsampling (Sec. 3.3), spacing from --jitter
 for _p in ALL_PATHS:
     if _p.endswith("+flat"):
         PATH_KW[_p] = PATH_KW[_p[:-len("+flat")]]
+for _p in ALL_PATHS:
+    if _p.endswith("+jitter"):
+        PATH_KW[_p] = dict(PATH_KW[_p[:-len("+jitter")]], jitter=6, seed=JITTER_SEED)
+
+
+def is_flat(name):
+    return "+flat" in name
 
 
 def log(*a):
@@ -52,14 +64,15 @@ def log(*a):
 def measured_traffic(kernel):
     """HBM bytes (read + written) per launch of `kernel` from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when none was taken
-    or the kernel's source has changed since (sha256 of its file)."""
+    or the kernel's source has changed since (sha256 of its file).  Kernel
+    names are written there without spaces (template arguments included)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "restore_1024x1024_k200_traffic.md")
     if not os.path.exists(path):
         return None
     for line in open(path):
         f = line.split()
-        if len(f) == 6 and f[0] == "traffic" and f[1] == kernel:
+        if len(f) == 6 and f[0] == "traffic" and f[1] == kernel.replace(" ", ""):
             src = os.path.join(ROOT, "paper_1710_08124_amd", "csrc", f[2])
             if not os.path.exists(src):
                 return None
@@ -113,6 +126,8 @@ def main():
                     help="comma-separated paths to time")
     ap.add_argument("--rho", type=float, default=0.95,
                     help="flat-tail share of the trace kept per component (Sec. 3.1)")
+    ap.add_argument("--jitter", type=int, default=6,
+                    help="grid spacing of the jittered subsampling paths (Sec. 3.3)")
     ap.add_argument("--batch", type=int, default=48,
                     help="images of the uneven batch workload (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -167,10 +182,21 @@ def main():
     # algorithmic flops per launch of each timed stage (None: data-dependent)
     mlp_flops = 2.0 * (65 * 256 + 256 * 256 + 256 * K)
 
+    n_sub = {}  # jittered paths: mean patches per iteration (measured)
+
     def select_flops(name):
         if "proposal" in name:
             return 8 * 2.0 * 64 * 64 * Np
-        return flops_flat if name.endswith("+flat") else flops_launch
+        f = flops_flat if is_flat(name) else flops_launch
+        if "jitter" in name:
+            return f / Np * n_sub[name] if name in n_sub else None
+        return f
+
+    def kw_of(name):
+        kw = dict(PATH_KW[name])
+        if "jitter" in kw:
+            kw["jitter"] = args.jitter
+        return kw
 
     def stage_flops(name, stage):
         if stage == "select":
@@ -178,8 +204,29 @@ def main():
         if stage == "propose":
             return mlp_flops * Np
         if stage == "wiener":
-            return 2.0 * 64 * 64 * Np
+            return 2.0 * 64 * 64 * (n_sub[name] if name in n_sub else Np)
         return None
+
+    def roofline(name, pr):
+        """The dominant kernel of a path against its roofline."""
+        dom = pr["dominant"]
+        sel_peak, sel_kernel, _ = PATH_INFO[name]
+        if dom == "ola_update":
+            # algorithmic bytes: the chosen patches' estimates, y and x
+            npat = n_sub.get(name, Np)
+            gbs = (256.0 * npat + 8.0 * H * W) / (pr["dominant_ms"] / 1e3) / 1e9
+            return {"bound": "hbm", "kernel": "ola_update_kernel", "achieved": round(gbs, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "traffic": None}
+        kern, peak = {"select": (sel_kernel, sel_peak),
+                      "propose": ("propose_bf16_kernel", MFMA_BF16_PEAK_TFLOPS),
+                      "wiener": ("wiener_f32_kernel", MFMA_F32_PEAK_TFLOPS)}.get(
+                          dom, (dom, sel_peak))
+        tf = pr["dominant_tflops"] or 0.0
+        return {"bound": "mfma", "kernel": kern, "achieved": round(tf, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+                "traffic": (measured_traffic(kern) if dom == "select" and args.size == 1024
+                            else None)}
 
     blob_path = os.path.join(os.path.dirname(F.__file__), "data", "proposal_k200_gmm12.bin")
     if K == 200 and os.path.exists(blob_path):
@@ -190,8 +237,12 @@ def main():
         have_prop = False
 
     def run_path(name):
-        kw = PATH_KW[name]
-        g = gf if name.endswith("+flat") else g0
+        kw = kw_of(name)
+        g = gf if is_flat(name) else g0
+        if "jitter" in name:
+            # patches per iteration of this path, from its labels (K: not chosen)
+            _, lab = F.restore(g, y, sigma, out=out, return_labels=True, **kw)
+            n_sub[name] = float((lab < K).sum().item()) / lab.shape[0]
         for i in range(args.warmup):
             F.restore(g, y, sigma, out=out, **kw)
             log(f"{name} warmup {i + 1}/{args.warmup}")
@@ -222,7 +273,8 @@ def main():
         return {"mpix_s": H * W * args.steps / dt / 1e6, "ms_per_step": dt / args.steps * 1e3,
                 "graph_mpix_s": H * W * args.steps / dtg / 1e6,
                 "estep_ms": est_ms / est_n,
-                "estep_tflops": select_flops(name) / (est_ms / est_n / 1e3) / 1e12,
+                "estep_tflops": (select_flops(name) / (est_ms / est_n / 1e3) / 1e12
+                                 if select_flops(name) else None),
                 "dominant": dom, "dominant_ms": dom_s * 1e3,
                 "dominant_tflops": (fl / dom_s / 1e12) if fl else None,
                 "stages_ms": {k: round(v[0] / v[1], 4) for k, v in prof.items() if v[1]},
@@ -243,9 +295,7 @@ def main():
     ok = [p for p in names if abs(paths[p]["dpsnr"]) <= 0.05]
     head = max(ok, key=lambda p: paths[p]["mpix_s"])
     hp = paths[head]
-    peak, sel_kernel, head_dtype = PATH_INFO[head]
-    if hp["dominant"] == "propose":
-        peak = MFMA_BF16_PEAK_TFLOPS
+    head_dtype = PATH_INFO[head][2]
     res = {
         "metric": METRIC, "value": round(hp["mpix_s"], 4), "unit": "Mpixels/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(hp["ms_per_step"], 3),
@@ -254,13 +304,7 @@ def main():
         "config": {"workload": f"{H}x{W} dead leaves + 1/f texture (std 10), sigma 25, "
                                f"K={K} GMM, T=5 HQS iterations",
                    "path": head, "K": K, "image": [H, W], "T": 5},
-        "roofline": {"bound": "mfma",
-                     "kernel": {"select": sel_kernel,
-                                "propose": "propose_bf16_kernel"}.get(hp["dominant"], hp["dominant"]),
-                     "achieved": round(hp["dominant_tflops"], 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(hp["dominant_tflops"] / peak, 4),
-                     "traffic": (measured_traffic(sel_kernel) if hp["dominant"] == "select"
-                                 and args.size == 1024 else None)},
+        "roofline": roofline(head, hp),
         "speedup_vs_plain_fp32": round(hp["mpix_s"] / fp32["mpix_s"], 3),
         "graph_replay_mpix_s": round(hp["graph_mpix_s"], 4),
     }
@@ -271,7 +315,7 @@ def main():
             "mpix_s": round(pr["mpix_s"], 4), "graph_mpix_s": round(pr["graph_mpix_s"], 4),
             "estep_ms": round(pr["estep_ms"], 4),
             "estep_frac_of_peak": (round(pr["estep_tflops"] / pk, 4)
-                                   if "proposal" not in p else None),
+                                   if "proposal" not in p and pr["estep_tflops"] else None),
             "stages_ms": pr["stages_ms"], "psnr_db": round(pr["psnr"], 4),
             "dpsnr_vs_fp32_path_db": round(pr["dpsnr"], 4),
             "speedup_vs_plain_fp32": round(pr["mpix_s"] / fp32["mpix_s"], 3)}
@@ -279,11 +323,11 @@ def main():
     # included (context only, never the headline value)
     yh = np.asarray(c["y"], np.float32)
     oh = np.empty_like(yh)
-    gh = gf if head.endswith("+flat") else g
-    F.restore(gh, yh, sigma, out=oh, **PATH_KW[head])
+    gh = gf if is_flat(head) else g
+    F.restore(gh, yh, sigma, out=oh, **kw_of(head))
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        F.restore(gh, yh, sigma, out=oh, **PATH_KW[head])
+        F.restore(gh, yh, sigma, out=oh, **kw_of(head))
     res["host_buffers_mpix_s"] = round(H * W * args.steps / (time.perf_counter() - t0) / 1e6, 4)
     # share of patches whose float32 selection needed the float64 recheck
     fl = []
@@ -294,15 +338,19 @@ def main():
 
     res["flat_tail"] = {"rho": args.rho, "rank_mean": round(float(ranks.mean()), 3),
                         "rank_max": int(ranks.max()), "rank_min": int(ranks.min())}
+    res["jitter"] = {"s": args.jitter, "seed": JITTER_SEED,
+                     "patches_per_iteration": {p: round(v, 1) for p, v in n_sub.items()},
+                     "all_patches": Np}
     if batch:
-        res["batch"] = run_batch(F, torch, np, g, gf, batch, names, args.batch_steps)
+        res["batch"] = run_batch(F, torch, np, g, gf, batch, names, args.batch_steps,
+                                 args.jitter)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(res), flush=True)
 
 
-def run_batch(F, torch, np, g0, gf, batch, names, steps):
+def run_batch(F, torch, np, g0, gf, batch, names, steps, args_jitter):
     """The uneven batch (48 images, 256^2 .. 1024 x 1536, sigma ~ U[5, 50]) in
     one fepll_restore_batch call per step, replayed from its captured graph;
     launch shapes from the autotuner."""
@@ -316,8 +364,10 @@ def run_batch(F, torch, np, g0, gf, batch, names, steps):
     log(f"batch autotune {tuned} in {time.perf_counter() - t0:.1f} s")
     rows = {}
     for p in names:
-        kw = PATH_KW[p]
-        g = gf if p.endswith("+flat") else g0
+        kw = dict(PATH_KW[p])
+        if "jitter" in kw:
+            kw["jitter"] = args_jitter
+        g = gf if is_flat(p) else g0
         F.restore_batch(g, ys, sig, outs=outs, **kw)  # constants, plan, graph capture
         torch.cuda.synchronize()
         t0 = time.perf_counter()

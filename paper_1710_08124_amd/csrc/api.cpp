@@ -88,6 +88,8 @@ struct fepll_gmm {
   int32_t* jlist = nullptr;
   size_t jcount_cap = 0;
   int32_t* jcount = nullptr;
+  size_t jpart_cap = 0;
+  float4* jpart = nullptr;  // partial results of the component-split list selection
   float* ybuf = nullptr;
   float* xa = nullptr;
   float* xb = nullptr;
@@ -559,9 +561,14 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
     if (o.precision == FEPLL_FP32) continue;
     const int slot = d.slot0 + t;
     if (o.precision == FEPLL_FP8) {
-      HIPX(launch_estep_fp8_list(g->d + i, Np, t, x, g->tb.Uf, g->tb.Ue, g->tb.L32, g->tb.rk,
+      const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter), Np);
+      // the split needs its scratch (sized by ensure_jitter); without it, one pass
+      float4* part = (g->jpart && (size_t)(fp8_list_split(lmax, g->K) * lmax) <= g->jpart_cap)
+                         ? g->jpart
+                         : nullptr;
+      HIPX(launch_estep_fp8_list(g->d + i, lmax, t, x, g->tb.Uf, g->tb.Ue, g->tb.L32, g->tb.rk,
                                  g->tb.Pinv, g->K, g->jcount + i, g->jlist + d.np, labels,
-                                 nullptr, nullptr, st));
+                                 nullptr, nullptr, part, st));
     } else {
       BF16Args a{};
       a.x = x + d.px;
@@ -577,6 +584,26 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
       a.Pinv = g->tb.Pinv + (size_t)slot * K;
       HIPX(launch_estep_bf16_mode(kModeListFull, a, st));
     }
+  }
+  return FEPLL_OK;
+}
+
+// Scratch of the jittered selection for the planned batch (allocated before
+// any capture).
+fepll_status ensure_jitter(fepll_gmm* g, const fepll_options& o) {
+  if (!o.jitter || o.precision != FEPLL_FP8) return FEPLL_OK;
+  size_t need = 0;
+  for (const ImgDesc& d : g->hd) {
+    const int64_t Np = (int64_t)(d.H - 7) * (d.W - 7);
+    const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter), Np);
+    need = std::max(need, (size_t)(fp8_list_split(lmax, g->K) * lmax));
+  }
+  if (need > g->jpart_cap || !g->jpart) {
+    if (g->used) HIPX(hipStreamSynchronize(g->last_stream));
+    dfree(g->jpart);
+    g->jpart_cap = 0;
+    HIPX(dalloc(&g->jpart, need));
+    g->jpart_cap = need;
   }
   return FEPLL_OK;
 }
@@ -682,7 +709,7 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
                         g->pWb,   g->pbias,   g->cand,  g->fb_list,
                         g->psorted, g->pcost, g->phist, g->pseg,
                         g->tb.rk,   g->tb.Pinv, g->zop,  g->znz,
-                        g->jflags,  g->jlist,   g->jcount};
+                        g->jflags,  g->jlist,   g->jcount, g->jpart};
   for (const void* p : ptrs) put(key, p);
   if (g->gexec && key == g->gkey) {
     *result = (T % 2) ? g->xb : g->xa;
@@ -866,6 +893,7 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->jflags);
   dfree(g->jlist);
   dfree(g->jcount);
+  dfree(g->jpart);
   dfree(g->phist);
   dfree(g->pseg);
   dfree(g->pWb);
@@ -921,6 +949,7 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, 
   for (double b : betas) bvals.push_back((float)(b * sigma * sigma));
   if ((s = make_plan(g, 1, &H, &W, T, bvals, st)) != FEPLL_OK) return s;
   if ((s = ensure_consts(g, betas, table_mask(o), st)) != FEPLL_OK) return s;
+  if ((s = ensure_jitter(g, o)) != FEPLL_OK) return s;
 
   HIPX(copy_in(g->ybuf, y, st));
   if (o.init) HIPX(copy_in(g->xa, o.init, st));
@@ -979,6 +1008,7 @@ fepll_status fepll_restore_batch(fepll_gmm* g, int32_t n, const fepll_image* y,
   g->profiling = o.profile != 0;
   if ((s = make_plan(g, n, Hs.data(), Ws.data(), kDefaultT, bvals, st)) != FEPLL_OK) return s;
   if ((s = ensure_consts(g, betas, table_mask(o), st)) != FEPLL_OK) return s;
+  if ((s = ensure_jitter(g, o)) != FEPLL_OK) return s;
   for (int i = 0; i < n; ++i) HIPX(copy_in(g->ybuf + g->hd[i].px, &y[i], st));
   const int64_t px = g->hd[n - 1].px + (int64_t)Hs[n - 1] * Ws[n - 1];
   HIPX(hipMemcpyAsync(g->xa, g->ybuf, sizeof(float) * px, hipMemcpyDeviceToDevice, st));

@@ -172,15 +172,21 @@ hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t
                               hipStream_t st);
 hipError_t launch_jitter_compact(int Np, int K, const int32_t* flags, int32_t* labels,
                                  int32_t* count, int32_t* list, hipStream_t st);
-// e4m3 selection of the patches in list (*count entries, indices within the
-// image) of the one image d[0] of a batch at iteration t; x, the tables,
-// labels / best / second: packed batch buffers and all-slot tables, as for
-// launch_estep_fp8_batch; Np: the image's patch count (grid size)
-hipError_t launch_estep_fp8_list(const ImgDesc* d, int Np, int t, const float* x,
+// e4m3 selection of the patches in list (*count <= list_max entries,
+// indices within the image) of the one image d[0] of a batch at iteration
+// t; x, the tables, labels / best / second: packed batch buffers and
+// all-slot tables, as for launch_estep_fp8_batch.  part: NULL, or
+// fp8_list_split(list_max, K) x list_max float4 of scratch, which lets a
+// short list be split over the components (same labels).
+int fp8_list_split(int64_t list_max, int K);
+hipError_t launch_estep_fp8_list(const ImgDesc* d, int64_t list_max, int t, const float* x,
                                  const uint8_t* Uf, const int32_t* Ue, const float* L32,
                                  const int32_t* rk, const float* Pinv, int K,
                                  const int32_t* count, const int32_t* list, int32_t* labels,
-                                 float* best, float* second, hipStream_t st);
+                                 float* best, float* second, float4* part, hipStream_t st);
+// Bound on the number of patches the jittered grid of spacing s chooses in
+// an H x W image (grid points).
+int64_t jitter_points_max(int H, int W, int s);
 
 // Image of tile `tile` given each image's first tile (first[0] = 0,
 // ascending): the last i with first[i] <= tile.

@@ -22,6 +22,8 @@
 // The per-component operand (4 KB) is staged through double-buffered LDS
 // shared by the workgroup's 4 waves.  The launch is persistent over the
 // selection tiles of a batch of images, each with its own beta.
+#include <algorithm>
+
 #include "common.h"
 #include "wave_ops.h"
 
@@ -94,7 +96,11 @@ __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, 
 // LIST: the patches of a list (a jittered subset, Sec. 3.3) of the one image
 // dsc[0] instead of the batch's tiles: 512 list entries per work item (128
 // per wave, as 4 blocks of 32), the list length read on the device, a fixed
-// grid striding over the items.
+// grid striding over the items.  A short list is also split over the
+// components (blockIdx.y of nsplit takes a contiguous component range and
+// writes its best, second and label per entry to part; fp8_merge_kernel
+// combines them): the costs are the same, and merging the ranges in order
+// keeps ties on the lower component, so the labels are those of one pass.
 template <bool FLAT, bool LIST>
 __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const ImgDesc* __restrict__ dsc, const int32_t* __restrict__ est_img, int n_est, int t,
@@ -102,7 +108,8 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const int32_t* __restrict__ Ue_all, const float* __restrict__ L_all,
     const int32_t* __restrict__ rkt, const float* __restrict__ P_all, int K,
     int32_t* __restrict__ labels_b, float* __restrict__ best_b, float* __restrict__ second_b,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count) {
+    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count, int nsplit,
+    float4* __restrict__ part, int pcap) {
   __shared__ uint4 Ash[2][256];
   __shared__ int Esh[kMaxK];
   __shared__ float Lsh[kMaxK];
@@ -176,22 +183,25 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
         Rsh[k] = rkt[k];
       }
     }
+    // component range of this workgroup (LIST with a split; all K otherwise)
+    const int kbeg = (LIST && nsplit > 1) ? (int)(((int64_t)K * blockIdx.y) / nsplit) : 0;
+    const int kend = (LIST && nsplit > 1) ? (int)(((int64_t)K * (blockIdx.y + 1)) / nsplit) : K;
     float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
-    int kA = 0, kB = 0;
+    int kA = kbeg, kB = kbeg;
     const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                          0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     // (flat tail: the eigen blocks of 32 beyond the kept rank are zero and
     // neither staged nor multiplied)
     const int tid = threadIdx.x;
-    int rn = FLAT ? rkt[0] : kP;
+    int rn = FLAT ? rkt[kbeg] : kP;
     uint4 pre = make_uint4(0, 0, 0, 0);
-    if (tid < 128 * ((rn + 31) >> 5)) pre = Uf[tid];
-    for (int k = 0; k < K; ++k) {
+    if (tid < 128 * ((rn + 31) >> 5)) pre = Uf[(size_t)kbeg * 256 + tid];
+    for (int k = kbeg; k < kend; ++k) {
       uint4* As = Ash[k & 1];
       const int nb = (rn + 31) >> 5;
       if (tid < 128 * nb) As[tid] = pre;
       __syncthreads();
-      if (k + 1 < K) {
+      if (k + 1 < kend) {
         rn = FLAT ? rkt[k + 1] : kP;
         if (tid < 128 * ((rn + 31) >> 5)) pre = Uf[(size_t)(k + 1) * 256 + tid];
       }
@@ -240,6 +250,12 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
           pi = pidx[q];
         }
       if (!v) continue;
+      if (LIST && nsplit > 1) {
+        const int e = item * 512 + wave * 128 + 32 * pb + col;
+        part[(size_t)blockIdx.y * pcap + e] =
+            make_float4(p ? bB : bA, p ? sB : sA, __int_as_float(p ? kB : kA), 0.f);
+        continue;
+      }
       const int64_t i = d.np + (int64_t)pi;
       labels_b[i] = p ? kB : kA;
       if (best_b) best_b[i] = p ? bB : bA;
@@ -258,30 +274,76 @@ hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t*
   if (rk)
     hipLaunchKernelGGL((estep_fp8_kernel<true, false>), dim3(blocks), dim3(256), 0, st, b.d,
                        b.est_img, b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk,
-                       Pinv, K, labels, best, second, nullptr, nullptr);
+                       Pinv, K, labels, best, second, nullptr, nullptr, 1, nullptr, 0);
   else
     hipLaunchKernelGGL((estep_fp8_kernel<false, false>), dim3(blocks), dim3(256), 0, st, b.d,
                        b.est_img, b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk,
-                       Pinv, K, labels, best, second, nullptr, nullptr);
+                       Pinv, K, labels, best, second, nullptr, nullptr, 1, nullptr, 0);
   return hipGetLastError();
 }
 
-hipError_t launch_estep_fp8_list(const ImgDesc* d, int Np, int t, const float* x,
+// Per list entry: the best, second and label over the nsplit component
+// ranges, in range order (ties stay on the lower component).
+__global__ __launch_bounds__(256) void fp8_merge_kernel(const ImgDesc* __restrict__ d,
+                                                        const int32_t* __restrict__ count,
+                                                        const int32_t* __restrict__ list,
+                                                        const float4* __restrict__ part,
+                                                        int pcap, int nsplit,
+                                                        int32_t* __restrict__ labels_b,
+                                                        float* __restrict__ best_b,
+                                                        float* __restrict__ second_b) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= *count) return;
+  float b = INFINITY, s = INFINITY;
+  int k = 0;
+  for (int j = 0; j < nsplit; ++j) {
+    const float4 q = part[(size_t)j * pcap + e];
+    if (q.x < b) {
+      s = fminf(b, q.y);
+      b = q.x;
+      k = __float_as_int(q.z);
+    } else {
+      s = fminf(s, q.x);
+    }
+  }
+  const int64_t i = d->np + (int64_t)list[e];
+  labels_b[i] = k;
+  if (best_b) best_b[i] = b;
+  if (second_b) second_b[i] = s;
+}
+
+int fp8_list_split(int64_t list_max, int K) {
+  // enough workgroups to fill the chip (4 per compute unit) for a short list
+  const int64_t items = (list_max + 511) / 512;
+  int64_t ns = (1024 + items - 1) / std::max<int64_t>(items, 1);
+  ns = std::min<int64_t>(ns, std::min(16, K));
+  return (int)std::max<int64_t>(ns, 1);
+}
+
+hipError_t launch_estep_fp8_list(const ImgDesc* d, int64_t list_max, int t, const float* x,
                                  const uint8_t* Uf, const int32_t* Ue, const float* L32,
                                  const int32_t* rk, const float* Pinv, int K,
                                  const int32_t* count, const int32_t* list, int32_t* labels,
-                                 float* best, float* second, hipStream_t st) {
+                                 float* best, float* second, float4* part, hipStream_t st) {
   // the list length is on the device: a fixed grid strides over its chunks
-  int blocks = (Np + 511) / 512;
+  int64_t blocks = (list_max + 511) / 512;
   if (blocks > 768) blocks = 768;
+  if (blocks < 1) return hipSuccess;
+  const int ns = part ? fp8_list_split(list_max, K) : 1;
+  const int pcap = (int)list_max;
+  const dim3 grid((unsigned)blocks, ns);
   if (rk)
-    hipLaunchKernelGGL((estep_fp8_kernel<true, true>), dim3(blocks), dim3(256), 0, st, d, nullptr,
-                       0, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels,
-                       best, second, list, count);
+    hipLaunchKernelGGL((estep_fp8_kernel<true, true>), grid, dim3(256), 0, st, d, nullptr, 0, t,
+                       x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels, best,
+                       second, list, count, ns, part, pcap);
   else
-    hipLaunchKernelGGL((estep_fp8_kernel<false, true>), dim3(blocks), dim3(256), 0, st, d,
-                       nullptr, 0, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K,
-                       labels, best, second, list, count);
+    hipLaunchKernelGGL((estep_fp8_kernel<false, true>), grid, dim3(256), 0, st, d, nullptr, 0, t,
+                       x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels, best,
+                       second, list, count, ns, part, pcap);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ns == 1) return e;
+  hipLaunchKernelGGL(fp8_merge_kernel, dim3((unsigned)((list_max + 255) / 256)), dim3(256), 0, st,
+                     d, count, list, part, pcap, ns, labels, best, second);
   return hipGetLastError();
 }
 

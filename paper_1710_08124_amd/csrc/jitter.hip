@@ -105,6 +105,10 @@ __global__ __launch_bounds__(1024) void jitter_compact_kernel(int Np, int K,
 // Upper bound of the grid points per axis for n patch starts.
 static int grid_points_max(int n, int s) { return (n - 1 + 2 * 3 + 2 * s) / s + 2; }
 
+int64_t jitter_points_max(int H, int W, int s) {
+  return (int64_t)grid_points_max(H - 7, s) * grid_points_max(W - 7, s);
+}
+
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
                               hipStream_t st) {
   const int amax = grid_points_max(H - 7, s), cmax = grid_points_max(W - 7, s);

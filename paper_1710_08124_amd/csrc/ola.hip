@@ -73,7 +73,19 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
   const int cfirst = x0 - 7;
 
   float4 pre[PER];
-  float pin[SUB ? PER : 1];  // SUB: 1 when the patch is in the subset
+  float pin[SUB ? PER : 1];      // SUB: 1 when the patch is in the subset
+  int32_t lnext[SUB ? PER : 1];  // SUB: the labels of the next patch row, loaded a row ahead
+  // SUB: labels of patch row r for this thread's entries (K outside the image)
+  auto fetch_labels = [&](int r) {
+    if (!SUB) return;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int c = cfirst + (e >> 4);
+      const bool in = e < F4 && r >= 0 && r < Hp && c >= 0 && c < Wp;
+      lnext[u] = in ? labels[(size_t)r * Wp + c] : K;
+    }
+  };
   auto fetch = [&](int r) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -83,12 +95,13 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
       const int c = cfirst + p;
       bool ok = e < F4 && r >= 0 && r < Hp && c >= 0 && c < Wp;
       if (SUB) {
-        ok = ok && labels[(size_t)r * Wp + c] < K;
+        ok = ok && lnext[u] < K;
         pin[u] = ok ? 1.f : 0.f;
       }
       if (ok) v = *reinterpret_cast<const float4*>(Zhat + ((size_t)r * Wp + c) * kP + 4 * f);
       pre[u] = v;
     }
+    fetch_labels(r + 1);  // (SUB) ready by the next fetch
   };
   auto stash = [&](float* B) {
 #pragma unroll
@@ -113,6 +126,7 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
   int ya = rb + ((j - rb) & 3);
   float acc_a = 0.f, acc_b = 0.f;
   float cnt_a = 0.f, cnt_b = 0.f;  // SUB: subset patches covering rows ya, ya + 4
+  fetch_labels(rb);
   fetch(rb);
   for (int r = rb; r <= re; ++r) {
     float* B = buf[(r - rb) & 1];
