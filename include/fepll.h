@@ -259,10 +259,12 @@ fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta,
  * read.  Stages: 0 selection (E-step; with the proposal: exact rescoring of
  * the candidates), 1 float64 re-selection, 2 bucketing, 3 patch
  * estimation, 4 reprojection + image estimation, 5 per-beta constants,
- * 6 proposal network, 7 full-K selection of the fallback patches.  ms[s]
- * receives the summed event time of stage s in milliseconds and
- * launches[s] the number of timed launches (either pointer may be NULL); n
- * is the number of entries provided (at most 8 are written).
+ * 6 proposal network, 7 full-K selection of the fallback patches, 8 the
+ * jittered patch subset (positions, list, and the merge of a selection
+ * split over components).  ms[s] receives the summed event time of stage s
+ * in milliseconds and launches[s] the number of timed launches (either
+ * pointer may be NULL); n is the number of entries provided (at most 9 are
+ * written).
  * Synchronises with the recorded events, then clears the accumulators.
  */
 fepll_status fepll_profile(fepll_gmm* g, double* ms, int32_t* launches, int32_t n);

@@ -156,7 +156,8 @@ def _image(t) -> Image:
     return Image(t.data_ptr(), t.shape[0], t.shape[1], t.stride(0), 1 if t.is_cuda else 0)
 
 
-STAGES = ("select", "recheck", "bucket", "wiener", "ola_update", "prep", "propose", "fallback")
+STAGES = ("select", "recheck", "bucket", "wiener", "ola_update", "prep", "propose", "fallback",
+          "subset")
 
 
 def _options(precision="fp32", recheck=True, init=None, stream=None, profile=False,
@@ -260,9 +261,10 @@ def cov_eig(Sigma):
 
 def profile(gmm: GMM):
     """Stage times (ms) and launch counts accumulated since the last read."""
-    ms = (c_double * 8)()
-    n = (c_int32 * 8)()
-    _check(lib().fepll_profile(gmm.handle, ms, n, 8))
+    ns = len(STAGES)
+    ms = (c_double * ns)()
+    n = (c_int32 * ns)()
+    _check(lib().fepll_profile(gmm.handle, ms, n, ns))
     return {s: (ms[i], n[i]) for i, s in enumerate(STAGES)}
 
 

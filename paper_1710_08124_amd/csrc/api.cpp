@@ -130,7 +130,7 @@ struct fepll_gmm {
 
 namespace {
 
-constexpr int kStages = 8;
+constexpr int kStages = 9;
 constexpr int kDefaultT = 5;
 const double kDefaultB[kDefaultT] = {1.0, 4.0, 8.0, 16.0, 32.0};
 
@@ -547,18 +547,26 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
         return s;
     }
   }
-  StageTimer tm(g, 0, st);  // (float32: the positions only; its selection timed above)
-  hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n);
-  HIPX(hipGetLastError());
-  hipLaunchKernelGGL(zero_i32_kernel, dim3((b.n + 255) / 256), dim3(256), 0, st, g->jcount, b.n);
-  HIPX(hipGetLastError());
+  {
+    // the chosen patches of every image (stage 8: subset)
+    StageTimer tm(g, 8, st);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n);
+    HIPX(hipGetLastError());
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((b.n + 255) / 256), dim3(256), 0, st, g->jcount,
+                       b.n);
+    HIPX(hipGetLastError());
+    for (int i = 0; i < b.n; ++i) {
+      const ImgDesc& d = g->hd[i];
+      const int Np = (d.H - 7) * (d.W - 7);
+      HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, st));
+      HIPX(launch_jitter_compact(Np, g->K, g->jflags + d.np, labels + d.np, g->jcount + i,
+                                 g->jlist + d.np, st));
+    }
+  }
+  if (o.precision == FEPLL_FP32) return FEPLL_OK;
   for (int i = 0; i < b.n; ++i) {
     const ImgDesc& d = g->hd[i];
     const int Np = (d.H - 7) * (d.W - 7);
-    HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, st));
-    HIPX(launch_jitter_compact(Np, g->K, g->jflags + d.np, labels + d.np, g->jcount + i,
-                               g->jlist + d.np, st));
-    if (o.precision == FEPLL_FP32) continue;
     const int slot = d.slot0 + t;
     if (o.precision == FEPLL_FP8) {
       const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter), Np);
@@ -566,10 +574,18 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
       float4* part = (g->jpart && (size_t)(fp8_list_split(lmax, g->K) * lmax) <= g->jpart_cap)
                          ? g->jpart
                          : nullptr;
-      HIPX(launch_estep_fp8_list(g->d + i, lmax, t, x, g->tb.Uf, g->tb.Ue, g->tb.L32, g->tb.rk,
-                                 g->tb.Pinv, g->K, g->jcount + i, g->jlist + d.np, labels,
-                                 nullptr, nullptr, part, st));
+      int ns = 1;
+      {
+        StageTimer tm(g, 0, st);  // the selection kernel alone
+        HIPX(launch_estep_fp8_list(g->d + i, lmax, t, x, g->tb.Uf, g->tb.Ue, g->tb.L32,
+                                   g->tb.rk, g->tb.Pinv, g->K, g->jcount + i, g->jlist + d.np,
+                                   labels, nullptr, nullptr, part, &ns, st));
+      }
+      StageTimer tm(g, 8, st);  // the merge of the component ranges
+      HIPX(launch_fp8_merge(g->d + i, lmax, g->jcount + i, g->jlist + d.np, part, ns, labels,
+                            nullptr, nullptr, st));
     } else {
+      StageTimer tm(g, 0, st);
       BF16Args a{};
       a.x = x + d.px;
       a.H = d.H;

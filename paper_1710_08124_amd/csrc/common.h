@@ -177,13 +177,19 @@ hipError_t launch_jitter_compact(int Np, int K, const int32_t* flags, int32_t* l
 // t; x, the tables, labels / best / second: packed batch buffers and
 // all-slot tables, as for launch_estep_fp8_batch.  part: NULL, or
 // fp8_list_split(list_max, K) x list_max float4 of scratch, which lets a
-// short list be split over the components (same labels).
+// short list be split over the components (same labels): *nsplit receives
+// the number of component ranges, and when it is above 1 launch_fp8_merge
+// must follow to write the results.
 int fp8_list_split(int64_t list_max, int K);
 hipError_t launch_estep_fp8_list(const ImgDesc* d, int64_t list_max, int t, const float* x,
                                  const uint8_t* Uf, const int32_t* Ue, const float* L32,
                                  const int32_t* rk, const float* Pinv, int K,
                                  const int32_t* count, const int32_t* list, int32_t* labels,
-                                 float* best, float* second, float4* part, hipStream_t st);
+                                 float* best, float* second, float4* part, int* nsplit,
+                                 hipStream_t st);
+hipError_t launch_fp8_merge(const ImgDesc* d, int64_t list_max, const int32_t* count,
+                            const int32_t* list, const float4* part, int nsplit, int32_t* labels,
+                            float* best, float* second, hipStream_t st);
 // Bound on the number of patches the jittered grid of spacing s chooses in
 // an H x W image (grid points).
 int64_t jitter_points_max(int H, int W, int s);

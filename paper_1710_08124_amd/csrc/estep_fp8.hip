@@ -324,7 +324,9 @@ hipError_t launch_estep_fp8_list(const ImgDesc* d, int64_t list_max, int t, cons
                                  const uint8_t* Uf, const int32_t* Ue, const float* L32,
                                  const int32_t* rk, const float* Pinv, int K,
                                  const int32_t* count, const int32_t* list, int32_t* labels,
-                                 float* best, float* second, float4* part, hipStream_t st) {
+                                 float* best, float* second, float4* part, int* nsplit,
+                                 hipStream_t st) {
+  *nsplit = 1;
   // the list length is on the device: a fixed grid strides over its chunks
   int64_t blocks = (list_max + 511) / 512;
   if (blocks > 768) blocks = 768;
@@ -340,10 +342,16 @@ hipError_t launch_estep_fp8_list(const ImgDesc* d, int64_t list_max, int t, cons
     hipLaunchKernelGGL((estep_fp8_kernel<false, true>), grid, dim3(256), 0, st, d, nullptr, 0, t,
                        x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels, best,
                        second, list, count, ns, part, pcap);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || ns == 1) return e;
+  *nsplit = ns;
+  return hipGetLastError();
+}
+
+hipError_t launch_fp8_merge(const ImgDesc* d, int64_t list_max, const int32_t* count,
+                            const int32_t* list, const float4* part, int nsplit, int32_t* labels,
+                            float* best, float* second, hipStream_t st) {
+  if (nsplit <= 1) return hipSuccess;
   hipLaunchKernelGGL(fp8_merge_kernel, dim3((unsigned)((list_max + 255) / 256)), dim3(256), 0, st,
-                     d, count, list, part, pcap, ns, labels, best, second);
+                     d, count, list, part, (int)list_max, nsplit, labels, best, second);
   return hipGetLastError();
 }
 

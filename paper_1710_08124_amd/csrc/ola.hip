@@ -25,14 +25,7 @@
 // The per-pixel patch count of the valid patch set is the product of a row
 // and a column factor, cnt(y, x) = n(y, H) n(x, W) with
 // n(v, S) = min(v, S-8) - max(0, v-7) + 1.
-//
-// SUB: a subset of the patches (the jittered subsampling of Sec. 3.3; a
-// patch is in it when its label is below K).  Patches outside it are
-// neither read nor counted: the spare slot of each staged patch (entry 64
-// of its pitch) holds 1 or 0, summed like the entries into the pixel's
-// count, and the average divides by that count (at least 1: the subset
-// covers every pixel).  With every patch in the subset the sums, counts and
-// results are the same bits as the full-set kernel's.
+
 #include "common.h"
 
 namespace fepll {
@@ -46,14 +39,12 @@ constexpr int F4 = NP * 16;      // float4 of one patch row
 constexpr int PER = (F4 + 255) / 256;
 }  // namespace
 
-template <int TY, bool SUB>
+template <int TY>
 __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
                                                          const float* __restrict__ Zhat_b,
                                                          const float* __restrict__ y_b,
                                                          const float* __restrict__ bvals, int it,
-                                                         float* __restrict__ xnew_b,
-                                                         const int32_t* __restrict__ labels_b,
-                                                         int K) {
+                                                         float* __restrict__ xnew_b) {
   __shared__ float buf[2][ROW];
   const int G8 = gridDim.x;  // a multiple of 8
   const int lin = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
@@ -63,7 +54,6 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
   const int Hp = H - 7, Wp = W - 7;
   const float b = bvals[d.slot0 + it];
   const float* Zhat = Zhat_b + (size_t)d.np * kP;
-  const int32_t* labels = SUB ? labels_b + d.np : nullptr;
   const float* y = y_b + d.px;
   float* xnew = xnew_b + d.px;
   const int nty = (H + TY - 1) / TY;
@@ -73,19 +63,6 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
   const int cfirst = x0 - 7;
 
   float4 pre[PER];
-  float pin[SUB ? PER : 1];      // SUB: 1 when the patch is in the subset
-  int32_t lnext[SUB ? PER : 1];  // SUB: the labels of the next patch row, loaded a row ahead
-  // SUB: labels of patch row r for this thread's entries (K outside the image)
-  auto fetch_labels = [&](int r) {
-    if (!SUB) return;
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      const int c = cfirst + (e >> 4);
-      const bool in = e < F4 && r >= 0 && r < Hp && c >= 0 && c < Wp;
-      lnext[u] = in ? labels[(size_t)r * Wp + c] : K;
-    }
-  };
   auto fetch = [&](int r) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
@@ -93,15 +70,10 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       const int p = e >> 4, f = e & 15;
       const int c = cfirst + p;
-      bool ok = e < F4 && r >= 0 && r < Hp && c >= 0 && c < Wp;
-      if (SUB) {
-        ok = ok && lnext[u] < K;
-        pin[u] = ok ? 1.f : 0.f;
-      }
-      if (ok) v = *reinterpret_cast<const float4*>(Zhat + ((size_t)r * Wp + c) * kP + 4 * f);
+      if (e < F4 && r >= 0 && r < Hp && c >= 0 && c < Wp)
+        v = *reinterpret_cast<const float4*>(Zhat + ((size_t)r * Wp + c) * kP + 4 * f);
       pre[u] = v;
     }
-    fetch_labels(r + 1);  // (SUB) ready by the next fetch
   };
   auto stash = [&](float* B) {
 #pragma unroll
@@ -113,7 +85,6 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
         q[1] = pre[u].y;
         q[2] = pre[u].z;
         q[3] = pre[u].w;
-        if (SUB && (e & 15) == 15) q[4] = pin[u];  // entry 64: in the subset
       }
     }
   };
@@ -125,8 +96,6 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
   // pixel rows in flight of this thread: ya (closer to final) and ya + 4
   int ya = rb + ((j - rb) & 3);
   float acc_a = 0.f, acc_b = 0.f;
-  float cnt_a = 0.f, cnt_b = 0.f;  // SUB: subset patches covering rows ya, ya + 4
-  fetch_labels(rb);
   fetch(rb);
   for (int r = rb; r <= re; ++r) {
     float* B = buf[(r - rb) & 1];
@@ -143,25 +112,134 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
     }
     acc_a += sa;
     acc_b += sb;
-    if (SUB) {
-      float n = 0.f;
-#pragma unroll
-      for (int dx = 0; dx < 8; ++dx) n += S[64 - dx * PITCH];
-      cnt_a += n;
-      cnt_b += n;
-    }
     if (da == 0) {  // row ya has all its patch rows
       if (ya >= y0 && ya < H && xx < W) {
         const float nrow = (float)(min(ya, H - 8) - max(0, ya - 7) + 1);
-        const float xt = acc_a / (SUB ? cnt_a : nrow * ncol);
+        const float xt = acc_a / (nrow * ncol);
         const size_t o = (size_t)ya * W + xx;
         xnew[o] = (y[o] + b * xt) / onepb;
       }
       ya += 4;
       acc_a = acc_b;
       acc_b = 0.f;
-      cnt_a = cnt_b;
-      cnt_b = 0.f;
+    }
+  }
+}
+
+// ---- subset reprojection (jittered subsampling, Sec. 3.3).  The same
+// tiles; a tile first lists the chosen patches of its window (the
+// (TY + 7) x 71 patches that touch it; a patch is chosen when its label is
+// below K) in raster order, by a ballot compaction into LDS, then stages
+// their estimates 64 patches at a time in LDS, and every thread adds, to the
+// pixels it owns (column tx, rows j, j + 4, ...), the entries of the listed
+// patches that cover them, in list order, counting them: a fixed order, no
+// atomics, and work in proportion to the chosen patches, not to all.
+template <int TY>
+__global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* __restrict__ Zhat_b,
+                                                         const float* __restrict__ y_b,
+                                                         const float* __restrict__ bvals, int it,
+                                                         float* __restrict__ xnew_b,
+                                                         const int32_t* __restrict__ labels_b,
+                                                         int K) {
+  constexpr int WR = TY + 7;          // patch rows of the window
+  constexpr int WIN = WR * NP;        // patches of the window
+  constexpr int CH = 64;              // patches staged at a time
+  constexpr int NR = TY / 4;          // pixel rows per thread
+  __shared__ int16_t plist[WIN];      // chosen patches: window row * NP + column
+  __shared__ float zs[CH * PITCH];
+  __shared__ int wcnt[4], wpre[4];
+  __shared__ int ntot;
+  const int G8 = gridDim.x;
+  const int lin = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
+  if (lin >= bt.n_ola) return;
+  const ImgDesc d = bt.d[bt.ola_img[lin]];
+  const int H = d.H, W = d.W;
+  const int Hp = H - 7, Wp = W - 7;
+  const float b = bvals[d.slot0 + it];
+  const float* Zhat = Zhat_b + (size_t)d.np * kP;
+  const int32_t* labels = labels_b + d.np;
+  const float* y = y_b + d.px;
+  float* xnew = xnew_b + d.px;
+  const int nty = (H + TY - 1) / TY;
+  const int lt = lin - d.ola0;
+  const int x0 = (lt / nty) * TX, y0 = (lt % nty) * TY;
+  const int tx = threadIdx.x & 63, j = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rfirst = y0 - 7, cfirst = x0 - 7;
+
+  // 1. the window's chosen patches, raster order
+  if (threadIdx.x == 0) ntot = 0;
+  __syncthreads();
+  for (int base = 0; base < WIN; base += 256) {
+    const int w = base + threadIdx.x;
+    bool in = false;
+    if (w < WIN) {
+      const int r = rfirst + w / NP, c = cfirst + w % NP;
+      in = r >= 0 && r < Hp && c >= 0 && c < Wp && labels[(size_t)r * Wp + c] < K;
+    }
+    const uint64_t m = __ballot(in);
+    if (lane == 0) wcnt[wave] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int run = ntot;
+      for (int v = 0; v < 4; ++v) {
+        wpre[v] = run;
+        run += wcnt[v];
+      }
+      ntot = run;
+    }
+    __syncthreads();
+    if (in) plist[wpre[wave] + __popcll(m & ((1ull << lane) - 1ull))] = (int16_t)w;
+    __syncthreads();
+  }
+  const int n = ntot;
+
+  // 2. accumulate, CH patches at a time
+  float acc[NR], cnt[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) acc[i] = cnt[i] = 0.f;
+  const int xx = x0 + tx;
+  for (int c0 = 0; c0 < n; c0 += CH) {
+    const int m = min(CH, n - c0);
+    // stage: 16 float4 per patch
+    for (int e = threadIdx.x; e < m * 16; e += 256) {
+      const int q = e >> 4, f = e & 15;
+      const int w = plist[c0 + q];
+      const int r = rfirst + w / NP, c = cfirst + w % NP;
+      const float4 v = *reinterpret_cast<const float4*>(Zhat + ((size_t)r * Wp + c) * kP + 4 * f);
+      float* zp = zs + q * PITCH + 4 * f;
+      zp[0] = v.x;
+      zp[1] = v.y;
+      zp[2] = v.z;
+      zp[3] = v.w;
+    }
+    __syncthreads();
+    for (int q = 0; q < m; ++q) {
+      const int w = plist[c0 + q];
+      const int r = rfirst + w / NP, c = cfirst + w % NP;
+      const int dx = xx - c;
+      if (dx < 0 || dx >= 8) continue;
+      const float* zp = zs + q * PITCH + dx;
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int dy = y0 + j + 4 * i - r;
+        if (dy >= 0 && dy < 8) {
+          acc[i] += zp[8 * dy];
+          cnt[i] += 1.f;
+        }
+      }
+    }
+    __syncthreads();  // zs is restaged
+  }
+
+  // 3. average and image update
+  const float onepb = 1.f + b;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int yy = y0 + j + 4 * i;
+    if (yy < H && xx < W) {
+      const size_t o = (size_t)yy * W + xx;
+      xnew[o] = (y[o] + b * (acc[i] / cnt[i])) / onepb;
     }
   }
 }
@@ -170,15 +248,27 @@ template <bool SUB>
 static void launch_ola_rows(const Batch& b, int blocks, const float* Zhat, const float* y,
                             const float* bvals, int t, float* xnew, const int32_t* labels, int K,
                             hipStream_t st) {
+  if (SUB) {
+    if (b.ola_rows == 16)
+      hipLaunchKernelGGL(ola_subset_kernel<16>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
+                         t, xnew, labels, K);
+    else if (b.ola_rows == 64)
+      hipLaunchKernelGGL(ola_subset_kernel<64>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
+                         t, xnew, labels, K);
+    else
+      hipLaunchKernelGGL(ola_subset_kernel<32>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
+                         t, xnew, labels, K);
+    return;
+  }
   if (b.ola_rows == 16)
-    hipLaunchKernelGGL((ola_update_kernel<16, SUB>), dim3(blocks), dim3(256), 0, st, b, Zhat, y,
-                       bvals, t, xnew, labels, K);
+    hipLaunchKernelGGL(ola_update_kernel<16>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals, t,
+                       xnew);
   else if (b.ola_rows == 64)
-    hipLaunchKernelGGL((ola_update_kernel<64, SUB>), dim3(blocks), dim3(256), 0, st, b, Zhat, y,
-                       bvals, t, xnew, labels, K);
+    hipLaunchKernelGGL(ola_update_kernel<64>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals, t,
+                       xnew);
   else
-    hipLaunchKernelGGL((ola_update_kernel<32, SUB>), dim3(blocks), dim3(256), 0, st, b, Zhat, y,
-                       bvals, t, xnew, labels, K);
+    hipLaunchKernelGGL(ola_update_kernel<32>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals, t,
+                       xnew);
 }
 
 hipError_t launch_ola_batch(const Batch& b, const float* Zhat, const float* y,
