@@ -215,9 +215,10 @@ def main():
             # algorithmic bytes: the chosen patches' estimates, y and x
             npat = n_sub.get(name, Np)
             gbs = (256.0 * npat + 8.0 * H * W) / (pr["dominant_ms"] / 1e3) / 1e9
-            return {"bound": "hbm", "kernel": "ola_update_kernel", "achieved": round(gbs, 1),
+            kern = ("ola_subset_kernel<32>" if "jitter" in name else "ola_update_kernel<32>")
+            return {"bound": "hbm", "kernel": kern, "achieved": round(gbs, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                    "traffic": None}
+                    "traffic": measured_traffic(kern) if args.size == 1024 else None}
         kern, peak = {"select": (sel_kernel, sel_peak),
                       "propose": ("propose_bf16_kernel", MFMA_BF16_PEAK_TFLOPS),
                       "wiener": ("wiener_f32_kernel", MFMA_F32_PEAK_TFLOPS)}.get(
@@ -386,8 +387,11 @@ def run_batch(F, torch, np, g0, gf, batch, names, steps, args_jitter):
     base = rows["fp32"]
     base_psnr = np.asarray(base["psnr_db"])
     for p in names:
+        # per image: fp32 PSNR minus the path's (positive: the path loses)
         d = base_psnr - np.asarray(rows[p]["psnr_db"])
         rows[p]["dpsnr_vs_fp32_max_abs_db"] = round(float(np.abs(d).max()), 4)
+        rows[p]["dpsnr_vs_fp32_min_max_db"] = [round(float(d.min()), 4), round(float(d.max()), 4)]
+        rows[p]["images_within_0.05db"] = int(np.sum(np.abs(d) <= 0.05))
         rows[p]["speedup_vs_plain_fp32"] = round(rows[p]["mpix_s"] / base["mpix_s"], 3)
         rows[p]["psnr_db_mean"] = round(float(np.mean(rows[p].pop("psnr_db"))), 4)
     return {"workload": f"{len(batch)} images, 256x256 to 1024x1536, {mpix:.2f} Mpixels, "

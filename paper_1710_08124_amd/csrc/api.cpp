@@ -31,6 +31,13 @@ __global__ void zero_i32_kernel(int32_t* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
 }
+
+// two buffers zeroed by one launch: p[0..n) and q[0..m), m <= n
+__global__ void zero2_i32_kernel(int32_t* p, int n, int32_t* q, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+  if (i < m) q[i] = 0;
+}
 }  // namespace
 
 namespace fepll {
@@ -550,10 +557,9 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
   {
     // the chosen patches of every image (stage 8: subset)
     StageTimer tm(g, 8, st);
-    hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n);
-    HIPX(hipGetLastError());
-    hipLaunchKernelGGL(zero_i32_kernel, dim3((b.n + 255) / 256), dim3(256), 0, st, g->jcount,
-                       b.n);
+    // (n_patches >= images: one launch clears both)
+    hipLaunchKernelGGL(zero2_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n,
+                       g->jcount, b.n);
     HIPX(hipGetLastError());
     for (int i = 0; i < b.n; ++i) {
       const ImgDesc& d = g->hd[i];

@@ -147,8 +147,7 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
   constexpr int NR = TY / 4;          // pixel rows per thread
   __shared__ int16_t plist[WIN];      // chosen patches: window row * NP + column
   __shared__ float zs[CH * PITCH];
-  __shared__ int wcnt[4], wpre[4];
-  __shared__ int ntot;
+  __shared__ int wcnt[4];
   const int G8 = gridDim.x;
   const int lin = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
   if (lin >= bt.n_ola) return;
@@ -167,32 +166,37 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rfirst = y0 - 7, cfirst = x0 - 7;
 
-  // 1. the window's chosen patches, raster order
-  if (threadIdx.x == 0) ntot = 0;
-  __syncthreads();
-  for (int base = 0; base < WIN; base += 256) {
-    const int w = base + threadIdx.x;
-    bool in = false;
-    if (w < WIN) {
-      const int r = rfirst + w / NP, c = cfirst + w % NP;
-      in = r >= 0 && r < Hp && c >= 0 && c < Wp && labels[(size_t)r * Wp + c] < K;
-    }
-    const uint64_t m = __ballot(in);
-    if (lane == 0) wcnt[wave] = __popcll(m);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int run = ntot;
-      for (int v = 0; v < 4; ++v) {
-        wpre[v] = run;
-        run += wcnt[v];
-      }
-      ntot = run;
-    }
-    __syncthreads();
-    if (in) plist[wpre[wave] + __popcll(m & ((1ull << lane) - 1ull))] = (int16_t)w;
-    __syncthreads();
+  // 1. the window's chosen patches, raster order: thread t tests window
+  // entries t * PT .. t * PT + PT - 1 (all its label loads in flight at
+  // once), then a block-wide exclusive scan of the counts places them
+  constexpr int PT = (WIN + 255) / 256;
+  bool in[PT];
+  int mine = 0;
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int w = threadIdx.x * PT + u;
+    const int r = rfirst + w / NP, c = cfirst + w % NP;
+    in[u] = w < WIN && r >= 0 && r < Hp && c >= 0 && c < Wp &&
+            labels[(size_t)r * Wp + c] < K;
   }
-  const int n = ntot;
+#pragma unroll
+  for (int u = 0; u < PT; ++u) mine += in[u] ? 1 : 0;
+  int incl = mine;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off);
+    if (lane >= off) incl += v;
+  }
+  if (lane == 63) wcnt[wave] = incl;
+  __syncthreads();
+  int pos = incl - mine;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) pos += (v < wave) ? wcnt[v] : 0;
+  const int n = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+#pragma unroll
+  for (int u = 0; u < PT; ++u)
+    if (in[u]) plist[pos++] = (int16_t)(threadIdx.x * PT + u);
+  __syncthreads();
 
   // 2. accumulate, CH patches at a time
   float acc[NR], cnt[NR];
