@@ -247,3 +247,54 @@ def mlp_init(K: int = 200, seed: int = 700, d_in: int = 65, hidden: int = 256):
         p[f"W{i}"] = g.uniform(-a, a, (o, n))
         p[f"b{i}"] = np.zeros(o)
     return p
+
+
+# ----------------------------------------------------------- deblurring
+
+def blur_kernel(size: int = 9, seed: int = 800, steps: int = 60):
+    """A seeded motion-blur-like kernel (size x size, odd, centred, sums to
+    1): the visits of a random walk with momentum started at the centre,
+    smoothed by a 3-tap binomial filter.  Stands in for the blur kernel of
+    the paper's deblurring experiments, which is not available here."""
+    if size % 2 == 0:
+        raise ValueError("size must be odd")
+    g = rng(seed)
+    k = np.zeros((size, size))
+    c = size // 2
+    p = np.array([float(c), float(c)])
+    v = g.normal(size=2)
+    v /= np.linalg.norm(v)
+    for _ in range(steps):
+        v = 0.8 * v + 0.45 * g.normal(size=2)
+        v /= max(np.linalg.norm(v), 1e-9)
+        p = np.clip(p + 0.5 * v, 0, size - 1)
+        k[int(round(p[0])), int(round(p[1]))] += 1.0
+    b = np.array([0.25, 0.5, 0.25])
+    k = np.apply_along_axis(lambda r: np.convolve(r, b, mode="same"), 0, k)
+    k = np.apply_along_axis(lambda r: np.convolve(r, b, mode="same"), 1, k)
+    return k / k.sum()
+
+
+def blurred(x: np.ndarray, h: np.ndarray, sigma: float, seed: int):
+    """y = h (*) x + n: periodic convolution of x with the centred kernel h
+    (entry (u, v) of h weighs x[i - (u - c), j - (v - c)]), then Gaussian
+    noise of std sigma (seeded)."""
+    H, W = x.shape
+    kh, kw = h.shape
+    e = np.zeros((H, W))
+    for u in range(kh):
+        for v in range(kw):
+            e[(u - kh // 2) % H, (v - kw // 2) % W] += h[u, v]
+    y = np.real(np.fft.ifft2(np.fft.fft2(x) * np.fft.fft2(e)))
+    return y + sigma * rng(seed).standard_normal((H, W))
+
+
+def config_deblur(size: int = 512, sigma: float = 0.5, ksize: int = 9):
+    """The deblurring workload: the size^2 test image blurred by a 9x9
+    seeded motion kernel, noise sigma 0.5 (the paper's deblurring noise
+    level), K = 200 GMM (seed 12)."""
+    x = test_image(size, size, 104)
+    h = blur_kernel(ksize, 801)
+    y = blurred(x, h, sigma, 206)
+    U, lam, w = gmm(200, 12)
+    return dict(x=x, y=y, h=h, sigma=sigma, U=U, lam=lam, w=w)
