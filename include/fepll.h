@@ -167,15 +167,34 @@ fepll_status fepll_gmm_flat_tail(fepll_gmm* g, double rho, int32_t* ranks);
 /* Release a handle (NULL is a no-op).  Synchronises the device first. */
 void fepll_gmm_destroy(fepll_gmm* g);
 
+/* Degradation operator A of the restoration problem (Sec. 2: y = A x + n). */
+enum { FEPLL_OP_IDENTITY = 0, FEPLL_OP_CONVOLUTION = 1 };
+typedef struct {
+  int32_t kind;         /* FEPLL_OP_IDENTITY or FEPLL_OP_CONVOLUTION          */
+  /* FEPLL_OP_CONVOLUTION: periodic convolution with a centred kernel,
+   * (A x)[i, j] = sum_{u,v} kernel[u * kw + v] x[i - (u - kh/2), j - (v - kw/2)]
+   * (indices modulo the image size); kh, kw odd, at most the image's
+   * height and width; kernel: host float32, finite.                        */
+  int32_t kh, kw;
+  const float* kernel;
+} fepll_operator;
+
 /*
- * Restore y by T iterations of Alg. 1 (denoising: A = identity).
- *   y:      noisy image (host or device).  Finite values only (EINVAL).
- *   H:      the degradation operator A; only NULL (identity) is supported,
- *           anything else returns EUNSUPPORTED.
+ * Restore y by T iterations of Alg. 1.
+ *   y:      degraded image (host or device).  Finite values only (EINVAL).
+ *   H:      the degradation operator A: NULL or FEPLL_OP_IDENTITY for
+ *           denoising; FEPLL_OP_CONVOLUTION for deblurring, where the image
+ *           estimation (A^t A + beta sigma^2 I)^-1 (A^t y + beta sigma^2 x~)
+ *           is solved with float64 FFTs, the default schedule is
+ *           beta = lambda sigma^-2 {1, 4, 8, 16, 32} with lambda =
+ *           min(|A^t A|_F^2 / (N |A|_2^2), 250 sigma^2) and the default
+ *           start (options.init NULL) is (A^t A + 0.2 sigma^2 / lambda Lap)^-1
+ *           A^t y, Lap the periodic 5-point Laplacian (Sec. 6, "Parameter
+ *           settings"); runs without graph capture.
  *   sigma:  noise standard deviation on the image's scale, > 0.
  *   beta_schedule: T absolute values of beta (the HQS coupling weight of
- *           eq:qhs), each > 0; NULL = {1, 4, 8, 16, 32} / sigma^2 with T = 5
- *           (T must then be 5 or 0, where 0 means 5).
+ *           eq:qhs), each > 0; NULL = {1, 4, 8, 16, 32} / sigma^2 (denoising,
+ *           lambda = 1) with T = 5 (T must then be 5 or 0, where 0 means 5).
  *   T:      1..16 iterations.
  *   out:    H x W output (host or device); may alias y.
  *   opt:    NULL = defaults.
@@ -185,9 +204,9 @@ void fepll_gmm_destroy(fepll_gmm* g);
  * Host images are copied in and out and the call returns after the result
  * is in `out`.  Device images: the work is enqueued and the call returns.
  */
-fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* H, double sigma,
-                           const double* beta_schedule, int32_t T, fepll_image* out,
-                           const fepll_options* opt, int32_t* labels_out);
+fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const fepll_operator* H,
+                           double sigma, const double* beta_schedule, int32_t T,
+                           fepll_image* out, const fepll_options* opt, int32_t* labels_out);
 
 /*
  * Restore n independent images, each by the default schedule (T = 5,

@@ -44,6 +44,12 @@ class Options(ctypes.Structure):
                 ("seed", ctypes.c_uint64)]
 
 
+class Operator(ctypes.Structure):
+    """fepll_operator: the degradation A (kind 0 identity, 1 periodic
+    convolution with a centred odd-sized float32 kernel)."""
+    _fields_ = [("kind", c_int32), ("kh", c_int32), ("kw", c_int32), ("kernel", c_void_p)]
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("est_blocks", c_int32), ("wiener_blocks", c_int32), ("ola_rows", c_int32),
                 ("reserved", c_int32)]
@@ -270,12 +276,14 @@ def profile(gmm: GMM):
 
 def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
             recheck=True, return_labels=False, out=None, profile=False, proposal=False,
-            top_m=8, margin=0.5, jitter=0, seed=0):
+            top_m=8, margin=0.5, jitter=0, seed=0, blur=None):
     """Denoise y (2-D float32 torch tensor, CUDA or CPU, or numpy array).
 
     betas: absolute beta values (default {1,4,8,16,32}/sigma^2).
     jitter: 0, or the grid spacing s of the jittered patch subsampling
     (Sec. 3.3) with its Philox seed.
+    blur: None (denoising), or the centred odd-sized kernel of a periodic
+    convolution A (deblurring; the Sec. 6 schedule and start by default).
     Returns the restored image (same kind and device as y) and, with
     return_labels, the (T, Np) int32 labels of every iteration (K for the
     patches an iteration did not choose).
@@ -303,7 +311,15 @@ def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
         else:
             labels = np.empty((Tn, Np), dtype=np.int32)
         lptr = _ptr(labels)
-    _check(lib().fepll_restore(gmm.handle, ctypes.byref(yi), None, float(sigma), bptr, T,
+    op = None
+    if blur is not None:
+        k = np.ascontiguousarray(blur, dtype=np.float32)
+        if k.ndim != 2:
+            raise ValueError("blur must be a 2-D kernel")
+        op = Operator(1, k.shape[0], k.shape[1], k.ctypes.data)
+        op._keep = k
+    _check(lib().fepll_restore(gmm.handle, ctypes.byref(yi),
+                               ctypes.byref(op) if op is not None else None, float(sigma), bptr, T,
                                ctypes.byref(oi), ctypes.byref(o), lptr))
     return (out, labels) if return_labels else out
 

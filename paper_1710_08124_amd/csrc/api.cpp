@@ -5,6 +5,7 @@
 // reprojection + image estimation), run eagerly or replayed from a captured
 // HIP graph.  A single restoration is a batch of one.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -97,6 +98,19 @@ struct fepll_gmm {
   int32_t* jcount = nullptr;
   size_t jpart_cap = 0;
   float4* jpart = nullptr;  // partial results of the component-split list selection
+  // deblurring (periodic convolution): float64 FFT plans and spectra of the
+  // last image size
+  struct Deblur {
+    int H = 0, W = 0;
+    hipfftHandle fwd = 0, inv = 0;
+    bool plans = false;
+    size_t n_cap = 0, m_cap = 0;
+    double* r = nullptr;      // H x W real
+    double2* Hh = nullptr;    // half spectrum of the kernel
+    double2* AtY = nullptr;   // conj(Hh) Yh
+    double* a2 = nullptr;     // |Hh|^2
+    double2* X = nullptr;     // scratch spectrum
+  } db;
   float* ybuf = nullptr;
   float* xa = nullptr;
   float* xb = nullptr;
@@ -666,8 +680,24 @@ fepll_status select_batch(fepll_gmm* g, int t, const fepll_options& o, const flo
 // T iterations of Alg. 1 over the planned batch, from g->xa (y in g->ybuf);
 // *result receives the buffer holding the restored images.  labels_out
 // (single image only): per-iteration copies of the labels.
+// Image estimation of a periodic convolution A on the single image of the
+// plan: x (float, H x W) holds x~ on entry and the estimate on return.
+fepll_status deblur_update(fepll_gmm* g, float* x, double b, hipStream_t st) {
+  auto& D = g->db;
+  const int n = D.H * D.W, m = D.H * (D.W / 2 + 1);
+  HIPX(launch_f2d(x, D.r, n, st));
+  if (hipfftExecD2Z(D.fwd, D.r, reinterpret_cast<hipfftDoubleComplex*>(D.X)) != HIPFFT_SUCCESS)
+    return fail(FEPLL_EDEVICE, "hipfftExecD2Z failed");
+  HIPX(launch_spec_update(D.AtY, D.a2, D.X, m, b, st));
+  if (hipfftExecZ2D(D.inv, reinterpret_cast<hipfftDoubleComplex*>(D.X), D.r) != HIPFFT_SUCCESS)
+    return fail(FEPLL_EDEVICE, "hipfftExecZ2D failed");
+  HIPX(launch_d2f_scale(D.r, x, n, 1.0 / n, st));
+  return FEPLL_OK;
+}
+
 fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* labels_out,
-                     hipMemcpyKind lkind, float** result, hipStream_t st) {
+                     hipMemcpyKind lkind, float** result, hipStream_t st,
+                     const std::vector<double>* deblur_b = nullptr) {
   const Batch& b = g->batch;
   float* xc = g->xa;
   float* xn = g->xb;
@@ -690,7 +720,11 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     {
       StageTimer tm(g, 4, st);
       HIPX(launch_ola_batch(b, g->Zhat, g->ybuf, g->bvals, t, xn,
-                            o.jitter ? g->labels : nullptr, g->K, st));
+                            o.jitter ? g->labels : nullptr, g->K, deblur_b ? 1 : 0, st));
+      if (deblur_b) {
+        fepll_status s2 = deblur_update(g, xn, (*deblur_b)[t], st);
+        if (s2 != FEPLL_OK) return s2;
+      }
     }
     std::swap(xc, xn);
   }
@@ -764,6 +798,83 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
   g->gkey = std::move(key);
   *result = res;
   HIPX(hipGraphLaunch(g->gexec, st));
+  return FEPLL_OK;
+}
+
+// Plans and spectrum buffers of the deblurring for an H x W image.
+fepll_status ensure_deblur(fepll_gmm* g, int H, int W, hipStream_t st) {
+  auto& D = g->db;
+  const size_t n = (size_t)H * W, m = (size_t)H * (W / 2 + 1);
+  if (g->used) HIPX(hipStreamSynchronize(g->last_stream));
+  if (!D.plans || D.H != H || D.W != W) {
+    if (D.plans) {
+      (void)hipfftDestroy(D.fwd);
+      (void)hipfftDestroy(D.inv);
+      D.plans = false;
+    }
+    if (hipfftPlan2d(&D.fwd, H, W, HIPFFT_D2Z) != HIPFFT_SUCCESS)
+      return fail(FEPLL_EDEVICE, "hipfftPlan2d (D2Z) failed");
+    if (hipfftPlan2d(&D.inv, H, W, HIPFFT_Z2D) != HIPFFT_SUCCESS) {
+      (void)hipfftDestroy(D.fwd);
+      return fail(FEPLL_EDEVICE, "hipfftPlan2d (Z2D) failed");
+    }
+    D.plans = true;
+    D.H = H;
+    D.W = W;
+  }
+  if (hipfftSetStream(D.fwd, st) != HIPFFT_SUCCESS || hipfftSetStream(D.inv, st) != HIPFFT_SUCCESS)
+    return fail(FEPLL_EDEVICE, "hipfftSetStream failed");
+  if (n > D.n_cap || !D.r) {
+    dfree(D.r);
+    D.n_cap = 0;
+    HIPX(dalloc(&D.r, n));
+    D.n_cap = n;
+  }
+  if (m > D.m_cap || !D.Hh) {
+    dfree(D.Hh);
+    dfree(D.AtY);
+    dfree(D.a2);
+    dfree(D.X);
+    D.m_cap = 0;
+    HIPX(dalloc(&D.Hh, m));
+    HIPX(dalloc(&D.AtY, m));
+    HIPX(dalloc(&D.a2, m));
+    HIPX(dalloc(&D.X, m));
+    D.m_cap = m;
+  }
+  return FEPLL_OK;
+}
+
+// The kernel's spectrum (into D.Hh) and lambda = min(|A^t A|_F^2 /
+// (N |A|_2^2), 250 sigma^2) over the full spectrum (Hermitian half:
+// the columns other than 0 and W/2 stand for two), on the host in float64.
+fepll_status deblur_spectrum(fepll_gmm* g, const fepll_operator* op, double sigma,
+                             double* lambda, hipStream_t st) {
+  auto& D = g->db;
+  const int H = D.H, W = D.W, Wh = W / 2 + 1;
+  std::vector<double> e((size_t)H * W, 0.0);
+  for (int u = 0; u < op->kh; ++u)
+    for (int v = 0; v < op->kw; ++v) {
+      const int r = ((u - op->kh / 2) % H + H) % H, c = ((v - op->kw / 2) % W + W) % W;
+      e[(size_t)r * W + c] += (double)op->kernel[u * op->kw + v];
+    }
+  HIPX(hipMemcpyAsync(D.r, e.data(), sizeof(double) * e.size(), hipMemcpyHostToDevice, st));
+  if (hipfftExecD2Z(D.fwd, D.r, reinterpret_cast<hipfftDoubleComplex*>(D.Hh)) != HIPFFT_SUCCESS)
+    return fail(FEPLL_EDEVICE, "hipfftExecD2Z failed");
+  std::vector<double2> h((size_t)H * Wh);
+  HIPX(hipMemcpyAsync(h.data(), D.Hh, sizeof(double2) * h.size(), hipMemcpyDeviceToHost, st));
+  HIPX(hipStreamSynchronize(st));
+  double s4 = 0.0, mx = 0.0;
+  for (int k = 0; k < H; ++k)
+    for (int l = 0; l < Wh; ++l) {
+      const double2 z = h[(size_t)k * Wh + l];
+      const double a = z.x * z.x + z.y * z.y;
+      const double wgt = (l == 0 || 2 * l == W) ? 1.0 : 2.0;
+      s4 += wgt * a * a;
+      mx = std::max(mx, a);
+    }
+  if (!(mx > 0.0)) return fail(FEPLL_EINVAL, "H: the blur kernel's spectrum is zero");
+  *lambda = std::min(s4 / ((double)H * W) / mx, 250.0 * sigma * sigma);
   return FEPLL_OK;
 }
 
@@ -916,6 +1027,15 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->jlist);
   dfree(g->jcount);
   dfree(g->jpart);
+  if (g->db.plans) {
+    (void)hipfftDestroy(g->db.fwd);
+    (void)hipfftDestroy(g->db.inv);
+  }
+  dfree(g->db.r);
+  dfree(g->db.Hh);
+  dfree(g->db.AtY);
+  dfree(g->db.a2);
+  dfree(g->db.X);
   dfree(g->phist);
   dfree(g->pseg);
   dfree(g->pWb);
@@ -926,15 +1046,25 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   delete g;
 }
 
-fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, double sigma,
-                           const double* beta_schedule, int32_t T, fepll_image* out,
-                           const fepll_options* opt, int32_t* labels_out) {
+fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const fepll_operator* Hop,
+                           double sigma, const double* beta_schedule, int32_t T,
+                           fepll_image* out, const fepll_options* opt, int32_t* labels_out) {
   g_err.clear();
   if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
   fepll_status s;
   if ((s = check_image(y, "y")) != FEPLL_OK) return s;
   if ((s = check_image(out, "out")) != FEPLL_OK) return s;
-  if (Hop) return fail(FEPLL_EUNSUPPORTED, "only the identity degradation (H = NULL) is supported");
+  const bool conv = Hop && Hop->kind == FEPLL_OP_CONVOLUTION;
+  if (Hop && Hop->kind != FEPLL_OP_IDENTITY && !conv)
+    return fail(FEPLL_EINVAL, "H->kind must be FEPLL_OP_IDENTITY or FEPLL_OP_CONVOLUTION");
+  if (conv) {
+    if (!Hop->kernel) return fail(FEPLL_EINVAL, "H->kernel is NULL");
+    if (Hop->kh < 1 || Hop->kw < 1 || Hop->kh % 2 == 0 || Hop->kw % 2 == 0 ||
+        Hop->kh > y->height || Hop->kw > y->width)
+      return fail(FEPLL_EINVAL, "H: kernel sizes must be odd and at most the image's");
+    for (int i = 0; i < Hop->kh * Hop->kw; ++i)
+      if (!std::isfinite(Hop->kernel[i])) return fail(FEPLL_EINVAL, "H: non-finite kernel entry");
+  }
   if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(FEPLL_EINVAL, "sigma must be > 0");
   if (out->height != y->height || out->width != y->width)
     return fail(FEPLL_EINVAL, "out must have the shape of y");
@@ -942,10 +1072,19 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, 
   fepll_options_default(&o);
   if (opt) o = *opt;
   if ((s = check_opt(g, &o)) != FEPLL_OK) return s;
+  const int H = y->height, W = y->width;
+  hipStream_t st = (hipStream_t)o.stream;
+  // deblurring: the kernel's spectrum and lambda (Sec. 6) before the schedule
+  double lambda = 1.0;
+  if (conv) {
+    if ((s = use_stream(g, st)) != FEPLL_OK) return s;
+    if ((s = ensure_deblur(g, H, W, st)) != FEPLL_OK) return s;
+    if ((s = deblur_spectrum(g, Hop, sigma, &lambda, st)) != FEPLL_OK) return s;
+  }
   std::vector<double> betas;
   if (!beta_schedule) {
     if (T != 0 && T != kDefaultT) return fail(FEPLL_EINVAL, "default schedule has T = 5");
-    for (int t = 0; t < kDefaultT; ++t) betas.push_back(kDefaultB[t] / (sigma * sigma));
+    for (int t = 0; t < kDefaultT; ++t) betas.push_back(lambda * kDefaultB[t] / (sigma * sigma));
   } else {
     if (T < 1 || T > kMaxT) return fail(FEPLL_EINVAL, "T must be in 1..16");
     for (int t = 0; t < T; ++t) {
@@ -963,8 +1102,6 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, 
   }
   if ((s = host_finite(y, "y")) != FEPLL_OK) return s;
 
-  const int H = y->height, W = y->width;
-  hipStream_t st = (hipStream_t)o.stream;
   if ((s = use_stream(g, st)) != FEPLL_OK) return s;
   g->profiling = o.profile != 0;
   std::vector<float> bvals;
@@ -975,10 +1112,31 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const void* Hop, 
 
   HIPX(copy_in(g->ybuf, y, st));
   if (o.init) HIPX(copy_in(g->xa, o.init, st));
-  else HIPX(hipMemcpyAsync(g->xa, g->ybuf, sizeof(float) * H * W, hipMemcpyDeviceToDevice, st));
+  else if (!conv)
+    HIPX(hipMemcpyAsync(g->xa, g->ybuf, sizeof(float) * H * W, hipMemcpyDeviceToDevice, st));
 
   float* res = nullptr;
-  if (o.profile || labels_out)
+  if (conv) {
+    // A^t y once; the Sec. 6 start unless options.init is given; then the
+    // iterations with the Fourier image estimation (eager: no capture)
+    auto& D = g->db;
+    const int n = H * W, m = H * (W / 2 + 1);
+    HIPX(launch_f2d(g->ybuf, D.r, n, st));
+    if (hipfftExecD2Z(D.fwd, D.r, reinterpret_cast<hipfftDoubleComplex*>(D.X)) != HIPFFT_SUCCESS)
+      return fail(FEPLL_EDEVICE, "hipfftExecD2Z failed");
+    HIPX(launch_spec_prep(D.Hh, D.X, D.AtY, D.a2, m, st));
+    if (!o.init) {
+      HIPX(launch_spec_init(D.AtY, D.a2, D.X, H, W, 0.2 * sigma * sigma / lambda, st));
+      if (hipfftExecZ2D(D.inv, reinterpret_cast<hipfftDoubleComplex*>(D.X), D.r) !=
+          HIPFFT_SUCCESS)
+        return fail(FEPLL_EDEVICE, "hipfftExecZ2D failed");
+      HIPX(launch_d2f_scale(D.r, g->xa, n, 1.0 / n, st));
+    }
+    std::vector<double> bb;
+    for (double bt : betas) bb.push_back(bt * sigma * sigma);
+    s = run_hqs(g, T, o, labels_out,
+                y->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, &res, st, &bb);
+  } else if (o.profile || labels_out)
     s = run_hqs(g, T, o, labels_out,
                 y->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, &res, st);
   else

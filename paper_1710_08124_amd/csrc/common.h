@@ -160,9 +160,21 @@ hipError_t launch_wiener_batch(const Batch& b, const float* x, const float* Wt, 
 // subset_labels: NULL (every patch), or the packed labels, a patch being in
 // the subset when its label is below K (the average then runs over the
 // subset's patches only).
+// raw: write x~ itself (the image estimation of an operator A follows).
 hipError_t launch_ola_batch(const Batch& b, const float* Zhat, const float* y,
                             const float* bvals, int t, float* xnew, const int32_t* subset_labels,
-                            int K, hipStream_t st);
+                            int K, int raw, hipStream_t st);
+
+// Deblurring (periodic convolution A), float64 half spectra of m = H (W/2+1)
+// complex entries (double2): see deblur.hip.
+hipError_t launch_f2d(const float* in, double* out, int n, hipStream_t st);
+hipError_t launch_d2f_scale(const double* in, float* out, int n, double scale, hipStream_t st);
+hipError_t launch_spec_prep(const void* Hh, const void* Yh, void* AtY, double* a2, int m,
+                            hipStream_t st);
+hipError_t launch_spec_update(const void* AtY, const double* a2, void* X, int m, double b,
+                              hipStream_t st);
+hipError_t launch_spec_init(const void* AtY, const double* a2, void* X, int H, int W, double c,
+                            hipStream_t st);
 
 // Jittered subsampling (Sec. 3.3) of one image, iteration t: flags (Np,
 // zeroed before) of the chosen patches set to 1; then every flagged patch

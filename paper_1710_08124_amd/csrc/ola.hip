@@ -1,6 +1,8 @@
 // Patch reprojection + image estimation (Alg. 1), fused:
 //   x~ = (sum_i P_i^t P_i)^-1 sum_i P_i^t z^_i      (average of overlapping patches)
 //   x  = (y + b x~) / (1 + b),  b = beta sigma^2     (A = identity)
+// (raw: x~ itself, for an operator A whose image estimation follows in the
+// Fourier basis, deblur.hip)
 //
 // A gather, not a scatter: each output pixel sums the (up to 64) patch
 // entries that cover it in a fixed order -- patch rows ascending (dy
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
                                                          const float* __restrict__ Zhat_b,
                                                          const float* __restrict__ y_b,
                                                          const float* __restrict__ bvals, int it,
-                                                         float* __restrict__ xnew_b) {
+                                                         float* __restrict__ xnew_b, int raw) {
   __shared__ float buf[2][ROW];
   const int G8 = gridDim.x;  // a multiple of 8
   const int lin = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
         const float nrow = (float)(min(ya, H - 8) - max(0, ya - 7) + 1);
         const float xt = acc_a / (nrow * ncol);
         const size_t o = (size_t)ya * W + xx;
-        xnew[o] = (y[o] + b * xt) / onepb;
+        xnew[o] = raw ? xt : (y[o] + b * xt) / onepb;
       }
       ya += 4;
       acc_a = acc_b;
@@ -140,7 +142,7 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
                                                          const float* __restrict__ bvals, int it,
                                                          float* __restrict__ xnew_b,
                                                          const int32_t* __restrict__ labels_b,
-                                                         int K) {
+                                                         int K, int raw) {
   constexpr int WR = TY + 7;          // patch rows of the window
   constexpr int WIN = WR * NP;        // patches of the window
   constexpr int CH = 64;              // patches staged at a time
@@ -243,7 +245,8 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
     const int yy = y0 + j + 4 * i;
     if (yy < H && xx < W) {
       const size_t o = (size_t)yy * W + xx;
-      xnew[o] = (y[o] + b * (acc[i] / cnt[i])) / onepb;
+      const float xt = acc[i] / cnt[i];
+      xnew[o] = raw ? xt : (y[o] + b * xt) / onepb;
     }
   }
 }
@@ -251,38 +254,38 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
 template <bool SUB>
 static void launch_ola_rows(const Batch& b, int blocks, const float* Zhat, const float* y,
                             const float* bvals, int t, float* xnew, const int32_t* labels, int K,
-                            hipStream_t st) {
+                            int raw, hipStream_t st) {
   if (SUB) {
     if (b.ola_rows == 16)
       hipLaunchKernelGGL(ola_subset_kernel<16>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
-                         t, xnew, labels, K);
+                         t, xnew, labels, K, raw);
     else if (b.ola_rows == 64)
       hipLaunchKernelGGL(ola_subset_kernel<64>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
-                         t, xnew, labels, K);
+                         t, xnew, labels, K, raw);
     else
       hipLaunchKernelGGL(ola_subset_kernel<32>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
-                         t, xnew, labels, K);
+                         t, xnew, labels, K, raw);
     return;
   }
   if (b.ola_rows == 16)
     hipLaunchKernelGGL(ola_update_kernel<16>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals, t,
-                       xnew);
+                       xnew, raw);
   else if (b.ola_rows == 64)
     hipLaunchKernelGGL(ola_update_kernel<64>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals, t,
-                       xnew);
+                       xnew, raw);
   else
     hipLaunchKernelGGL(ola_update_kernel<32>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals, t,
-                       xnew);
+                       xnew, raw);
 }
 
 hipError_t launch_ola_batch(const Batch& b, const float* Zhat, const float* y,
                             const float* bvals, int t, float* xnew, const int32_t* subset_labels,
-                            int K, hipStream_t st) {
+                            int K, int raw, hipStream_t st) {
   const int blocks = (b.n_ola + 7) & ~7;  // whole rounds over the 8 XCDs
   if (subset_labels)
-    launch_ola_rows<true>(b, blocks, Zhat, y, bvals, t, xnew, subset_labels, K, st);
+    launch_ola_rows<true>(b, blocks, Zhat, y, bvals, t, xnew, subset_labels, K, raw, st);
   else
-    launch_ola_rows<false>(b, blocks, Zhat, y, bvals, t, xnew, nullptr, K, st);
+    launch_ola_rows<false>(b, blocks, Zhat, y, bvals, t, xnew, nullptr, K, raw, st);
   return hipGetLastError();
 }
 

@@ -44,7 +44,8 @@ def test_struct_layouts_match_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
-    fields = {"fepll_image": F.Image, "fepll_options": F.Options, "fepll_tuning": F.Tuning}
+    fields = {"fepll_image": F.Image, "fepll_options": F.Options, "fepll_tuning": F.Tuning,
+              "fepll_operator": F.Operator}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fepll.h"', "int main(void) {"]
     for cname, py in fields.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
