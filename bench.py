@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--batch", type=int, default=48,
                     help="images of the uneven batch workload (0: skip it)")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--deblur", type=int, default=1,
+                    help="also time the deblurring workload (1) or not (0)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -342,6 +344,8 @@ def main():
     res["jitter"] = {"s": args.jitter, "seed": JITTER_SEED,
                      "patches_per_iteration": {p: round(v, 1) for p, v in n_sub.items()},
                      "all_patches": Np}
+    if args.deblur:
+        res["deblur"] = run_deblur(F, torch, np, fs, g, gf, args)
     if batch:
         res["batch"] = run_batch(F, torch, np, g, gf, batch, names, args.batch_steps,
                                  args.jitter)
@@ -349,6 +353,40 @@ def main():
         log("cpu baseline")
         res["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(res), flush=True)
+
+
+def run_deblur(F, torch, np, fs, g0, gf, args):
+    """The deblurring workload (second workload of the paper, Table 3):
+    the test image blurred by a 9x9 seeded motion kernel, noise sigma 0.5,
+    A a periodic convolution; Sec. 6 schedule and start, T = 5.  Eager runs
+    (no graph capture on this path)."""
+    c = fs.config_deblur(size=args.size)
+    y = torch.from_numpy(np.asarray(c["y"], np.float32)).cuda()
+    out = torch.empty_like(y)
+    H, W = y.shape
+    rows = {}
+    for p in ("fp32", "fp8", "fp8+flat", "fp8+flat+jitter"):
+        kw = dict(PATH_KW[p])
+        if "jitter" in kw:
+            kw["jitter"] = args.jitter
+        g = gf if is_flat(p) else g0
+        F.restore(g, y, c["sigma"], out=out, blur=c["h"], **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            F.restore(g, y, c["sigma"], out=out, blur=c["h"], **kw)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        rows[p] = {"mpix_s": round(H * W / dt / 1e6, 3), "ms_per_step": round(dt * 1e3, 3),
+                   "psnr_db": round(psnr(c["x"], out.cpu().numpy()), 4)}
+        log(f"deblur {p}: {H * W / dt / 1e6:.1f} Mpixels/s")
+    for p in rows:
+        rows[p]["dpsnr_vs_fp32_path_db"] = round(rows["fp32"]["psnr_db"] - rows[p]["psnr_db"], 4)
+        rows[p]["speedup_vs_plain_fp32"] = round(rows[p]["mpix_s"] / rows["fp32"]["mpix_s"], 3)
+    return {"workload": f"{H}x{W} test image, 9x9 seeded motion blur (periodic), sigma 0.5, "
+                        "K=200, T=5, Sec. 6 schedule and start",
+            "psnr_blurred_db": round(psnr(c["x"], np.asarray(c["y"], np.float32)), 4),
+            "paths": rows}
 
 
 def run_batch(F, torch, np, g0, gf, batch, names, steps, args_jitter):
