@@ -33,15 +33,19 @@ PATH_INFO = {
     "bf16+jitter": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel<2, false>", "bf16"),
     "fp8+jitter": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<false, true>", "fp8-e4m3"),
     "fp8+flat+jitter": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<true, true>", "fp8-e4m3"),
+    "bf16+tree": (MFMA_BF16_PEAK_TFLOPS, "pairs_bf16_kernel<false>", "bf16"),
+    "bf16+tree+flat": (MFMA_BF16_PEAK_TFLOPS, "pairs_bf16_kernel<true>", "bf16"),
 }
 ALL_PATHS = ("fp32", "bf16", "fp8", "bf16+proposal", "bf16+flat", "fp8+flat",
-             "bf16+proposal+flat", "bf16+jitter", "fp8+jitter", "fp8+flat+jitter")
+             "bf16+proposal+flat", "bf16+jitter", "fp8+jitter", "fp8+flat+jitter", "bf16+tree",
+             "bf16+tree+flat")
 JITTER_SEED = 20171023
 PATH_KW = {
     "fp32": dict(precision="fp32"),
     "bf16": dict(precision="bf16"),
     "fp8": dict(precision="fp8"),
     "bf16+proposal": dict(precision="bf16", proposal=True, top_m=8, margin=0.5),
+    "bf16+tree": dict(precision="bf16", tree=True),
 }
 # "+flat": the same options on the flat-tailed mixture (Sec. 3.1);
 # "+jitter": jittered patch subsampling (Sec. 3.3), spacing from --jitter
@@ -185,10 +189,13 @@ def main():
     mlp_flops = 2.0 * (65 * 256 + 256 * 256 + 256 * K)
 
     n_sub = {}  # jittered paths: mean patches per iteration (measured)
+    tree_flops = {}  # tree paths: flops of one descent (from the labels)
 
     def select_flops(name):
         if "proposal" in name:
             return 8 * 2.0 * 64 * 64 * Np
+        if "tree" in name:
+            return tree_flops.get(name)
         f = flops_flat if is_flat(name) else flops_launch
         if "jitter" in name:
             return f / Np * n_sub[name] if name in n_sub else None
@@ -239,9 +246,31 @@ def main():
     else:
         have_prop = False
 
+    # search tree of the mixture (Sec. 3.2), built offline on the host
+    tree_nch = None
+    if K == 200:
+        from paper_1710_08124_amd import tree as btree
+        sizes, parents = btree.build_tree(c["U"], c["lam"], c["w"])
+        g.set_tree(sizes, parents)
+        gf.set_tree(sizes, parents)
+        # per leaf: the candidates scored on its path (children of each node)
+        nL = len(sizes)
+        up = [np.asarray(p) for p in parents]
+        cnt = [np.bincount(up[n], minlength=sizes[n]) for n in range(nL - 1)]
+        tree_nch = np.zeros(K)
+        node = np.arange(K)
+        for n in range(nL - 2, -1, -1):  # parent level n of level n + 1
+            par = up[n][node]
+            tree_nch += cnt[n][par]
+            node = par
+
     def run_path(name):
         kw = kw_of(name)
         g = gf if is_flat(name) else g0
+        if "tree" in name:
+            _, lab = F.restore(g, y, sigma, out=out, return_labels=True, **kw)
+            lab = lab.cpu().numpy()
+            tree_flops[name] = 2.0 * 64 * 64 * float(tree_nch[lab].sum()) / lab.shape[0]
         if "jitter" in name:
             # patches per iteration of this path, from its labels (K: not chosen)
             _, lab = F.restore(g, y, sigma, out=out, return_labels=True, **kw)
@@ -285,7 +314,8 @@ def main():
 
     want = args.paths.split(",")
     names = [p for p in ALL_PATHS
-             if p in want and ("proposal" not in p or have_prop)]
+             if p in want and ("proposal" not in p or have_prop)
+             and ("tree" not in p or tree_nch is not None)]
     for p in ("fp32", "bf16"):
         if p not in names:
             names.insert(0 if p == "fp32" else 1, p)

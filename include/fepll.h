@@ -102,6 +102,12 @@ typedef struct {
    * labels_out gives K for the patches not chosen.                        */
   int32_t jitter;
   uint64_t seed;
+  /* Nonzero: Gaussian selection by the search tree of fepll_gmm_set_tree
+   * (Sec. 3.2): from the root, each patch follows the child of smallest
+   * selection cost down to a leaf.  Needs FEPLL_BF16 (the costs are those of
+   * the bfloat16 selection, flat-tailed with the mixture); not with
+   * use_proposal or jitter (EUNSUPPORTED).                                 */
+  int32_t use_tree;
 } fepll_options;
 
 /* Fill *opt with the defaults above. */
@@ -163,6 +169,24 @@ fepll_status fepll_cov_eig(const double* Sigma, int32_t K, int32_t d, double* U,
  * the spectra).  EDEVICE / ENOMEM on a device failure.
  */
 fepll_status fepll_gmm_flat_tail(fepll_gmm* g, double rho, int32_t* ranks);
+
+/*
+ * Search tree of the mixture (Sec. 3.2), for options.use_tree.
+ *   nlevels: levels of the tree, 2..16, the root first; 0 removes the tree.
+ *   sizes:   nlevels node counts: sizes[0] = 1 (the root), sizes[nlevels-1]
+ *            = K (the leaves are the mixture's components, in order).
+ *   parents: for each level n = 1..nlevels-1 in turn, sizes[n] int32 giving
+ *            the node of level n-1 that each node of level n belongs to;
+ *            every node above the leaves has 1..8 children.
+ * The nodes above the leaves are zero-mean Gaussians made from the leaves
+ * by moment matching (weights summed, covariances averaged with the
+ * weights), level by level, and eigendecomposed in float64 on the host; the
+ * flat tail of fepll_gmm_flat_tail applies to them as to the leaves.  A
+ * balanced tree is built offline (e.g. by paper_1710_08124_amd.tree).
+ * EINVAL on a malformed tree.  Synchronises the device.
+ */
+fepll_status fepll_gmm_set_tree(fepll_gmm* g, int32_t nlevels, const int32_t* sizes,
+                                const int32_t* parents);
 
 /* Release a handle (NULL is a no-op).  Synchronises the device first. */
 void fepll_gmm_destroy(fepll_gmm* g);

@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("recheck", c_int32), ("use_proposal", c_int32),
                 ("top_m", c_int32), ("margin_nats", c_double), ("init", POINTER(Image)),
                 ("stream", c_void_p), ("profile", c_int32), ("jitter", c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("use_tree", c_int32)]
 
 
 class Operator(ctypes.Structure):
@@ -91,6 +91,8 @@ def lib():
     L.fepll_gmm_destroy.restype = None
     L.fepll_gmm_flat_tail.argtypes = [c_void_p, c_double, c_void_p]
     L.fepll_gmm_flat_tail.restype = c_int32
+    L.fepll_gmm_set_tree.argtypes = [c_void_p, c_int32, c_void_p, c_void_p]
+    L.fepll_gmm_set_tree.restype = c_int32
     L.fepll_restore.argtypes = [c_void_p, POINTER(Image), c_void_p, c_double, c_void_p, c_int32,
                                 POINTER(Image), POINTER(Options), c_void_p]
     L.fepll_restore.restype = c_int32
@@ -167,7 +169,7 @@ STAGES = ("select", "recheck", "bucket", "wiener", "ola_update", "prep", "propos
 
 
 def _options(precision="fp32", recheck=True, init=None, stream=None, profile=False,
-             proposal=False, top_m=8, margin=0.5, jitter=0, seed=0) -> Options:
+             proposal=False, top_m=8, margin=0.5, jitter=0, seed=0, tree=False) -> Options:
     o = Options()
     lib().fepll_options_default(ctypes.byref(o))
     o.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
@@ -182,6 +184,7 @@ def _options(precision="fp32", recheck=True, init=None, stream=None, profile=Fal
     o.margin_nats = float(margin)
     o.jitter = int(jitter)
     o.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    o.use_tree = 1 if tree else 0
     return o
 
 
@@ -237,6 +240,23 @@ class GMM:
         _check(lib().fepll_gmm_flat_tail(self._h, float(rho), r.ctypes.data))
         return r
 
+    def set_tree(self, sizes, parents):
+        """Search tree for the selection (Sec. 3.2): level sizes, root first
+        (1, ..., K), and per level below the root the parent of each node in
+        the level above (e.g. from paper_1710_08124_amd.tree.build_tree).
+        sizes = None removes the tree."""
+        if sizes is None:
+            _check(lib().fepll_gmm_set_tree(self._h, 0, None, None))
+            return
+        sz = np.ascontiguousarray(sizes, dtype=np.int32)
+        if len(parents) != sz.size - 1:
+            raise ValueError("one parent array per level below the root")
+        for n, p in enumerate(parents):
+            if np.asarray(p).shape != (int(sz[n + 1]),):
+                raise ValueError("parents[n] must hold one entry per node of level n + 1")
+        par = np.ascontiguousarray(np.concatenate([np.asarray(p, np.int32) for p in parents]))
+        _check(lib().fepll_gmm_set_tree(self._h, int(sz.size), sz.ctypes.data, par.ctypes.data))
+
     def load_proposal(self, blob: bytes):
         """Attach a serialized proposal network (see MLP.serialize)."""
         buf = ctypes.create_string_buffer(bytes(blob), len(blob))
@@ -276,12 +296,13 @@ def profile(gmm: GMM):
 
 def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
             recheck=True, return_labels=False, out=None, profile=False, proposal=False,
-            top_m=8, margin=0.5, jitter=0, seed=0, blur=None):
+            top_m=8, margin=0.5, jitter=0, seed=0, blur=None, tree=False):
     """Denoise y (2-D float32 torch tensor, CUDA or CPU, or numpy array).
 
     betas: absolute beta values (default {1,4,8,16,32}/sigma^2).
     jitter: 0, or the grid spacing s of the jittered patch subsampling
     (Sec. 3.3) with its Philox seed.
+    tree: select through the search tree of gmm.set_tree (Sec. 3.2; bf16).
     blur: None (denoising), or the centred odd-sized kernel of a periodic
     convolution A (deblurring; the Sec. 6 schedule and start by default).
     Returns the restored image (same kind and device as y) and, with
@@ -294,7 +315,7 @@ def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
         out = torch.empty_like(y) if isinstance(y, torch.Tensor) else np.empty_like(y)
     oi = _image(out)
     o = _options(precision, recheck, init, _stream_of(y), profile, proposal, top_m, margin,
-                 jitter, seed)
+                 jitter, seed, tree)
     if betas is None:
         bptr, T = None, 0
         Tn = 5
@@ -339,13 +360,14 @@ def _batch_args(ys, sigmas, outs):
 
 
 def restore_batch(gmm: GMM, ys, sigmas, precision="bf16", recheck=True, outs=None,
-                  profile=False, proposal=False, top_m=8, margin=0.5, jitter=0, seed=0):
+                  profile=False, proposal=False, top_m=8, margin=0.5, jitter=0, seed=0,
+                  tree=False):
     """Denoise a list of images (2-D float32 tensors or arrays, any sizes),
     each with its own noise level, in one batched call (default schedule).
     Returns the list of restored images."""
     n, yi, oi, sg, outs = _batch_args(ys, sigmas, outs)
     o = _options(precision, recheck, None, _stream_of(ys[0]), profile, proposal, top_m, margin,
-                 jitter, seed)
+                 jitter, seed, tree)
     _check(lib().fepll_restore_batch(gmm.handle, n, yi, sg.ctypes.data, oi, ctypes.byref(o)))
     return outs
 
@@ -374,7 +396,7 @@ def autotune(gmm: GMM, ys, sigmas, precision="bf16", proposal=False, top_m=8, ma
 
 
 def select(gmm: GMM, x, beta: float, recheck=True, precision="fp32", proposal=False, top_m=8,
-           margin=0.5):
+           margin=0.5, tree=False):
     """One Gaussian-selection step on the CUDA image x.
     Returns (labels int32, best f32, second f32, flags int32), each of
     length (H-7)*(W-7)."""
@@ -386,7 +408,8 @@ def select(gmm: GMM, x, beta: float, recheck=True, precision="fp32", proposal=Fa
     best = torch.empty(Np, dtype=torch.float32, device=dev)
     second = torch.empty(Np, dtype=torch.float32, device=dev)
     flags = torch.empty(Np, dtype=torch.int32, device=dev)
-    o = _options(precision, recheck, None, _stream_of(x), False, proposal, top_m, margin)
+    o = _options(precision, recheck, None, _stream_of(x), False, proposal, top_m, margin,
+                 tree=tree)
     _check(lib().fepll_select(gmm.handle, ctypes.byref(xi), float(beta), lab.data_ptr(),
                               best.data_ptr(), second.data_ptr(), flags.data_ptr(),
                               ctypes.byref(o)))

@@ -33,6 +33,11 @@ __global__ void zero_i32_kernel(int32_t* p, int n) {
   if (i < n) p[i] = 0;
 }
 
+__global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // two buffers zeroed by one launch: p[0..n) and q[0..m), m <= n
 __global__ void zero2_i32_kernel(int32_t* p, int n, int32_t* q, int m) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -58,6 +63,7 @@ struct fepll_gmm {
   // the spectra as created, and the flat-tail approximation in use (Sec.
   // 3.1; rho = 1: none)
   std::vector<double> lam_h;
+  std::vector<double> U_h;  // [K][64][64], as created
   double rho = 1.0;
   std::vector<int32_t> h_rk;
   int32_t* rk = nullptr;  // [K] kept ranks, device
@@ -111,6 +117,22 @@ struct fepll_gmm {
     double* a2 = nullptr;     // |Hh|^2
     double2* X = nullptr;     // scratch spectrum
   } db;
+  // search tree (Sec. 3.2): all nodes, leaves first (ids 0..K-1), then the
+  // levels above from the one over the leaves up to the root
+  struct Tree {
+    int Kall = 0, root = 0, nlevels = 0, maxch = 0;
+    std::vector<int> lvl_size;           // root first
+    std::vector<double> U_h, lam_h, w_h;  // all nodes, spectra before any flat tail
+    double* U64 = nullptr;
+    double* lam64 = nullptr;
+    double* w64 = nullptr;
+    int32_t* rk = nullptr;
+    uint16_t* children = nullptr;  // [Kall][8]
+    ConstTables tb{};
+    std::vector<double> cbeta;
+    size_t S_cap = 0;
+    double* dbeta = nullptr;
+  } tree;
   float* ybuf = nullptr;
   float* xa = nullptr;
   float* xb = nullptr;
@@ -207,6 +229,77 @@ int table_mask(const fepll_options& o) {
   if (o.precision == FEPLL_FP8) return kTabF8;
   if (o.precision == FEPLL_BF16) return kTabBF16;
   return kTabF32;
+}
+
+// Sec. 3.1 on n spectra of kP eigenvalues (in place): ranks r_k (kP: no
+// tail) and the tail replaced by its average; the trace, the partial sums
+// and the tail sum in index order.  rho >= 1: no change, ranks kP.
+void flat_tail_host(std::vector<double>& lam, int n, double rho, std::vector<int32_t>& rk) {
+  rk.assign(n, kP);
+  if (rho >= 1.0) return;
+  for (int k = 0; k < n; ++k) {
+    double* l = lam.data() + (size_t)k * kP;
+    double cum[kP];
+    double c = 0.0;
+    for (int j = 0; j < kP; ++j) cum[j] = (c += l[j]);
+    const double goal = rho * cum[kP - 1];
+    int r = kP;
+    for (int j = 0; j < kP; ++j)
+      if (cum[j] >= goal) {
+        r = j + 1;
+        break;
+      }
+    rk[k] = r;
+    if (r < kP) {
+      double tail = 0.0;
+      for (int j = r; j < kP; ++j) tail += l[j];
+      const double avg = tail / (kP - r);
+      for (int j = r; j < kP; ++j) l[j] = avg;
+    }
+  }
+}
+
+// The tree's spectra on the device, flat-tailed like the mixture.
+fepll_status tree_upload_spectra(fepll_gmm* g) {
+  auto& T = g->tree;
+  std::vector<double> lam = T.lam_h;
+  std::vector<int32_t> rk;
+  flat_tail_host(lam, T.Kall, g->rho, rk);
+  HIPX(hipMemcpy(T.lam64, lam.data(), sizeof(double) * lam.size(), hipMemcpyHostToDevice));
+  HIPX(hipMemcpy(T.rk, rk.data(), sizeof(int32_t) * rk.size(), hipMemcpyHostToDevice));
+  T.tb.rk = (g->rho < 1.0) ? T.rk : nullptr;
+  T.cbeta.clear();
+  return FEPLL_OK;
+}
+
+// bfloat16 tables of the tree's nodes for the beta slots `betas`.
+fepll_status ensure_tree_consts(fepll_gmm* g, const std::vector<double>& betas, hipStream_t st) {
+  auto& T = g->tree;
+  if (T.cbeta == betas) return FEPLL_OK;
+  const size_t S = betas.size(), K = T.Kall;
+  if (S > T.S_cap) {
+    HIPX(hipStreamSynchronize(st));
+    dfree(T.dbeta);
+    dfree(T.tb.Ub);
+    dfree(T.tb.Wt);
+    dfree(T.tb.L32);
+    dfree(T.tb.Pinv);
+    T.S_cap = 0;
+    HIPX(dalloc(&T.dbeta, S));
+    HIPX(dalloc(&T.tb.Ub, S * K * kTileStride));
+    HIPX(dalloc(&T.tb.Wt, S * K * kTileStride));
+    HIPX(dalloc(&T.tb.L32, S * K));
+    HIPX(dalloc(&T.tb.Pinv, S * K));
+    T.S_cap = S;
+  }
+  HIPX(hipMemcpyAsync(T.dbeta, betas.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+  {
+    StageTimer tm(g, 5, st);
+    HIPX(launch_prep(T.U64, T.lam64, T.w64, T.Kall, T.dbeta, (int)S, kTabBF16, T.tb, st));
+  }
+  HIPX(hipStreamSynchronize(st));
+  T.cbeta = betas;
+  return FEPLL_OK;
 }
 
 // Per-beta tables for the beta slots `betas` (at least the tables in mask).
@@ -311,6 +404,13 @@ fepll_status check_opt(const fepll_gmm* g, const fepll_options* o) {
   if (o->jitter < 0 || o->jitter > 8) return fail(FEPLL_EINVAL, "options.jitter must be in 0..8");
   if (o->jitter && o->use_proposal)
     return fail(FEPLL_EUNSUPPORTED, "jittered subsampling does not run with the proposal");
+  if (o->use_tree) {
+    if (!g->tree.Kall) return fail(FEPLL_EINVAL, "no search tree is set (fepll_gmm_set_tree)");
+    if (o->precision != FEPLL_BF16)
+      return fail(FEPLL_EUNSUPPORTED, "the tree descent runs with FEPLL_BF16 costs");
+    if (o->use_proposal || o->jitter)
+      return fail(FEPLL_EUNSUPPORTED, "the tree descent runs alone (no proposal, no jitter)");
+  }
   return FEPLL_OK;
 }
 
@@ -402,9 +502,11 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
       g->pcost_cap = 8 * npmax;
     }
     const size_t nb2 = (npmax + kPairBlock - 1) / kPairBlock;
-    if ((s = grow(&g->phist, g->phist_cap, (size_t)K * nb2)) != FEPLL_OK) return s;
-    if ((s = grow(&g->pseg, g->pseg_cap, pair_seg_size(npmax, K))) != FEPLL_OK) return s;
-    if (g->has_proposal) {
+    // (the tree descent buckets over all its nodes)
+    const int Kp = std::max(K, g->tree.Kall);
+    if ((s = grow(&g->phist, g->phist_cap, (size_t)Kp * nb2)) != FEPLL_OK) return s;
+    if ((s = grow(&g->pseg, g->pseg_cap, pair_seg_size(npmax, Kp))) != FEPLL_OK) return s;
+    if (g->has_proposal || g->tree.Kall) {
       if ((s = grow(&g->zop, g->zop_cap, 64 * npmax)) != FEPLL_OK) return s;
       if ((s = grow(&g->znz, g->znz_cap, npmax)) != FEPLL_OK) return s;
     }
@@ -466,6 +568,43 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
 __global__ void mark_kernel(const int32_t* count, const int32_t* list, int32_t* flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < *count) flags[list[i]] = 1;
+}
+
+// Gaussian selection of one image by the search tree (Sec. 3.2) with the
+// tree tables of beta slot `slot`: the patches' bfloat16 records, then per
+// level the children of each patch's current node as candidates, bucketed
+// by node and scored exactly as in the all-K selection, the best one kept
+// (no fallback); the last level leaves a leaf, the label.
+fepll_status select_tree(fepll_gmm* g, const float* x, int H, int W, int slot,
+                         int32_t* labels, float* best, float* second, int32_t* flags,
+                         hipStream_t st) {
+  auto& T = g->tree;
+  const int Np = (H - 7) * (W - 7);
+  const size_t K = T.Kall;
+  StageTimer tm(g, 0, st);
+  HIPX(launch_records_bf16(x, H, W, g->zop, g->znz, st));
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, labels, Np,
+                     T.root);
+  HIPX(hipGetLastError());
+  if (flags) {
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, flags, Np);
+    HIPX(hipGetLastError());
+  }
+  const uint16_t* Ub = T.tb.Ub + (size_t)slot * K * kTileStride;
+  const float* L = T.tb.L32 + (size_t)slot * K;
+  const float* Pinv = T.tb.Pinv + (size_t)slot * K;
+  for (int lev = 1; lev < T.nlevels; ++lev) {
+    HIPX(launch_tree_cand(labels, Np, T.children, g->cand, st));
+    HIPX(launch_pair_bucket(g->cand, Np, T.maxch, T.Kall, g->phist, g->pseg, g->psorted, st));
+    HIPX(launch_pair_scores_bf16(g->zop, g->znz, Np, Ub, L, T.tb.rk, Pinv, T.Kall, T.maxch,
+                                 g->pseg, g->psorted, g->pcost, st));
+    // (best / second: the leaf level's, among the last node's children)
+    const bool last = lev == T.nlevels - 1;
+    HIPX(launch_pair_reduce(g->cand, g->pcost, Np, T.maxch, T.Kall, -INFINITY, labels,
+                            last ? best : nullptr, last ? second : nullptr, g->count, g->fb_list,
+                            st));
+  }
+  return FEPLL_OK;
 }
 
 // One Gaussian selection of one image x with the tables of beta slot
@@ -650,6 +789,17 @@ fepll_status select_batch(fepll_gmm* g, int t, const fepll_options& o, const flo
   const Batch& b = g->batch;
   const int blocks = g->tune.est_blocks;
   if (o.jitter) return select_jitter(g, t, o, x, labels, st);
+  if (o.use_tree) {
+    fepll_status s;
+    for (int i = 0; i < b.n; ++i) {
+      const ImgDesc& d = g->hd[i];
+      if ((s = select_tree(g, x + d.px, d.H, d.W, d.slot0 + t, labels + d.np,
+                           best ? best + d.np : nullptr, second ? second + d.np : nullptr,
+                           flags ? flags + d.np : nullptr, st)) != FEPLL_OK)
+        return s;
+    }
+    return FEPLL_OK;
+  }
   if (o.precision == FEPLL_FP8 || (o.precision == FEPLL_BF16 && !o.use_proposal)) {
     if (flags) {
       const int n = (int)b.n_patches;
@@ -753,6 +903,8 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
   put(key, o.margin_nats);
   put(key, o.jitter);
   put(key, o.seed);
+  put(key, o.use_tree);
+  put(key, g->tree.Kall);
   put(key, g->tune);
   put(key, g->rho);
   for (const ImgDesc& d : g->hd) put(key, d);
@@ -765,7 +917,9 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
                         g->pWb,   g->pbias,   g->cand,  g->fb_list,
                         g->psorted, g->pcost, g->phist, g->pseg,
                         g->tb.rk,   g->tb.Pinv, g->zop,  g->znz,
-                        g->jflags,  g->jlist,   g->jcount, g->jpart};
+                        g->jflags,  g->jlist,   g->jcount, g->jpart,
+                        g->tree.tb.Ub, g->tree.tb.L32, g->tree.tb.Pinv, g->tree.rk,
+                        g->tree.children};
   for (const void* p : ptrs) put(key, p);
   if (g->gexec && key == g->gkey) {
     *result = (T % 2) ? g->xb : g->xa;
@@ -950,6 +1104,7 @@ fepll_status fepll_gmm_create(const double* U, const double* lambda, const doubl
   if ((e = hipMemcpy(g->w64, w, sizeof(double) * K, hipMemcpyHostToDevice)) != hipSuccess)
     return bad(e);
   g->lam_h.assign(lambda, lambda + (size_t)K * d);
+  g->U_h.assign(U, U + (size_t)K * d * d);
   *out = g;
   return FEPLL_OK;
 }
@@ -1031,6 +1186,16 @@ void fepll_gmm_destroy(fepll_gmm* g) {
     (void)hipfftDestroy(g->db.fwd);
     (void)hipfftDestroy(g->db.inv);
   }
+  dfree(g->tree.U64);
+  dfree(g->tree.lam64);
+  dfree(g->tree.w64);
+  dfree(g->tree.rk);
+  dfree(g->tree.children);
+  dfree(g->tree.dbeta);
+  dfree(g->tree.tb.Ub);
+  dfree(g->tree.tb.Wt);
+  dfree(g->tree.tb.L32);
+  dfree(g->tree.tb.Pinv);
   dfree(g->db.r);
   dfree(g->db.Hh);
   dfree(g->db.AtY);
@@ -1109,6 +1274,7 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const fepll_opera
   if ((s = make_plan(g, 1, &H, &W, T, bvals, st)) != FEPLL_OK) return s;
   if ((s = ensure_consts(g, betas, table_mask(o), st)) != FEPLL_OK) return s;
   if ((s = ensure_jitter(g, o)) != FEPLL_OK) return s;
+  if (o.use_tree && (s = ensure_tree_consts(g, betas, st)) != FEPLL_OK) return s;
 
   HIPX(copy_in(g->ybuf, y, st));
   if (o.init) HIPX(copy_in(g->xa, o.init, st));
@@ -1189,6 +1355,7 @@ fepll_status fepll_restore_batch(fepll_gmm* g, int32_t n, const fepll_image* y,
   if ((s = make_plan(g, n, Hs.data(), Ws.data(), kDefaultT, bvals, st)) != FEPLL_OK) return s;
   if ((s = ensure_consts(g, betas, table_mask(o), st)) != FEPLL_OK) return s;
   if ((s = ensure_jitter(g, o)) != FEPLL_OK) return s;
+  if (o.use_tree && (s = ensure_tree_consts(g, betas, st)) != FEPLL_OK) return s;
   for (int i = 0; i < n; ++i) HIPX(copy_in(g->ybuf + g->hd[i].px, &y[i], st));
   const int64_t px = g->hd[n - 1].px + (int64_t)Hs[n - 1] * Ws[n - 1];
   HIPX(hipMemcpyAsync(g->xa, g->ybuf, sizeof(float) * px, hipMemcpyDeviceToDevice, st));
@@ -1300,29 +1467,8 @@ fepll_status fepll_gmm_flat_tail(fepll_gmm* g, double rho, int32_t* ranks) {
   // the trace; the eigenvalues after it are replaced by their average.  The
   // trace, the partial sums and the tail sum are taken in index order.
   std::vector<double> lam = g->lam_h;
-  std::vector<int32_t> rk(K, kP);
-  if (rho < 1.0) {
-    for (int k = 0; k < K; ++k) {
-      double* l = lam.data() + (size_t)k * kP;
-      double cum[kP];
-      double c = 0.0;
-      for (int j = 0; j < kP; ++j) cum[j] = (c += l[j]);
-      const double goal = rho * cum[kP - 1];
-      int r = kP;
-      for (int j = 0; j < kP; ++j)
-        if (cum[j] >= goal) {
-          r = j + 1;
-          break;
-        }
-      rk[k] = r;
-      if (r < kP) {
-        double tail = 0.0;
-        for (int j = r; j < kP; ++j) tail += l[j];
-        const double avg = tail / (kP - r);
-        for (int j = r; j < kP; ++j) l[j] = avg;
-      }
-    }
-  }
+  std::vector<int32_t> rk;
+  flat_tail_host(lam, K, rho, rk);
   // tables and captured work of earlier calls read the spectra: let them end
   HIPX(hipDeviceSynchronize());
   if (!g->rk) HIPX(dalloc(&g->rk, (size_t)K));
@@ -1333,8 +1479,150 @@ fepll_status fepll_gmm_flat_tail(fepll_gmm* g, double rho, int32_t* ranks) {
   g->h_rk = rk;
   g->cbeta.clear();  // every per-beta table is rebuilt on next use
   g->cmask = 0;
+  if (g->tree.Kall) {
+    fepll_status s = tree_upload_spectra(g);
+    if (s != FEPLL_OK) return s;
+  }
   if (ranks) std::memcpy(ranks, rk.data(), sizeof(int32_t) * K);
   return FEPLL_OK;
+}
+
+fepll_status fepll_gmm_set_tree(fepll_gmm* g, int32_t nlevels, const int32_t* sizes,
+                                const int32_t* parents) {
+  g_err.clear();
+  if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
+  auto& T = g->tree;
+  const int K = g->K;
+  HIPX(hipDeviceSynchronize());
+  auto clear = [&]() {
+    dfree(T.U64);
+    dfree(T.lam64);
+    dfree(T.w64);
+    dfree(T.rk);
+    dfree(T.children);
+    T = fepll_gmm::Tree{};
+  };
+  if (nlevels == 0) {
+    dfree(T.dbeta);
+    dfree(T.tb.Ub);
+    dfree(T.tb.Wt);
+    dfree(T.tb.L32);
+    dfree(T.tb.Pinv);
+    clear();
+    return FEPLL_OK;
+  }
+  if (nlevels < 2 || nlevels > 16) return fail(FEPLL_EINVAL, "nlevels must be in 2..16");
+  if (!sizes || !parents) return fail(FEPLL_EINVAL, "sizes and parents must be non-NULL");
+  if (sizes[0] != 1) return fail(FEPLL_EINVAL, "sizes[0] must be 1 (the root)");
+  if (sizes[nlevels - 1] != K) return fail(FEPLL_EINVAL, "the last level must have the K leaves");
+  int64_t total = 0;
+  for (int n = 0; n < nlevels; ++n) {
+    if (sizes[n] < 1) return fail(FEPLL_EINVAL, "every level needs a node");
+    total += sizes[n];
+  }
+  if (total > kMaxK) return fail(FEPLL_EUNSUPPORTED, "more than 1024 nodes in all");
+  // parents per level, and every node above the leaves with 1..8 children
+  std::vector<const int32_t*> par(nlevels, nullptr);
+  {
+    const int32_t* p = parents;
+    for (int n = 1; n < nlevels; ++n) {
+      par[n] = p;
+      std::vector<int> cnt(sizes[n - 1], 0);
+      for (int i = 0; i < sizes[n]; ++i) {
+        if (p[i] < 0 || p[i] >= sizes[n - 1])
+          return fail(FEPLL_EINVAL, "a parent index is out of its level");
+        cnt[p[i]]++;
+      }
+      for (int c : cnt)
+        if (c < 1 || c > 8) return fail(FEPLL_EINVAL, "every inner node needs 1..8 children");
+      p += sizes[n];
+    }
+  }
+  // node ids: leaves 0..K-1, then the levels nlevels-2 .. 0
+  std::vector<int> base(nlevels, 0);
+  int next = K;
+  for (int n = nlevels - 2; n >= 0; --n) {
+    base[n] = next;
+    next += sizes[n];
+  }
+  const int Kall = next;
+  // moment matching, leaves upwards, in float64
+  std::vector<double> w((size_t)Kall, 0.0), Sg((size_t)Kall * kP * kP, 0.0);
+  {
+    std::vector<double> wl(K);
+    HIPX(hipMemcpy(wl.data(), g->w64, sizeof(double) * K, hipMemcpyDeviceToHost));
+    for (int k = 0; k < K; ++k) {
+      w[k] = wl[k];
+      const double* U = g->U_h.data() + (size_t)k * kP * kP;
+      const double* l = g->lam_h.data() + (size_t)k * kP;
+      double* S = Sg.data() + (size_t)k * kP * kP;
+      for (int p = 0; p < kP; ++p)
+        for (int q = 0; q < kP; ++q) {
+          double a = 0.0;
+          for (int j = 0; j < kP; ++j) a += U[p * kP + j] * l[j] * U[q * kP + j];
+          S[p * kP + q] = a;
+        }
+    }
+  }
+  auto id = [&](int n, int i) { return (n == nlevels - 1) ? i : base[n] + i; };
+  // an inner node first holds sum_{leaves below} w_l Sigma_l (its children's
+  // weighted covariances for leaves, their sums for inner nodes), divided by
+  // its weight once every level below is in
+  for (int n = nlevels - 1; n >= 1; --n)
+    for (int i = 0; i < sizes[n]; ++i) {
+      const int c = id(n, i), q = id(n - 1, par[n][i]);
+      w[q] += w[c];
+      const double f = (n == nlevels - 1) ? w[c] : 1.0;
+      const double* Sc = Sg.data() + (size_t)c * kP * kP;
+      double* Sq = Sg.data() + (size_t)q * kP * kP;
+      for (int e = 0; e < kP * kP; ++e) Sq[e] += f * Sc[e];
+    }
+  for (int n = nlevels - 2; n >= 0; --n)
+    for (int i = 0; i < sizes[n]; ++i) {
+      const int q = id(n, i);
+      double* Sq = Sg.data() + (size_t)q * kP * kP;
+      for (int e = 0; e < kP * kP; ++e) Sq[e] /= w[q];
+    }
+  // eigendecomposition of the inner nodes (leaves keep their own)
+  std::vector<double> Uall((size_t)Kall * kP * kP), lall((size_t)Kall * kP);
+  std::copy(g->U_h.begin(), g->U_h.end(), Uall.begin());
+  std::copy(g->lam_h.begin(), g->lam_h.end(), lall.begin());
+  if (Kall > K) {
+    fepll_status s = fepll_cov_eig(Sg.data() + (size_t)K * kP * kP, Kall - K, kP,
+                                   Uall.data() + (size_t)K * kP * kP, lall.data() + (size_t)K * kP);
+    if (s != FEPLL_OK) return s;
+  }
+  // children table
+  std::vector<uint16_t> ch((size_t)Kall * 8, 0xffffu);
+  int maxch = 0;
+  for (int n = nlevels - 1; n >= 1; --n)
+    for (int i = 0; i < sizes[n]; ++i) {
+      const int q = id(n - 1, par[n][i]);
+      uint16_t* row = ch.data() + (size_t)q * 8;
+      int j = 0;
+      while (row[j] != 0xffffu) ++j;
+      row[j] = (uint16_t)id(n, i);  // children in ascending index: ties to the lower one
+      maxch = std::max(maxch, j + 1);
+    }
+  clear();
+  T.Kall = Kall;
+  T.root = id(0, 0);
+  T.nlevels = nlevels;
+  T.maxch = maxch;
+  T.lvl_size.assign(sizes, sizes + nlevels);
+  T.U_h = std::move(Uall);
+  T.lam_h = std::move(lall);
+  T.w_h = w;
+  HIPX(dalloc(&T.U64, T.U_h.size()));
+  HIPX(dalloc(&T.lam64, T.lam_h.size()));
+  HIPX(dalloc(&T.w64, (size_t)Kall));
+  HIPX(dalloc(&T.rk, (size_t)Kall));
+  HIPX(dalloc(&T.children, ch.size()));
+  HIPX(hipMemcpy(T.U64, T.U_h.data(), sizeof(double) * T.U_h.size(), hipMemcpyHostToDevice));
+  HIPX(hipMemcpy(T.w64, w.data(), sizeof(double) * Kall, hipMemcpyHostToDevice));
+  HIPX(hipMemcpy(T.children, ch.data(), sizeof(uint16_t) * ch.size(), hipMemcpyHostToDevice));
+  g->plan_valid = false;  // the pair scratch is sized for the tree's nodes
+  return tree_upload_spectra(g);
 }
 
 fepll_status fepll_gmm_load_proposal(fepll_gmm* g, const void* blob, size_t nbytes) {
@@ -1401,6 +1689,8 @@ fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta, int32
   const std::vector<float> bv(1, 1.f);
   if ((s = make_plan(g, 1, &H, &W, 1, bv, st)) != FEPLL_OK) return s;
   if ((s = ensure_consts(g, std::vector<double>(1, beta), table_mask(o), st)) != FEPLL_OK)
+    return s;
+  if (o.use_tree && (s = ensure_tree_consts(g, std::vector<double>(1, beta), st)) != FEPLL_OK)
     return s;
   HIPX(copy_in(g->xa, x, st));
   return select_batch(g, 0, o, g->xa, labels, best, second, flags, st);

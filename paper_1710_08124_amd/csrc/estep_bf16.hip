@@ -482,6 +482,57 @@ __global__ __launch_bounds__(1024) void pair_reduce_kernel(
   if (fb) fb_list[wbase[wave] + __popcll(mask & ((1ull << lane) - 1ull))] = i;
 }
 
+// The bfloat16 selection operand of every patch of one image as a record
+// (8 uint4 per patch, row dy at uint4 dy) and its float32 squared norm --
+// load_patch's arithmetic, so a record scores bit for bit as in the all-K
+// selection.  A wave covers 16 consecutive patches (lane group g: rows g and
+// 4 + g of patch l & 15).
+__global__ __launch_bounds__(256) void records_bf16_kernel(const float* __restrict__ x, int H,
+                                                           int W, uint4* __restrict__ zop,
+                                                           float* __restrict__ znz) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, col = lane & 15;
+  const int Hp = H - 7, Wp = W - 7;
+  const int64_t Np = (int64_t)Hp * Wp;
+  const int64_t p0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (p0 >= Np) return;  // (wave-uniform)
+  const int64_t p = min(p0 + col, Np - 1);
+  const int r = (int)(p / Wp), c = (int)(p - (int64_t)r * Wp);
+  uint4 zb[2];
+  float nz = 0.f;
+  load_patch<true>(x, W, r, c, g, zb, nz);
+  if (p0 + col < Np) {
+    zop[p * 8 + g] = zb[0];
+    zop[p * 8 + 4 + g] = zb[1];
+    if (g == 0) znz[p] = nz;
+  }
+}
+
+// Candidates of the tree descent: the children of each patch's current node
+// (children: 8 entries per node, 0xffff after the last).
+__global__ __launch_bounds__(256) void tree_cand_kernel(const int32_t* __restrict__ cur, int Np,
+                                                        const uint4* __restrict__ children,
+                                                        uint4* __restrict__ cand) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < Np) cand[i] = children[cur[i]];
+}
+
+hipError_t launch_records_bf16(const float* x, int H, int W, uint16_t* zop, float* znz,
+                               hipStream_t st) {
+  const int64_t Np = (int64_t)(H - 7) * (W - 7);
+  const int64_t waves = (Np + 15) / 16;
+  hipLaunchKernelGGL(records_bf16_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, x,
+                     H, W, reinterpret_cast<uint4*>(zop), znz);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree_cand(const int32_t* cur, int Np, const uint16_t* children, uint16_t* cand,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(tree_cand_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, cur, Np,
+                     reinterpret_cast<const uint4*>(children), reinterpret_cast<uint4*>(cand));
+  return hipGetLastError();
+}
+
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st) {
   if (mode == kModeListFull) {
     const int Np = (args.H - 7) * (args.W - 7);

@@ -57,6 +57,14 @@ hipError_t launch_pair_reduce(const uint16_t* cand, const float* pair_cost, int 
                               float margin, int32_t* labels, float* best, float* second,
                               int32_t* fb_count, int32_t* fb_list, hipStream_t st);
 
+// Search-tree descent (Sec. 3.2): every patch's bfloat16 operand record and
+// squared norm (as the network writes them), and the candidates of a level
+// (the children of each patch's current node; children: 8 uint16 per node).
+hipError_t launch_records_bf16(const float* x, int H, int W, uint16_t* zop, float* znz,
+                               hipStream_t st);
+hipError_t launch_tree_cand(const int32_t* cur, int Np, const uint16_t* children, uint16_t* cand,
+                            hipStream_t st);
+
 // Network inference + top-m: cand[i] gets the m best classes of patch i in
 // decreasing logit order (ties to the lower class), 0xffff after the m-th.
 // Wb / bias: see propose.hip.  zop (Np x 64 bfloat16) / znz (Np floats):
