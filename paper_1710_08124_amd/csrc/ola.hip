@@ -129,13 +129,21 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
 }
 
 // ---- subset reprojection (jittered subsampling, Sec. 3.3).  The same
-// tiles; a tile first lists the chosen patches of its window (the
-// (TY + 7) x 71 patches that touch it; a patch is chosen when its label is
-// below K) in raster order, by a ballot compaction into LDS, then stages
-// their estimates 64 patches at a time in LDS, and every thread adds, to the
-// pixels it owns (column tx, rows j, j + 4, ...), the entries of the listed
-// patches that cover them, in list order, counting them: a fixed order, no
-// atomics, and work in proportion to the chosen patches, not to all.
+// tiles.  A tile's window is the (TY + 7) x 71 patches that touch it; a
+// patch is chosen when its label is below K.
+//   1. one bit per window patch: each window row is two ballots (columns
+//      0..63 and 64..70) over coalesced label loads; a wave scan of the rows'
+//      popcounts gives every chosen patch its slot in raster order, and the
+//      slots are listed (plist) in LDS;
+//   2. the chosen patches' estimates are staged in LDS, CH slots at a time,
+//      every load of a chunk in flight at once;
+//   3. a thread owns column tx and pixel rows j, j + 4, ...; the patches
+//      covering pixel (y, x) start in window rows y - y0 .. y - y0 + 7 and
+//      window columns tx .. tx + 7, so each window row the thread touches
+//      gives an 8-bit field of its mask, and a set bit's slot is the row's
+//      base plus the popcount of the bits before it.  A pixel sums its
+//      patches' entries in raster order of the patches (fixed, no atomics),
+//      and its count is the popcount of its 8 fields.
 template <int TY>
 __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* __restrict__ Zhat_b,
                                                          const float* __restrict__ y_b,
@@ -145,11 +153,15 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
                                                          int K, int raw) {
   constexpr int WR = TY + 7;          // patch rows of the window
   constexpr int WIN = WR * NP;        // patches of the window
-  constexpr int CH = 64;              // patches staged at a time
+  constexpr int CH = 128;             // patches staged at a time
   constexpr int NR = TY / 4;          // pixel rows per thread
-  __shared__ int16_t plist[WIN];      // chosen patches: window row * NP + column
+  constexpr int RPW = (WR + 3) / 4;   // window rows per wave in step 1
+  constexpr int SPT = CH * 16 / 256;  // float4 staged per thread per chunk
+  static_assert(WR <= 128, "two window rows per lane in the scan");
+  __shared__ uint64_t mlo[WR], mhi[WR];  // chosen: columns 0..63, 64..70
+  __shared__ int rbase[WR + 1];          // chosen patches in the rows above
+  __shared__ int16_t plist[WIN];         // slot -> window row * NP + column
   __shared__ float zs[CH * PITCH];
-  __shared__ int wcnt[4];
   const int G8 = gridDim.x;
   const int lin = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
   if (lin >= bt.n_ola) return;
@@ -165,80 +177,120 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
   const int lt = lin - d.ola0;
   const int x0 = (lt / nty) * TX, y0 = (lt % nty) * TY;
   const int tx = threadIdx.x & 63, j = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = tx, wave = j;
   const int rfirst = y0 - 7, cfirst = x0 - 7;
 
-  // 1. the window's chosen patches, raster order: thread t tests window
-  // entries t * PT .. t * PT + PT - 1 (all its label loads in flight at
-  // once), then a block-wide exclusive scan of the counts places them
-  constexpr int PT = (WIN + 255) / 256;
-  bool in[PT];
-  int mine = 0;
+  // 1. masks: wave w takes window rows w, w + 4, ... (all loads first)
+  {
+    int la[RPW], lb[RPW];
+    const int c = cfirst + lane, c2 = cfirst + 64 + lane;
 #pragma unroll
-  for (int u = 0; u < PT; ++u) {
-    const int w = threadIdx.x * PT + u;
-    const int r = rfirst + w / NP, c = cfirst + w % NP;
-    in[u] = w < WIN && r >= 0 && r < Hp && c >= 0 && c < Wp &&
-            labels[(size_t)r * Wp + c] < K;
+    for (int u = 0; u < RPW; ++u) {
+      const int rw = wave + 4 * u, r = rfirst + rw;
+      const bool row = rw < WR && r >= 0 && r < Hp;
+      la[u] = (row && c >= 0 && c < Wp) ? labels[(size_t)r * Wp + c] : K;
+      lb[u] = (row && lane < NP - 64 && c2 >= 0 && c2 < Wp) ? labels[(size_t)r * Wp + c2] : K;
+    }
+#pragma unroll
+    for (int u = 0; u < RPW; ++u) {
+      const int rw = wave + 4 * u;
+      const uint64_t A = __ballot(la[u] < K), B = __ballot(lb[u] < K);
+      if (rw < WR && lane == 0) {
+        mlo[rw] = A;
+        mhi[rw] = B;
+      }
+    }
   }
-#pragma unroll
-  for (int u = 0; u < PT; ++u) mine += in[u] ? 1 : 0;
-  int incl = mine;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int v = __shfl_up(incl, off);
-    if (lane >= off) incl += v;
-  }
-  if (lane == 63) wcnt[wave] = incl;
   __syncthreads();
-  int pos = incl - mine;
+  if (wave == 0) {
+    const int c0 = lane < WR ? __popcll(mlo[lane]) + __popcll(mhi[lane]) : 0;
+    const int c1 = lane + 64 < WR ? __popcll(mlo[lane + 64]) + __popcll(mhi[lane + 64]) : 0;
+    int s0 = c0, s1 = c1;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) pos += (v < wave) ? wcnt[v] : 0;
-  const int n = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-#pragma unroll
-  for (int u = 0; u < PT; ++u)
-    if (in[u]) plist[pos++] = (int16_t)(threadIdx.x * PT + u);
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v0 = __shfl_up(s0, off), v1 = __shfl_up(s1, off);
+      if (lane >= off) {
+        s0 += v0;
+        s1 += v1;
+      }
+    }
+    const int t0 = __shfl(s0, 63), t1 = __shfl(s1, 63);
+    if (lane < WR) rbase[lane] = s0 - c0;
+    if (lane + 64 < WR) rbase[lane + 64] = t0 + s1 - c1;
+    if (lane == 0) rbase[WR] = t0 + t1;
+  }
+  __syncthreads();
+  for (int rw = wave; rw < WR; rw += 4) {
+    const uint64_t A = mlo[rw], B = mhi[rw];
+    const uint64_t below = (1ull << lane) - 1ull;
+    if ((A >> lane) & 1ull) plist[rbase[rw] + __popcll(A & below)] = (int16_t)(rw * NP + lane);
+    if (lane < NP - 64 && ((B >> lane) & 1ull))
+      plist[rbase[rw] + __popcll(A) + __popcll(B & below)] = (int16_t)(rw * NP + 64 + lane);
+  }
+  const int n = rbase[WR];
   __syncthreads();
 
-  // 2. accumulate, CH patches at a time
+  // 3. per window row the thread touches (u = 0 .. 4 NR + 3: row j + u),
+  // its 8-bit field at columns tx .. tx + 7 and the slot of its first bit
   float acc[NR], cnt[NR];
 #pragma unroll
   for (int i = 0; i < NR; ++i) acc[i] = cnt[i] = 0.f;
   const int xx = x0 + tx;
   for (int c0 = 0; c0 < n; c0 += CH) {
     const int m = min(CH, n - c0);
-    // stage: 16 float4 per patch
-    for (int e = threadIdx.x; e < m * 16; e += 256) {
-      const int q = e >> 4, f = e & 15;
+    // 2. stage slots c0 .. c0 + m - 1 (clamped loads, all in flight)
+    float4 v[SPT];
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int q = min(e >> 4, m - 1), f = e & 15;
       const int w = plist[c0 + q];
       const int r = rfirst + w / NP, c = cfirst + w % NP;
-      const float4 v = *reinterpret_cast<const float4*>(Zhat + ((size_t)r * Wp + c) * kP + 4 * f);
-      float* zp = zs + q * PITCH + 4 * f;
-      zp[0] = v.x;
-      zp[1] = v.y;
-      zp[2] = v.z;
-      zp[3] = v.w;
+      v[u] = *reinterpret_cast<const float4*>(Zhat + ((size_t)r * Wp + c) * kP + 4 * f);
+    }
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      if ((e >> 4) < m) {
+        float* zp = zs + (e >> 4) * PITCH + 4 * (e & 15);
+        zp[0] = v[u].x;
+        zp[1] = v[u].y;
+        zp[2] = v[u].z;
+        zp[3] = v[u].w;
+      }
     }
     __syncthreads();
-    for (int q = 0; q < m; ++q) {
-      const int w = plist[c0 + q];
-      const int r = rfirst + w / NP, c = cfirst + w % NP;
-      const int dx = xx - c;
-      if (dx < 0 || dx >= 8) continue;
-      const float* zp = zs + q * PITCH + dx;
 #pragma unroll
-      for (int i = 0; i < NR; ++i) {
-        const int dy = y0 + j + 4 * i - r;
-        if (dy >= 0 && dy < 8) {
-          acc[i] += zp[8 * dy];
-          cnt[i] += 1.f;
+    for (int u = 0; u < 4 * NR + 4; ++u) {
+      const int rw = j + u;  // < 4 NR + 7 = WR
+      const uint64_t A = mlo[rw], B = mhi[rw];
+      // bits tx .. tx + 7 of the row's 71-bit mask
+      const uint32_t f8 =
+          (uint32_t)((tx + 8 <= 64 ? (A >> tx) : ((A >> tx) | (B << (64 - tx)))) & 0xffull);
+      if (c0 == 0) {
+        const float pc = (float)__popc(f8);
+        if (u / 4 < NR) cnt[u / 4] += pc;
+        if (u / 4 >= 1 && u / 4 - 1 < NR) cnt[u / 4 - 1] += pc;
+      }
+      if (!f8) continue;
+      int sl = rbase[rw] + __popcll(A & ((1ull << tx) - 1ull)) - c0;
+      uint32_t bits = f8;
+      while (bits) {
+        const int k = __ffs(bits) - 1;  // window column tx + k: dx = 7 - k
+        bits &= bits - 1u;
+        if (sl >= 0 && sl < m) {
+          const float* zp = zs + sl * PITCH + (7 - k);
+          // pixel row i = u / 4 (dy = 7 - u % 4) and i = u / 4 - 1 (dy = 3 - u % 4)
+          if (u / 4 < NR) acc[u / 4] += zp[8 * (7 - u % 4)];
+          if (u / 4 >= 1 && u / 4 - 1 < NR) acc[u / 4 - 1] += zp[8 * (3 - u % 4)];
         }
+        ++sl;
       }
     }
     __syncthreads();  // zs is restaged
   }
 
-  // 3. average and image update
+  // 4. average and image update
   const float onepb = 1.f + b;
 #pragma unroll
   for (int i = 0; i < NR; ++i) {
