@@ -25,14 +25,14 @@ HBM_PEAK_GBS = 8000.0
 PATH_INFO = {
     "fp32": (MFMA_F32_PEAK_TFLOPS, "estep_f32_kernel", "f32"),
     "bf16": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel<0, false>", "bf16"),
-    "fp8": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<false, false>", "fp8-e4m3"),
+    "fp8": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<false>", "fp8-e4m3"),
     "bf16+proposal": (MFMA_BF16_PEAK_TFLOPS, "pairs_bf16_kernel<false>", "bf16"),
     "bf16+flat": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel<0, true>", "bf16"),
-    "fp8+flat": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<true, false>", "fp8-e4m3"),
+    "fp8+flat": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<true>", "fp8-e4m3"),
     "bf16+proposal+flat": (MFMA_BF16_PEAK_TFLOPS, "pairs_bf16_kernel<true>", "bf16"),
     "bf16+jitter": (MFMA_BF16_PEAK_TFLOPS, "estep_bf16_kernel<2, false>", "bf16"),
-    "fp8+jitter": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<false, true>", "fp8-e4m3"),
-    "fp8+flat+jitter": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_kernel<true, true>", "fp8-e4m3"),
+    "fp8+jitter": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_list_kernel<false>", "fp8-e4m3"),
+    "fp8+flat+jitter": (MFMA_FP8_PEAK_TFLOPS, "estep_fp8_list_kernel<true>", "fp8-e4m3"),
     "bf16+tree": (MFMA_BF16_PEAK_TFLOPS, "pairs_bf16_kernel<false>", "bf16"),
     "bf16+tree+flat": (MFMA_BF16_PEAK_TFLOPS, "pairs_bf16_kernel<true>", "bf16"),
 }

@@ -39,11 +39,6 @@ __global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
 }
 
 // two buffers zeroed by one launch: p[0..n) and q[0..m), m <= n
-__global__ void zero2_i32_kernel(int32_t* p, int n, int32_t* q, int m) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
-  if (i < m) q[i] = 0;
-}
 }  // namespace
 
 namespace fepll {
@@ -99,6 +94,7 @@ struct fepll_gmm {
   // jittered subsampling: chosen-patch flags and list (packed like labels),
   // list length per image
   int32_t* jflags = nullptr;
+  bool jflags_dirty = true;  // jflags may hold set entries (cleared on next use)
   int32_t* jlist = nullptr;
   size_t jcount_cap = 0;
   int32_t* jcount = nullptr;
@@ -489,6 +485,11 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     HIPX(dalloc(&g->jflags, NP));
     HIPX(dalloc(&g->jlist, NP));
     g->np_cap = NP;
+    // the subset flags start (and stay, between calls) all zero
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((NP + 255) / 256)), dim3(256), 0, st,
+                       g->jflags, (int)NP);
+    HIPX(hipGetLastError());
+    g->jflags_dirty = false;
   }
   {
     // pair scratch of the proposal path, sized for the largest image
@@ -708,19 +709,25 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
     }
   }
   {
-    // the chosen patches of every image (stage 8: subset)
+    // the chosen patches of every image (stage 8: subset).  The position
+    // flags are all zero between calls (the compaction clears what the
+    // marking set); after a new allocation or an interrupted call they are
+    // cleared first.
     StageTimer tm(g, 8, st);
-    // (n_patches >= images: one launch clears both)
-    hipLaunchKernelGGL(zero2_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n,
-                       g->jcount, b.n);
-    HIPX(hipGetLastError());
+    if (g->jflags_dirty) {
+      hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n);
+      HIPX(hipGetLastError());
+    }
+    g->jflags_dirty = true;
     for (int i = 0; i < b.n; ++i) {
       const ImgDesc& d = g->hd[i];
       const int Np = (d.H - 7) * (d.W - 7);
-      HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, st));
+      HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, g->jcount + i,
+                              st));
       HIPX(launch_jitter_compact(Np, g->K, g->jflags + d.np, labels + d.np, g->jcount + i,
                                  g->jlist + d.np, st));
     }
+    g->jflags_dirty = false;
   }
   if (o.precision == FEPLL_FP32) return FEPLL_OK;
   for (int i = 0; i < b.n; ++i) {

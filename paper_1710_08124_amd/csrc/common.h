@@ -177,12 +177,12 @@ hipError_t launch_spec_init(const void* AtY, const double* a2, void* X, int H, i
                             hipStream_t st);
 
 // Jittered subsampling (Sec. 3.3) of one image, iteration t: flags (Np,
-// zeroed before) of the chosen patches set to 1; then every flagged patch
-// appended to list (*count zeroed before; any order) and every other
-// patch's label set to K.
+// all zero before) of the chosen patches set to 1 and *count zeroed; then
+// every flagged patch appended to list (any order), its flag cleared, and
+// every other patch's label set to K.
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
-                              hipStream_t st);
-hipError_t launch_jitter_compact(int Np, int K, const int32_t* flags, int32_t* labels,
+                              int32_t* count, hipStream_t st);
+hipError_t launch_jitter_compact(int Np, int K, int32_t* flags, int32_t* labels,
                                  int32_t* count, int32_t* list, hipStream_t st);
 // e4m3 selection of the patches in list (*count <= list_max entries,
 // indices within the image) of the one image d[0] of a batch at iteration

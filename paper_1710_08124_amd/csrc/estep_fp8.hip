@@ -45,21 +45,13 @@ __device__ __forceinline__ int fp8_exponent(float mx) {
   return max(e, -127);
 }
 
-// e4m3 B operand (32 bytes) and E8M0 scale of the patch at (r, c) for lane
-// half h: rows 4 h .. 4 h + 3.  The mean is a float32 sum of the lane's 32
-// pixels in order, plus the other half's sum.
-// With NZ, nz receives the float32 squared norm of the (unrounded)
-// DC-removed patch, the same in both lanes of its column.
+// e4m3 B operand (32 bytes) and E8M0 scale of a patch from the lane's 32
+// pixels v (rows 4 h .. 4 h + 3 of it, row-major): the mean is a float32 sum
+// of the lane's 32 pixels in order, plus the other half's sum.  With NZ, nz
+// receives the float32 squared norm of the (unrounded) DC-removed patch,
+// the same in both lanes of its column.
 template <bool NZ>
-__device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, int r, int c,
-                                            int h, i32x8& zq, int& code, float& nz) {
-  float v[32];
-#pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const float* row = x + (size_t)(r + 4 * h + rr) * W + c;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) v[8 * rr + e] = row[e];
-  }
+__device__ __forceinline__ void quantize_patch8(float (&v)[32], i32x8& zq, int& code, float& nz) {
   float s = v[0];
 #pragma unroll
   for (int i = 1; i < 32; ++i) s += v[i];
@@ -85,6 +77,20 @@ __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, 
     zq[w] = p;
   }
 }
+
+// the same for the patch at (r, c) of x, lane half h, read from the image
+template <bool NZ>
+__device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, int r, int c,
+                                            int h, i32x8& zq, int& code, float& nz) {
+  float v[32];
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const float* row = x + (size_t)(r + 4 * h + rr) * W + c;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[8 * rr + e] = row[e];
+  }
+  quantize_patch8<NZ>(v, zq, code, nz);
+}
 }  // namespace
 
 // FLAT: the flat-tail form (Sec. 3.1) -- only the eigen blocks of 32 that
@@ -92,24 +98,13 @@ __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, 
 // cost is L_k + Pk |z~|^2 minus their squared projections (the operand's
 // columns carry sqrt(1/nu_P - 1/nu_j), Pk = 1/nu_P); a component without a
 // tail (rk = 64) takes the plain form.
-//
-// LIST: the patches of a list (a jittered subset, Sec. 3.3) of the one image
-// dsc[0] instead of the batch's tiles: 512 list entries per work item (128
-// per wave, as 4 blocks of 32), the list length read on the device, a fixed
-// grid striding over the items.  A short list is also split over the
-// components (blockIdx.y of nsplit takes a contiguous component range and
-// writes its best, second and label per entry to part; fp8_merge_kernel
-// combines them): the costs are the same, and merging the ranges in order
-// keeps ties on the lower component, so the labels are those of one pass.
-template <bool FLAT, bool LIST>
+template <bool FLAT>
 __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const ImgDesc* __restrict__ dsc, const int32_t* __restrict__ est_img, int n_est, int t,
     const float* __restrict__ xb, const uint4* __restrict__ Uf_all,
     const int32_t* __restrict__ Ue_all, const float* __restrict__ L_all,
     const int32_t* __restrict__ rkt, const float* __restrict__ P_all, int K,
-    int32_t* __restrict__ labels_b, float* __restrict__ best_b, float* __restrict__ second_b,
-    const int32_t* __restrict__ list, const int32_t* __restrict__ list_count, int nsplit,
-    float4* __restrict__ part, int pcap) {
+    int32_t* __restrict__ labels_b, float* __restrict__ best_b, float* __restrict__ second_b) {
   __shared__ uint4 Ash[2][256];
   __shared__ int Esh[kMaxK];
   __shared__ float Lsh[kMaxK];
@@ -121,12 +116,9 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
   const int col = lane & 31;
 
   // persistent: each workgroup loops over selection tiles (4 patch rows x
-  // 128 columns) of the batch, or over 512-entry chunks of the list; the
-  // loop is workgroup-uniform
-  const int nlist = LIST ? *list_count : 0;
-  const int nitems = LIST ? (nlist + 511) / 512 : n_est;
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const ImgDesc d = dsc[LIST ? 0 : est_img[item]];
+  // 128 columns) of the batch; the loop is workgroup-uniform
+  for (int item = blockIdx.x; item < n_est; item += gridDim.x) {
+    const ImgDesc d = dsc[est_img[item]];
     const int W = d.W, Hp = d.H - 7, Wp = d.W - 7;
     const float* x = xb + d.px;
     const size_t slot = (size_t)(d.slot0 + t);
@@ -138,15 +130,7 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     // whether it is a real patch (tile edge / list end otherwise)
     int pidx[PB];
     bool pval[PB];
-    if (LIST) {
-      const int base = item * 512 + wave * 128;
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) {
-        const int e = base + 32 * pb + col;
-        pval[pb] = e < nlist;
-        pidx[pb] = list[pval[pb] ? e : item * 512];
-      }
-    } else {
+    {
       const int ntx = (Wp + kEstCols - 1) / kEstCols;
       const int lt = item - d.est0;
       const int tr = lt / ntx, tc = lt - tr * ntx;
@@ -183,9 +167,7 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
         Rsh[k] = rkt[k];
       }
     }
-    // component range of this workgroup (LIST with a split; all K otherwise)
-    const int kbeg = (LIST && nsplit > 1) ? (int)(((int64_t)K * blockIdx.y) / nsplit) : 0;
-    const int kend = (LIST && nsplit > 1) ? (int)(((int64_t)K * (blockIdx.y + 1)) / nsplit) : K;
+    const int kbeg = 0, kend = K;
     float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
     int kA = kbeg, kB = kbeg;
     const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
@@ -250,16 +232,222 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
           pi = pidx[q];
         }
       if (!v) continue;
-      if (LIST && nsplit > 1) {
-        const int e = item * 512 + wave * 128 + 32 * pb + col;
-        part[(size_t)blockIdx.y * pcap + e] =
-            make_float4(p ? bB : bA, p ? sB : sA, __int_as_float(p ? kB : kA), 0.f);
-        continue;
-      }
       const int64_t i = d.np + (int64_t)pi;
       labels_b[i] = p ? kB : kA;
       if (best_b) best_b[i] = p ? bB : bA;
       if (second_b) second_b[i] = p ? sB : sA;
+    }
+  }
+}
+
+
+// LIST: the patches of a list (a jittered subset, Sec. 3.3) of the one image
+// dsc[0]: 128 list entries per workgroup of 8 waves, the list length read on
+// the device (a workgroup past its end exits).
+//  1. waves 0..3 each gather a block of 32 patches, one patch per load
+//     instruction (lane 8 dy + dx reads pixel (dy, dx): 8 row segments of
+//     32 bytes), transpose them through LDS to the operand layout of
+//     load_patch8 and quantize them (quantize_patch8), once;
+//  2. every wave takes 1/8 of the workgroup's component range and all 128
+//     patches (operands from LDS), each component's e4m3 table read from
+//     global memory one component ahead;
+//  3. the 8 waves' best, second and label per patch are merged in wave
+//     order, so ties stay on the lower component, as in one pass.
+// A short list is also split over the components across workgroups
+// (blockIdx.y of nsplit takes a contiguous component range and writes its
+// best, second and label per entry to part; fp8_merge_kernel combines them
+// in range order).  The costs are those of the tiled kernel, bit for bit.
+constexpr int kListItem = 128;
+constexpr int kListWaves = 8;
+constexpr int XP = 68;  // LDS pitch (floats) of a gathered patch
+
+template <bool FLAT>
+__global__ __launch_bounds__(512) void estep_fp8_list_kernel(
+    const ImgDesc* __restrict__ dsc, int t, const float* __restrict__ xb,
+    const uint4* __restrict__ Uf_all, const int32_t* __restrict__ Ue_all,
+    const float* __restrict__ L_all, const int32_t* __restrict__ rkt,
+    const float* __restrict__ P_all, int K, int32_t* __restrict__ labels_b,
+    float* __restrict__ best_b, float* __restrict__ second_b, const int32_t* __restrict__ list,
+    const int32_t* __restrict__ list_count, int nsplit, float4* __restrict__ part, int pcap) {
+  __shared__ float4 Xs4[PB * 32 * XP / 4];  // gathered pixels, then the waves' results
+  __shared__ i32x8 Zq[PB][64];
+  __shared__ int Zc[PB][64];
+  __shared__ float Nz[FLAT ? PB : 1][64];
+  __shared__ int Esh[kMaxK];
+  __shared__ float Lsh[kMaxK];
+  __shared__ float Psh[FLAT ? kMaxK : 1];
+  __shared__ int Rsh[FLAT ? kMaxK : 1];
+  static_assert(kListWaves * kListItem <= PB * 32 * XP / 4, "results fit the pixel buffer");
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const int col = lane & 31;
+  const int nlist = *list_count;
+  const int base = blockIdx.x * kListItem;
+  if (base >= nlist) return;  // (workgroup-uniform)
+  const ImgDesc d = dsc[0];
+  const int W = d.W, Wp = d.W - 7;
+  const float* x = xb + d.px;
+  const size_t slot = (size_t)(d.slot0 + t);
+  const uint4* Uf = Uf_all + slot * K * (kTileStride / 16);
+  const int32_t* Ue = Ue_all + slot * K;
+  const float* L = L_all + slot * K;
+  const float* Pk_t = FLAT ? P_all + slot * K : nullptr;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    Esh[k] = Ue[k];
+    Lsh[k] = L[k];
+    if (FLAT) {
+      Psh[k] = Pk_t[k];
+      Rsh[k] = rkt[k];
+    }
+  }
+  float* Xs = reinterpret_cast<float*>(Xs4);
+
+  // 1. gather (entries past the list end repeat a valid one; never written)
+  if (wave < PB) {
+    const int pid = list[min(base + 32 * wave + col, nlist - 1)];
+    const int pr = pid / Wp, pc = pid - pr * Wp;
+    const int dy = lane >> 3, dx = lane & 7;
+    float v[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      const int ri = __builtin_amdgcn_readlane(pr, i), ci = __builtin_amdgcn_readlane(pc, i);
+      v[i] = x[(size_t)(ri + dy) * W + ci + dx];
+    }
+    float* X = Xs + wave * 32 * XP;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) X[i * XP + lane] = v[i];
+  }
+  __syncthreads();
+  if (wave < PB) {
+    const float4* X = reinterpret_cast<const float4*>(Xs + wave * 32 * XP + col * XP + 32 * h);
+    float v[32];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float4 f = X[q];
+      v[4 * q] = f.x;
+      v[4 * q + 1] = f.y;
+      v[4 * q + 2] = f.z;
+      v[4 * q + 3] = f.w;
+    }
+    i32x8 zq;
+    int code;
+    float nz = 0.f;
+    quantize_patch8<FLAT>(v, zq, code, nz);
+    Zq[wave][lane] = zq;
+    Zc[wave][lane] = code;
+    if (FLAT) Nz[wave][lane] = nz;
+  }
+  __syncthreads();
+
+  // 2. this wave's component range
+  i32x8 zq[PB];
+  int zc[PB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb) {
+    zq[pb] = Zq[pb][lane];
+    zc[pb] = Zc[pb][lane];
+  }
+  const float nzA = FLAT ? Nz[FLAT ? h : 0][lane] : 0.f;
+  const float nzB = FLAT ? Nz[FLAT ? 2 + h : 0][lane] : 0.f;
+  const int kb = (int)(((int64_t)K * blockIdx.y) / nsplit);
+  const int ke = (int)(((int64_t)K * (blockIdx.y + 1)) / nsplit);
+  const int k0 = kb + ((ke - kb) * wave) / kListWaves;
+  const int k1 = kb + ((ke - kb) * (wave + 1)) / kListWaves;
+  float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
+  int kA = k0, kB = k0;
+  const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
+                       0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // operands of the next kPre components in a register ring (the loop is
+  // unrolled by kPre so the ring's slots are static); flat tail: the eigen
+  // blocks of 32 beyond the kept rank are zero and neither read nor
+  // multiplied
+  constexpr int kPre = 4;
+  uint4 pre[kPre][4];
+  auto fetch = [&](int k, uint4(&dst)[4]) {
+    const uint4* u = Uf + (size_t)k * 256 + lane;
+    dst[0] = u[0];
+    dst[1] = u[64];
+    if (!FLAT || Rsh[k] > 32) {
+      dst[2] = u[128];
+      dst[3] = u[192];
+    }
+  };
+#pragma unroll
+  for (int j = 0; j < kPre; ++j)
+    if (k0 + j < k1) fetch(k0 + j, pre[j]);
+  for (int kk = k0; kk < k1; kk += kPre) {
+#pragma unroll
+    for (int j = 0; j < kPre; ++j) {
+      const int k = kk + j;
+      if (k >= k1) break;
+      const int nb = ((FLAT ? Rsh[k] : kP) + 31) >> 5;
+      const uint4 cur[4] = {pre[j][0], pre[j][1], pre[j][2], pre[j][3]};
+      if (k + kPre < k1) fetch(k + kPre, pre[j]);
+      const int ek = Esh[k];
+      float q[PB];
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        if (rb >= nb) break;
+        const uint4 a0 = cur[2 * rb], a1 = cur[2 * rb + 1];
+        const i32x8 A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
+                         (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+        f32x16 acc[PB];
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb)
+          acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, zq[pb], zero, 0, 0, 0, ek,
+                                                                    0, zc[pb]);
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+      }
+      const float Lk = Lsh[k];
+      const float mA = pair_sum32(q[0], q[1]), mB = pair_sum32(q[2], q[3]);
+      if (FLAT) {
+        const float Pk = Psh[k], sg = (Rsh[k] < kP) ? -1.f : 1.f;
+        keep_best(fmaf(sg, mA, fmaf(Pk, nzA, Lk)), k, bA, sA, kA);
+        keep_best(fmaf(sg, mB, fmaf(Pk, nzB, Lk)), k, bB, sB, kB);
+      } else {
+        keep_best(Lk + mA, k, bA, sA, kA);
+        keep_best(Lk + mB, k, bB, sB, kB);
+      }
+    }
+  }
+
+  // 3. merge the waves' ranges in order (the pixel buffer is free since the
+  // second barrier)
+  float4* M = Xs4;
+  M[wave * kListItem + 32 * h + col] = make_float4(bA, sA, __int_as_float(kA), 0.f);
+  M[wave * kListItem + 32 * (2 + h) + col] = make_float4(bB, sB, __int_as_float(kB), 0.f);
+  __syncthreads();
+  if (threadIdx.x < kListItem) {
+    const int qi = threadIdx.x;
+    float b = INFINITY, s2 = INFINITY;
+    int k = kb;
+#pragma unroll
+    for (int w = 0; w < kListWaves; ++w) {
+      const float4 r = M[w * kListItem + qi];
+      if (r.x < b) {
+        s2 = fminf(b, r.y);
+        b = r.x;
+        k = __float_as_int(r.z);
+      } else {
+        s2 = fminf(s2, r.x);
+      }
+    }
+    const int e = base + qi;
+    if (e < nlist) {
+      if (nsplit > 1) {
+        part[(size_t)blockIdx.y * pcap + e] = make_float4(b, s2, __int_as_float(k), 0.f);
+      } else {
+        const int64_t i = d.np + (int64_t)list[e];
+        labels_b[i] = k;
+        if (best_b) best_b[i] = b;
+        if (second_b) second_b[i] = s2;
+      }
     }
   }
 }
@@ -272,13 +460,13 @@ hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t*
   if (blocks <= 0 || blocks > b.n_est) blocks = b.n_est;
   if (blocks < 1) return hipSuccess;
   if (rk)
-    hipLaunchKernelGGL((estep_fp8_kernel<true, false>), dim3(blocks), dim3(256), 0, st, b.d,
-                       b.est_img, b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk,
-                       Pinv, K, labels, best, second, nullptr, nullptr, 1, nullptr, 0);
+    hipLaunchKernelGGL((estep_fp8_kernel<true>), dim3(blocks), dim3(256), 0, st, b.d, b.est_img,
+                       b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K,
+                       labels, best, second);
   else
-    hipLaunchKernelGGL((estep_fp8_kernel<false, false>), dim3(blocks), dim3(256), 0, st, b.d,
-                       b.est_img, b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk,
-                       Pinv, K, labels, best, second, nullptr, nullptr, 1, nullptr, 0);
+    hipLaunchKernelGGL((estep_fp8_kernel<false>), dim3(blocks), dim3(256), 0, st, b.d, b.est_img,
+                       b.n_est, t, x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K,
+                       labels, best, second);
   return hipGetLastError();
 }
 
@@ -313,9 +501,11 @@ __global__ __launch_bounds__(256) void fp8_merge_kernel(const ImgDesc* __restric
 }
 
 int fp8_list_split(int64_t list_max, int K) {
-  // enough workgroups to fill the chip (4 per compute unit) for a short list
-  const int64_t items = (list_max + 511) / 512;
-  int64_t ns = (1024 + items - 1) / std::max<int64_t>(items, 1);
+  // a list of at least 128 workgroups runs in one pass; a shorter one is
+  // split over the components up to about 256 workgroups
+  const int64_t items = (list_max + kListItem - 1) / kListItem;
+  if (items >= 128) return 1;
+  int64_t ns = (256 + items - 1) / std::max<int64_t>(items, 1);
   ns = std::min<int64_t>(ns, std::min(16, K));
   return (int)std::max<int64_t>(ns, 1);
 }
@@ -327,19 +517,19 @@ hipError_t launch_estep_fp8_list(const ImgDesc* d, int64_t list_max, int t, cons
                                  float* best, float* second, float4* part, int* nsplit,
                                  hipStream_t st) {
   *nsplit = 1;
-  // the list length is on the device: a fixed grid strides over its chunks
-  int64_t blocks = (list_max + 511) / 512;
-  if (blocks > 768) blocks = 768;
+  // one workgroup per 128 entries of the longest list; the actual length is
+  // read on the device
+  const int64_t blocks = (list_max + kListItem - 1) / kListItem;
   if (blocks < 1) return hipSuccess;
   const int ns = part ? fp8_list_split(list_max, K) : 1;
   const int pcap = (int)list_max;
   const dim3 grid((unsigned)blocks, ns);
   if (rk)
-    hipLaunchKernelGGL((estep_fp8_kernel<true, true>), grid, dim3(256), 0, st, d, nullptr, 0, t,
-                       x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels, best,
+    hipLaunchKernelGGL((estep_fp8_list_kernel<true>), grid, dim3(64 * kListWaves), 0, st, d, t, x,
+                       reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels, best,
                        second, list, count, ns, part, pcap);
   else
-    hipLaunchKernelGGL((estep_fp8_kernel<false, true>), grid, dim3(256), 0, st, d, nullptr, 0, t,
+    hipLaunchKernelGGL((estep_fp8_list_kernel<false>), grid, dim3(64 * kListWaves), 0, st, d, t,
                        x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels, best,
                        second, list, count, ns, part, pcap);
   *nsplit = ns;

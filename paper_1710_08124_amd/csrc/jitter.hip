@@ -51,7 +51,8 @@ __device__ __forceinline__ int grid_first(int g, int s, int b) {
 
 __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, uint32_t k0,
                                                           uint32_t k1, int t, int amax, int cmax,
-                                                          int32_t* __restrict__ flags) {
+                                                          int32_t* __restrict__ flags,
+                                                          int32_t* __restrict__ count) {
   const int Hp = H - 7, Wp = W - 7;
   const int b = (8 - s) / 2;
   const U4 sh = philox4x32_10(U4{(uint32_t)t, 0xffffffffu, 0xffffffffu, 0u}, k0, k1);
@@ -62,6 +63,7 @@ __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, u
   const int na = (Hp - 1 + b - fy + s - 1) / s + 1;
   const int nc = (Wp - 1 + b - fx + s - 1) / s + 1;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *count = 0;  // the compaction that follows counts the subset
   if (i >= amax * cmax) return;
   const int a = i / cmax, c = i - a * cmax;
   if (a >= na || c >= nc) return;
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, u
 }
 
 __global__ __launch_bounds__(1024) void jitter_compact_kernel(int Np, int K,
-                                                              const int32_t* __restrict__ flags,
+                                                              int32_t* __restrict__ flags,
                                                               int32_t* __restrict__ labels,
                                                               int32_t* __restrict__ count,
                                                               int32_t* __restrict__ list) {
@@ -82,6 +84,7 @@ __global__ __launch_bounds__(1024) void jitter_compact_kernel(int Np, int K,
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool in = i < Np && flags[i] != 0;
+  if (in) flags[i] = 0;  // all zero again for the next marking
   if (i < Np && !in) labels[i] = K;
   // one global atomic per workgroup (ballots, LDS prefix)
   const uint64_t mask = __ballot(in);
@@ -110,16 +113,16 @@ int64_t jitter_points_max(int H, int W, int s) {
 }
 
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
-                              hipStream_t st) {
+                              int32_t* count, hipStream_t st) {
   const int amax = grid_points_max(H - 7, s), cmax = grid_points_max(W - 7, s);
   const int n = amax * cmax;
   hipLaunchKernelGGL(jitter_mark_kernel, dim3((n + 255) / 256), dim3(256), 0, st, H, W, s,
                      (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), t, amax, cmax,
-                     flags);
+                     flags, count);
   return hipGetLastError();
 }
 
-hipError_t launch_jitter_compact(int Np, int K, const int32_t* flags, int32_t* labels,
+hipError_t launch_jitter_compact(int Np, int K, int32_t* flags, int32_t* labels,
                                  int32_t* count, int32_t* list, hipStream_t st) {
   hipLaunchKernelGGL(jitter_compact_kernel, dim3((Np + 1023) / 1024), dim3(1024), 0, st, Np, K,
                      flags, labels, count, list);
