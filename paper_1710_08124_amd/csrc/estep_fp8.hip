@@ -358,63 +358,107 @@ __global__ __launch_bounds__(512) void estep_fp8_list_kernel(
   int kA = k0, kB = k0;
   const f32x16 zero = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f,
                        0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  // operands of the next kPre components in a register ring (the loop is
-  // unrolled by kPre so the ring's slots are static); flat tail: the eigen
-  // blocks of 32 beyond the kept rank are zero and neither read nor
-  // multiplied
+  // The component loop runs over units: one component, or (flat tail) two
+  // consecutive components whose kept ranks are both at most 16, packed in
+  // one 32-direction block (lanes with bit 4 set read the second one's
+  // directions, each with its own scale), so one MFMA projects on both.  A
+  // direction beyond a component's rank has a zero operand row, so each
+  // component's sum of squares, taken over its own 16 rows in the same
+  // order, is the one of a single-component block bit for bit.  Operands of
+  // the next kPre units wait in a register queue (slot 0 is consumed, the
+  // others move up, the new unit enters the last slot); eigen blocks of 32
+  // beyond a kept rank are neither read nor multiplied.
   constexpr int kPre = 4;
   uint4 pre[kPre][4];
-  auto fetch = [&](int k, uint4(&dst)[4]) {
-    const uint4* u = Uf + (size_t)k * 256 + lane;
-    dst[0] = u[0];
-    dst[1] = u[64];
-    if (!FLAT || Rsh[k] > 32) {
-      dst[2] = u[128];
-      dst[3] = u[192];
+  int uk[kPre];     // first component of the unit in each slot (k1: none)
+  bool up[kPre];    // the slot holds a pair
+  int kf = k0;      // first component of the next unit to fetch
+  const int hi16 = (lane >> 4) & 1;
+  auto fetch = [&](uint4(&dst)[4], int& dk, bool& dp) __attribute__((always_inline)) {
+    dk = k1;
+    dp = false;
+    if (kf >= k1) return;
+    const int k = kf;
+    const bool pair = FLAT && k + 1 < k1 && Rsh[k] <= 16 && Rsh[k + 1] <= 16;
+    dk = k;
+    dp = pair;
+    if (pair) {
+      const uint4* u = Uf + (size_t)(k + hi16) * 256 + (lane & ~16);
+      dst[0] = u[0];
+      dst[1] = u[64];
+    } else {
+      const uint4* u = Uf + (size_t)k * 256 + lane;
+      dst[0] = u[0];
+      dst[1] = u[64];
+      if (!FLAT || Rsh[k] > 32) {
+        dst[2] = u[128];
+        dst[3] = u[192];
+      }
+    }
+    kf = k + (pair ? 2 : 1);
+  };
+  // cost of component k from its squared projections q (per patch block)
+  auto score = [&](int k, const float(&q)[PB]) __attribute__((always_inline)) {
+    const float Lk = Lsh[k];
+    const float mA = pair_sum32(q[0], q[1]), mB = pair_sum32(q[2], q[3]);
+    if (FLAT) {
+      const float Pk = Psh[k], sg = (Rsh[k] < kP) ? -1.f : 1.f;
+      keep_best(fmaf(sg, mA, fmaf(Pk, nzA, Lk)), k, bA, sA, kA);
+      keep_best(fmaf(sg, mB, fmaf(Pk, nzB, Lk)), k, bB, sB, kB);
+    } else {
+      keep_best(Lk + mA, k, bA, sA, kA);
+      keep_best(Lk + mB, k, bB, sB, kB);
     }
   };
 #pragma unroll
-  for (int j = 0; j < kPre; ++j)
-    if (k0 + j < k1) fetch(k0 + j, pre[j]);
-  for (int kk = k0; kk < k1; kk += kPre) {
+  for (int j = 0; j < kPre; ++j) fetch(pre[j], uk[j], up[j]);
+  while (uk[0] < k1) {
+    const int k = uk[0];
+    const bool pair = up[0];
+    const uint4 cur[4] = {pre[0][0], pre[0][1], pre[0][2], pre[0][3]};
 #pragma unroll
-    for (int j = 0; j < kPre; ++j) {
-      const int k = kk + j;
-      if (k >= k1) break;
-      const int nb = ((FLAT ? Rsh[k] : kP) + 31) >> 5;
-      const uint4 cur[4] = {pre[j][0], pre[j][1], pre[j][2], pre[j][3]};
-      if (k + kPre < k1) fetch(k + kPre, pre[j]);
-      const int ek = Esh[k];
-      float q[PB];
+    for (int j = 0; j + 1 < kPre; ++j) {
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
+      for (int e = 0; e < 4; ++e) pre[j][e] = pre[j + 1][e];
+      uk[j] = uk[j + 1];
+      up[j] = up[j + 1];
+    }
+    fetch(pre[kPre - 1], uk[kPre - 1], up[kPre - 1]);
+    const int nb = pair ? 1 : ((FLAT ? Rsh[k] : kP) + 31) >> 5;
+    const int ek = Esh[pair ? k + hi16 : k];
+    float q[PB], q2[PB];
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb) {
-        if (rb >= nb) break;
-        const uint4 a0 = cur[2 * rb], a1 = cur[2 * rb + 1];
-        const i32x8 A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
-                         (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
-        f32x16 acc[PB];
+    for (int pb = 0; pb < PB; ++pb) q[pb] = q2[pb] = 0.f;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+      if (rb >= nb) break;
+      const uint4 a0 = cur[2 * rb], a1 = cur[2 * rb + 1];
+      const i32x8 A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
+                       (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+      f32x16 acc[PB];
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb)
+        acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, zq[pb], zero, 0, 0, 0, ek, 0,
+                                                                  zc[pb]);
+      // accumulator i holds direction 8 (i / 4) + 4 h + i % 4: i < 8 the
+      // block's first 16 directions, i >= 8 the others
+      if (pair) {
 #pragma unroll
         for (int pb = 0; pb < PB; ++pb)
-          acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, zq[pb], zero, 0, 0, 0, ek,
-                                                                    0, zc[pb]);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+            q2[pb] = fmaf(acc[pb][8 + i], acc[pb][8 + i], q2[pb]);
+          }
+      } else {
 #pragma unroll
         for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
           for (int i = 0; i < 16; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
       }
-      const float Lk = Lsh[k];
-      const float mA = pair_sum32(q[0], q[1]), mB = pair_sum32(q[2], q[3]);
-      if (FLAT) {
-        const float Pk = Psh[k], sg = (Rsh[k] < kP) ? -1.f : 1.f;
-        keep_best(fmaf(sg, mA, fmaf(Pk, nzA, Lk)), k, bA, sA, kA);
-        keep_best(fmaf(sg, mB, fmaf(Pk, nzB, Lk)), k, bB, sB, kB);
-      } else {
-        keep_best(Lk + mA, k, bA, sA, kA);
-        keep_best(Lk + mB, k, bB, sB, kB);
-      }
     }
+    score(k, q);
+    if (pair) score(k + 1, q2);
   }
 
   // 3. merge the waves' ranges in order (the pixel buffer is free since the
