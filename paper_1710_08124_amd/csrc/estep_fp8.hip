@@ -99,7 +99,7 @@ __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, 
 // columns carry sqrt(1/nu_P - 1/nu_j), Pk = 1/nu_P); a component without a
 // tail (rk = 64) takes the plain form.
 template <bool FLAT>
-__global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
+__global__ __launch_bounds__(256, FLAT ? 2 : 3) void estep_fp8_kernel(
     const ImgDesc* __restrict__ dsc, const int32_t* __restrict__ est_img, int n_est, int t,
     const float* __restrict__ xb, const uint4* __restrict__ Uf_all,
     const int32_t* __restrict__ Ue_all, const float* __restrict__ L_all,
@@ -175,26 +175,49 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     // (flat tail: the eigen blocks of 32 beyond the kept rank are zero and
     // neither staged nor multiplied)
     const int tid = threadIdx.x;
-    int rn = FLAT ? rkt[kbeg] : kP;
+    const int hi16 = (lane >> 4) & 1;
+    // units: one component, or two consecutive flat-tailed ones with kept
+    // ranks <= 16 sharing one 32-direction block (as in the list kernel
+    // below: the second one's directions in the rows with bit 4 set, each
+    // component's squares summed over its own 16 rows, bit for bit the
+    // single-component sums); staged 256 entries: the pair's two blocks, or
+    // the component's nb blocks of 128
+    auto is_pair = [&](int k) { return FLAT && k + 1 < kend && rkt[k] <= 16 && rkt[k + 1] <= 16; };
+    auto stage_src = [&](int k, bool pair, int nb) -> const uint4* {
+      if (pair) return tid < 256 ? Uf + (size_t)(k + (tid >> 7)) * 256 + (tid & 127) : nullptr;
+      return tid < 128 * nb ? Uf + (size_t)k * 256 + tid : nullptr;
+    };
+    int k = kbeg;
+    bool pair = is_pair(k);
+    int nb = pair ? 1 : ((FLAT ? rkt[k] : kP) + 31) >> 5;
     uint4 pre = make_uint4(0, 0, 0, 0);
-    if (tid < 128 * ((rn + 31) >> 5)) pre = Uf[(size_t)kbeg * 256 + tid];
-    for (int k = kbeg; k < kend; ++k) {
-      uint4* As = Ash[k & 1];
-      const int nb = (rn + 31) >> 5;
-      if (tid < 128 * nb) As[tid] = pre;
+    {
+      const uint4* src = stage_src(k, pair, nb);
+      if (src) pre = *src;
+    }
+    for (int u = 0; k < kend; ++u) {
+      uint4* As = Ash[u & 1];
+      const bool staged = pair ? tid < 256 : tid < 128 * nb;
+      if (staged) As[tid] = pre;
       __syncthreads();
-      if (k + 1 < kend) {
-        rn = FLAT ? rkt[k + 1] : kP;
-        if (tid < 128 * ((rn + 31) >> 5)) pre = Uf[(size_t)(k + 1) * 256 + tid];
+      const int kn = k + (pair ? 2 : 1);
+      bool pairn = false;
+      int nbn = 0;
+      if (kn < kend) {
+        pairn = is_pair(kn);
+        nbn = pairn ? 1 : ((FLAT ? rkt[kn] : kP) + 31) >> 5;
+        const uint4* src = stage_src(kn, pairn, nbn);
+        if (src) pre = *src;
       }
-      const int ek = Esh[k];
-      float q[PB];
+      const int ek = Esh[pair ? k + hi16 : k];
+      float q[PB], q2[PB];
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb) q[pb] = 0.f;
+      for (int pb = 0; pb < PB; ++pb) q[pb] = q2[pb] = 0.f;
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb) {
         if (FLAT && rb >= nb) break;
-        const uint4 a0 = As[(2 * rb) * 64 + lane], a1 = As[(2 * rb + 1) * 64 + lane];
+        const int ia = pair ? 128 * hi16 + (lane & ~16) : (2 * rb) * 64 + lane;
+        const uint4 a0 = As[ia], a1 = As[ia + 64];
         const i32x8 A = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
                          (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
         f32x16 acc[PB];
@@ -202,21 +225,41 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
         for (int pb = 0; pb < PB; ++pb)
           acc[pb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, zq[pb], zero, 0, 0, 0, ek,
                                                                     0, zc[pb]);
+        // accumulator i holds direction 8 (i / 4) + 4 h + i % 4
+        if (FLAT && pair) {
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb)
+          for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-          for (int i = 0; i < 16; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+            for (int i = 0; i < 8; ++i) {
+              q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+              q2[pb] = fmaf(acc[pb][8 + i], acc[pb][8 + i], q2[pb]);
+            }
+        } else {
+#pragma unroll
+          for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+        }
       }
-      const float Lk = Lsh[k];
-      const float mA = pair_sum32(q[0], q[1]), mB = pair_sum32(q[2], q[3]);
-      if (FLAT) {
-        const float Pk = Psh[k], sg = (Rsh[k] < kP) ? -1.f : 1.f;
-        keep_best(fmaf(sg, mA, fmaf(Pk, nzA, Lk)), k, bA, sA, kA);
-        keep_best(fmaf(sg, mB, fmaf(Pk, nzB, Lk)), k, bB, sB, kB);
-      } else {
-        keep_best(Lk + mA, k, bA, sA, kA);
-        keep_best(Lk + mB, k, bB, sB, kB);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c == 1 && !pair) break;
+        const int kc = k + c;
+        const float* qc = c ? q2 : q;
+        const float Lk = Lsh[kc];
+        const float mA = pair_sum32(qc[0], qc[1]), mB = pair_sum32(qc[2], qc[3]);
+        if (FLAT) {
+          const float Pk = Psh[kc], sg = (Rsh[kc] < kP) ? -1.f : 1.f;
+          keep_best(fmaf(sg, mA, fmaf(Pk, nzA, Lk)), kc, bA, sA, kA);
+          keep_best(fmaf(sg, mB, fmaf(Pk, nzB, Lk)), kc, bB, sB, kB);
+        } else {
+          keep_best(Lk + mA, kc, bA, sA, kA);
+          keep_best(Lk + mB, kc, bB, sB, kB);
+        }
       }
+      k = kn;
+      pair = pairn;
+      nb = nbn;
     }
     __syncthreads();  // the staging buffers are reused by the next tile
     // lane's own patches after the half exchange: blocks h and 2 + h
@@ -500,8 +543,17 @@ hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t*
                                   const int32_t* Ue, const float* L32, const int32_t* rk,
                                   const float* Pinv, int K, int t, int32_t* labels, float* best,
                                   float* second, int blocks, hipStream_t st) {
-  // persistent: a fixed number of workgroups looping over the tiles
+  // persistent: a fixed number of workgroups looping over the tiles, no
+  // more than fit on the device at once (the flat variant holds 2
+  // workgroups per compute unit, the plain one 3)
   if (blocks <= 0 || blocks > b.n_est) blocks = b.n_est;
+  if (rk) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+      blocks = std::min(blocks, 2 * cus);
+  }
   if (blocks < 1) return hipSuccess;
   if (rk)
     hipLaunchKernelGGL((estep_fp8_kernel<true>), dim3(blocks), dim3(256), 0, st, b.d, b.est_img,
