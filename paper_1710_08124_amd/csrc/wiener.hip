@@ -37,7 +37,11 @@ __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const floa
   // stays in the CU's L1), and consecutive ranges go to workgroups of the
   // same XCD (workgroups are dealt round-robin over the 8 XCDs), so each
   // XCD's L2 holds only the filters of its part of the list.
-  const int G = gridDim.x;
+  // With fewer tiles than the grid has waves (a patch subset), only the
+  // workgroups needed for one tile per wave take part, still dealt over all
+  // 8 XCDs.  (The grid is a multiple of 8.)
+  const int G = min((int)gridDim.x, max(8, (((total + 3) >> 2) + 7) & ~7));
+  if ((int)blockIdx.x >= G) return;
   const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
   const int per = (total + G - 1) / G;
   const int t_end = min(total, (lb + 1) * per);

@@ -163,9 +163,10 @@ def test_error_paths(F):
     import ctypes
     yi = F._image(y)
     oi = F._image(torch.empty_like(y))
-    st = F.lib().fepll_restore(g.handle, ctypes.byref(yi), ctypes.c_void_p(1), 20.0, None, 0,
+    op = F.Operator(99, 1, 1, None)  # an operator kind the library does not know
+    st = F.lib().fepll_restore(g.handle, ctypes.byref(yi), ctypes.byref(op), 20.0, None, 0,
                                ctypes.byref(oi), None, None)
-    assert st == -4
+    assert st == -1
     bad = np.array(c["y"], np.float32)
     bad[3, 4] = np.nan
     with pytest.raises(F.FepllError):
