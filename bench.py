@@ -299,7 +299,13 @@ def main():
         log(name, "timed", args.steps, "steps in", round(dt, 4), "s; graph replay",
             round(dtg, 4), "s")
         est_ms, est_n = prof["select"]
-        dom = max((k for k in prof if prof[k][1]), key=lambda k: prof[k][0])
+        # the dominant kernel: the longest stage that is one kernel (the
+        # bucketing, subset, fallback and recheck stages are several small
+        # launches each; so is the tree's level-by-level selection)
+        single = {"wiener", "ola_update", "propose"}
+        if "tree" not in name and "proposal" not in name:
+            single.add("select")
+        dom = max((k for k in prof if prof[k][1] and k in single), key=lambda k: prof[k][0])
         dom_s = prof[dom][0] / prof[dom][1] / 1e3
         fl = stage_flops(name, dom)
         return {"mpix_s": H * W * args.steps / dt / 1e6, "ms_per_step": dt / args.steps * 1e3,
