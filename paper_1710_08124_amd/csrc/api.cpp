@@ -859,6 +859,13 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
   float* xc = g->xa;
   float* xn = g->xb;
   fepll_status s;
+  // bound of any image's Wiener tile count (a jittered subset: its points)
+  int64_t max_tiles_image = 0;
+  for (const ImgDesc& d : g->hd) {
+    int64_t n = (int64_t)(d.H - 7) * (d.W - 7);
+    if (o.jitter) n = std::min<int64_t>(n, jitter_points_max(d.H, d.W, o.jitter));
+    max_tiles_image = std::max<int64_t>(max_tiles_image, n / kWienerTile + g->K);
+  }
   for (int t = 0; t < T; ++t) {
     if ((s = select_batch(g, t, o, xc, g->labels, nullptr, nullptr, nullptr, st)) != FEPLL_OK)
       return s;
@@ -867,7 +874,8 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
                           sizeof(int32_t) * b.n_patches, lkind, st));
     {
       StageTimer tm(g, 2, st);
-      HIPX(launch_bucket_batch(b, g->labels, g->K, g->hist, g->seg, g->perm, g->wbase, st));
+      HIPX(launch_bucket_batch(b, g->labels, g->K, g->hist, g->seg, g->perm, g->wbase,
+                               max_tiles_image, st));
     }
     {
       StageTimer tm(g, 3, st);

@@ -313,19 +313,136 @@ hipError_t launch_pair_bucket(const uint16_t* cand, int Np, int m, int K, int32_
   return hipGetLastError();
 }
 
+// ---- the tables of a short tile list (a patch subset) in one launch: one
+// workgroup per image does A (each component's exclusive scan over its
+// block counts: a wave per component, 64 counts per load, the loads of up to
+// kCompPerWave components in flight at once), B (a workgroup scan of counts
+// and tile counts) and C (the tile table), and with one image the Wiener
+// bases too.
+constexpr int kCompPerWave = 8;
+
+__global__ __launch_bounds__(1024) void tables_small_kernel(Batch b, int K,
+                                                            int32_t* __restrict__ hist_b,
+                                                            int32_t* __restrict__ seg_b,
+                                                            int32_t* __restrict__ wbase) {
+  __shared__ int32_t tp[kMaxK + 1];
+  __shared__ int32_t cnt[kMaxK];
+  __shared__ int32_t wa[16], wb[16];
+  const ImgDesc d = b.d[blockIdx.x];
+  const int Np = (d.H - 7) * (d.W - 7);
+  const int nb = (Np + kSortBlock - 1) / kSortBlock;
+  int32_t* hist = hist_b + (size_t)K * d.sort0;
+  int32_t* seg = seg_b + d.seg;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // A: wave w scans components w, w + 16, ...
+  for (int k0 = wave; k0 < K; k0 += 16 * kCompPerWave) {
+    int32_t carry[kCompPerWave];
+#pragma unroll
+    for (int i = 0; i < kCompPerWave; ++i) carry[i] = 0;
+    for (int j0 = 0; j0 < nb; j0 += 64) {
+      int32_t v[kCompPerWave];
+#pragma unroll
+      for (int i = 0; i < kCompPerWave; ++i) {
+        const int k = k0 + 16 * i;
+        v[i] = (k < K && j0 + lane < nb) ? hist[(size_t)k * nb + j0 + lane] : 0;
+      }
+#pragma unroll
+      for (int i = 0; i < kCompPerWave; ++i) {
+        const int k = k0 + 16 * i;
+        int32_t x = v[i];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int32_t u = __shfl_up(x, off);
+          if (lane >= off) x += u;
+        }
+        if (k < K && j0 + lane < nb) hist[(size_t)k * nb + j0 + lane] = carry[i] + x - v[i];
+        carry[i] += __shfl(x, 63);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kCompPerWave; ++i) {
+      const int k = k0 + 16 * i;
+      if (k < K && lane == 0) cnt[k] = carry[i];
+    }
+  }
+  __syncthreads();
+  const int32_t c = (tid < K) ? cnt[tid] : 0;
+  // B
+  const int32_t nt = (c + kWienerTile - 1) / kWienerTile;
+  int32_t sa = c, st = nt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t ua = __shfl_up(sa, off), ub = __shfl_up(st, off);
+    if (lane >= off) {
+      sa += ua;
+      st += ub;
+    }
+  }
+  if (lane == 63) {
+    wa[wave] = sa;
+    wb[wave] = st;
+  }
+  __syncthreads();
+  int32_t pa = 0, pt = 0, tot_c = 0, tot_t = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    pa += (w < wave) ? wa[w] : 0;
+    pt += (w < wave) ? wb[w] : 0;
+    tot_c += wa[w];
+    tot_t += wb[w];
+  }
+  if (tid < K) {
+    seg[tid] = pa + sa - c;                 // start[k]
+    seg[(K + 1) + tid] = c;                 // count[k]
+    seg[(2 * K + 1) + tid] = pt + st - nt;  // tile prefix
+    tp[tid] = pt + st - nt;
+  }
+  if (tid == 0) {
+    seg[K] = tot_c;
+    seg[3 * K + 1] = tot_t;
+    seg[3 * K + 2] = tot_t;
+    tp[K] = tot_t;
+    if (wbase) {
+      wbase[0] = 0;
+      wbase[1] = tot_t;
+    }
+  }
+  __syncthreads();
+  // C: entry t = k | (tile in k) << 10, k the last with tp[k] <= t
+  for (int tl = tid; tl < tot_t; tl += blockDim.x) {
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tp[mid] <= tl)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    seg[(3 * K + 3) + tl] = lo | ((tl - tp[lo]) << 10);
+  }
+}
+
 hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int32_t* hist,
-                               int32_t* seg, int32_t* perm, int32_t* wbase, hipStream_t st) {
+                               int32_t* seg, int32_t* perm, int32_t* wbase,
+                               int64_t max_tiles_image, hipStream_t st) {
   hipLaunchKernelGGL(hist_kernel, dim3(b.n_sort), dim3(1024), K * sizeof(int32_t), st, b, labels,
                      K, hist);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_seg_tables<true>(b, hist, seg, 0, K, kWienerTile, b.n,
-                              b.max_np / kWienerTile + K, st);
+  const bool small = max_tiles_image <= kSmallTiles;
+  if (small) {
+    hipLaunchKernelGGL(tables_small_kernel, dim3(b.n), dim3(1024), 0, st, b, K, hist, seg,
+                       b.n == 1 ? wbase : nullptr);
+    e = hipGetLastError();
+  } else {
+    e = launch_seg_tables<true>(b, hist, seg, 0, K, kWienerTile, b.n,
+                                b.max_np / kWienerTile + K, st);
+  }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(scatter_kernel, dim3(b.n_sort), dim3(1024), K * sizeof(int32_t), st, b,
                      labels, K, hist, seg, perm);
   e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || (small && b.n == 1)) return e;
   hipLaunchKernelGGL(wbase_kernel, dim3(1), dim3(1024), 0, st, b, K, seg, wbase);
   return hipGetLastError();
 }

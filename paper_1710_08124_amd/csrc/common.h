@@ -134,8 +134,12 @@ hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t*
 constexpr int kSortBlock = 16384;
 constexpr int kWienerTile = 32;
 inline size_t seg_size(size_t Np, int K) { return 3 * (size_t)K + 3 + Np / kWienerTile + K + 1; }
+// max_tiles_image bounds every image's tile count; at most kSmallTiles (a
+// patch subset), one workgroup per image builds its tables in one launch.
+constexpr int64_t kSmallTiles = 4096;
 hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int32_t* hist,
-                               int32_t* seg, int32_t* perm, int32_t* wbase, hipStream_t st);
+                               int32_t* seg, int32_t* perm, int32_t* wbase,
+                               int64_t max_tiles_image, hipStream_t st);
 
 // Pairs (patch i, candidate j < m) of the proposal, sorted by component:
 // hist [K][nb] with nb = ceil(Np / kPairBlock); seg as above with tiles of
