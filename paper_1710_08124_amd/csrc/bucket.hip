@@ -49,14 +49,17 @@ __global__ __launch_bounds__(1024) void hist_kernel(Batch b, const int32_t* __re
   int32_t* hist = hist_b + (size_t)K * sb.d.sort0;
   for (int k = threadIdx.x; k < K; k += blockDim.x) h[k] = 0;
   __syncthreads();
+  // the block's labels, all loads in flight (label K: not in the patch subset)
   const int base = sb.lb * kSortBlock;
-  for (int i = threadIdx.x; i < kSortBlock; i += blockDim.x) {
-    const int g = base + i;
-    if (g < sb.Np) {
-      const int k = labels[g];
-      if (k < K) atomicAdd(&h[k], 1);  // (label K: not in the patch subset)
-    }
+  int lab[kSortBlock / 1024];
+#pragma unroll
+  for (int u = 0; u < kSortBlock / 1024; ++u) {
+    const int g = base + u * 1024 + (int)threadIdx.x;
+    lab[u] = (g < sb.Np) ? labels[g] : K;
   }
+#pragma unroll
+  for (int u = 0; u < kSortBlock / 1024; ++u)
+    if (lab[u] < K) atomicAdd(&h[lab[u]], 1);
   __syncthreads();
   for (int k = threadIdx.x; k < K; k += blockDim.x) hist[(size_t)k * sb.nb + sb.lb] = h[k];
 }
@@ -225,13 +228,15 @@ __global__ __launch_bounds__(1024) void scatter_kernel(Batch b, const int32_t* _
     cur[k] = start[k] + offs[(size_t)k * sb.nb + sb.lb];
   __syncthreads();
   const int base = sb.lb * kSortBlock;
-  for (int i = threadIdx.x; i < kSortBlock; i += blockDim.x) {
-    const int g = base + i;
-    if (g < sb.Np) {
-      const int k = labels[g];
-      if (k < K) perm[atomicAdd(&cur[k], 1)] = g;
-    }
+  int lab[kSortBlock / 1024];
+#pragma unroll
+  for (int u = 0; u < kSortBlock / 1024; ++u) {
+    const int g = base + u * 1024 + (int)threadIdx.x;
+    lab[u] = (g < sb.Np) ? labels[g] : K;
   }
+#pragma unroll
+  for (int u = 0; u < kSortBlock / 1024; ++u)
+    if (lab[u] < K) perm[atomicAdd(&cur[lab[u]], 1)] = base + u * 1024 + (int)threadIdx.x;
 }
 
 // First Wiener tile of each image across the batch (exclusive prefix of the

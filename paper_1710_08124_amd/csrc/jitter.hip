@@ -74,33 +74,71 @@ __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, u
   flags[(size_t)r * Wp + q] = 1;
 }
 
+// 16 384 patches per workgroup (16 per thread, all flag loads in flight);
+// the list slots of the block's chosen patches follow raster order within
+// the block (a wave scan over the 16 x 16 wave counts), one global atomic
+// per block
+constexpr int kCompactPer = 16;
+
 __global__ __launch_bounds__(1024) void jitter_compact_kernel(int Np, int K,
                                                               int32_t* __restrict__ flags,
                                                               int32_t* __restrict__ labels,
                                                               int32_t* __restrict__ count,
                                                               int32_t* __restrict__ list) {
-  __shared__ int wcnt[16];
-  __shared__ int wbase[16];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ int wcnt[kCompactPer * 16];  // [chunk u][wave], then exclusive offsets
+  __shared__ int base;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const bool in = i < Np && flags[i] != 0;
-  if (in) flags[i] = 0;  // all zero again for the next marking
-  if (i < Np && !in) labels[i] = K;
-  // one global atomic per workgroup (ballots, LDS prefix)
-  const uint64_t mask = __ballot(in);
-  if (lane == 0) wcnt[wave] = __popcll(mask);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      wbase[w] = run;
-      run += wcnt[w];
-    }
-    const int base = run ? atomicAdd(count, run) : 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) wbase[w] += base;
+  const int b0 = blockIdx.x * (kCompactPer * 1024) + (int)threadIdx.x;
+  bool in[kCompactPer];
+#pragma unroll
+  for (int u = 0; u < kCompactPer; ++u) {
+    const int i = b0 + u * 1024;
+    in[u] = i < Np && flags[i] != 0;
+  }
+#pragma unroll
+  for (int u = 0; u < kCompactPer; ++u) {
+    const int i = b0 + u * 1024;
+    if (in[u])
+      flags[i] = 0;  // all zero again for the next marking
+    else if (i < Np)
+      labels[i] = K;
+  }
+  uint64_t mask[kCompactPer];
+#pragma unroll
+  for (int u = 0; u < kCompactPer; ++u) {
+    mask[u] = __ballot(in[u]);
+    if (lane == 0) wcnt[u * 16 + wave] = __popcll(mask[u]);
   }
   __syncthreads();
-  if (in && list) list[wbase[wave] + __popcll(mask & ((1ull << lane) - 1ull))] = i;
+  if (wave == 0) {
+    // lane l: entries 4 l .. 4 l + 3 of the (u, wave) order
+    int v[4], s = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = wcnt[4 * lane + q];
+      s += v[q];
+    }
+    int incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
+    }
+    int run = incl - s;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      wcnt[4 * lane + q] = run;
+      run += v[q];
+    }
+    const int total = __shfl(incl, 63);
+    if (lane == 0) base = total ? atomicAdd(count, total) : 0;
+  }
+  __syncthreads();
+  if (!list) return;
+  const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int u = 0; u < kCompactPer; ++u)
+    if (in[u]) list[base + wcnt[u * 16 + wave] + __popcll(mask[u] & below)] = b0 + u * 1024;
 }
 
 }  // namespace
@@ -124,7 +162,8 @@ hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t
 
 hipError_t launch_jitter_compact(int Np, int K, int32_t* flags, int32_t* labels,
                                  int32_t* count, int32_t* list, hipStream_t st) {
-  hipLaunchKernelGGL(jitter_compact_kernel, dim3((Np + 1023) / 1024), dim3(1024), 0, st, Np, K,
+  const int per = kCompactPer * 1024;
+  hipLaunchKernelGGL(jitter_compact_kernel, dim3((Np + per - 1) / per), dim3(1024), 0, st, Np, K,
                      flags, labels, count, list);
   return hipGetLastError();
 }
