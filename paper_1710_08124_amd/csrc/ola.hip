@@ -129,8 +129,9 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
 }
 
 // ---- subset reprojection (jittered subsampling, Sec. 3.3).  The same
-// tiles.  A tile's window is the (TY + 7) x 71 patches that touch it; a
-// patch is chosen when its label is below K.
+// tiles, each cut into parts of TY rows, one workgroup per part.  A part's
+// window is the (TY + 7) x 71 patches that touch it; a patch is chosen when
+// its label is below K.
 //   1. one bit per window patch: each window row is two ballots (columns
 //      0..63 and 64..70) over coalesced label loads; a wave scan of the rows'
 //      popcounts gives every chosen patch its slot in raster order, and the
@@ -162,9 +163,13 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
   __shared__ int rbase[WR + 1];          // chosen patches in the rows above
   __shared__ int16_t plist[WIN];         // slot -> window row * NP + column
   __shared__ float zs[CH * PITCH];
+  // a planned tile (64 x ola_rows) is cut into ola_rows / TY workgroups of
+  // TY rows (short tiles: more workgroups in flight for a sparse subset)
   const int G8 = gridDim.x;
-  const int lin = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
-  if (lin >= bt.n_ola) return;
+  const int sub = bt.ola_rows / TY;
+  const int lin2 = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
+  if (lin2 >= bt.n_ola * sub) return;
+  const int lin = lin2 / sub, part = lin2 - lin * sub;
   const ImgDesc d = bt.d[bt.ola_img[lin]];
   const int H = d.H, W = d.W;
   const int Hp = H - 7, Wp = W - 7;
@@ -173,9 +178,10 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
   const int32_t* labels = labels_b + d.np;
   const float* y = y_b + d.px;
   float* xnew = xnew_b + d.px;
-  const int nty = (H + TY - 1) / TY;
+  const int nty = (H + bt.ola_rows - 1) / bt.ola_rows;
   const int lt = lin - d.ola0;
-  const int x0 = (lt / nty) * TX, y0 = (lt % nty) * TY;
+  const int x0 = (lt / nty) * TX, y0 = (lt % nty) * bt.ola_rows + part * TY;
+  if (y0 >= H) return;  // (a part below the image)
   const int tx = threadIdx.x & 63, j = threadIdx.x >> 6;
   const int lane = tx, wave = j;
   const int rfirst = y0 - 7, cfirst = x0 - 7;
@@ -308,15 +314,10 @@ static void launch_ola_rows(const Batch& b, int blocks, const float* Zhat, const
                             const float* bvals, int t, float* xnew, const int32_t* labels, int K,
                             int raw, hipStream_t st) {
   if (SUB) {
-    if (b.ola_rows == 16)
-      hipLaunchKernelGGL(ola_subset_kernel<16>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
-                         t, xnew, labels, K, raw);
-    else if (b.ola_rows == 64)
-      hipLaunchKernelGGL(ola_subset_kernel<64>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
-                         t, xnew, labels, K, raw);
-    else
-      hipLaunchKernelGGL(ola_subset_kernel<32>, dim3(blocks), dim3(256), 0, st, b, Zhat, y, bvals,
-                         t, xnew, labels, K, raw);
+    // 16-row parts of every planned tile (the planned heights are 16, 32, 64)
+    const int parts = ((int)(((int64_t)b.n_ola * (b.ola_rows / 16) + 7) & ~7));
+    hipLaunchKernelGGL(ola_subset_kernel<16>, dim3(parts), dim3(256), 0, st, b, Zhat, y, bvals, t,
+                       xnew, labels, K, raw);
     return;
   }
   if (b.ola_rows == 16)
