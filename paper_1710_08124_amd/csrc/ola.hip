@@ -185,6 +185,14 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
   const int tx = threadIdx.x & 63, j = threadIdx.x >> 6;
   const int lane = tx, wave = j;
   const int rfirst = y0 - 7, cfirst = x0 - 7;
+  // y of the thread's pixels, loaded now so that the update at the end does
+  // not wait for them
+  float yv[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int yy = y0 + j + 4 * i;
+    yv[i] = (!raw && yy < H && x0 + tx < W) ? y[(size_t)yy * W + x0 + tx] : 0.f;
+  }
 
   // 1. masks: wave w takes window rows w, w + 4, ... (all loads first)
   {
@@ -304,7 +312,7 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
     if (yy < H && xx < W) {
       const size_t o = (size_t)yy * W + xx;
       const float xt = acc[i] / cnt[i];
-      xnew[o] = raw ? xt : (y[o] + b * xt) / onepb;
+      xnew[o] = raw ? xt : (yv[i] + b * xt) / onepb;
     }
   }
 }
