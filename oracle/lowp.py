@@ -167,7 +167,8 @@ def basis_operand(U: np.ndarray, nu: np.ndarray, mode: str, rank=None) -> np.nda
 
 # ----------------------------------------------------------- selection
 
-def lowp_costs(x, U, lam, w, beta, mode: str, acc_eps: float | None = None, rank=None):
+def lowp_costs(x, U, lam, w, beta, mode: str, acc_eps: float | None = None, rank=None,
+               patches=None):
     """Selection costs (Np x K, float64) of every valid patch of the float32
     image x in a reduced-precision mode: float32(L_k) + sum_j c_j^2 with c
     the exact product of the rounded operands.  With ``rank`` (lam then the
@@ -176,10 +177,15 @@ def lowp_costs(x, U, lam, w, beta, mode: str, acc_eps: float | None = None, rank
     With ``acc_eps``, also return a bound (Np x K) on how far an evaluation
     may land from these costs when it accumulates each projection c_j with a
     relative error of at most acc_eps of sum_p |Ut[p,j] z[p]| and the 64
-    squares, |z~|^2, and the terms of the cost in float32."""
+    squares, |z~|^2, and the terms of the cost in float32.
+
+    ``patches``: indices (r (W - 7) + c) of the valid patches to evaluate
+    (default: all, in that order)."""
     x = np.asarray(x, np.float32)
     H, W = x.shape
     r, c = o.patch_corners(H, W)
+    if patches is not None:
+        r, c = r[patches], c[patches]
     Z = o.extract(x.astype(np.float64), r, c).astype(np.float32)  # exact: x is float32
     Zt32 = dc_removed32(Z, mode)
     Zq = patch_operand(Zt32, mode)

@@ -139,6 +139,40 @@ def test_fp32_full_size_end_to_end(F):
     assert abs(d) < 0.01
 
 
+@pytest.mark.parametrize("rho", [None, 0.95])
+def test_e4m3_list_full_size_sampled(F, rho):
+    """The benchmarked configuration: 1024^2, K = 200, sigma 25, e4m3, s = 6
+    (29 346 chosen patches: one list workgroup per 128 entries, no component
+    split), plain and flat-tailed.  The chosen patches equal the reference's;
+    the labels of 3000 sampled chosen patches agree with the mode's
+    definition except at its near-ties."""
+    from oracle import flat_tail as ft
+    c = fs.config_c3()
+    y32 = np.asarray(c["y"], np.float32)
+    beta = float(o.default_betas(25.0)[0])
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    lam, r = c["lam"], None
+    if rho is not None:
+        r = g.flat_tail(rho)
+        lam, want_r = ft.flat_tail(c["lam"], rho)
+        np.testing.assert_array_equal(r, want_r)
+    seed = 20171023
+    _, lab = F.restore(g, dev(y32), 25.0, betas=[beta], precision="fp8", jitter=6, seed=seed,
+                       return_labels=True)
+    lab = lab.cpu().numpy()[0]
+    idx, _ = jt.positions(1024, 1024, 6, seed, 0)
+    np.testing.assert_array_equal(np.nonzero(lab < 200)[0], idx)
+    sel = np.sort(fs.rng(3).choice(idx, 3000, replace=False))
+    cost, bnd = lowp.lowp_costs(y32, c["U"], lam, c["w"], beta, "fp8", acc_eps=2.0 ** -12,
+                                rank=r, patches=sel)
+    srt = np.sort(cost, 1)
+    gap = srt[:, 1] - srt[:, 0]
+    tol = bnd.max(1)
+    same = lab[sel] == cost.argmin(1)
+    print(f"1024^2 e4m3 list rho={rho}: {idx.size} chosen, sampled agreement {same.mean():.5f}")
+    assert np.all(same | (gap <= 2 * tol))
+
+
 @pytest.mark.parametrize("mode", ["bf16", "fp8"])
 @pytest.mark.parametrize("s,shape", [(6, (96, 200)), (3, (40, 300)), (4, (71, 9))])
 def test_lowp_list_selection_matches_definition(F, mode, s, shape):
