@@ -124,11 +124,19 @@ struct fepll_gmm {
     double* w64 = nullptr;
     int32_t* rk = nullptr;
     uint16_t* children = nullptr;  // [Kall][8]
+    // the top levels scored densely (levels 1..dense_levels, each of at
+    // most kDenseNodes nodes): node ids in level order, their parents' ids,
+    // each level's end position
+    int dense_levels = 0, dense_n = 0;
+    int32_t* dnode = nullptr;
+    int32_t* dpar = nullptr;
+    int32_t* dlend = nullptr;
     ConstTables tb{};
     std::vector<double> cbeta;
     size_t S_cap = 0;
     double* dbeta = nullptr;
   } tree;
+  uint64_t tree_gen = 0;  // counts fepll_gmm_set_tree calls
   float* ybuf = nullptr;
   float* xa = nullptr;
   float* xb = nullptr;
@@ -170,6 +178,7 @@ struct fepll_gmm {
 namespace {
 
 constexpr int kStages = 9;
+constexpr int kDenseNodes = 16;  // tree levels of at most this many nodes are scored densely
 constexpr int kDefaultT = 5;
 const double kDefaultB[kDefaultT] = {1.0, 4.0, 8.0, 16.0, 32.0};
 
@@ -583,10 +592,6 @@ fepll_status select_tree(fepll_gmm* g, const float* x, int H, int W, int slot,
   const int Np = (H - 7) * (W - 7);
   const size_t K = T.Kall;
   StageTimer tm(g, 0, st);
-  HIPX(launch_records_bf16(x, H, W, g->zop, g->znz, st));
-  hipLaunchKernelGGL(fill_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, labels, Np,
-                     T.root);
-  HIPX(hipGetLastError());
   if (flags) {
     hipLaunchKernelGGL(zero_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, flags, Np);
     HIPX(hipGetLastError());
@@ -594,7 +599,35 @@ fepll_status select_tree(fepll_gmm* g, const float* x, int H, int W, int slot,
   const uint16_t* Ub = T.tb.Ub + (size_t)slot * K * kTileStride;
   const float* L = T.tb.L32 + (size_t)slot * K;
   const float* Pinv = T.tb.Pinv + (size_t)slot * K;
-  for (int lev = 1; lev < T.nlevels; ++lev) {
+  const bool sparse = T.dense_levels + 1 < T.nlevels;  // levels left after the dense ones
+  if (T.dense_levels > 0) {
+    TreeDenseArgs a{};
+    a.x = x;
+    a.H = H;
+    a.W = W;
+    a.Ub = Ub;
+    a.L = L;
+    a.rk = T.tb.rk;
+    a.Pinv = Pinv;
+    a.node = T.dnode;
+    a.par = T.dpar;
+    a.lend = T.dlend;
+    a.n = T.dense_n;
+    a.nlev = T.dense_levels;
+    a.root = T.root;
+    a.labels = labels;
+    a.best = sparse ? nullptr : best;
+    a.second = sparse ? nullptr : second;
+    a.zop = sparse ? reinterpret_cast<uint4*>(g->zop) : nullptr;
+    a.znz = sparse ? g->znz : nullptr;
+    HIPX(launch_tree_dense_bf16(a, st));
+  } else {
+    HIPX(launch_records_bf16(x, H, W, g->zop, g->znz, st));
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, labels, Np,
+                       T.root);
+    HIPX(hipGetLastError());
+  }
+  for (int lev = T.dense_levels + 1; lev < T.nlevels; ++lev) {
     HIPX(launch_tree_cand(labels, Np, T.children, g->cand, st));
     HIPX(launch_pair_bucket(g->cand, Np, T.maxch, T.Kall, g->phist, g->pseg, g->psorted, st));
     HIPX(launch_pair_scores_bf16(g->zop, g->znz, Np, Ub, L, T.tb.rk, Pinv, T.Kall, T.maxch,
@@ -934,8 +967,9 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
                         g->tb.rk,   g->tb.Pinv, g->zop,  g->znz,
                         g->jflags,  g->jlist,   g->jcount, g->jpart,
                         g->tree.tb.Ub, g->tree.tb.L32, g->tree.tb.Pinv, g->tree.rk,
-                        g->tree.children};
+                        g->tree.children, g->tree.dnode, g->tree.dpar, g->tree.dlend};
   for (const void* p : ptrs) put(key, p);
+  put(key, g->tree_gen);  // a new tree may reuse the old one's addresses
   if (g->gexec && key == g->gkey) {
     *result = (T % 2) ? g->xb : g->xa;
     HIPX(hipGraphLaunch(g->gexec, st));
@@ -1206,6 +1240,9 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->tree.w64);
   dfree(g->tree.rk);
   dfree(g->tree.children);
+  dfree(g->tree.dnode);
+  dfree(g->tree.dpar);
+  dfree(g->tree.dlend);
   dfree(g->tree.dbeta);
   dfree(g->tree.tb.Ub);
   dfree(g->tree.tb.Wt);
@@ -1509,12 +1546,16 @@ fepll_status fepll_gmm_set_tree(fepll_gmm* g, int32_t nlevels, const int32_t* si
   auto& T = g->tree;
   const int K = g->K;
   HIPX(hipDeviceSynchronize());
+  ++g->tree_gen;
   auto clear = [&]() {
     dfree(T.U64);
     dfree(T.lam64);
     dfree(T.w64);
     dfree(T.rk);
     dfree(T.children);
+    dfree(T.dnode);
+    dfree(T.dpar);
+    dfree(T.dlend);
     T = fepll_gmm::Tree{};
   };
   if (nlevels == 0) {
@@ -1636,6 +1677,29 @@ fepll_status fepll_gmm_set_tree(fepll_gmm* g, int32_t nlevels, const int32_t* si
   HIPX(hipMemcpy(T.U64, T.U_h.data(), sizeof(double) * T.U_h.size(), hipMemcpyHostToDevice));
   HIPX(hipMemcpy(T.w64, w.data(), sizeof(double) * Kall, hipMemcpyHostToDevice));
   HIPX(hipMemcpy(T.children, ch.data(), sizeof(uint16_t) * ch.size(), hipMemcpyHostToDevice));
+  {
+    // dense top levels: a level of few nodes costs less scored for every
+    // patch in one pass than sorted into (patch, child) pairs
+    std::vector<int32_t> dn, dp, de;
+    int lev = 1;
+    for (; lev < nlevels && sizes[lev] <= kDenseNodes; ++lev) {
+      for (int i = 0; i < sizes[lev]; ++i) {
+        dn.push_back(id(lev, i));
+        dp.push_back(id(lev - 1, par[lev][i]));
+      }
+      de.push_back((int32_t)dn.size());
+    }
+    T.dense_levels = lev - 1;
+    T.dense_n = (int)dn.size();
+    if (T.dense_levels > 0) {
+      HIPX(dalloc(&T.dnode, dn.size()));
+      HIPX(dalloc(&T.dpar, dp.size()));
+      HIPX(dalloc(&T.dlend, de.size()));
+      HIPX(hipMemcpy(T.dnode, dn.data(), sizeof(int32_t) * dn.size(), hipMemcpyHostToDevice));
+      HIPX(hipMemcpy(T.dpar, dp.data(), sizeof(int32_t) * dp.size(), hipMemcpyHostToDevice));
+      HIPX(hipMemcpy(T.dlend, de.data(), sizeof(int32_t) * de.size(), hipMemcpyHostToDevice));
+    }
+  }
   g->plan_valid = false;  // the pair scratch is sized for the tree's nodes
   return tree_upload_spectra(g);
 }

@@ -33,6 +33,8 @@
 // In the all-K modes the per-component operand is staged through
 // double-buffered LDS shared by the workgroup's 4 waves (one barrier per
 // component, the next component's operand already loading).
+#include <algorithm>
+
 #include "common.h"
 #include "propose.h"
 #include "wave_ops.h"
@@ -515,6 +517,125 @@ __global__ __launch_bounds__(256) void tree_cand_kernel(const int32_t* __restric
                                                         uint4* __restrict__ cand) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < Np) cand[i] = children[cur[i]];
+}
+
+// The top levels of the tree descent, dense: the spatial all-K loop over
+// the listed nodes instead of the K components (same staging, same score()),
+// each lane keeping, per own patch, the best child of its current node.
+template <bool FLAT>
+__global__ __launch_bounds__(256, 3) void tree_dense_bf16_kernel(TreeDenseArgs a) {
+  __shared__ uint4 Ash[2][512];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int col = lane & 15;
+  const int Hp = a.H - 7, Wp = a.W - 7;
+  const int ntx = (Wp + kEstCols - 1) / kEstCols;
+  const int items = ntx * ((Hp + 3) / 4);
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int tr = item / ntx, tc = item - (item / ntx) * ntx;
+    const int r = tr * 4 + wave;
+    const int c0 = tc * (16 * PB);
+    int idx[PB];
+    bool valid[PB];
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int c = c0 + 16 * pb + col;
+      valid[pb] = (r < Hp) && (c < Wp);
+      idx[pb] = min(r, Hp - 1) * Wp + min(c, Wp - 1);
+    }
+    uint4 zb[PB][2];
+    float nzA = 0.f, nzB = 0.f;
+    const int own = 4 * (g >> 1) + 2 * (g & 1);
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      float nz = 0.f;
+      const int pr = idx[pb] / Wp;
+      load_patch<FLAT>(a.x, a.W, pr, idx[pb] - pr * Wp, g, zb[pb], nz);
+      if (a.zop && valid[pb]) {  // the records of the levels below
+        a.zop[(size_t)idx[pb] * 8 + g] = zb[pb][0];
+        a.zop[(size_t)idx[pb] * 8 + 4 + g] = zb[pb][1];
+        if (FLAT && g == 0) a.znz[idx[pb]] = nz;
+      }
+      if (FLAT) {
+        nzA = (pb == own) ? nz : nzA;
+        nzB = (pb == own + 1) ? nz : nzB;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    int iA = idx[0], iB = idx[1];
+    bool vA = valid[0], vB = valid[1];
+#pragma unroll
+    for (int pb = 0; pb < PB; pb += 2)
+      if (pb == own) {
+        iA = idx[pb];
+        iB = idx[pb + 1];
+        vA = valid[pb];
+        vB = valid[pb + 1];
+      }
+    int curA = a.root, curB = a.root;
+    float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
+    int kA = a.root, kB = a.root;
+    {
+      const uint4* gsrc = reinterpret_cast<const uint4*>(a.Ub);
+      const int tid = threadIdx.x;
+      int id = a.node[0];
+      int rn = FLAT ? a.rk[id] : kP;
+      int nu4 = FLAT ? 128 * ((rn + 15) >> 4) : 512;
+      uint4 pre0 = make_uint4(0, 0, 0, 0), pre1 = make_uint4(0, 0, 0, 0);
+      if (tid < nu4) pre0 = gsrc[(size_t)id * 512 + tid];
+      if (256 + tid < nu4) pre1 = gsrc[(size_t)id * 512 + 256 + tid];
+      int lev = 0, lend = a.lend[0];
+      for (int j = 0; j < a.n; ++j) {
+        uint4* As = Ash[j & 1];
+        const int k = id, rk = rn;
+        if (tid < nu4) As[tid] = pre0;
+        if (256 + tid < nu4) As[256 + tid] = pre1;
+        __syncthreads();
+        if (j + 1 < a.n) {
+          id = a.node[j + 1];
+          rn = FLAT ? a.rk[id] : kP;
+          nu4 = FLAT ? 128 * ((rn + 15) >> 4) : 512;
+          if (tid < nu4) pre0 = gsrc[(size_t)id * 512 + tid];
+          if (256 + tid < nu4) pre1 = gsrc[(size_t)id * 512 + 256 + tid];
+        }
+        float cA, cB;
+        score<FLAT>(As + lane, zb, a.L[k], rk, FLAT ? a.Pinv[k] : 0.f, nzA, nzB, cA, cB);
+        const int p = a.par[j];
+        if (p == curA) keep_best(cA, k, bA, sA, kA);
+        if (p == curB) keep_best(cB, k, bB, sB, kB);
+        if (j + 1 == lend) {  // the level's end: move down (children in index order)
+          curA = kA;
+          curB = kB;
+          if (++lev < a.nlev) {
+            lend = a.lend[lev];
+            bA = sA = bB = sB = INFINITY;
+          }
+        }
+      }
+      __syncthreads();  // the staging buffers are reused by the next item
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (!(p ? vB : vA)) continue;
+      const int i = p ? iB : iA;
+      a.labels[i] = p ? curB : curA;
+      if (a.best) a.best[i] = p ? bB : bA;
+      if (a.second) a.second[i] = p ? sB : sA;
+    }
+  }
+}
+
+hipError_t launch_tree_dense_bf16(const TreeDenseArgs& a, hipStream_t st) {
+  const int Hp = a.H - 7, Wp = a.W - 7;
+  const int items = ((Wp + kEstCols - 1) / kEstCols) * ((Hp + 3) / 4);
+  const int blocks = std::min(items, 768);
+  if (blocks < 1 || a.n < 1) return hipSuccess;
+  if (a.rk)
+    hipLaunchKernelGGL(tree_dense_bf16_kernel<true>, dim3(blocks), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(tree_dense_bf16_kernel<false>, dim3(blocks), dim3(256), 0, st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_records_bf16(const float* x, int H, int W, uint16_t* zop, float* znz,

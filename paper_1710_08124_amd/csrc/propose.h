@@ -65,6 +65,34 @@ hipError_t launch_records_bf16(const float* x, int H, int W, uint16_t* zop, floa
 hipError_t launch_tree_cand(const int32_t* cur, int Np, const uint16_t* children, uint16_t* cand,
                             hipStream_t st);
 
+// The top levels of the descent in one pass over the image: positions
+// 0..n-1 list the nodes of those levels in order (node: node id, par: its
+// parent's id, lend: the end position of each of the nlev levels); every
+// patch starts at root, scores each node whose parent is its current node
+// (the bfloat16 selection cost of the tree tables Ub / L / rk / Pinv of one
+// beta, indexed by node id) and moves to the best at each level's end.
+// labels: the node reached; best / second (or NULL): the last level's; zop /
+// znz (or NULL): the patches' operand records, as launch_records_bf16 writes
+// them.
+struct TreeDenseArgs {
+  const float* x;
+  int H, W;
+  const uint16_t* Ub;
+  const float* L;
+  const int32_t* rk;  // NULL: plain form
+  const float* Pinv;
+  const int32_t* node;
+  const int32_t* par;
+  const int32_t* lend;
+  int n, nlev, root;
+  int32_t* labels;
+  float* best;
+  float* second;
+  uint4* zop;
+  float* znz;
+};
+hipError_t launch_tree_dense_bf16(const TreeDenseArgs& a, hipStream_t st);
+
 // Network inference + top-m: cand[i] gets the m best classes of patch i in
 // decreasing logit order (ties to the lower class), 0xffff after the m-th.
 // Wb / bias: see propose.hip.  zop (Np x 64 bfloat16) / znz (Np floats):
