@@ -99,7 +99,7 @@ __device__ __forceinline__ void load_patch8(const float* __restrict__ x, int W, 
 // columns carry sqrt(1/nu_P - 1/nu_j), Pk = 1/nu_P); a component without a
 // tail (rk = 64) takes the plain form.
 template <bool FLAT>
-__global__ __launch_bounds__(256, FLAT ? 2 : 3) void estep_fp8_kernel(
+__global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
     const ImgDesc* __restrict__ dsc, const int32_t* __restrict__ est_img, int n_est, int t,
     const float* __restrict__ xb, const uint4* __restrict__ Uf_all,
     const int32_t* __restrict__ Ue_all, const float* __restrict__ L_all,
@@ -543,17 +543,8 @@ hipError_t launch_estep_fp8_batch(const Batch& b, const float* x, const uint8_t*
                                   const int32_t* Ue, const float* L32, const int32_t* rk,
                                   const float* Pinv, int K, int t, int32_t* labels, float* best,
                                   float* second, int blocks, hipStream_t st) {
-  // persistent: a fixed number of workgroups looping over the tiles, no
-  // more than fit on the device at once (the flat variant holds 2
-  // workgroups per compute unit, the plain one 3)
+  // persistent: a fixed number of workgroups looping over the tiles
   if (blocks <= 0 || blocks > b.n_est) blocks = b.n_est;
-  if (rk) {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        cus > 0)
-      blocks = std::min(blocks, 2 * cus);
-  }
   if (blocks < 1) return hipSuccess;
   if (rk)
     hipLaunchKernelGGL((estep_fp8_kernel<true>), dim3(blocks), dim3(256), 0, st, b.d, b.est_img,
