@@ -169,7 +169,9 @@ struct fepll_gmm {
   struct Mark {
     int stage;
     hipEvent_t a, b;
+    bool own_a;  // false: a is the previous mark's b
   };
+  hipEvent_t chain_ev = nullptr;  // the last stage's end event, for a stage that follows at once
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
   bool profiling = false;
@@ -196,28 +198,42 @@ hipEvent_t take_event(fepll_gmm* g) {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // timing only: no system-scope fence (an L2 writeback and invalidation on
+  // every record, which would slow the stages being timed)
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
 // Brackets one stage with events when profiling is on.
+// chain: the stage follows the previous timed stage with no launch between,
+// so the previous end event is its start (one record fewer).
 struct StageTimer {
   fepll_gmm* g;
   int stage;
   hipStream_t st;
   hipEvent_t a = nullptr;
-  StageTimer(fepll_gmm* g_, int s_, hipStream_t st_) : g(g_), stage(s_), st(st_) {
-    if (g->profiling && (a = take_event(g))) (void)hipEventRecord(a, st);
+  bool own_a = true;
+  StageTimer(fepll_gmm* g_, int s_, hipStream_t st_, bool chain = false)
+      : g(g_), stage(s_), st(st_) {
+    if (!g->profiling) return;
+    if (chain && g->chain_ev) {
+      a = g->chain_ev;
+      own_a = false;
+    } else if ((a = take_event(g))) {
+      (void)hipEventRecord(a, st);
+    }
+    g->chain_ev = nullptr;
   }
   ~StageTimer() {
     if (!a) return;
     hipEvent_t b = take_event(g);
     if (!b) {
-      g->pool.push_back(a);
+      if (own_a) g->pool.push_back(a);
       return;
     }
     (void)hipEventRecord(b, st);
-    g->marks.push_back({stage, a, b});
+    g->marks.push_back({stage, a, b, own_a});
+    g->chain_ev = b;
   }
 };
 
@@ -775,7 +791,7 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
                          : nullptr;
       int ns = 1;
       {
-        StageTimer tm(g, 0, st);  // the selection kernel alone
+        StageTimer tm(g, 0, st, true);  // the selection kernel alone
         HIPX(launch_estep_fp8_list(g->d + i, lmax, t, x, g->tb.Uf, g->tb.Ue, g->tb.L32,
                                    g->tb.rk, g->tb.Pinv, g->K, g->jcount + i, g->jlist + d.np,
                                    labels, nullptr, nullptr, part, &ns, st));
@@ -906,17 +922,17 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
       HIPX(hipMemcpyAsync(labels_out + (size_t)t * b.n_patches, g->labels,
                           sizeof(int32_t) * b.n_patches, lkind, st));
     {
-      StageTimer tm(g, 2, st);
+      StageTimer tm(g, 2, st, labels_out == nullptr);
       HIPX(launch_bucket_batch(b, g->labels, g->K, g->hist, g->seg, g->perm, g->wbase,
                                max_tiles_image, st));
     }
     {
-      StageTimer tm(g, 3, st);
+      StageTimer tm(g, 3, st, true);
       HIPX(launch_wiener_batch(b, xc, g->tb.Wt, g->K, t, g->seg, g->perm, g->wbase, g->Zhat,
                                g->tune.wiener_blocks, st));
     }
     {
-      StageTimer tm(g, 4, st);
+      StageTimer tm(g, 4, st, true);
       HIPX(launch_ola_batch(b, g->Zhat, g->ybuf, g->bvals, t, xn,
                             o.jitter ? g->labels : nullptr, g->K, deblur_b ? 1 : 0, st));
       if (deblur_b) {
@@ -1173,10 +1189,11 @@ fepll_status fepll_profile(fepll_gmm* g, double* ms, int32_t* launches, int32_t 
       ret = fail(FEPLL_EDEVICE, std::string("event timing failed: ") + hipGetErrorString(e));
     acc[m.stage] += t;
     cnt[m.stage] += 1;
-    g->pool.push_back(m.a);
+    if (m.own_a) g->pool.push_back(m.a);
     g->pool.push_back(m.b);
   }
   g->marks.clear();
+  g->chain_ev = nullptr;
   for (int i = 0; i < n && i < kStages; ++i) {
     if (ms) ms[i] = acc[i];
     if (launches) launches[i] = cnt[i];
@@ -1188,7 +1205,7 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   if (!g) return;
   (void)hipDeviceSynchronize();
   for (auto& m : g->marks) {
-    (void)hipEventDestroy(m.a);
+    if (m.own_a) (void)hipEventDestroy(m.a);
     (void)hipEventDestroy(m.b);
   }
   for (auto e : g->pool) (void)hipEventDestroy(e);
