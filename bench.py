@@ -139,8 +139,9 @@ def main():
                     help="also time the deblurring workload (1) or not (0)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(images are independent; see the design notes on sharding)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the images of a batch are independent and would be split across GPUs)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -50,7 +50,7 @@ typedef enum {
   FEPLL_EINVAL = -1,       /* an argument is out of its documented range   */
   FEPLL_ENOMEM = -2,       /* a device or host allocation failed            */
   FEPLL_EDEVICE = -3,      /* a HIP runtime call failed                     */
-  FEPLL_EUNSUPPORTED = -4, /* a valid request this build does not implement */
+  FEPLL_EUNSUPPORTED = -4, /* a valid request the library does not implement */
   FEPLL_ECHECKSUM = -5     /* a serialized blob failed its integrity check  */
 } fepll_status;
 
