@@ -548,7 +548,7 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     g->px_cap = PX;
   }
   if (!g->count) HIPX(dalloc(&g->count, 64));
-  if ((s = grow(&g->jcount, g->jcount_cap, (size_t)n)) != FEPLL_OK) return s;
+  if ((s = grow(&g->jcount, g->jcount_cap, 2 * (size_t)n)) != FEPLL_OK) return s;
   if ((s = grow(&g->hist, g->hist_cap, (size_t)K * sort.size())) != FEPLL_OK) return s;
   if ((s = grow(&g->seg, g->seg_cap, (size_t)seg)) != FEPLL_OK) return s;
   if (!same) {
@@ -757,26 +757,40 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
         return s;
     }
   }
+  // the reduced-precision paths append each iteration's list to its own
+  // count (two alternating sets: run_hqs resets one while the other fills)
+  int32_t* cnt = g->jcount + ((o.precision == FEPLL_FP32) ? 0 : (size_t)(t & 1) * b.n);
   {
     // the chosen patches of every image (stage 8: subset).  The position
-    // flags are all zero between calls (the compaction clears what the
-    // marking set); after a new allocation or an interrupted call they are
-    // cleared first.
+    // flags are all zero between calls; after a new allocation or an
+    // interrupted call they are cleared first.
     StageTimer tm(g, 8, st);
-    if (g->jflags_dirty) {
-      hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n);
-      HIPX(hipGetLastError());
+    if (o.precision == FEPLL_FP32) {
+      // every patch was selected: flag the subset, then list it and give the
+      // others the label K (the compaction clears the flags again)
+      if (g->jflags_dirty) {
+        hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags,
+                           n);
+        HIPX(hipGetLastError());
+      }
+      g->jflags_dirty = true;
+      for (int i = 0; i < b.n; ++i) {
+        const ImgDesc& d = g->hd[i];
+        const int Np = (d.H - 7) * (d.W - 7);
+        HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, cnt + i,
+                                nullptr, st));
+        HIPX(launch_jitter_compact(Np, g->K, g->jflags + d.np, labels + d.np, cnt + i,
+                                   g->jlist + d.np, st));
+      }
+      g->jflags_dirty = false;
+    } else {
+      // every label is K here (run_hqs): list the subset as it is drawn
+      for (int i = 0; i < b.n; ++i) {
+        const ImgDesc& d = g->hd[i];
+        HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, cnt + i,
+                                g->jlist + d.np, st));
+      }
     }
-    g->jflags_dirty = true;
-    for (int i = 0; i < b.n; ++i) {
-      const ImgDesc& d = g->hd[i];
-      const int Np = (d.H - 7) * (d.W - 7);
-      HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, g->jcount + i,
-                              st));
-      HIPX(launch_jitter_compact(Np, g->K, g->jflags + d.np, labels + d.np, g->jcount + i,
-                                 g->jlist + d.np, st));
-    }
-    g->jflags_dirty = false;
   }
   if (o.precision == FEPLL_FP32) return FEPLL_OK;
   for (int i = 0; i < b.n; ++i) {
@@ -793,12 +807,12 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
       {
         StageTimer tm(g, 0, st, true);  // the selection kernel alone
         HIPX(launch_estep_fp8_list(g->d + i, lmax, t, x, g->tb.Uf, g->tb.Ue, g->tb.L32,
-                                   g->tb.rk, g->tb.Pinv, g->K, g->jcount + i, g->jlist + d.np,
+                                   g->tb.rk, g->tb.Pinv, g->K, cnt + i, g->jlist + d.np,
                                    labels, nullptr, nullptr, part, &ns, st));
       }
       StageTimer tm(g, 8, st);  // the merge of the component ranges
-      HIPX(launch_fp8_merge(g->d + i, lmax, g->jcount + i, g->jlist + d.np, part, ns, labels,
-                            nullptr, nullptr, st));
+      HIPX(launch_fp8_merge(g->d + i, lmax, cnt + i, g->jlist + d.np, part, ns, labels, nullptr,
+                            nullptr, st));
     } else {
       StageTimer tm(g, 0, st);
       BF16Args a{};
@@ -809,7 +823,7 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
       a.L = g->tb.L32 + (size_t)slot * K;
       a.K = g->K;
       a.labels = labels + d.np;
-      a.list_count = g->jcount + i;
+      a.list_count = cnt + i;
       a.list = g->jlist + d.np;
       a.rk = g->tb.rk;
       a.Pinv = g->tb.Pinv + (size_t)slot * K;
@@ -915,6 +929,24 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     if (o.jitter) n = std::min<int64_t>(n, jitter_points_max(d.H, d.W, o.jitter));
     max_tiles_image = std::max<int64_t>(max_tiles_image, n / kWienerTile + g->K);
   }
+  // jittered subsets in a reduced precision: each iteration lists its
+  // patches as it draws them, and the patches off the list keep the label K
+  // (set here for all, restored after every iteration for the listed ones)
+  const bool jit_list = o.jitter && o.precision != FEPLL_FP32;
+  if (jit_list) {
+    const int n = (int)b.n_patches;
+    if (g->jflags_dirty) {
+      hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n);
+      HIPX(hipGetLastError());
+    }
+    g->jflags_dirty = true;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->labels, n,
+                       g->K);
+    HIPX(hipGetLastError());
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((2 * b.n + 255) / 256), dim3(256), 0, st, g->jcount,
+                       2 * b.n);
+    HIPX(hipGetLastError());
+  }
   for (int t = 0; t < T; ++t) {
     if ((s = select_batch(g, t, o, xc, g->labels, nullptr, nullptr, nullptr, st)) != FEPLL_OK)
       return s;
@@ -940,8 +972,22 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
         if (s2 != FEPLL_OK) return s2;
       }
     }
+    if (jit_list) {
+      // the listed patches back to flag 0 and label K, the next count to 0
+      StageTimer tm(g, 8, st, !deblur_b);
+      int32_t* cur = g->jcount + (size_t)(t & 1) * b.n;
+      int32_t* nxt = g->jcount + (size_t)((t + 1) & 1) * b.n;
+      for (int i = 0; i < b.n; ++i) {
+        const ImgDesc& d = g->hd[i];
+        const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter),
+                                               (int64_t)(d.H - 7) * (d.W - 7));
+        HIPX(launch_jitter_reset(g->jlist + d.np, lmax, cur + i, nxt + i, g->jflags + d.np,
+                                 g->labels + d.np, g->K, st));
+      }
+    }
     std::swap(xc, xn);
   }
+  if (jit_list) g->jflags_dirty = false;
   *result = xc;
   return FEPLL_OK;
 }

@@ -180,12 +180,19 @@ hipError_t launch_spec_update(const void* AtY, const double* a2, void* X, int m,
 hipError_t launch_spec_init(const void* AtY, const double* a2, void* X, int H, int W, double c,
                             hipStream_t st);
 
-// Jittered subsampling (Sec. 3.3) of one image, iteration t: flags (Np,
-// all zero before) of the chosen patches set to 1 and *count zeroed; then
-// every flagged patch appended to list (any order), its flag cleared, and
-// every other patch's label set to K.
+// Jittered subsampling (Sec. 3.3) of one image, iteration t.  Without list:
+// flags (Np, all zero before) of the chosen patches set to 1 and *count
+// zeroed, then launch_jitter_compact appends every flagged patch to list
+// (any order), clears its flag and sets every other patch's label to K.
+// With list (*count zero before, every label K before): each chosen patch
+// is appended to list at *count and flagged; launch_jitter_reset, after the
+// iteration, clears their flags, sets their labels back to K and zeroes
+// *next_count.
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
-                              int32_t* count, hipStream_t st);
+                              int32_t* count, int32_t* list, hipStream_t st);
+hipError_t launch_jitter_reset(const int32_t* list, int64_t list_max, const int32_t* count,
+                               int32_t* next_count, int32_t* flags, int32_t* labels, int K,
+                               hipStream_t st);
 hipError_t launch_jitter_compact(int Np, int K, int32_t* flags, int32_t* labels,
                                  int32_t* count, int32_t* list, hipStream_t st);
 // e4m3 selection of the patches in list (*count <= list_max entries,

@@ -18,6 +18,8 @@
 // chosen patches set to 1 -- several points may land on one patch) and
 // compact (the flagged patches appended to a list in any order, the others'
 // labels set to K, the "not in the subset" mark every later stage reads).
+#include <algorithm>
+
 #include "common.h"
 
 namespace fepll {
@@ -49,10 +51,17 @@ __device__ __forceinline__ int grid_first(int g, int s, int b) {
   return g - s * n0;
 }
 
+// APPEND: each chosen patch is also appended to list at *count (wave-
+// aggregated atomics; a patch two grid points clamp to is taken once: its
+// flag is set by an exchange), and the flags stay set until
+// jitter_reset_kernel clears them.  Otherwise only the flags are set and
+// *count zeroed for jitter_compact_kernel.
+template <bool APPEND>
 __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, uint32_t k0,
                                                           uint32_t k1, int t, int amax, int cmax,
                                                           int32_t* __restrict__ flags,
-                                                          int32_t* __restrict__ count) {
+                                                          int32_t* __restrict__ count,
+                                                          int32_t* __restrict__ list) {
   const int Hp = H - 7, Wp = W - 7;
   const int b = (8 - s) / 2;
   const U4 sh = philox4x32_10(U4{(uint32_t)t, 0xffffffffu, 0xffffffffu, 0u}, k0, k1);
@@ -63,15 +72,45 @@ __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, u
   const int na = (Hp - 1 + b - fy + s - 1) / s + 1;
   const int nc = (Wp - 1 + b - fx + s - 1) / s + 1;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *count = 0;  // the compaction that follows counts the subset
-  if (i >= amax * cmax) return;
+  if (!APPEND && i == 0) *count = 0;  // the compaction that follows counts the subset
   const int a = i / cmax, c = i - a * cmax;
-  if (a >= na || c >= nc) return;
-  const U4 u = philox4x32_10(U4{(uint32_t)t, (uint32_t)a, (uint32_t)c, 0u}, k0, k1);
-  const uint32_t n = (uint32_t)(2 * b + 1);
-  const int r = min(max(fy + s * a + (int)(u.x % n) - b, 0), Hp - 1);
-  const int q = min(max(fx + s * c + (int)(u.y % n) - b, 0), Wp - 1);
-  flags[(size_t)r * Wp + q] = 1;
+  int p = 0;
+  bool take = false;
+  if (i < amax * cmax && a < na && c < nc) {
+    const U4 u = philox4x32_10(U4{(uint32_t)t, (uint32_t)a, (uint32_t)c, 0u}, k0, k1);
+    const uint32_t n = (uint32_t)(2 * b + 1);
+    const int r = min(max(fy + s * a + (int)(u.x % n) - b, 0), Hp - 1);
+    const int q = min(max(fx + s * c + (int)(u.y % n) - b, 0), Wp - 1);
+    p = r * Wp + q;
+    if (APPEND)
+      take = atomicExch(&flags[p], 1) == 0;
+    else
+      flags[p] = 1;
+  }
+  if (!APPEND) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t mask = __ballot(take);
+  int base = 0;
+  if (lane == 0 && mask) base = atomicAdd(count, __popcll(mask));
+  base = __shfl(base, 0);
+  if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = p;
+}
+
+// After an iteration on an appended list: its patches' flags cleared and
+// labels set back to K (so every patch not on the next list keeps K), and
+// the next iteration's count zeroed.
+__global__ __launch_bounds__(256) void jitter_reset_kernel(const int32_t* __restrict__ list,
+                                                           const int32_t* __restrict__ count,
+                                                           int32_t* __restrict__ next_count,
+                                                           int32_t* __restrict__ flags,
+                                                           int32_t* __restrict__ labels, int K) {
+  const int n = *count;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    const int p = list[e];
+    flags[p] = 0;
+    labels[p] = K;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
 }
 
 // 16 384 patches per workgroup (16 per thread, all flag loads in flight);
@@ -151,12 +190,25 @@ int64_t jitter_points_max(int H, int W, int s) {
 }
 
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
-                              int32_t* count, hipStream_t st) {
+                              int32_t* count, int32_t* list, hipStream_t st) {
   const int amax = grid_points_max(H - 7, s), cmax = grid_points_max(W - 7, s);
   const int n = amax * cmax;
-  hipLaunchKernelGGL(jitter_mark_kernel, dim3((n + 255) / 256), dim3(256), 0, st, H, W, s,
-                     (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), t, amax, cmax,
-                     flags, count);
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  if (list)
+    hipLaunchKernelGGL(jitter_mark_kernel<true>, dim3((n + 255) / 256), dim3(256), 0, st, H, W,
+                       s, k0, k1, t, amax, cmax, flags, count, list);
+  else
+    hipLaunchKernelGGL(jitter_mark_kernel<false>, dim3((n + 255) / 256), dim3(256), 0, st, H, W,
+                       s, k0, k1, t, amax, cmax, flags, count, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_jitter_reset(const int32_t* list, int64_t list_max, const int32_t* count,
+                               int32_t* next_count, int32_t* flags, int32_t* labels, int K,
+                               hipStream_t st) {
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((list_max + 255) / 256, 1024));
+  hipLaunchKernelGGL(jitter_reset_kernel, dim3((unsigned)blocks), dim3(256), 0, st, list, count,
+                     next_count, flags, labels, K);
   return hipGetLastError();
 }
 
