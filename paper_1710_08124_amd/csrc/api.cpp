@@ -933,6 +933,16 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
   // patches as it draws them, and the patches off the list keep the label K
   // (set here for all, restored after every iteration for the listed ones)
   const bool jit_list = o.jitter && o.precision != FEPLL_FP32;
+  // ... and sorts by label over those lists when their counts fit the
+  // histogram (chunks of kListChunk list entries per image)
+  int list_chunks = 0;
+  for (const ImgDesc& d : g->hd) {
+    const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, std::max(o.jitter, 1)),
+                                           (int64_t)(d.H - 7) * (d.W - 7));
+    list_chunks = std::max<int>(list_chunks, (int)((lmax + kListChunk - 1) / kListChunk));
+  }
+  const bool list_sort = jit_list && max_tiles_image <= kSmallTiles &&
+                         (size_t)list_chunks * b.n <= g->h_sort.size();
   if (jit_list) {
     const int n = (int)b.n_patches;
     if (g->jflags_dirty) {
@@ -955,8 +965,12 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
                           sizeof(int32_t) * b.n_patches, lkind, st));
     {
       StageTimer tm(g, 2, st, labels_out == nullptr);
-      HIPX(launch_bucket_batch(b, g->labels, g->K, g->hist, g->seg, g->perm, g->wbase,
-                               max_tiles_image, st));
+      if (list_sort)
+        HIPX(launch_bucket_list(b, g->labels, g->jlist, g->jcount + (size_t)(t & 1) * b.n,
+                                g->K, list_chunks, g->hist, g->seg, g->perm, g->wbase, st));
+      else
+        HIPX(launch_bucket_batch(b, g->labels, g->K, g->hist, g->seg, g->perm, g->wbase,
+                                 max_tiles_image, st));
     }
     {
       StageTimer tm(g, 3, st, true);

@@ -326,17 +326,20 @@ hipError_t launch_pair_bucket(const uint16_t* cand, int Np, int m, int K, int32_
 // bases too.
 constexpr int kCompPerWave = 8;
 
+// nbl > 0: the counts come from the list chunks of hist_list_kernel (nbl
+// per image, image i's at K nbl i) instead of the image's sort blocks.
 __global__ __launch_bounds__(1024) void tables_small_kernel(Batch b, int K,
                                                             int32_t* __restrict__ hist_b,
                                                             int32_t* __restrict__ seg_b,
-                                                            int32_t* __restrict__ wbase) {
+                                                            int32_t* __restrict__ wbase, int nbl) {
   __shared__ int32_t tp[kMaxK + 1];
   __shared__ int32_t cnt[kMaxK];
   __shared__ int32_t wa[16], wb[16];
   const ImgDesc d = b.d[blockIdx.x];
   const int Np = (d.H - 7) * (d.W - 7);
-  const int nb = (Np + kSortBlock - 1) / kSortBlock;
-  int32_t* hist = hist_b + (size_t)K * d.sort0;
+  const int nb = nbl > 0 ? nbl : (Np + kSortBlock - 1) / kSortBlock;
+  int32_t* hist =
+      hist_b + (size_t)K * (nbl > 0 ? (size_t)blockIdx.x * nbl : (size_t)d.sort0);
   int32_t* seg = seg_b + d.seg;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // A: wave w scans components w, w + 16, ...
@@ -437,7 +440,7 @@ hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int
   const bool small = max_tiles_image <= kSmallTiles;
   if (small) {
     hipLaunchKernelGGL(tables_small_kernel, dim3(b.n), dim3(1024), 0, st, b, K, hist, seg,
-                       b.n == 1 ? wbase : nullptr);
+                       b.n == 1 ? wbase : nullptr, 0);
     e = hipGetLastError();
   } else {
     e = launch_seg_tables<true>(b, hist, seg, 0, K, kWienerTile, b.n,
@@ -448,6 +451,80 @@ hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int
                      labels, K, hist, seg, perm);
   e = hipGetLastError();
   if (e != hipSuccess || (small && b.n == 1)) return e;
+  hipLaunchKernelGGL(wbase_kernel, dim3(1), dim3(1024), 0, st, b, K, seg, wbase);
+  return hipGetLastError();
+}
+
+// ---- the same sort over per-image patch lists (a jittered subset listed
+// as drawn; list + d.np, counts[i] entries): chunks of kListChunk list
+// entries (one per thread: the label gathers of many workgroups in flight)
+// take the place of the sort blocks (nbl per image, a 2-D grid of chunks x
+// images; a chunk past its list's end stores zero counts), so the work
+// follows the subset, not the image.
+__global__ __launch_bounds__(1024) void hist_list_kernel(Batch b,
+                                                         const int32_t* __restrict__ labels_b,
+                                                         const int32_t* __restrict__ list_b,
+                                                         const int32_t* __restrict__ counts, int K,
+                                                         int nbl, int32_t* __restrict__ hist_b) {
+  extern __shared__ int32_t h[];
+  const int img = blockIdx.y, ch = blockIdx.x;
+  const ImgDesc d = b.d[img];
+  const int n = counts[img];
+  const int32_t* list = list_b + d.np;
+  const int32_t* labels = labels_b + d.np;
+  int32_t* hist = hist_b + (size_t)K * ((size_t)img * nbl);
+  for (int k = threadIdx.x; k < K; k += blockDim.x) h[k] = 0;
+  __syncthreads();
+  const int e = ch * kListChunk + (int)threadIdx.x;
+  const int lab = (e < n) ? labels[list[e]] : K;
+  if (lab < K) atomicAdd(&h[lab], 1);
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += blockDim.x) hist[(size_t)k * nbl + ch] = h[k];
+}
+
+__global__ __launch_bounds__(1024) void scatter_list_kernel(Batch b,
+                                                            const int32_t* __restrict__ labels_b,
+                                                            const int32_t* __restrict__ list_b,
+                                                            const int32_t* __restrict__ counts,
+                                                            int K, int nbl,
+                                                            const int32_t* __restrict__ offs_b,
+                                                            const int32_t* __restrict__ seg_b,
+                                                            int32_t* __restrict__ perm_b) {
+  extern __shared__ int32_t cur[];
+  const int img = blockIdx.y, ch = blockIdx.x;
+  const ImgDesc d = b.d[img];
+  const int n = counts[img];
+  if (ch * kListChunk >= n) return;  // (workgroup-uniform)
+  const int32_t* list = list_b + d.np;
+  const int32_t* labels = labels_b + d.np;
+  const int32_t* offs = offs_b + (size_t)K * ((size_t)img * nbl);
+  const int32_t* start = seg_b + d.seg;
+  int32_t* perm = perm_b + d.np;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) cur[k] = start[k] + offs[(size_t)k * nbl + ch];
+  __syncthreads();
+  const int e = ch * kListChunk + (int)threadIdx.x;
+  if (e < n) {
+    const int p = list[e];
+    perm[atomicAdd(&cur[labels[p]], 1)] = p;
+  }
+}
+
+hipError_t launch_bucket_list(const Batch& b, const int32_t* labels, const int32_t* list,
+                              const int32_t* counts, int K, int nbl, int32_t* hist, int32_t* seg,
+                              int32_t* perm, int32_t* wbase, hipStream_t st) {
+  const dim3 grid((unsigned)nbl, (unsigned)b.n);
+  hipLaunchKernelGGL(hist_list_kernel, grid, dim3(1024), K * sizeof(int32_t), st, b, labels, list,
+                     counts, K, nbl, hist);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(tables_small_kernel, dim3(b.n), dim3(1024), 0, st, b, K, hist, seg,
+                     b.n == 1 ? wbase : nullptr, nbl);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scatter_list_kernel, grid, dim3(1024), K * sizeof(int32_t), st, b, labels,
+                     list, counts, K, nbl, hist, seg, perm);
+  e = hipGetLastError();
+  if (e != hipSuccess || b.n == 1) return e;
   hipLaunchKernelGGL(wbase_kernel, dim3(1), dim3(1024), 0, st, b, K, seg, wbase);
   return hipGetLastError();
 }

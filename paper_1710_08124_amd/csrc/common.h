@@ -140,6 +140,13 @@ constexpr int64_t kSmallTiles = 4096;
 hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int32_t* hist,
                                int32_t* seg, int32_t* perm, int32_t* wbase,
                                int64_t max_tiles_image, hipStream_t st);
+// The same sort over per-image patch lists (list + d.np, counts[i] entries,
+// labels below K; every tile list short): nbl chunks of kListChunk entries
+// per image, hist holding K x nbl counts per image (K nbl n in all).
+constexpr int kListChunk = 1024;
+hipError_t launch_bucket_list(const Batch& b, const int32_t* labels, const int32_t* list,
+                              const int32_t* counts, int K, int nbl, int32_t* hist, int32_t* seg,
+                              int32_t* perm, int32_t* wbase, hipStream_t st);
 
 // Pairs (patch i, candidate j < m) of the proposal, sorted by component:
 // hist [K][nb] with nb = ceil(Np / kPairBlock); seg as above with tiles of
