@@ -644,15 +644,11 @@ fepll_status select_tree(fepll_gmm* g, const float* x, int H, int W, int slot,
     HIPX(hipGetLastError());
   }
   for (int lev = T.dense_levels + 1; lev < T.nlevels; ++lev) {
-    HIPX(launch_tree_cand(labels, Np, T.children, g->cand, st));
-    HIPX(launch_pair_bucket(g->cand, Np, T.maxch, T.Kall, g->phist, g->pseg, g->psorted, st));
-    HIPX(launch_pair_scores_bf16(g->zop, g->znz, Np, Ub, L, T.tb.rk, Pinv, T.Kall, T.maxch,
-                                 g->pseg, g->psorted, g->pcost, st));
     // (best / second: the leaf level's, among the last node's children)
     const bool last = lev == T.nlevels - 1;
-    HIPX(launch_pair_reduce(g->cand, g->pcost, Np, T.maxch, T.Kall, -INFINITY, labels,
-                            last ? best : nullptr, last ? second : nullptr, g->count, g->fb_list,
-                            st));
+    HIPX(launch_tree_level_bf16(labels, Np, g->zop, g->znz, Ub, L, T.tb.rk, Pinv, T.Kall,
+                                T.children, g->cand, g->phist, g->pseg, g->psorted, labels,
+                                last ? best : nullptr, last ? second : nullptr, st));
   }
   return FEPLL_OK;
 }

@@ -429,6 +429,90 @@ __global__ __launch_bounds__(256, 3) void pairs_bf16_kernel(
   }
 }
 
+// One sparse level of the tree descent: the patches grouped by their
+// current node (pair ids 8 i from the pair sort with one candidate per
+// patch, the node), one wave per tile of up to 128 patches of one node; the
+// wave reads each patch's record once, scores the node's children in index
+// order (score(): the selection cost of the all-K modes) and keeps the best
+// (ties to the lower child), the patch's node at this level.  best /
+// second (or NULL): among the node's children.
+template <bool FLAT>
+__global__ __launch_bounds__(256, 3) void tree_level_bf16_kernel(
+    const uint4* __restrict__ zop, const float* __restrict__ znz,
+    const uint16_t* __restrict__ Ub, const float* __restrict__ L, const int32_t* __restrict__ rkt,
+    const float* __restrict__ Pinv, int K, const int32_t* __restrict__ seg,
+    const int32_t* __restrict__ sorted, const uint16_t* __restrict__ children,
+    int32_t* __restrict__ labels, float* __restrict__ best, float* __restrict__ second) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int g = lane >> 4;
+  const int col = lane & 15;
+  const int32_t* start = seg;
+  const int32_t* count = seg + (K + 1);
+  const int32_t* tinfo = seg + (3 * K + 3);
+  const int total = seg[3 * K + 2];
+  const uint4* up = reinterpret_cast<const uint4*>(Ub) + lane;
+  for (int t = blockIdx.x * 4 + wave; t < total; t += gridDim.x * 4) {
+    const int info = tinfo[t];
+    const int k = info & 1023;
+    const int first = (info >> 10) * kPairTile;
+    const int n = min(kPairTile, count[k] - first);
+    const int32_t* ids = sorted + start[k] + first;
+    int idx[PB];
+    bool valid[PB];
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int e = 16 * pb + col;
+      valid[pb] = e < n;
+      idx[pb] = ids[valid[pb] ? e : 0] >> 3;
+    }
+    const int own = 4 * (g >> 1) + 2 * (g & 1);
+    uint4 zb[PB][2];
+    float nzA = 0.f, nzB = 0.f;
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      float nz = 0.f;
+      load_operand<FLAT>(zop, znz, idx[pb], g, zb[pb], nz);
+      if (FLAT) {
+        nzA = (pb == own) ? nz : nzA;
+        nzB = (pb == own + 1) ? nz : nzB;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    float bA = INFINITY, sA = INFINITY, bB = INFINITY, sB = INFINITY;
+    int kA = 0, kB = 0;
+    for (int j = 0; j < 8; ++j) {
+      const int c = children[(size_t)k * 8 + j];
+      if (c == 0xffff) break;  // (wave-uniform)
+      float cA, cB;
+      score<FLAT>(up + (size_t)c * 512, zb, L[c], FLAT ? rkt[c] : kP, FLAT ? Pinv[c] : 0.f, nzA,
+                  nzB, cA, cB);
+      keep_best(cA, c, bA, sA, kA);
+      keep_best(cB, c, bB, sB, kB);
+    }
+#pragma unroll
+    for (int pb = 0; pb < PB; pb += 2)
+      if (pb == own) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+          if (!valid[pb + p]) continue;
+          const int i = idx[pb + p];
+          labels[i] = p ? kB : kA;
+          if (best) best[i] = p ? bB : bA;
+          if (second) second[i] = p ? sB : sA;
+        }
+      }
+  }
+}
+
+// The one-candidate "pairs" of a tree level: each patch's current node in
+// slot 0 (the pair sort then groups the patches by node).
+__global__ __launch_bounds__(256) void tree_group_kernel(const int32_t* __restrict__ cur, int Np,
+                                                         uint4* __restrict__ cand) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < Np) cand[i] = make_uint4((uint32_t)cur[i] | 0xffff0000u, ~0u, ~0u, ~0u);
+}
+
 // Per patch: the best and second best of its m rescored candidates (ties to
 // the lower component), its label, and the fallback decision: the patch
 // goes to the full-K list when half the exact gap (in nats) is below the
@@ -510,14 +594,6 @@ __global__ __launch_bounds__(256) void records_bf16_kernel(const float* __restri
   }
 }
 
-// Candidates of the tree descent: the children of each patch's current node
-// (children: 8 entries per node, 0xffff after the last).
-__global__ __launch_bounds__(256) void tree_cand_kernel(const int32_t* __restrict__ cur, int Np,
-                                                        const uint4* __restrict__ children,
-                                                        uint4* __restrict__ cand) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < Np) cand[i] = children[cur[i]];
-}
 
 // The top levels of the tree descent, dense: the spatial all-K loop over
 // the listed nodes instead of the K components (same staging, same score()),
@@ -647,12 +723,33 @@ hipError_t launch_records_bf16(const float* x, int H, int W, uint16_t* zop, floa
   return hipGetLastError();
 }
 
-hipError_t launch_tree_cand(const int32_t* cur, int Np, const uint16_t* children, uint16_t* cand,
-                            hipStream_t st) {
-  hipLaunchKernelGGL(tree_cand_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, cur, Np,
-                     reinterpret_cast<const uint4*>(children), reinterpret_cast<uint4*>(cand));
+hipError_t launch_tree_level_bf16(const int32_t* cur, int Np, const uint16_t* zop,
+                                  const float* znz, const uint16_t* Ub_t, const float* L32_t,
+                                  const int32_t* rk, const float* Pinv_t, int K,
+                                  const uint16_t* children, uint16_t* cand, int32_t* hist,
+                                  int32_t* seg, int32_t* sorted, int32_t* labels, float* best,
+                                  float* second, hipStream_t st) {
+  hipLaunchKernelGGL(tree_group_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, cur, Np,
+                     reinterpret_cast<uint4*>(cand));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_pair_bucket(cand, Np, 1, K, hist, seg, sorted, st)) != hipSuccess) return e;
+  // the tile total depends on the labels: a fixed grid walks the device list
+  int64_t blocks = ((int64_t)Np / kPairTile + K + 3) / 4;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  const uint4* z4 = reinterpret_cast<const uint4*>(zop);
+  if (rk)
+    hipLaunchKernelGGL(tree_level_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, z4,
+                       znz, Ub_t, L32_t, rk, Pinv_t, K, seg, sorted, children, labels, best,
+                       second);
+  else
+    hipLaunchKernelGGL(tree_level_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, z4,
+                       znz, Ub_t, L32_t, rk, Pinv_t, K, seg, sorted, children, labels, best,
+                       second);
   return hipGetLastError();
 }
+
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st) {
   if (mode == kModeListFull) {

@@ -58,12 +58,19 @@ hipError_t launch_pair_reduce(const uint16_t* cand, const float* pair_cost, int 
                               int32_t* fb_count, int32_t* fb_list, hipStream_t st);
 
 // Search-tree descent (Sec. 3.2): every patch's bfloat16 operand record and
-// squared norm (as the network writes them), and the candidates of a level
-// (the children of each patch's current node; children: 8 uint16 per node).
+// squared norm (as the network writes them).
 hipError_t launch_records_bf16(const float* x, int H, int W, uint16_t* zop, float* znz,
                                hipStream_t st);
-hipError_t launch_tree_cand(const int32_t* cur, int Np, const uint16_t* children, uint16_t* cand,
-                            hipStream_t st);
+// One level of the descent from the current nodes cur to their best
+// children (labels; may alias cur: cur is consumed first), with the pair
+// sort's scratch (cand: 8 uint16 per patch; hist, seg, sorted) grouping the
+// patches by node; records zop / znz as launch_records_bf16 writes them.
+hipError_t launch_tree_level_bf16(const int32_t* cur, int Np, const uint16_t* zop,
+                                  const float* znz, const uint16_t* Ub_t, const float* L32_t,
+                                  const int32_t* rk, const float* Pinv_t, int K,
+                                  const uint16_t* children, uint16_t* cand, int32_t* hist,
+                                  int32_t* seg, int32_t* sorted, int32_t* labels, float* best,
+                                  float* second, hipStream_t st);
 
 // The top levels of the descent in one pass over the image: positions
 // 0..n-1 list the nodes of those levels in order (node: node id, par: its
