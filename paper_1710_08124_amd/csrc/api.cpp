@@ -597,10 +597,12 @@ __global__ void mark_kernel(const int32_t* count, const int32_t* list, int32_t* 
 }
 
 // Gaussian selection of one image by the search tree (Sec. 3.2) with the
-// tree tables of beta slot `slot`: the patches' bfloat16 records, then per
-// level the children of each patch's current node as candidates, bucketed
-// by node and scored exactly as in the all-K selection, the best one kept
-// (no fallback); the last level leaves a leaf, the label.
+// tree tables of beta slot `slot`, every cost the bfloat16 selection cost of
+// the all-K modes: the top levels of few nodes in one dense pass over the
+// image (which also writes the patches' bfloat16 records), then each further
+// level with the patches grouped by their current node and that node's
+// children scored from the records, the best one kept (no fallback); the
+// last level leaves a leaf, the label.
 fepll_status select_tree(fepll_gmm* g, const float* x, int H, int W, int slot,
                          int32_t* labels, float* best, float* second, int32_t* flags,
                          hipStream_t st) {
