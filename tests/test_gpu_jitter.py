@@ -139,13 +139,13 @@ def test_fp32_full_size_end_to_end(F):
     assert abs(d) < 0.01
 
 
-@pytest.mark.parametrize("rho", [None, 0.95])
-def test_e4m3_list_full_size_sampled(F, rho):
-    """The benchmarked configuration: 1024^2, K = 200, sigma 25, e4m3, s = 6
-    (29 346 chosen patches: one list workgroup per 128 entries, no component
-    split), plain and flat-tailed.  The chosen patches equal the reference's;
-    the labels of 3000 sampled chosen patches agree with the mode's
-    definition except at its near-ties."""
+@pytest.mark.parametrize("mode,rho", [("fp8", None), ("fp8", 0.95), ("bf16", None)])
+def test_list_full_size_sampled(F, mode, rho):
+    """The benchmarked configurations: 1024^2, K = 200, sigma 25, s = 6
+    (about 29 000 chosen patches; e4m3: one list workgroup per 128 entries,
+    no component split), e4m3 plain and flat-tailed, bf16.  The chosen
+    patches equal the reference's; the labels of 3000 sampled chosen patches
+    agree with the mode's definition except at its near-ties."""
     from oracle import flat_tail as ft
     c = fs.config_c3()
     y32 = np.asarray(c["y"], np.float32)
@@ -157,19 +157,20 @@ def test_e4m3_list_full_size_sampled(F, rho):
         lam, want_r = ft.flat_tail(c["lam"], rho)
         np.testing.assert_array_equal(r, want_r)
     seed = 20171023
-    _, lab = F.restore(g, dev(y32), 25.0, betas=[beta], precision="fp8", jitter=6, seed=seed,
+    _, lab = F.restore(g, dev(y32), 25.0, betas=[beta], precision=mode, jitter=6, seed=seed,
                        return_labels=True)
     lab = lab.cpu().numpy()[0]
     idx, _ = jt.positions(1024, 1024, 6, seed, 0)
     np.testing.assert_array_equal(np.nonzero(lab < 200)[0], idx)
     sel = np.sort(fs.rng(3).choice(idx, 3000, replace=False))
-    cost, bnd = lowp.lowp_costs(y32, c["U"], lam, c["w"], beta, "fp8", acc_eps=2.0 ** -12,
-                                rank=r, patches=sel)
+    eps = {"bf16": 64 * 2.0 ** -24, "fp8": 2.0 ** -12}[mode]  # as in test_gpu_precision
+    cost, bnd = lowp.lowp_costs(y32, c["U"], lam, c["w"], beta, mode, acc_eps=eps, rank=r,
+                                patches=sel)
     srt = np.sort(cost, 1)
     gap = srt[:, 1] - srt[:, 0]
     tol = bnd.max(1)
     same = lab[sel] == cost.argmin(1)
-    print(f"1024^2 e4m3 list rho={rho}: {idx.size} chosen, sampled agreement {same.mean():.5f}")
+    print(f"1024^2 {mode} list rho={rho}: {idx.size} chosen, sampled agreement {same.mean():.5f}")
     assert np.all(same | (gap <= 2 * tol))
 
 

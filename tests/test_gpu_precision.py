@@ -107,6 +107,41 @@ def test_lowp_select_matches_definition(F, mode, sigma, t, shape):
     assert np.all((lab == cost.argmin(1)) | (gap <= 2 * tol))
 
 
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
+@pytest.mark.parametrize("rho", [None, 0.95])
+def test_full_size_select_sampled(F, mode, rho):
+    """The benchmarked configuration: the all-K selection of the 1024^2,
+    K = 200, sigma 25 image (first iteration, x = y) in the launch shape
+    bench.py times, plain and flat-tailed; 3000 sampled patches against the
+    mode's definition (labels equal except at its near-ties, best cost
+    within the bound)."""
+    from oracle import flat_tail as ft
+    c = fs.config_c3()
+    y32 = np.asarray(c["y"], np.float32)
+    beta = float(o.default_betas(25.0)[0])
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    lam, r = c["lam"], None
+    if rho is not None:
+        r = g.flat_tail(rho)
+        lam, _ = ft.flat_tail(c["lam"], rho)
+    lab, best, _, _ = F.select(g, dev(y32), beta, precision=mode)
+    lab, best = lab.cpu().numpy(), best.cpu().numpy()
+    Wp = 1024 - 7
+    sel = np.sort(fs.rng(5).choice(Wp * Wp, 3000, replace=False))
+    eps = {"bf16": 64 * 2.0 ** -24, "fp8": 2.0 ** -12}[mode]  # as above
+    cost, bnd = lowp.lowp_costs(y32, c["U"], lam, c["w"], beta, mode, acc_eps=eps, rank=r,
+                                patches=sel)
+    i = np.arange(sel.size)
+    tol = bnd.max(1)
+    srt = np.sort(cost, 1)
+    gap = srt[:, 1] - srt[:, 0]
+    same = lab[sel] == cost.argmin(1)
+    print(f"1024^2 {mode} rho={rho}: sampled agreement {same.mean():.5f}, max |best - def| / tol "
+          f"{np.max(np.abs(best[sel] - cost[i, lab[sel]]) / tol):.3f}")
+    assert np.all(np.abs(best[sel] - cost[i, lab[sel]]) <= tol)
+    assert np.all(same | (gap <= 2 * tol))
+
+
 def test_bf16_select_shape_and_range(F):
     c = fs.config_c1()
     g = F.GMM(c["U"], c["lam"], c["w"])
