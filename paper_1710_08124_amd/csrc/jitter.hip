@@ -88,12 +88,20 @@ __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, u
       flags[p] = 1;
   }
   if (!APPEND) return;
-  const int lane = threadIdx.x & 63;
+  // one global atomic per workgroup (ballots, LDS prefix over the 4 waves)
+  __shared__ int wcnt[4], wbase;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t mask = __ballot(take);
-  int base = 0;
-  if (lane == 0 && mask) base = atomicAdd(count, __popcll(mask));
-  base = __shfl(base, 0);
-  if (take) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = p;
+  if (lane == 0) wcnt[wave] = __popcll(mask);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    wbase = tot ? atomicAdd(count, tot) : 0;
+  }
+  __syncthreads();
+  int off = wbase;
+  for (int w = 0; w < wave; ++w) off += wcnt[w];
+  if (take) list[off + __popcll(mask & ((1ull << lane) - 1ull))] = p;
 }
 
 // After an iteration on an appended list: its patches' flags cleared and
