@@ -91,8 +91,9 @@ struct fepll_gmm {
   int32_t* seg = nullptr;
   int32_t* perm = nullptr;
   float* Zhat = nullptr;
-  // jittered subsampling: chosen-patch flags and list (packed like labels),
-  // list length per image
+  // jittered subsampling: chosen-patch flags and lists (two sets of np_cap
+  // each, packed like labels; iteration t uses set t & 1), list lengths per
+  // image (three sets of n; iteration t appends to set t % 3)
   int32_t* jflags = nullptr;
   bool jflags_dirty = true;  // jflags may hold set entries (cleared on next use)
   int32_t* jlist = nullptr;
@@ -507,12 +508,12 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     HIPX(dalloc(&g->Zhat, NP * kP));
     HIPX(dalloc(&g->cand, NP * 8));
     HIPX(dalloc(&g->fb_list, NP));
-    HIPX(dalloc(&g->jflags, NP));
-    HIPX(dalloc(&g->jlist, NP));
+    HIPX(dalloc(&g->jflags, 2 * NP));
+    HIPX(dalloc(&g->jlist, 2 * NP));
     g->np_cap = NP;
     // the subset flags start (and stay, between calls) all zero
-    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((NP + 255) / 256)), dim3(256), 0, st,
-                       g->jflags, (int)NP);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((2 * NP + 255) / 256)), dim3(256), 0, st,
+                       g->jflags, (int)(2 * NP));
     HIPX(hipGetLastError());
     g->jflags_dirty = false;
   }
@@ -548,7 +549,7 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     g->px_cap = PX;
   }
   if (!g->count) HIPX(dalloc(&g->count, 64));
-  if ((s = grow(&g->jcount, g->jcount_cap, 2 * (size_t)n)) != FEPLL_OK) return s;
+  if ((s = grow(&g->jcount, g->jcount_cap, 3 * (size_t)n)) != FEPLL_OK) return s;
   if ((s = grow(&g->hist, g->hist_cap, (size_t)K * sort.size())) != FEPLL_OK) return s;
   if ((s = grow(&g->seg, g->seg_cap, (size_t)seg)) != FEPLL_OK) return s;
   if (!same) {
@@ -736,6 +737,19 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
 // all-K reduced-precision modes run as one persistent launch over the
 // batch; float32 (with its recheck) and the proposal path run image by
 // image.  best / second / flags: packed like labels, or NULL.
+// The jittered subsets' flag set, list and counts of iteration t (float32
+// uses set 0 throughout), and the clearing of both flag sets.
+int32_t* jflags_of(fepll_gmm* g, int t) { return g->jflags + (size_t)(t & 1) * g->np_cap; }
+int32_t* jlist_of(fepll_gmm* g, int t) { return g->jlist + (size_t)(t & 1) * g->np_cap; }
+int32_t* jcount_of(fepll_gmm* g, int t) { return g->jcount + (size_t)(t % 3) * g->batch.n; }
+fepll_status clear_jflags(fepll_gmm* g, hipStream_t st) {
+  const size_t m = 2 * g->np_cap;
+  hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
+                     g->jflags, (int)m);
+  HIPX(hipGetLastError());
+  return FEPLL_OK;
+}
+
 // Jittered subsampling (Sec. 3.3) at iteration t: the chosen patches of every
 // image (flags, then the list and the label K for the others), and their
 // selection; float32 selects every patch first (its certification and
@@ -756,8 +770,12 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
     }
   }
   // the reduced-precision paths append each iteration's list to its own
-  // count (two alternating sets: run_hqs resets one while the other fills)
-  int32_t* cnt = g->jcount + ((o.precision == FEPLL_FP32) ? 0 : (size_t)(t & 1) * b.n);
+  // count, flag set and list (the previous iteration's are undone by the
+  // same launch)
+  const bool fp32 = o.precision == FEPLL_FP32;
+  int32_t* cnt = fp32 ? g->jcount : jcount_of(g, t);
+  int32_t* jflags = fp32 ? g->jflags : jflags_of(g, t);
+  int32_t* jlist = fp32 ? g->jlist : jlist_of(g, t);
   {
     // the chosen patches of every image (stage 8: subset).  The position
     // flags are all zero between calls; after a new allocation or an
@@ -766,27 +784,33 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
     if (o.precision == FEPLL_FP32) {
       // every patch was selected: flag the subset, then list it and give the
       // others the label K (the compaction clears the flags again)
-      if (g->jflags_dirty) {
-        hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags,
-                           n);
-        HIPX(hipGetLastError());
-      }
+      if (g->jflags_dirty && (s = clear_jflags(g, st)) != FEPLL_OK) return s;
       g->jflags_dirty = true;
       for (int i = 0; i < b.n; ++i) {
         const ImgDesc& d = g->hd[i];
         const int Np = (d.H - 7) * (d.W - 7);
-        HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, cnt + i,
-                                nullptr, st));
-        HIPX(launch_jitter_compact(Np, g->K, g->jflags + d.np, labels + d.np, cnt + i,
-                                   g->jlist + d.np, st));
+        HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, jflags + d.np, cnt + i, nullptr,
+                                JitterPrev{}, st));
+        HIPX(launch_jitter_compact(Np, g->K, jflags + d.np, labels + d.np, cnt + i,
+                                   jlist + d.np, st));
       }
       g->jflags_dirty = false;
     } else {
-      // every label is K here (run_hqs): list the subset as it is drawn
+      // every label not on the previous list is K here (run_hqs): list the
+      // subset as it is drawn, and undo the previous list (t > 0)
       for (int i = 0; i < b.n; ++i) {
         const ImgDesc& d = g->hd[i];
-        HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, g->jflags + d.np, cnt + i,
-                                g->jlist + d.np, st));
+        JitterPrev prev;
+        if (t > 0) {
+          prev.list = jlist_of(g, t - 1) + d.np;
+          prev.count = jcount_of(g, t - 1) + i;
+          prev.flags = jflags_of(g, t - 1) + d.np;
+          prev.labels = labels + d.np;
+          prev.K = g->K;
+          prev.zero = jcount_of(g, t + 1) + i;
+        }
+        HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, jflags + d.np, cnt + i,
+                                jlist + d.np, prev, st));
       }
     }
   }
@@ -805,11 +829,11 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
       {
         StageTimer tm(g, 0, st, true);  // the selection kernel alone
         HIPX(launch_estep_fp8_list(g->d + i, lmax, t, x, g->tb.Uf, g->tb.Ue, g->tb.L32,
-                                   g->tb.rk, g->tb.Pinv, g->K, cnt + i, g->jlist + d.np,
+                                   g->tb.rk, g->tb.Pinv, g->K, cnt + i, jlist + d.np,
                                    labels, nullptr, nullptr, part, &ns, st));
       }
       StageTimer tm(g, 8, st);  // the merge of the component ranges
-      HIPX(launch_fp8_merge(g->d + i, lmax, cnt + i, g->jlist + d.np, part, ns, labels, nullptr,
+      HIPX(launch_fp8_merge(g->d + i, lmax, cnt + i, jlist + d.np, part, ns, labels, nullptr,
                             nullptr, st));
     } else {
       StageTimer tm(g, 0, st);
@@ -822,7 +846,7 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
       a.K = g->K;
       a.labels = labels + d.np;
       a.list_count = cnt + i;
-      a.list = g->jlist + d.np;
+      a.list = jlist + d.np;
       a.rk = g->tb.rk;
       a.Pinv = g->tb.Pinv + (size_t)slot * K;
       HIPX(launch_estep_bf16_mode(kModeListFull, a, st));
@@ -929,7 +953,8 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
   }
   // jittered subsets in a reduced precision: each iteration lists its
   // patches as it draws them, and the patches off the list keep the label K
-  // (set here for all, restored after every iteration for the listed ones)
+  // (set here for all, restored for the listed ones by the next iteration's
+  // drawing, and after the last iteration)
   const bool jit_list = o.jitter && o.precision != FEPLL_FP32;
   // ... and sorts by label over those lists when their counts fit the
   // histogram (chunks of kListChunk list entries per image)
@@ -943,16 +968,13 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
                          (size_t)list_chunks * b.n <= g->h_sort.size();
   if (jit_list) {
     const int n = (int)b.n_patches;
-    if (g->jflags_dirty) {
-      hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->jflags, n);
-      HIPX(hipGetLastError());
-    }
+    if (g->jflags_dirty && (s = clear_jflags(g, st)) != FEPLL_OK) return s;
     g->jflags_dirty = true;
     hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->labels, n,
                        g->K);
     HIPX(hipGetLastError());
-    hipLaunchKernelGGL(zero_i32_kernel, dim3((2 * b.n + 255) / 256), dim3(256), 0, st, g->jcount,
-                       2 * b.n);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((3 * b.n + 255) / 256), dim3(256), 0, st, g->jcount,
+                       3 * b.n);
     HIPX(hipGetLastError());
   }
   for (int t = 0; t < T; ++t) {
@@ -964,8 +986,8 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     {
       StageTimer tm(g, 2, st, labels_out == nullptr);
       if (list_sort)
-        HIPX(launch_bucket_list(b, g->labels, g->jlist, g->jcount + (size_t)(t & 1) * b.n,
-                                g->K, list_chunks, g->hist, g->seg, g->perm, g->wbase, st));
+        HIPX(launch_bucket_list(b, g->labels, jlist_of(g, t), jcount_of(g, t), g->K,
+                                list_chunks, g->hist, g->seg, g->perm, g->wbase, st));
       else
         HIPX(launch_bucket_batch(b, g->labels, g->K, g->hist, g->seg, g->perm, g->wbase,
                                  max_tiles_image, st));
@@ -984,20 +1006,18 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
         if (s2 != FEPLL_OK) return s2;
       }
     }
-    if (jit_list) {
-      // the listed patches back to flag 0 and label K, the next count to 0
-      StageTimer tm(g, 8, st, !deblur_b);
-      int32_t* cur = g->jcount + (size_t)(t & 1) * b.n;
-      int32_t* nxt = g->jcount + (size_t)((t + 1) & 1) * b.n;
-      for (int i = 0; i < b.n; ++i) {
-        const ImgDesc& d = g->hd[i];
-        const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter),
-                                               (int64_t)(d.H - 7) * (d.W - 7));
-        HIPX(launch_jitter_reset(g->jlist + d.np, lmax, cur + i, nxt + i, g->jflags + d.np,
-                                 g->labels + d.np, g->K, st));
-      }
-    }
     std::swap(xc, xn);
+  }
+  if (jit_list && T > 0) {
+    // the last list's patches back to flag 0 and label K
+    StageTimer tm(g, 8, st);
+    for (int i = 0; i < b.n; ++i) {
+      const ImgDesc& d = g->hd[i];
+      const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter),
+                                             (int64_t)(d.H - 7) * (d.W - 7));
+      HIPX(launch_jitter_reset(jlist_of(g, T - 1) + d.np, lmax, jcount_of(g, T - 1) + i,
+                               nullptr, jflags_of(g, T - 1) + d.np, g->labels + d.np, g->K, st));
+    }
   }
   if (jit_list) g->jflags_dirty = false;
   *result = xc;

@@ -318,6 +318,73 @@ hipError_t launch_pair_bucket(const uint16_t* cand, int Np, int m, int K, int32_
   return hipGetLastError();
 }
 
+// B and C of the tables for one image from its per-component counts cnt[]
+// (in LDS): the starts, counts and tile prefixes written to seg (and with
+// one image the Wiener bases), then the tile table; returns start[tid] for
+// tid < K.  Called by all 1024 threads, after the barrier that completes
+// cnt; `write` false computes the starts only.
+__device__ __forceinline__ int32_t tables_bc(int K, const int32_t* cnt, int32_t* tp, int32_t* wa,
+                                             int32_t* wb, int32_t* seg, int32_t* wbase,
+                                             bool write) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t c = (tid < K) ? cnt[tid] : 0;
+  const int32_t nt = (c + kWienerTile - 1) / kWienerTile;
+  int32_t sa = c, st = nt;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t ua = __shfl_up(sa, off), ub = __shfl_up(st, off);
+    if (lane >= off) {
+      sa += ua;
+      st += ub;
+    }
+  }
+  if (lane == 63) {
+    wa[wave] = sa;
+    wb[wave] = st;
+  }
+  __syncthreads();
+  int32_t pa = 0, pt = 0, tot_c = 0, tot_t = 0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    pa += (w < wave) ? wa[w] : 0;
+    pt += (w < wave) ? wb[w] : 0;
+    tot_c += wa[w];
+    tot_t += wb[w];
+  }
+  const int32_t start = pa + sa - c;
+  if (!write) return start;
+  if (tid < K) {
+    seg[tid] = start;                       // start[k]
+    seg[(K + 1) + tid] = c;                 // count[k]
+    seg[(2 * K + 1) + tid] = pt + st - nt;  // tile prefix
+    tp[tid] = pt + st - nt;
+  }
+  if (tid == 0) {
+    seg[K] = tot_c;
+    seg[3 * K + 1] = tot_t;
+    seg[3 * K + 2] = tot_t;
+    tp[K] = tot_t;
+    if (wbase) {
+      wbase[0] = 0;
+      wbase[1] = tot_t;
+    }
+  }
+  __syncthreads();
+  // C: entry t = k | (tile in k) << 10, k the last with tp[k] <= t
+  for (int tl = tid; tl < tot_t; tl += blockDim.x) {
+    int lo = 0, hi = K - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tp[mid] <= tl)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    seg[(3 * K + 3) + tl] = lo | ((tl - tp[lo]) << 10);
+  }
+  return start;
+}
+
 // ---- the tables of a short tile list (a patch subset) in one launch: one
 // workgroup per image does A (each component's exclusive scan over its
 // block counts: a wave per component, 64 counts per load, the loads of up to
@@ -374,60 +441,7 @@ __global__ __launch_bounds__(1024) void tables_small_kernel(Batch b, int K,
     }
   }
   __syncthreads();
-  const int32_t c = (tid < K) ? cnt[tid] : 0;
-  // B
-  const int32_t nt = (c + kWienerTile - 1) / kWienerTile;
-  int32_t sa = c, st = nt;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int32_t ua = __shfl_up(sa, off), ub = __shfl_up(st, off);
-    if (lane >= off) {
-      sa += ua;
-      st += ub;
-    }
-  }
-  if (lane == 63) {
-    wa[wave] = sa;
-    wb[wave] = st;
-  }
-  __syncthreads();
-  int32_t pa = 0, pt = 0, tot_c = 0, tot_t = 0;
-#pragma unroll
-  for (int w = 0; w < 16; ++w) {
-    pa += (w < wave) ? wa[w] : 0;
-    pt += (w < wave) ? wb[w] : 0;
-    tot_c += wa[w];
-    tot_t += wb[w];
-  }
-  if (tid < K) {
-    seg[tid] = pa + sa - c;                 // start[k]
-    seg[(K + 1) + tid] = c;                 // count[k]
-    seg[(2 * K + 1) + tid] = pt + st - nt;  // tile prefix
-    tp[tid] = pt + st - nt;
-  }
-  if (tid == 0) {
-    seg[K] = tot_c;
-    seg[3 * K + 1] = tot_t;
-    seg[3 * K + 2] = tot_t;
-    tp[K] = tot_t;
-    if (wbase) {
-      wbase[0] = 0;
-      wbase[1] = tot_t;
-    }
-  }
-  __syncthreads();
-  // C: entry t = k | (tile in k) << 10, k the last with tp[k] <= t
-  for (int tl = tid; tl < tot_t; tl += blockDim.x) {
-    int lo = 0, hi = K - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (tp[mid] <= tl)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    seg[(3 * K + 3) + tl] = lo | ((tl - tp[lo]) << 10);
-  }
+  tables_bc(K, cnt, tp, wa, wb, seg, wbase, true);
 }
 
 hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int32_t* hist,
@@ -509,6 +523,68 @@ __global__ __launch_bounds__(1024) void scatter_list_kernel(Batch b,
   }
 }
 
+// With at most 64 chunks per image the tables need no launch of their own:
+// every scatter workgroup reads its image's whole chunk histogram (a wave
+// per component, one count per lane) and takes both sums it needs, the
+// counts of the chunks before its own and the component totals; the scan of
+// the totals is then the workgroup scan of tables_bc, and chunk 0 of each
+// image also writes the image's tables.  Same slots as scatter_list_kernel
+// after tables_small_kernel.
+constexpr int kFusedChunks = 64;
+
+__global__ __launch_bounds__(1024) void scatter_tables_list_kernel(
+    Batch b, const int32_t* __restrict__ labels_b, const int32_t* __restrict__ list_b,
+    const int32_t* __restrict__ counts, int K, int nbl, const int32_t* __restrict__ hist_b,
+    int32_t* __restrict__ seg_b, int32_t* __restrict__ perm_b, int32_t* __restrict__ wbase) {
+  __shared__ int32_t tp[kMaxK + 1];
+  __shared__ int32_t cnt[kMaxK];
+  __shared__ int32_t cur[kMaxK];
+  __shared__ int32_t wa[16], wb[16];
+  const int img = blockIdx.y, ch = blockIdx.x;
+  const ImgDesc d = b.d[img];
+  const int n = counts[img];
+  const bool tables = ch == 0;
+  if (!tables && ch * kListChunk >= n) return;  // (workgroup-uniform)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the entry's label first: its two dependent loads overlap the scans
+  const int e = ch * kListChunk + tid;
+  int p = 0, lab = K;
+  if (e < n) {
+    p = list_b[d.np + e];
+    lab = labels_b[d.np + p];
+  }
+  const int32_t* hist = hist_b + (size_t)K * ((size_t)img * nbl);
+  for (int k0 = wave; k0 < K; k0 += 16 * kCompPerWave) {
+    int32_t v[kCompPerWave];
+#pragma unroll
+    for (int i = 0; i < kCompPerWave; ++i) {
+      const int k = k0 + 16 * i;
+      v[i] = (k < K && lane < nbl) ? hist[(size_t)k * nbl + lane] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kCompPerWave; ++i) {
+      const int k = k0 + 16 * i;
+      int32_t x = v[i];
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int32_t u = __shfl_up(x, off);
+        if (lane >= off) x += u;
+      }
+      const int32_t before = ch > 0 ? __shfl(x, ch - 1) : 0;
+      const int32_t total = __shfl(x, 63);
+      if (k < K && lane == 0) {
+        cur[k] = before;
+        cnt[k] = total;
+      }
+    }
+  }
+  __syncthreads();
+  const int32_t start = tables_bc(K, cnt, tp, wa, wb, seg_b + d.seg, wbase, tables);
+  if (tid < K) cur[tid] += start;
+  __syncthreads();
+  if (lab < K) perm_b[d.np + atomicAdd(&cur[lab], 1)] = p;
+}
+
 hipError_t launch_bucket_list(const Batch& b, const int32_t* labels, const int32_t* list,
                               const int32_t* counts, int K, int nbl, int32_t* hist, int32_t* seg,
                               int32_t* perm, int32_t* wbase, hipStream_t st) {
@@ -517,13 +593,19 @@ hipError_t launch_bucket_list(const Batch& b, const int32_t* labels, const int32
                      counts, K, nbl, hist);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(tables_small_kernel, dim3(b.n), dim3(1024), 0, st, b, K, hist, seg,
-                     b.n == 1 ? wbase : nullptr, nbl);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(scatter_list_kernel, grid, dim3(1024), K * sizeof(int32_t), st, b, labels,
-                     list, counts, K, nbl, hist, seg, perm);
-  e = hipGetLastError();
+  if (nbl <= kFusedChunks) {
+    hipLaunchKernelGGL(scatter_tables_list_kernel, grid, dim3(1024), 0, st, b, labels, list,
+                       counts, K, nbl, hist, seg, perm, b.n == 1 ? wbase : nullptr);
+    e = hipGetLastError();
+  } else {
+    hipLaunchKernelGGL(tables_small_kernel, dim3(b.n), dim3(1024), 0, st, b, K, hist, seg,
+                       b.n == 1 ? wbase : nullptr, nbl);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scatter_list_kernel, grid, dim3(1024), K * sizeof(int32_t), st, b,
+                       labels, list, counts, K, nbl, hist, seg, perm);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess || b.n == 1) return e;
   hipLaunchKernelGGL(wbase_kernel, dim3(1), dim3(1024), 0, st, b, K, seg, wbase);
   return hipGetLastError();

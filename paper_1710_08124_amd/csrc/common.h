@@ -191,12 +191,25 @@ hipError_t launch_spec_init(const void* AtY, const double* a2, void* X, int H, i
 // flags (Np, all zero before) of the chosen patches set to 1 and *count
 // zeroed, then launch_jitter_compact appends every flagged patch to list
 // (any order), clears its flag and sets every other patch's label to K.
-// With list (*count zero before, every label K before): each chosen patch
-// is appended to list at *count and flagged; launch_jitter_reset, after the
-// iteration, clears their flags, sets their labels back to K and zeroes
-// *next_count.
+// With list (*count zero before, flags all zero before): each chosen patch
+// is appended to list at *count and flagged.  The same launch first undoes
+// the previous iteration's list when prev.list is set: its prev.count
+// entries get flag 0 in prev.flags (the other flag set) and label K (every
+// label not on the new list is K before the selection), and *prev.zero (the
+// count the iteration after this one appends to) is zeroed.
+// launch_jitter_reset does the same for the last list of a restoration
+// (next_count may be NULL).
+struct JitterPrev {
+  const int32_t* list = nullptr;
+  const int32_t* count = nullptr;
+  int32_t* flags = nullptr;
+  int32_t* labels = nullptr;
+  int K = 0;
+  int32_t* zero = nullptr;
+};
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
-                              int32_t* count, int32_t* list, hipStream_t st);
+                              int32_t* count, int32_t* list, const JitterPrev& prev,
+                              hipStream_t st);
 hipError_t launch_jitter_reset(const int32_t* list, int64_t list_max, const int32_t* count,
                                int32_t* next_count, int32_t* flags, int32_t* labels, int K,
                                hipStream_t st);

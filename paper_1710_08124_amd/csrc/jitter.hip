@@ -14,10 +14,14 @@
 // (likewise for columns): consecutive starts differ by at most s + 2 b <= 8
 // and the first and last clamp to the image's edges.
 //
-// Two launches per iteration: mark (one thread per grid point, flags of the
-// chosen patches set to 1 -- several points may land on one patch) and
-// compact (the flagged patches appended to a list in any order, the others'
-// labels set to K, the "not in the subset" mark every later stage reads).
+// After a selection of every patch (float32): two launches per iteration,
+// mark (one thread per grid point, flags of the chosen patches set to 1 --
+// several points may land on one patch) and compact (the flagged patches
+// appended to a list in any order, the others' labels set to K, the "not in
+// the subset" mark every later stage reads).  Before a selection of the
+// subset alone: one launch, mark appending to the list as it draws, which
+// also undoes the previous iteration's list (two flag sets and two lists
+// alternate, so the undo and the new marks never touch the same flag).
 #include <algorithm>
 
 #include "common.h"
@@ -53,15 +57,28 @@ __device__ __forceinline__ int grid_first(int g, int s, int b) {
 
 // APPEND: each chosen patch is also appended to list at *count (wave-
 // aggregated atomics; a patch two grid points clamp to is taken once: its
-// flag is set by an exchange), and the flags stay set until
-// jitter_reset_kernel clears them.  Otherwise only the flags are set and
-// *count zeroed for jitter_compact_kernel.
+// flag is set by an exchange), and the flags stay set until the next
+// iteration's launch (or jitter_reset_kernel) clears them; that launch
+// first undoes the previous list (prev, one entry per thread: a list never
+// holds more entries than the grid has points) in the other flag set.
+// Otherwise only the flags are set and *count zeroed for
+// jitter_compact_kernel.
 template <bool APPEND>
 __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, uint32_t k0,
                                                           uint32_t k1, int t, int amax, int cmax,
                                                           int32_t* __restrict__ flags,
                                                           int32_t* __restrict__ count,
-                                                          int32_t* __restrict__ list) {
+                                                          int32_t* __restrict__ list,
+                                                          JitterPrev prev) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (APPEND && prev.list) {
+    if (i < *prev.count) {
+      const int q = prev.list[i];
+      prev.flags[q] = 0;
+      prev.labels[q] = prev.K;
+    }
+    if (i == 0) *prev.zero = 0;
+  }
   const int Hp = H - 7, Wp = W - 7;
   const int b = (8 - s) / 2;
   const U4 sh = philox4x32_10(U4{(uint32_t)t, 0xffffffffu, 0xffffffffu, 0u}, k0, k1);
@@ -71,7 +88,6 @@ __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, u
   // last patch row / column
   const int na = (Hp - 1 + b - fy + s - 1) / s + 1;
   const int nc = (Wp - 1 + b - fx + s - 1) / s + 1;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (!APPEND && i == 0) *count = 0;  // the compaction that follows counts the subset
   const int a = i / cmax, c = i - a * cmax;
   int p = 0;
@@ -118,7 +134,7 @@ __global__ __launch_bounds__(256) void jitter_reset_kernel(const int32_t* __rest
     flags[p] = 0;
     labels[p] = K;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+  if (next_count && blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
 }
 
 // 16 384 patches per workgroup (16 per thread, all flag loads in flight);
@@ -198,16 +214,17 @@ int64_t jitter_points_max(int H, int W, int s) {
 }
 
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
-                              int32_t* count, int32_t* list, hipStream_t st) {
+                              int32_t* count, int32_t* list, const JitterPrev& prev,
+                              hipStream_t st) {
   const int amax = grid_points_max(H - 7, s), cmax = grid_points_max(W - 7, s);
   const int n = amax * cmax;
   const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
   if (list)
     hipLaunchKernelGGL(jitter_mark_kernel<true>, dim3((n + 255) / 256), dim3(256), 0, st, H, W,
-                       s, k0, k1, t, amax, cmax, flags, count, list);
+                       s, k0, k1, t, amax, cmax, flags, count, list, prev);
   else
     hipLaunchKernelGGL(jitter_mark_kernel<false>, dim3((n + 255) / 256), dim3(256), 0, st, H, W,
-                       s, k0, k1, t, amax, cmax, flags, count, list);
+                       s, k0, k1, t, amax, cmax, flags, count, list, JitterPrev{});
   return hipGetLastError();
 }
 
