@@ -320,12 +320,13 @@ hipError_t launch_pair_bucket(const uint16_t* cand, int Np, int m, int K, int32_
 
 // B and C of the tables for one image from its per-component counts cnt[]
 // (in LDS): the starts, counts and tile prefixes written to seg (and with
-// one image the Wiener bases), then the tile table; returns start[tid] for
-// tid < K.  Called by all 1024 threads, after the barrier that completes
-// cnt; `write` false computes the starts only.
+// one image the Wiener bases) when `write`, and part `part` of `nparts` of
+// the tile table (entries part * 1024 + tid, stride nparts * 1024); returns
+// start[tid] for tid < K.  Called by all 1024 threads, after the barrier
+// that completes cnt (`write`, `part`, `nparts`: workgroup-uniform).
 __device__ __forceinline__ int32_t tables_bc(int K, const int32_t* cnt, int32_t* tp, int32_t* wa,
                                              int32_t* wb, int32_t* seg, int32_t* wbase,
-                                             bool write) {
+                                             bool write, int part = 0, int nparts = 1) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int32_t c = (tid < K) ? cnt[tid] : 0;
   const int32_t nt = (c + kWienerTile - 1) / kWienerTile;
@@ -352,26 +353,27 @@ __device__ __forceinline__ int32_t tables_bc(int K, const int32_t* cnt, int32_t*
     tot_t += wb[w];
   }
   const int32_t start = pa + sa - c;
-  if (!write) return start;
-  if (tid < K) {
-    seg[tid] = start;                       // start[k]
-    seg[(K + 1) + tid] = c;                 // count[k]
-    seg[(2 * K + 1) + tid] = pt + st - nt;  // tile prefix
-    tp[tid] = pt + st - nt;
-  }
-  if (tid == 0) {
-    seg[K] = tot_c;
-    seg[3 * K + 1] = tot_t;
-    seg[3 * K + 2] = tot_t;
-    tp[K] = tot_t;
-    if (wbase) {
-      wbase[0] = 0;
-      wbase[1] = tot_t;
+  if (tid < K) tp[tid] = pt + st - nt;
+  if (tid == 0) tp[K] = tot_t;
+  if (write) {
+    if (tid < K) {
+      seg[tid] = start;                       // start[k]
+      seg[(K + 1) + tid] = c;                 // count[k]
+      seg[(2 * K + 1) + tid] = pt + st - nt;  // tile prefix
+    }
+    if (tid == 0) {
+      seg[K] = tot_c;
+      seg[3 * K + 1] = tot_t;
+      seg[3 * K + 2] = tot_t;
+      if (wbase) {
+        wbase[0] = 0;
+        wbase[1] = tot_t;
+      }
     }
   }
   __syncthreads();
   // C: entry t = k | (tile in k) << 10, k the last with tp[k] <= t
-  for (int tl = tid; tl < tot_t; tl += blockDim.x) {
+  for (int tl = part * blockDim.x + tid; tl < tot_t; tl += nparts * blockDim.x) {
     int lo = 0, hi = K - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -527,10 +529,11 @@ __global__ __launch_bounds__(1024) void scatter_list_kernel(Batch b,
 // every scatter workgroup reads its image's whole chunk histogram (a wave
 // per component, one count per lane) and takes both sums it needs, the
 // counts of the chunks before its own and the component totals; the scan of
-// the totals is then the workgroup scan of tables_bc, and chunk 0 of each
-// image also writes the image's tables.  Same slots as scatter_list_kernel
-// after tables_small_kernel.
+// the totals is then the workgroup scan of tables_bc, chunk 0 of each image
+// writes the image's tables and the chunks that hold entries share its tile
+// table.  Same slots as scatter_list_kernel after tables_small_kernel.
 constexpr int kFusedChunks = 64;
+constexpr int kFusedCompPerWave = 16;  // K <= 256: one round of loads
 
 __global__ __launch_bounds__(1024) void scatter_tables_list_kernel(
     Batch b, const int32_t* __restrict__ labels_b, const int32_t* __restrict__ list_b,
@@ -543,8 +546,8 @@ __global__ __launch_bounds__(1024) void scatter_tables_list_kernel(
   const int img = blockIdx.y, ch = blockIdx.x;
   const ImgDesc d = b.d[img];
   const int n = counts[img];
-  const bool tables = ch == 0;
-  if (!tables && ch * kListChunk >= n) return;  // (workgroup-uniform)
+  const int nact = max(1, (n + kListChunk - 1) / kListChunk);  // chunks at work
+  if (ch >= nact) return;  // (workgroup-uniform)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // the entry's label first: its two dependent loads overlap the scans
   const int e = ch * kListChunk + tid;
@@ -554,15 +557,15 @@ __global__ __launch_bounds__(1024) void scatter_tables_list_kernel(
     lab = labels_b[d.np + p];
   }
   const int32_t* hist = hist_b + (size_t)K * ((size_t)img * nbl);
-  for (int k0 = wave; k0 < K; k0 += 16 * kCompPerWave) {
-    int32_t v[kCompPerWave];
+  for (int k0 = wave; k0 < K; k0 += 16 * kFusedCompPerWave) {
+    int32_t v[kFusedCompPerWave];
 #pragma unroll
-    for (int i = 0; i < kCompPerWave; ++i) {
+    for (int i = 0; i < kFusedCompPerWave; ++i) {
       const int k = k0 + 16 * i;
       v[i] = (k < K && lane < nbl) ? hist[(size_t)k * nbl + lane] : 0;
     }
 #pragma unroll
-    for (int i = 0; i < kCompPerWave; ++i) {
+    for (int i = 0; i < kFusedCompPerWave; ++i) {
       const int k = k0 + 16 * i;
       int32_t x = v[i];
 #pragma unroll
@@ -579,7 +582,7 @@ __global__ __launch_bounds__(1024) void scatter_tables_list_kernel(
     }
   }
   __syncthreads();
-  const int32_t start = tables_bc(K, cnt, tp, wa, wb, seg_b + d.seg, wbase, tables);
+  const int32_t start = tables_bc(K, cnt, tp, wa, wb, seg_b + d.seg, wbase, ch == 0, ch, nact);
   if (tid < K) cur[tid] += start;
   __syncthreads();
   if (lab < K) perm_b[d.np + atomicAdd(&cur[lab], 1)] = p;
