@@ -101,6 +101,10 @@ struct fepll_gmm {
   int32_t* jcount = nullptr;
   size_t jpart_cap = 0;
   float4* jpart = nullptr;  // partial results of the component-split list selection
+  // the restoration under way sorts its lists in jit_nbl chunks per image
+  // (0: no list sort), and the selection counts the chunks' labels itself
+  int jit_nbl = 0;
+  bool jit_hist = false;
   // deblurring (periodic convolution): float64 FFT plans and spectra of the
   // last image size
   struct Deblur {
@@ -774,6 +778,18 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
   // same launch)
   const bool fp32 = o.precision == FEPLL_FP32;
   int32_t* cnt = fp32 ? g->jcount : jcount_of(g, t);
+  // the one-pass e4m3 list selection adds its label counts to the list
+  // sort's histogram (cleared by the drawing) when every image runs in one
+  // pass
+  bool sel_hist = o.precision == FEPLL_FP8 && g->jit_nbl > 0;
+  for (int i = 0; i < b.n && sel_hist; ++i) {
+    const ImgDesc& d = g->hd[i];
+    const int64_t Np = (int64_t)(d.H - 7) * (d.W - 7);
+    if (fp8_list_split(std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter), Np), g->K) > 1)
+      sel_hist = false;
+  }
+  g->jit_hist = sel_hist;
+  const size_t hist_n = K * (size_t)g->jit_nbl;
   int32_t* jflags = fp32 ? g->jflags : jflags_of(g, t);
   int32_t* jlist = fp32 ? g->jlist : jlist_of(g, t);
   {
@@ -809,6 +825,10 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
           prev.K = g->K;
           prev.zero = jcount_of(g, t + 1) + i;
         }
+        if (sel_hist) {
+          prev.clear = g->hist + hist_n * i;
+          prev.nclear = (int)hist_n;
+        }
         HIPX(launch_jitter_mark(d.H, d.W, o.jitter, o.seed, t, jflags + d.np, cnt + i,
                                 jlist + d.np, prev, st));
       }
@@ -822,15 +842,17 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
     if (o.precision == FEPLL_FP8) {
       const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter), Np);
       // the split needs its scratch (sized by ensure_jitter); without it, one pass
-      float4* part = (g->jpart && (size_t)(fp8_list_split(lmax, g->K) * lmax) <= g->jpart_cap)
-                         ? g->jpart
-                         : nullptr;
+      float4* part =
+          (!sel_hist && g->jpart && (size_t)(fp8_list_split(lmax, g->K) * lmax) <= g->jpart_cap)
+              ? g->jpart
+              : nullptr;
       int ns = 1;
       {
         StageTimer tm(g, 0, st, true);  // the selection kernel alone
         HIPX(launch_estep_fp8_list(g->d + i, lmax, t, x, g->tb.Uf, g->tb.Ue, g->tb.L32,
                                    g->tb.rk, g->tb.Pinv, g->K, cnt + i, jlist + d.np,
-                                   labels, nullptr, nullptr, part, &ns, st));
+                                   labels, nullptr, nullptr, part, &ns,
+                                   sel_hist ? g->hist + hist_n * i : nullptr, g->jit_nbl, st));
       }
       StageTimer tm(g, 8, st);  // the merge of the component ranges
       HIPX(launch_fp8_merge(g->d + i, lmax, cnt + i, jlist + d.np, part, ns, labels, nullptr,
@@ -966,6 +988,8 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
   }
   const bool list_sort = jit_list && max_tiles_image <= kSmallTiles &&
                          (size_t)list_chunks * b.n <= g->h_sort.size();
+  g->jit_nbl = list_sort ? list_chunks : 0;
+  g->jit_hist = false;
   if (jit_list) {
     const int n = (int)b.n_patches;
     if (g->jflags_dirty && (s = clear_jflags(g, st)) != FEPLL_OK) return s;
@@ -987,7 +1011,8 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
       StageTimer tm(g, 2, st, labels_out == nullptr);
       if (list_sort)
         HIPX(launch_bucket_list(b, g->labels, jlist_of(g, t), jcount_of(g, t), g->K,
-                                list_chunks, g->hist, g->seg, g->perm, g->wbase, st));
+                                list_chunks, g->hist, g->seg, g->perm, g->wbase, g->jit_hist,
+                                st));
       else
         HIPX(launch_bucket_batch(b, g->labels, g->K, g->hist, g->seg, g->perm, g->wbase,
                                  max_tiles_image, st));

@@ -590,12 +590,15 @@ __global__ __launch_bounds__(1024) void scatter_tables_list_kernel(
 
 hipError_t launch_bucket_list(const Batch& b, const int32_t* labels, const int32_t* list,
                               const int32_t* counts, int K, int nbl, int32_t* hist, int32_t* seg,
-                              int32_t* perm, int32_t* wbase, hipStream_t st) {
+                              int32_t* perm, int32_t* wbase, bool have_hist, hipStream_t st) {
   const dim3 grid((unsigned)nbl, (unsigned)b.n);
-  hipLaunchKernelGGL(hist_list_kernel, grid, dim3(1024), K * sizeof(int32_t), st, b, labels, list,
-                     counts, K, nbl, hist);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
+  if (!have_hist) {
+    hipLaunchKernelGGL(hist_list_kernel, grid, dim3(1024), K * sizeof(int32_t), st, b, labels,
+                       list, counts, K, nbl, hist);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (nbl <= kFusedChunks) {
     hipLaunchKernelGGL(scatter_tables_list_kernel, grid, dim3(1024), 0, st, b, labels, list,
                        counts, K, nbl, hist, seg, perm, b.n == 1 ? wbase : nullptr);

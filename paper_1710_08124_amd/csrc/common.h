@@ -142,11 +142,13 @@ hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int
                                int64_t max_tiles_image, hipStream_t st);
 // The same sort over per-image patch lists (list + d.np, counts[i] entries,
 // labels below K; every tile list short): nbl chunks of kListChunk entries
-// per image, hist holding K x nbl counts per image (K nbl n in all).
+// per image, hist holding K x nbl counts per image (K nbl n in all,
+// component-major per image).  have_hist: the selection has already
+// counted them (launch_estep_fp8_list with hist), no histogram launch.
 constexpr int kListChunk = 1024;
 hipError_t launch_bucket_list(const Batch& b, const int32_t* labels, const int32_t* list,
                               const int32_t* counts, int K, int nbl, int32_t* hist, int32_t* seg,
-                              int32_t* perm, int32_t* wbase, hipStream_t st);
+                              int32_t* perm, int32_t* wbase, bool have_hist, hipStream_t st);
 
 // Pairs (patch i, candidate j < m) of the proposal, sorted by component:
 // hist [K][nb] with nb = ceil(Np / kPairBlock); seg as above with tiles of
@@ -198,7 +200,8 @@ hipError_t launch_spec_init(const void* AtY, const double* a2, void* X, int H, i
 // label not on the new list is K before the selection), and *prev.zero (the
 // count the iteration after this one appends to) is zeroed.
 // launch_jitter_reset does the same for the last list of a restoration
-// (next_count may be NULL).
+// (next_count may be NULL).  With clear set, the launch also zeroes its
+// nclear words (the chunk histogram the selection then adds to).
 struct JitterPrev {
   const int32_t* list = nullptr;
   const int32_t* count = nullptr;
@@ -206,6 +209,8 @@ struct JitterPrev {
   int32_t* labels = nullptr;
   int K = 0;
   int32_t* zero = nullptr;
+  int32_t* clear = nullptr;
+  int nclear = 0;
 };
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
                               int32_t* count, int32_t* list, const JitterPrev& prev,
@@ -222,14 +227,17 @@ hipError_t launch_jitter_compact(int Np, int K, int32_t* flags, int32_t* labels,
 // fp8_list_split(list_max, K) x list_max float4 of scratch, which lets a
 // short list be split over the components (same labels): *nsplit receives
 // the number of component ranges, and when it is above 1 launch_fp8_merge
-// must follow to write the results.
+// must follow to write the results.  hist: NULL, or the image's K x nbl
+// chunk histogram of launch_bucket_list (zero before), to which a one-pass
+// selection adds the counts of its labels per chunk of kListChunk entries
+// (NULL required with part).
 int fp8_list_split(int64_t list_max, int K);
 hipError_t launch_estep_fp8_list(const ImgDesc* d, int64_t list_max, int t, const float* x,
                                  const uint8_t* Uf, const int32_t* Ue, const float* L32,
                                  const int32_t* rk, const float* Pinv, int K,
                                  const int32_t* count, const int32_t* list, int32_t* labels,
                                  float* best, float* second, float4* part, int* nsplit,
-                                 hipStream_t st);
+                                 int32_t* hist, int nbl, hipStream_t st);
 hipError_t launch_fp8_merge(const ImgDesc* d, int64_t list_max, const int32_t* count,
                             const int32_t* list, const float4* part, int nsplit, int32_t* labels,
                             float* best, float* second, hipStream_t st);

@@ -295,7 +295,10 @@ __global__ __launch_bounds__(256, 3) void estep_fp8_kernel(
 //     patches (operands from LDS), each component's e4m3 table read from
 //     global memory one component ahead;
 //  3. the 8 waves' best, second and label per patch are merged in wave
-//     order, so ties stay on the lower component, as in one pass.
+//     order, so ties stay on the lower component, as in one pass;
+//  4. with hist, the workgroup counts its labels in LDS and adds the counts
+//     to its sort chunk's column of the list sort's histogram (one atomic
+//     per component present), which saves the sort its histogram launch.
 // A short list is also split over the components across workgroups
 // (blockIdx.y of nsplit takes a contiguous component range and writes its
 // best, second and label per entry to part; fp8_merge_kernel combines them
@@ -311,7 +314,8 @@ __global__ __launch_bounds__(512) void estep_fp8_list_kernel(
     const float* __restrict__ L_all, const int32_t* __restrict__ rkt,
     const float* __restrict__ P_all, int K, int32_t* __restrict__ labels_b,
     float* __restrict__ best_b, float* __restrict__ second_b, const int32_t* __restrict__ list,
-    const int32_t* __restrict__ list_count, int nsplit, float4* __restrict__ part, int pcap) {
+    const int32_t* __restrict__ list_count, int nsplit, float4* __restrict__ part, int pcap,
+    int32_t* __restrict__ hist, int nbl) {
   __shared__ float4 Xs4[PB * 32 * XP / 4];  // gathered pixels, then the waves' results
   __shared__ i32x8 Zq[PB][64];
   __shared__ int Zc[PB][64];
@@ -320,7 +324,9 @@ __global__ __launch_bounds__(512) void estep_fp8_list_kernel(
   __shared__ float Lsh[kMaxK];
   __shared__ float Psh[FLAT ? kMaxK : 1];
   __shared__ int Rsh[FLAT ? kMaxK : 1];
+  __shared__ int Hsh[kMaxK];  // label counts of the workgroup (with hist)
   static_assert(kListWaves * kListItem <= PB * 32 * XP / 4, "results fit the pixel buffer");
+  static_assert(kListChunk % kListItem == 0, "a workgroup's entries lie in one sort chunk");
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int h = lane >> 5;
@@ -343,6 +349,7 @@ __global__ __launch_bounds__(512) void estep_fp8_list_kernel(
       Psh[k] = Pk_t[k];
       Rsh[k] = rkt[k];
     }
+    Hsh[k] = 0;
   }
   float* Xs = reinterpret_cast<float*>(Xs4);
 
@@ -534,8 +541,16 @@ __global__ __launch_bounds__(512) void estep_fp8_list_kernel(
         labels_b[i] = k;
         if (best_b) best_b[i] = b;
         if (second_b) second_b[i] = s2;
+        if (hist) atomicAdd(&Hsh[k], 1);
       }
     }
+  }
+  // 4. (one pass) the labels' counts added to this chunk's histogram column
+  if (hist) {
+    __syncthreads();
+    const int ch = base / kListChunk;
+    for (int k = threadIdx.x; k < K; k += blockDim.x)
+      if (Hsh[k]) atomicAdd(&hist[(size_t)k * nbl + ch], Hsh[k]);
   }
 }
 
@@ -602,8 +617,9 @@ hipError_t launch_estep_fp8_list(const ImgDesc* d, int64_t list_max, int t, cons
                                  const int32_t* rk, const float* Pinv, int K,
                                  const int32_t* count, const int32_t* list, int32_t* labels,
                                  float* best, float* second, float4* part, int* nsplit,
-                                 hipStream_t st) {
+                                 int32_t* hist, int nbl, hipStream_t st) {
   *nsplit = 1;
+  if (hist && part) return hipErrorInvalidValue;
   // one workgroup per 128 entries of the longest list; the actual length is
   // read on the device
   const int64_t blocks = (list_max + kListItem - 1) / kListItem;
@@ -614,11 +630,11 @@ hipError_t launch_estep_fp8_list(const ImgDesc* d, int64_t list_max, int t, cons
   if (rk)
     hipLaunchKernelGGL((estep_fp8_list_kernel<true>), grid, dim3(64 * kListWaves), 0, st, d, t, x,
                        reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels, best,
-                       second, list, count, ns, part, pcap);
+                       second, list, count, ns, part, pcap, hist, nbl);
   else
     hipLaunchKernelGGL((estep_fp8_list_kernel<false>), grid, dim3(64 * kListWaves), 0, st, d, t,
                        x, reinterpret_cast<const uint4*>(Uf), Ue, L32, rk, Pinv, K, labels, best,
-                       second, list, count, ns, part, pcap);
+                       second, list, count, ns, part, pcap, hist, nbl);
   *nsplit = ns;
   return hipGetLastError();
 }

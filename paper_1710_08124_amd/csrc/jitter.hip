@@ -71,14 +71,14 @@ __global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, u
                                                           int32_t* __restrict__ list,
                                                           JitterPrev prev) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (APPEND && prev.list) {
-    if (i < *prev.count) {
-      const int q = prev.list[i];
-      prev.flags[q] = 0;
-      prev.labels[q] = prev.K;
-    }
-    if (i == 0) *prev.zero = 0;
+  if (APPEND && prev.list && i < *prev.count) {
+    const int q = prev.list[i];
+    prev.flags[q] = 0;
+    prev.labels[q] = prev.K;
   }
+  if (APPEND && prev.zero && i == 0) *prev.zero = 0;
+  if (APPEND && prev.clear)
+    for (int j = i; j < prev.nclear; j += gridDim.x * blockDim.x) prev.clear[j] = 0;
   const int Hp = H - 7, Wp = W - 7;
   const int b = (8 - s) / 2;
   const U4 sh = philox4x32_10(U4{(uint32_t)t, 0xffffffffu, 0xffffffffu, 0u}, k0, k1);

@@ -284,3 +284,67 @@ def test_bad_jitter_options(F):
     with pytest.raises(F.FepllError, match="EUNSUPPORTED"):
         F.restore(g, y, c["sigma"], precision="bf16", proposal=True, jitter=6)
     assert math.isfinite(float(F.restore(g, y, c["sigma"], jitter=8).cpu().sum()))
+
+
+@pytest.mark.parametrize("shape,mode", [((1024, 1024), "fp8"), ((4096, 1024), "bf16")])
+def test_list_iteration_sampled_pixels(F, shape, mode):
+    """One iteration of a reduced-precision list path at full size (K = 200,
+    sigma 25, s = 6), through the sort, the patch estimation and the
+    reprojection: at 600 sampled pixels the image equals the FP64 update
+    (Alg. 1: each covering chosen patch's Wiener estimate under the label
+    the GPU chose, their average, the image update).  The 1024^2 list (29
+    chunks of 1024 entries) sorts with the tables inside its scatter; the
+    4096 x 1024 one (116 chunks) with a launch of its own for the tables."""
+    H, W = shape
+    c = fs.config_c2(25.0)
+    U, lam, w = c["U"], c["lam"], c["w"]
+    x0 = fs.test_image(H, W, 41)
+    y32 = f32(fs.noisy(x0, 25.0, 42))
+    beta = float(o.default_betas(25.0)[1])
+    seed = 4242
+    g = F.GMM(U, lam, w)
+    got, lab = F.restore(g, dev(y32), 25.0, betas=[beta], precision=mode, jitter=6, seed=seed,
+                         return_labels=True)
+    got = got.cpu().numpy().astype(np.float64)
+    lab = lab.cpu().numpy()[0]
+    idx, _ = jt.positions(H, W, 6, seed, 0)
+    np.testing.assert_array_equal(np.nonzero(lab < 200)[0], idx)
+    Wp = W - 7
+    chosen = np.zeros((H - 7) * Wp, bool)
+    chosen[idx] = True
+    _, _, gamma, _ = o.eigen_terms(lam, w, beta)
+    R = fs.rng(43)
+    py, px = R.integers(0, H, 600), R.integers(0, W, 600)
+    worst = 0.0
+    for yy, xx in zip(py, px):
+        rr, cc = np.meshgrid(np.arange(max(yy - 7, 0), min(yy, H - 8) + 1),
+                             np.arange(max(xx - 7, 0), min(xx, W - 8) + 1), indexing="ij")
+        rr, cc = rr.ravel(), cc.ravel()
+        on = chosen[rr * Wp + cc]
+        rr, cc = rr[on], cc[on]
+        assert rr.size > 0  # every pixel covered
+        Zt, m = o.remove_dc(o.extract(y32, rr, cc))
+        Zh = o.patch_estimate(Zt, m, lab[rr * Wp + cc], U, gamma)
+        xt = np.mean(Zh[np.arange(rr.size), 8 * (yy - rr) + (xx - cc)])
+        want = o.image_update(y32[yy, xx], xt, beta, 25.0)
+        worst = max(worst, abs(got[yy, xx] - want))
+    print(f"{mode} {H}x{W} list iteration: {idx.size} chosen, worst sampled pixel error {worst:.2e}")
+    assert worst <= TOL
+
+
+def test_state_between_calls(F):
+    """The subset flags and lists persist between calls (all flags zero
+    after a complete restoration): a list-path restoration is unchanged by
+    float32 and other list-path restorations run before it, on other
+    images, with other seeds and iteration counts."""
+    c = fs.config_c2(25.0)
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    y = dev(c["y"][100:228, 60:250])
+    other = dev(c["y"][300:397, 10:131])
+    first = F.restore(g, y, 25.0, precision="fp8", jitter=6, seed=11).cpu().numpy()
+    F.restore(g, other, 25.0, precision="fp32", jitter=4, seed=12)
+    F.restore(g, other, 25.0, precision="bf16", jitter=3, seed=13,
+              betas=list(o.default_betas(25.0)[:2]))
+    F.restore(g, y, 25.0, precision="fp8", jitter=6, seed=14, betas=list(o.default_betas(25.0)[:3]))
+    again = F.restore(g, y, 25.0, precision="fp8", jitter=6, seed=11).cpu().numpy()
+    np.testing.assert_array_equal(again, first)
