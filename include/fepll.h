@@ -85,8 +85,12 @@ typedef struct {
   /* Start of the iterations; NULL = y (Alg. 1 starts from x = y).          */
   const fepll_image* init;
   void* stream;           /* hipStream_t; NULL = default stream             */
-  /* Nonzero: bracket every kernel stage with HIP events on `stream` and
-   * accumulate the stage times in the handle (read with fepll_profile).    */
+  /* Stage timing (forces an eager run, no graph): bracket kernel stages
+   * with HIP events on `stream` and accumulate their times in the handle
+   * (read with fepll_profile).  0 = off; 1 (bit 0) = every stage; else bit
+   * s + 1 set = stage s timed (the stages of fepll_profile), so that a
+   * run can time one stage with two events per launch.  EINVAL when
+   * negative or above bit 9.                                               */
   int32_t profile;
   /* Jittered stochastic patch subsampling (Sec. 3.3): 0 (default) = every
    * patch; s in 1..8 = each iteration runs on the patches of a grid of

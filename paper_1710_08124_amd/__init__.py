@@ -178,7 +178,11 @@ def _options(precision="fp32", recheck=True, init=None, stream=None, profile=Fal
         o._init_img = _image(init)  # keep alive with the struct
         o.init = ctypes.pointer(o._init_img)
     o.stream = stream
-    o.profile = 1 if profile else 0
+    # stage timing: False, True (every stage) or a list of stage names
+    if isinstance(profile, (list, tuple)):
+        o.profile = sum(2 << STAGES.index(st) for st in profile)
+    else:
+        o.profile = 1 if profile else 0
     o.use_proposal = 1 if proposal else 0
     o.top_m = int(top_m)
     o.margin_nats = float(margin)

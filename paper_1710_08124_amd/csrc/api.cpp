@@ -179,7 +179,7 @@ struct fepll_gmm {
   hipEvent_t chain_ev = nullptr;  // the last stage's end event, for a stage that follows at once
   std::vector<Mark> marks;
   std::vector<hipEvent_t> pool;
-  bool profiling = false;
+  uint32_t profiling = 0;  // bit s: stage s is timed
 };
 
 namespace {
@@ -209,6 +209,13 @@ hipEvent_t take_event(fepll_gmm* g) {
   return e;
 }
 
+// The stages options.profile times: bit 0 every stage, else bit s + 1
+// stage s.
+uint32_t profile_mask(int32_t profile) {
+  if (profile & 1) return 0xffffffffu;
+  return (uint32_t)profile >> 1;
+}
+
 // Brackets one stage with events when profiling is on.
 // chain: the stage follows the previous timed stage with no launch between,
 // so the previous end event is its start (one record fewer).
@@ -220,7 +227,10 @@ struct StageTimer {
   bool own_a = true;
   StageTimer(fepll_gmm* g_, int s_, hipStream_t st_, bool chain = false)
       : g(g_), stage(s_), st(st_) {
-    if (!g->profiling) return;
+    if (!((g->profiling >> stage) & 1u)) {
+      g->chain_ev = nullptr;  // a timed stage after this one starts its own interval
+      return;
+    }
     if (chain && g->chain_ev) {
       a = g->chain_ev;
       own_a = false;
@@ -428,6 +438,8 @@ fepll_status check_opt(const fepll_gmm* g, const fepll_options* o) {
   }
   if (std::isnan(o->margin_nats)) return fail(FEPLL_EINVAL, "options.margin_nats is NaN");
   if (o->jitter < 0 || o->jitter > 8) return fail(FEPLL_EINVAL, "options.jitter must be in 0..8");
+  if (o->profile < 0 || o->profile >= (2 << kStages))
+    return fail(FEPLL_EINVAL, "options.profile must be 0, 1 or a mask of stages (bits 1..9)");
   if (o->jitter && o->use_proposal)
     return fail(FEPLL_EUNSUPPORTED, "jittered subsampling does not run with the proposal");
   if (o->use_tree) {
@@ -1440,7 +1452,7 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const fepll_opera
   if ((s = host_finite(y, "y")) != FEPLL_OK) return s;
 
   if ((s = use_stream(g, st)) != FEPLL_OK) return s;
-  g->profiling = o.profile != 0;
+  g->profiling = profile_mask(o.profile);
   std::vector<float> bvals;
   for (double b : betas) bvals.push_back((float)(b * sigma * sigma));
   if ((s = make_plan(g, 1, &H, &W, T, bvals, st)) != FEPLL_OK) return s;
@@ -1523,7 +1535,7 @@ fepll_status fepll_restore_batch(fepll_gmm* g, int32_t n, const fepll_image* y,
   }
   hipStream_t st = (hipStream_t)o.stream;
   if ((s = use_stream(g, st)) != FEPLL_OK) return s;
-  g->profiling = o.profile != 0;
+  g->profiling = profile_mask(o.profile);
   if ((s = make_plan(g, n, Hs.data(), Ws.data(), kDefaultT, bvals, st)) != FEPLL_OK) return s;
   if ((s = ensure_consts(g, betas, table_mask(o), st)) != FEPLL_OK) return s;
   if ((s = ensure_jitter(g, o)) != FEPLL_OK) return s;
@@ -1884,7 +1896,7 @@ fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta, int32
   const int H = x->height, W = x->width;
   hipStream_t st = (hipStream_t)o.stream;
   if ((s = use_stream(g, st)) != FEPLL_OK) return s;
-  g->profiling = o.profile != 0;
+  g->profiling = profile_mask(o.profile);
   const std::vector<float> bv(1, 1.f);
   if ((s = make_plan(g, 1, &H, &W, 1, bv, st)) != FEPLL_OK) return s;
   if ((s = ensure_consts(g, std::vector<double>(1, beta), table_mask(o), st)) != FEPLL_OK)

@@ -134,6 +134,29 @@ def test_single_restore_graph_equals_eager(F, gm, small_batch):
         np.testing.assert_array_equal(F.restore(g, y, s, precision="fp8").cpu().numpy(), eager)
 
 
+def test_profile_stage_mask(F, gm, small_batch):
+    """options.profile as a stage mask: only the named stages are timed,
+    each as often as with every stage timed (a chained stage after an
+    untimed one opens its own interval); the results are unchanged."""
+    g = F.GMM(*gm)
+    y = dev(small_batch[2]["y"])
+    s = small_batch[2]["sigma"]
+    kw = dict(precision="fp8", jitter=6, seed=7)
+    F.restore(g, y, s, profile=True, **kw)  # (the first call also builds the constants)
+    F.profile(g)
+    ref = F.restore(g, y, s, profile=True, **kw).cpu().numpy()
+    allst = F.profile(g)
+    for stages in (["select"], ["wiener"], ["select", "ola_update"], ["bucket", "wiener"]):
+        got = F.restore(g, y, s, profile=stages, **kw).cpu().numpy()
+        np.testing.assert_array_equal(got, ref)
+        p = F.profile(g)
+        for k, (ms, n) in p.items():
+            if k in stages:
+                assert n == allst[k][1] and n > 0 and ms > 0.0, (stages, k, p[k], allst[k])
+            else:
+                assert n == 0, (stages, k, p[k])
+
+
 def test_autotune_and_shapes_keep_results(F, gm, small_batch):
     g = F.GMM(*gm)
     sig = [d["sigma"] for d in small_batch]
