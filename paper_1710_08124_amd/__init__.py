@@ -178,9 +178,12 @@ def _options(precision="fp32", recheck=True, init=None, stream=None, profile=Fal
         o._init_img = _image(init)  # keep alive with the struct
         o.init = ctypes.pointer(o._init_img)
     o.stream = stream
-    # stage timing: False, True (every stage) or a list of stage names
+    # stage timing: False, True (every stage), a list of stage names, or the
+    # raw options.profile value (an int)
     if isinstance(profile, (list, tuple)):
         o.profile = sum(2 << STAGES.index(st) for st in profile)
+    elif isinstance(profile, int) and not isinstance(profile, bool):
+        o.profile = profile
     else:
         o.profile = 1 if profile else 0
     o.use_proposal = 1 if proposal else 0

@@ -155,6 +155,9 @@ def test_profile_stage_mask(F, gm, small_batch):
                 assert n == allst[k][1] and n > 0 and ms > 0.0, (stages, k, p[k], allst[k])
             else:
                 assert n == 0, (stages, k, p[k])
+    for bad in (-1, 2 << 9):
+        with pytest.raises(F.FepllError, match="EINVAL"):
+            F.restore(g, y, s, profile=bad, **kw)
 
 
 def test_autotune_and_shapes_keep_results(F, gm, small_batch):
