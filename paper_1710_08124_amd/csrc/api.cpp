@@ -91,9 +91,9 @@ struct fepll_gmm {
   int32_t* seg = nullptr;
   int32_t* perm = nullptr;
   float* Zhat = nullptr;
-  // jittered subsampling: chosen-patch flags and lists (two sets of np_cap
-  // each, packed like labels; iteration t uses set t & 1), list lengths per
-  // image (three sets of n; iteration t appends to set t % 3)
+  // jittered subsampling: chosen-patch flags and lists (three sets of np_cap
+  // each, packed like labels; iteration t uses set t % 3), list lengths per
+  // image (four sets of n; iteration t appends to set t % 4)
   int32_t* jflags = nullptr;
   bool jflags_dirty = true;  // jflags may hold set entries (cleared on next use)
   int32_t* jlist = nullptr;
@@ -105,6 +105,8 @@ struct fepll_gmm {
   // (0: no list sort), and the selection counts the chunks' labels itself
   int jit_nbl = 0;
   bool jit_hist = false;
+  // ... and draws the next iteration's subset inside the reprojection
+  bool jit_fused = false;
   // deblurring (periodic convolution): float64 FFT plans and spectra of the
   // last image size
   struct Deblur {
@@ -524,12 +526,12 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     HIPX(dalloc(&g->Zhat, NP * kP));
     HIPX(dalloc(&g->cand, NP * 8));
     HIPX(dalloc(&g->fb_list, NP));
-    HIPX(dalloc(&g->jflags, 2 * NP));
-    HIPX(dalloc(&g->jlist, 2 * NP));
+    HIPX(dalloc(&g->jflags, 3 * NP));
+    HIPX(dalloc(&g->jlist, 3 * NP));
     g->np_cap = NP;
     // the subset flags start (and stay, between calls) all zero
-    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((2 * NP + 255) / 256)), dim3(256), 0, st,
-                       g->jflags, (int)(2 * NP));
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((3 * NP + 255) / 256)), dim3(256), 0, st,
+                       g->jflags, (int)(3 * NP));
     HIPX(hipGetLastError());
     g->jflags_dirty = false;
   }
@@ -565,7 +567,7 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     g->px_cap = PX;
   }
   if (!g->count) HIPX(dalloc(&g->count, 64));
-  if ((s = grow(&g->jcount, g->jcount_cap, 3 * (size_t)n)) != FEPLL_OK) return s;
+  if ((s = grow(&g->jcount, g->jcount_cap, 4 * (size_t)n)) != FEPLL_OK) return s;
   if ((s = grow(&g->hist, g->hist_cap, (size_t)K * sort.size())) != FEPLL_OK) return s;
   if ((s = grow(&g->seg, g->seg_cap, (size_t)seg)) != FEPLL_OK) return s;
   if (!same) {
@@ -755,11 +757,11 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
 // image.  best / second / flags: packed like labels, or NULL.
 // The jittered subsets' flag set, list and counts of iteration t (float32
 // uses set 0 throughout), and the clearing of both flag sets.
-int32_t* jflags_of(fepll_gmm* g, int t) { return g->jflags + (size_t)(t & 1) * g->np_cap; }
-int32_t* jlist_of(fepll_gmm* g, int t) { return g->jlist + (size_t)(t & 1) * g->np_cap; }
-int32_t* jcount_of(fepll_gmm* g, int t) { return g->jcount + (size_t)(t % 3) * g->batch.n; }
+int32_t* jflags_of(fepll_gmm* g, int t) { return g->jflags + (size_t)(t % 3) * g->np_cap; }
+int32_t* jlist_of(fepll_gmm* g, int t) { return g->jlist + (size_t)(t % 3) * g->np_cap; }
+int32_t* jcount_of(fepll_gmm* g, int t) { return g->jcount + (size_t)(t % 4) * g->batch.n; }
 fepll_status clear_jflags(fepll_gmm* g, hipStream_t st) {
-  const size_t m = 2 * g->np_cap;
+  const size_t m = 3 * g->np_cap;
   hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st,
                      g->jflags, (int)m);
   HIPX(hipGetLastError());
@@ -823,9 +825,10 @@ fepll_status select_jitter(fepll_gmm* g, int t, const fepll_options& o, const fl
                                    jlist + d.np, st));
       }
       g->jflags_dirty = false;
-    } else {
+    } else if (!(g->jit_fused && t > 0)) {
       // every label not on the previous list is K here (run_hqs): list the
-      // subset as it is drawn, and undo the previous list (t > 0)
+      // subset as it is drawn, and undo the previous list (t > 0).  (Drawn
+      // by the previous reprojection when run_hqs fuses them.)
       for (int i = 0; i < b.n; ++i) {
         const ImgDesc& d = g->hd[i];
         JitterPrev prev;
@@ -1002,6 +1005,10 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
                          (size_t)list_chunks * b.n <= g->h_sort.size();
   g->jit_nbl = list_sort ? list_chunks : 0;
   g->jit_hist = false;
+  // one image, its list sorted, no labels returned: the reprojection of
+  // iteration t also draws the subset of t + 1 (it then takes its patches
+  // from the flags; the labels of earlier lists are left as they are)
+  g->jit_fused = list_sort && b.n == 1 && labels_out == nullptr;
   if (jit_list) {
     const int n = (int)b.n_patches;
     if (g->jflags_dirty && (s = clear_jflags(g, st)) != FEPLL_OK) return s;
@@ -1009,8 +1016,8 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     hipLaunchKernelGGL(fill_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, g->labels, n,
                        g->K);
     HIPX(hipGetLastError());
-    hipLaunchKernelGGL(zero_i32_kernel, dim3((3 * b.n + 255) / 256), dim3(256), 0, st, g->jcount,
-                       3 * b.n);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((4 * b.n + 255) / 256), dim3(256), 0, st, g->jcount,
+                       4 * b.n);
     HIPX(hipGetLastError());
   }
   for (int t = 0; t < T; ++t) {
@@ -1036,8 +1043,36 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     }
     {
       StageTimer tm(g, 4, st, true);
-      HIPX(launch_ola_batch(b, g->Zhat, g->ybuf, g->bvals, t, xn,
-                            o.jitter ? g->labels : nullptr, g->K, deblur_b ? 1 : 0, st));
+      if (g->jit_fused && t + 1 < T) {
+        // the drawing of t + 1: undoes the list of t - 1 (flags only), zeroes
+        // the count t + 2 appends to, clears the selection's histogram
+        const ImgDesc& d = g->hd[0];
+        JitterPrev prev;
+        if (t >= 1) {
+          prev.list = jlist_of(g, t - 1) + d.np;
+          prev.count = jcount_of(g, t - 1);
+          prev.flags = jflags_of(g, t - 1) + d.np;
+          prev.K = g->K;
+        }
+        prev.zero = jcount_of(g, t + 2);
+        if (g->jit_hist) {
+          prev.clear = g->hist;
+          prev.nclear = g->K * g->jit_nbl;
+        }
+        int blocks = 0;
+        const JitterDraw dr =
+            make_jitter_draw(d.H, d.W, o.jitter, o.seed, t + 1, jflags_of(g, t + 1) + d.np,
+                             jcount_of(g, t + 1), jlist_of(g, t + 1) + d.np, prev, &blocks);
+        HIPX(launch_ola_batch(b, g->Zhat, g->ybuf, g->bvals, t, xn, jflags_of(g, t), 0,
+                              deblur_b ? 1 : 0, &dr, st));
+      } else if (g->jit_fused) {
+        HIPX(launch_ola_batch(b, g->Zhat, g->ybuf, g->bvals, t, xn, jflags_of(g, t), 0,
+                              deblur_b ? 1 : 0, nullptr, st));
+      } else {
+        HIPX(launch_ola_batch(b, g->Zhat, g->ybuf, g->bvals, t, xn,
+                              o.jitter ? g->labels : nullptr, g->K, deblur_b ? 1 : 0, nullptr,
+                              st));
+      }
       if (deblur_b) {
         fepll_status s2 = deblur_update(g, xn, (*deblur_b)[t], st);
         if (s2 != FEPLL_OK) return s2;
@@ -1046,15 +1081,17 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     std::swap(xc, xn);
   }
   if (jit_list && T > 0) {
-    // the last list's patches back to flag 0 and label K
+    // the last list's patches (the last two when fused) back to flag 0 and
+    // label K
     StageTimer tm(g, 8, st);
-    for (int i = 0; i < b.n; ++i) {
-      const ImgDesc& d = g->hd[i];
-      const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter),
-                                             (int64_t)(d.H - 7) * (d.W - 7));
-      HIPX(launch_jitter_reset(jlist_of(g, T - 1) + d.np, lmax, jcount_of(g, T - 1) + i,
-                               nullptr, jflags_of(g, T - 1) + d.np, g->labels + d.np, g->K, st));
-    }
+    for (int u = (g->jit_fused && T >= 2) ? T - 2 : T - 1; u < T; ++u)
+      for (int i = 0; i < b.n; ++i) {
+        const ImgDesc& d = g->hd[i];
+        const int64_t lmax = std::min<int64_t>(jitter_points_max(d.H, d.W, o.jitter),
+                                               (int64_t)(d.H - 7) * (d.W - 7));
+        HIPX(launch_jitter_reset(jlist_of(g, u) + d.np, lmax, jcount_of(g, u) + i, nullptr,
+                                 jflags_of(g, u) + d.np, g->labels + d.np, g->K, st));
+      }
   }
   if (jit_list) g->jflags_dirty = false;
   *result = xc;

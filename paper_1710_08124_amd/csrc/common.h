@@ -169,14 +169,19 @@ hipError_t launch_wiener_batch(const Batch& b, const float* x, const float* Wt, 
                                const int32_t* seg, const int32_t* perm, const int32_t* wbase,
                                float* Zhat, int blocks, hipStream_t st);
 
+struct JitterDraw;
+
 // Reprojection + image update of iteration t: bvals[slot] = beta sigma^2.
-// subset_labels: NULL (every patch), or the packed labels, a patch being in
-// the subset when its label is below K (the average then runs over the
+// member: NULL (every patch), or packed per-patch words, a patch being in
+// the subset when its word differs from `none` (the labels with none = K,
+// or the subset flags with none = 0; the average then runs over the
 // subset's patches only).
 // raw: write x~ itself (the image estimation of an operator A follows).
+// draw: NULL, or (with member) a jittered drawing run by extra workgroups
+// of the same launch; it must touch no word the reprojection reads.
 hipError_t launch_ola_batch(const Batch& b, const float* Zhat, const float* y,
-                            const float* bvals, int t, float* xnew, const int32_t* subset_labels,
-                            int K, int raw, hipStream_t st);
+                            const float* bvals, int t, float* xnew, const int32_t* member,
+                            int none, int raw, const JitterDraw* draw, hipStream_t st);
 
 // Deblurring (periodic convolution A), float64 half spectra of m = H (W/2+1)
 // complex entries (double2): see deblur.hip.
@@ -212,6 +217,20 @@ struct JitterPrev {
   int32_t* clear = nullptr;
   int nclear = 0;
 };
+// A drawing's launch arguments (make_jitter_draw) and its workgroups of 256
+// threads (*blocks), for a launch of its own (launch_jitter_mark) or as the
+// extra workgroups of the subset reprojection (launch_ola_batch).
+struct JitterDraw {
+  int H = 0, W = 0, s = 0;
+  uint32_t k0 = 0, k1 = 0;
+  int t = 0, amax = 0, cmax = 0;
+  int32_t* flags = nullptr;
+  int32_t* count = nullptr;
+  int32_t* list = nullptr;
+  JitterPrev prev;
+};
+JitterDraw make_jitter_draw(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
+                            int32_t* count, int32_t* list, const JitterPrev& prev, int* blocks);
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
                               int32_t* count, int32_t* list, const JitterPrev& prev,
                               hipStream_t st);

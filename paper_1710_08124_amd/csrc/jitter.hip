@@ -24,100 +24,15 @@
 // alternate, so the undo and the new marks never touch the same flag).
 #include <algorithm>
 
-#include "common.h"
+#include "jitter_draw.h"
 
 namespace fepll {
 
 namespace {
 
-struct U4 {
-  uint32_t x, y, z, w;
-};
-
-__device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1) {
-  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
-    const uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
-    c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
-    k0 += W0;  // (the bump after the last round is unused)
-    k1 += W1;
-  }
-  return c;
-}
-
-// first grid coordinate along an axis with shift g: g - s n0, n0 the
-// smallest n with g - s n <= -b
-__device__ __forceinline__ int grid_first(int g, int s, int b) {
-  const int n0 = (g + b + s - 1) / s;
-  return g - s * n0;
-}
-
-// APPEND: each chosen patch is also appended to list at *count (wave-
-// aggregated atomics; a patch two grid points clamp to is taken once: its
-// flag is set by an exchange), and the flags stay set until the next
-// iteration's launch (or jitter_reset_kernel) clears them; that launch
-// first undoes the previous list (prev, one entry per thread: a list never
-// holds more entries than the grid has points) in the other flag set.
-// Otherwise only the flags are set and *count zeroed for
-// jitter_compact_kernel.
 template <bool APPEND>
-__global__ __launch_bounds__(256) void jitter_mark_kernel(int H, int W, int s, uint32_t k0,
-                                                          uint32_t k1, int t, int amax, int cmax,
-                                                          int32_t* __restrict__ flags,
-                                                          int32_t* __restrict__ count,
-                                                          int32_t* __restrict__ list,
-                                                          JitterPrev prev) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (APPEND && prev.list && i < *prev.count) {
-    const int q = prev.list[i];
-    prev.flags[q] = 0;
-    prev.labels[q] = prev.K;
-  }
-  if (APPEND && prev.zero && i == 0) *prev.zero = 0;
-  if (APPEND && prev.clear)
-    for (int j = i; j < prev.nclear; j += gridDim.x * blockDim.x) prev.clear[j] = 0;
-  const int Hp = H - 7, Wp = W - 7;
-  const int b = (8 - s) / 2;
-  const U4 sh = philox4x32_10(U4{(uint32_t)t, 0xffffffffu, 0xffffffffu, 0u}, k0, k1);
-  const int fy = grid_first((int)(sh.x % (uint32_t)s), s, b);
-  const int fx = grid_first((int)(sh.y % (uint32_t)s), s, b);
-  // grid extent: points up to the first one whose lowest start reaches the
-  // last patch row / column
-  const int na = (Hp - 1 + b - fy + s - 1) / s + 1;
-  const int nc = (Wp - 1 + b - fx + s - 1) / s + 1;
-  if (!APPEND && i == 0) *count = 0;  // the compaction that follows counts the subset
-  const int a = i / cmax, c = i - a * cmax;
-  int p = 0;
-  bool take = false;
-  if (i < amax * cmax && a < na && c < nc) {
-    const U4 u = philox4x32_10(U4{(uint32_t)t, (uint32_t)a, (uint32_t)c, 0u}, k0, k1);
-    const uint32_t n = (uint32_t)(2 * b + 1);
-    const int r = min(max(fy + s * a + (int)(u.x % n) - b, 0), Hp - 1);
-    const int q = min(max(fx + s * c + (int)(u.y % n) - b, 0), Wp - 1);
-    p = r * Wp + q;
-    if (APPEND)
-      take = atomicExch(&flags[p], 1) == 0;
-    else
-      flags[p] = 1;
-  }
-  if (!APPEND) return;
-  // one global atomic per workgroup (ballots, LDS prefix over the 4 waves)
-  __shared__ int wcnt[4], wbase;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t mask = __ballot(take);
-  if (lane == 0) wcnt[wave] = __popcll(mask);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-    wbase = tot ? atomicAdd(count, tot) : 0;
-  }
-  __syncthreads();
-  int off = wbase;
-  for (int w = 0; w < wave; ++w) off += wcnt[w];
-  if (take) list[off + __popcll(mask & ((1ull << lane) - 1ull))] = p;
+__global__ __launch_bounds__(256) void jitter_mark_kernel(JitterDraw a) {
+  jitter_draw_block<APPEND>(a, blockIdx.x, gridDim.x);
 }
 
 // After an iteration on an appended list: its patches' flags cleared and
@@ -213,18 +128,35 @@ int64_t jitter_points_max(int H, int W, int s) {
   return (int64_t)grid_points_max(H - 7, s) * grid_points_max(W - 7, s);
 }
 
+JitterDraw make_jitter_draw(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
+                            int32_t* count, int32_t* list, const JitterPrev& prev, int* blocks) {
+  JitterDraw a;
+  a.H = H;
+  a.W = W;
+  a.s = s;
+  a.k0 = (uint32_t)(seed & 0xffffffffu);
+  a.k1 = (uint32_t)(seed >> 32);
+  a.t = t;
+  a.amax = grid_points_max(H - 7, s);
+  a.cmax = grid_points_max(W - 7, s);
+  a.flags = flags;
+  a.count = count;
+  a.list = list;
+  a.prev = prev;
+  *blocks = (a.amax * a.cmax + 255) / 256;
+  return a;
+}
+
 hipError_t launch_jitter_mark(int H, int W, int s, uint64_t seed, int t, int32_t* flags,
                               int32_t* count, int32_t* list, const JitterPrev& prev,
                               hipStream_t st) {
-  const int amax = grid_points_max(H - 7, s), cmax = grid_points_max(W - 7, s);
-  const int n = amax * cmax;
-  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  int blocks = 0;
+  const JitterDraw a =
+      make_jitter_draw(H, W, s, seed, t, flags, count, list, list ? prev : JitterPrev{}, &blocks);
   if (list)
-    hipLaunchKernelGGL(jitter_mark_kernel<true>, dim3((n + 255) / 256), dim3(256), 0, st, H, W,
-                       s, k0, k1, t, amax, cmax, flags, count, list, prev);
+    hipLaunchKernelGGL(jitter_mark_kernel<true>, dim3(blocks), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(jitter_mark_kernel<false>, dim3((n + 255) / 256), dim3(256), 0, st, H, W,
-                       s, k0, k1, t, amax, cmax, flags, count, list, JitterPrev{});
+    hipLaunchKernelGGL(jitter_mark_kernel<false>, dim3(blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

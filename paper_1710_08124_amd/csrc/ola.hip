@@ -28,7 +28,7 @@
 // and a column factor, cnt(y, x) = n(y, H) n(x, W) with
 // n(v, S) = min(v, S-8) - max(0, v-7) + 1.
 
-#include "common.h"
+#include "jitter_draw.h"
 
 namespace fepll {
 
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void ola_update_kernel(Batch bt,
 // ---- subset reprojection (jittered subsampling, Sec. 3.3).  The same
 // tiles, each cut into parts of TY rows, one workgroup per part.  A part's
 // window is the (TY + 7) x 71 patches that touch it; a patch is chosen when
-// its label is below K.
+// its member word differs from `none` (a label below K, or a set flag).
 //   1. one bit per window patch: each window row is two ballots (columns
 //      0..63 and 64..70) over coalesced label loads; a wave scan of the rows'
 //      popcounts gives every chosen patch its slot in raster order, and the
@@ -150,8 +150,9 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
                                                          const float* __restrict__ y_b,
                                                          const float* __restrict__ bvals, int it,
                                                          float* __restrict__ xnew_b,
-                                                         const int32_t* __restrict__ labels_b,
-                                                         int K, int raw) {
+                                                         const int32_t* __restrict__ member_b,
+                                                         int none, int raw, int nparts,
+                                                         JitterDraw draw, int draw_blocks) {
   constexpr int WR = TY + 7;          // patch rows of the window
   constexpr int WIN = WR * NP;        // patches of the window
   constexpr int CH = 128;             // patches staged at a time
@@ -163,9 +164,15 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
   __shared__ int rbase[WR + 1];          // chosen patches in the rows above
   __shared__ int16_t plist[WIN];         // slot -> window row * NP + column
   __shared__ float zs[CH * PITCH];
+  // workgroups past the nparts of the reprojection run the drawing of the
+  // next iteration (disjoint words: other flags, list and count)
+  if ((int)blockIdx.x >= nparts) {
+    jitter_draw_block<true>(draw, (int)blockIdx.x - nparts, draw_blocks);
+    return;
+  }
   // a planned tile (64 x ola_rows) is cut into ola_rows / TY workgroups of
   // TY rows (short tiles: more workgroups in flight for a sparse subset)
-  const int G8 = gridDim.x;
+  const int G8 = nparts;
   const int sub = bt.ola_rows / TY;
   const int lin2 = (blockIdx.x & 7) * (G8 >> 3) + (blockIdx.x >> 3);
   if (lin2 >= bt.n_ola * sub) return;
@@ -175,7 +182,7 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
   const int Hp = H - 7, Wp = W - 7;
   const float b = bvals[d.slot0 + it];
   const float* Zhat = Zhat_b + (size_t)d.np * kP;
-  const int32_t* labels = labels_b + d.np;
+  const int32_t* member = member_b + d.np;
   const float* y = y_b + d.px;
   float* xnew = xnew_b + d.px;
   const int nty = (H + bt.ola_rows - 1) / bt.ola_rows;
@@ -202,13 +209,13 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
     for (int u = 0; u < RPW; ++u) {
       const int rw = wave + 4 * u, r = rfirst + rw;
       const bool row = rw < WR && r >= 0 && r < Hp;
-      la[u] = (row && c >= 0 && c < Wp) ? labels[(size_t)r * Wp + c] : K;
-      lb[u] = (row && lane < NP - 64 && c2 >= 0 && c2 < Wp) ? labels[(size_t)r * Wp + c2] : K;
+      la[u] = (row && c >= 0 && c < Wp) ? member[(size_t)r * Wp + c] : none;
+      lb[u] = (row && lane < NP - 64 && c2 >= 0 && c2 < Wp) ? member[(size_t)r * Wp + c2] : none;
     }
 #pragma unroll
     for (int u = 0; u < RPW; ++u) {
       const int rw = wave + 4 * u;
-      const uint64_t A = __ballot(la[u] < K), B = __ballot(lb[u] < K);
+      const uint64_t A = __ballot(la[u] != none), B = __ballot(lb[u] != none);
       if (rw < WR && lane == 0) {
         mlo[rw] = A;
         mhi[rw] = B;
@@ -319,13 +326,20 @@ __global__ __launch_bounds__(256) void ola_subset_kernel(Batch bt, const float* 
 
 template <bool SUB>
 static void launch_ola_rows(const Batch& b, int blocks, const float* Zhat, const float* y,
-                            const float* bvals, int t, float* xnew, const int32_t* labels, int K,
-                            int raw, hipStream_t st) {
+                            const float* bvals, int t, float* xnew, const int32_t* member,
+                            int none, int raw, const JitterDraw* draw, hipStream_t st) {
   if (SUB) {
-    // 16-row parts of every planned tile (the planned heights are 16, 32, 64)
+    // 16-row parts of every planned tile (the planned heights are 16, 32, 64),
+    // then the drawing's workgroups
     const int parts = ((int)(((int64_t)b.n_ola * (b.ola_rows / 16) + 7) & ~7));
-    hipLaunchKernelGGL(ola_subset_kernel<16>, dim3(parts), dim3(256), 0, st, b, Zhat, y, bvals, t,
-                       xnew, labels, K, raw);
+    int dblocks = 0;
+    JitterDraw a;
+    if (draw) {
+      a = *draw;
+      dblocks = (a.amax * a.cmax + 255) / 256;
+    }
+    hipLaunchKernelGGL(ola_subset_kernel<16>, dim3(parts + dblocks), dim3(256), 0, st, b, Zhat, y,
+                       bvals, t, xnew, member, none, raw, parts, a, dblocks);
     return;
   }
   if (b.ola_rows == 16)
@@ -340,13 +354,14 @@ static void launch_ola_rows(const Batch& b, int blocks, const float* Zhat, const
 }
 
 hipError_t launch_ola_batch(const Batch& b, const float* Zhat, const float* y,
-                            const float* bvals, int t, float* xnew, const int32_t* subset_labels,
-                            int K, int raw, hipStream_t st) {
+                            const float* bvals, int t, float* xnew, const int32_t* member,
+                            int none, int raw, const JitterDraw* draw, hipStream_t st) {
   const int blocks = (b.n_ola + 7) & ~7;  // whole rounds over the 8 XCDs
-  if (subset_labels)
-    launch_ola_rows<true>(b, blocks, Zhat, y, bvals, t, xnew, subset_labels, K, raw, st);
+  if (draw && !member) return hipErrorInvalidValue;
+  if (member)
+    launch_ola_rows<true>(b, blocks, Zhat, y, bvals, t, xnew, member, none, raw, draw, st);
   else
-    launch_ola_rows<false>(b, blocks, Zhat, y, bvals, t, xnew, nullptr, K, raw, st);
+    launch_ola_rows<false>(b, blocks, Zhat, y, bvals, t, xnew, nullptr, none, raw, nullptr, st);
   return hipGetLastError();
 }
 
