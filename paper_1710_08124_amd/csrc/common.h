@@ -200,10 +200,11 @@ hipError_t launch_spec_init(const void* AtY, const double* a2, void* X, int H, i
 // (any order), clears its flag and sets every other patch's label to K.
 // With list (*count zero before, flags all zero before): each chosen patch
 // is appended to list at *count and flagged.  The same launch first undoes
-// the previous iteration's list when prev.list is set: its prev.count
-// entries get flag 0 in prev.flags (the other flag set) and label K (every
-// label not on the new list is K before the selection), and *prev.zero (the
-// count the iteration after this one appends to) is zeroed.
+// an earlier iteration's list when prev.list is set: its prev.count
+// entries get flag 0 in prev.flags (another flag set) and, with
+// prev.labels, label K (every label not on the new list is K before the
+// selection), and *prev.zero (a count a later drawing appends to) is
+// zeroed.
 // launch_jitter_reset does the same for the last list of a restoration
 // (next_count may be NULL).  With clear set, the launch also zeroes its
 // nclear words (the chunk histogram the selection then adds to).

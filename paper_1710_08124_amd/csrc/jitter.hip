@@ -20,8 +20,10 @@
 // appended to a list in any order, the others' labels set to K, the "not in
 // the subset" mark every later stage reads).  Before a selection of the
 // subset alone: one launch, mark appending to the list as it draws, which
-// also undoes the previous iteration's list (two flag sets and two lists
-// alternate, so the undo and the new marks never touch the same flag).
+// also undoes an earlier iteration's list (three flag sets and lists
+// alternate, so the undo and the new marks never touch the same flag);
+// the same drawing can also run inside the subset reprojection
+// (jitter_draw.h).
 #include <algorithm>
 
 #include "jitter_draw.h"
