@@ -403,7 +403,7 @@ def main():
 def run_deblur(F, torch, np, fs, g0, gf, args):
     """The deblurring workload (second workload of the paper, Table 3):
     the test image blurred by a 9x9 seeded motion kernel, noise sigma 0.5,
-    A a periodic convolution; Sec. 6 schedule and start, T = 5.  Eager runs
+    A a periodic convolution; Sec. 5 schedule and start, T = 5.  Eager runs
     (no graph capture on this path)."""
     c = fs.config_deblur(size=args.size)
     y = torch.from_numpy(np.asarray(c["y"], np.float32)).cuda()
@@ -429,7 +429,7 @@ def run_deblur(F, torch, np, fs, g0, gf, args):
         rows[p]["dpsnr_vs_fp32_path_db"] = round(rows["fp32"]["psnr_db"] - rows[p]["psnr_db"], 4)
         rows[p]["speedup_vs_plain_fp32"] = round(rows[p]["mpix_s"] / rows["fp32"]["mpix_s"], 3)
     return {"workload": f"{H}x{W} test image, 9x9 seeded motion blur (periodic), sigma 0.5, "
-                        "K=200, T=5, Sec. 6 schedule and start",
+                        "K=200, T=5, Sec. 5 schedule and start",
             "psnr_blurred_db": round(psnr(c["x"], np.asarray(c["y"], np.float32)), 4),
             "paths": rows}
 

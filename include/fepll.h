@@ -9,7 +9,7 @@
  * ingredients for a 100x speed-up" (arXiv 1710.08124) -- patch extraction,
  * Gaussian selection, patch estimation, patch reprojection, image
  * estimation -- with selection and estimation in each component's
- * eigenbasis (Sec. 2.1, eq:projection_eigenspace / eq:selection_eigenspace).
+ * eigenbasis (Sec. 2.1, Eq. (7) / Eq. (8)).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -124,7 +124,7 @@ void fepll_options_default(fepll_options* opt);
  *           of the j-th eigenvector of Sigma_k (columns are eigenvectors);
  *           each U_k must be orthonormal (max |U^t U - I| <= 1e-8).
  *   lambda: K x d float64, host, the diagonal of S_k, finite and >= 0.
- *   w:      K float64, host, the mixture weights (eq:prior): w_k > 0 and
+ *   w:      K float64, host, the mixture weights (Eq. (2)): w_k > 0 and
  *           |sum w - 1| <= 1e-6 (never renormalised).
  *   K:      1..1024.   d: must be 64 (8x8 patches).
  * The library copies what it keeps.  EINVAL on any violated condition,
@@ -217,11 +217,11 @@ typedef struct {
  *           beta = lambda sigma^-2 {1, 4, 8, 16, 32} with lambda =
  *           min(|A^t A|_F^2 / (N |A|_2^2), 250 sigma^2) and the default
  *           start (options.init NULL) is (A^t A + 0.2 sigma^2 / lambda Lap)^-1
- *           A^t y, Lap the periodic 5-point Laplacian (Sec. 6, "Parameter
+ *           A^t y, Lap the periodic 5-point Laplacian (Sec. 5, "Parameter
  *           settings"); runs without graph capture.
  *   sigma:  noise standard deviation on the image's scale, > 0.
  *   beta_schedule: T absolute values of beta (the HQS coupling weight of
- *           eq:qhs), each > 0; NULL = {1, 4, 8, 16, 32} / sigma^2 (denoising,
+ *           Eq. (3)), each > 0; NULL = {1, 4, 8, 16, 32} / sigma^2 (denoising,
  *           lambda = 1) with T = 5 (T must then be 5 or 0, where 0 means 5).
  *   T:      1..16 iterations.
  *   out:    H x W output (host or device); may alias y.
@@ -319,7 +319,7 @@ fepll_status fepll_profile(fepll_gmm* g, double* ms, int32_t* launches, int32_t 
 /* ------------------------------------------------------------------------
  * Component-proposal network.  Not part of the paper: the paper limits the
  * components scored by a search tree (Sec. 3.2) and reviews a gating network
- * that approximates the selection score (Sec. 5); here a network
+ * that approximates the selection score (Sec. 4); here a network
  * [z~/128, log sigma_beta] (65) -> 256 -> 256 -> K, exact-erf GELU after the
  * hidden layers, proposes components that the selection step then rescores
  * with the exact cost.  Parameters are one float32 vector

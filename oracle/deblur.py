@@ -8,7 +8,7 @@ never does, and this module imports nothing from it.
 Alg. 1's image estimation solves (A^t A + beta sigma^2 I) x = A^t y +
 beta sigma^2 x~; for a periodic convolution A is diagonal in the Fourier
 basis, so the solve is a pointwise division between two 2-D FFTs (Sec. 2.1,
-the complexity discussion of the image-estimation step).  Sec. 6
+the complexity discussion of the image-estimation step).  Sec. 5
 ("Parameter settings") fixes, for inverse problems:
 
 * beta = lambda sigma^-2 {1, 4, 8, 16, 32} with
@@ -56,7 +56,7 @@ def laplacian_spectrum(H: int, W: int):
 
 
 def lambda_param(h, H: int, W: int, sigma: float) -> float:
-    """lambda = min(N^-1 |A^t A|_F^2 |A|_2^-2, 250 sigma^2) (Sec. 6): with
+    """lambda = min(N^-1 |A^t A|_F^2 |A|_2^-2, 250 sigma^2) (Sec. 5): with
     A's eigenvalues a_w, |A^t A|_F^2 = sum |a_w|^4 and |A|_2 = max |a_w|."""
     a2 = np.abs(kernel_spectrum(h, H, W)) ** 2
     return float(min(np.sum(a2 * a2) / (H * W) / a2.max(), 250.0 * sigma * sigma))
@@ -67,7 +67,7 @@ def default_betas(h, H, W, sigma):
 
 
 def initial_estimate(y, h, sigma):
-    """x = (A^t A + 0.2 sigma^2 / lambda Lap)^-1 A^t y (Sec. 6)."""
+    """x = (A^t A + 0.2 sigma^2 / lambda Lap)^-1 A^t y (Sec. 5)."""
     H, W = y.shape
     Hh = kernel_spectrum(h, H, W)
     lam = lambda_param(h, H, W, sigma)
@@ -101,8 +101,8 @@ def hqs_iteration(xh, y, h, U, lam, w, sigma, beta):
 
 
 def restore(y, h, U, lam, w, sigma, betas=None, init=None, trace=False):
-    """EPLL deblurring: T iterations of Alg. 1 from the Sec. 6 start (or
-    ``init``) over the Sec. 6 schedule (or ``betas``)."""
+    """EPLL deblurring: T iterations of Alg. 1 from the Sec. 5 start (or
+    ``init``) over the Sec. 5 schedule (or ``betas``)."""
     y = np.asarray(y, dtype=np.float64)
     H, W = y.shape
     if betas is None:

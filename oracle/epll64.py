@@ -8,16 +8,16 @@ What it computes (Parameswaran, Deledalle, Denis, Nguyen, "Accelerating
 GMM-based patch priors for image restoration", arXiv 1710.08124):
 
 * the EPLL MAP problem with a zero-mean GMM patch prior on DC-removed 8x8
-  patches (Sec. 2, eq. (1) "eq:epll" and eq. (2) "eq:prior");
-* approximated by half-quadratic splitting (eq. "eq:qhs") with the five
+  patches (Sec. 2, Eq. (1) and Eq. (2));
+* approximated by half-quadratic splitting (Eq. (3)) with the five
   steps of Algorithm 1 -- patch extraction, Gaussian selection, patch
   estimation, patch reprojection, image estimation -- for denoising (A = I);
 * the selection and estimation steps written in each component's eigenbasis
-  (Sec. 2.1, eqs. "eq:projection_eigenspace" and "eq:selection_eigenspace"
+  (Sec. 2.1, Eqs. (7) and (8)
   and the two lines after them), with iota_k = -2 log w_k,
   nu_kj = S_kjj + 1/beta and gamma_kj = S_kjj / nu_kj;
 * the schedule T = 5, beta = {1, 4, 8, 16, 32} / sigma^2 and the start
-  x = y (end of Sec. 2 "Algorithm"; lambda = 1 for denoising, Sec. 6
+  x = y (end of Sec. 2 "Algorithm"; lambda = 1 for denoising, Sec. 5
   "Parameter settings").
 
 Readings taken where the paper is silent (each one is listed in the design
@@ -105,9 +105,9 @@ def eigen_terms(lam: np.ndarray, w: np.ndarray, beta: float):
 
 def selection_costs(Zt: np.ndarray, U: np.ndarray, nu: np.ndarray, L: np.ndarray):
     """Selection objective of every component for every patch, (n, K):
-    c^k = U_k^t z~ (eq:projection_eigenspace) and
+    c^k = U_k^t z~ (Eq. (7)) and
     cost_k = iota_k + sum_j (log nu_kj + c_j^2 / nu_kj)
-    (eq:selection_eigenspace)."""
+    (Eq. (8))."""
     n = Zt.shape[0]
     K = U.shape[0]
     cost = np.empty((n, K))

@@ -4,11 +4,11 @@ TEST INFRASTRUCTURE ONLY (imported by tests, the smoke check and the
 benchmark's CPU-baseline leg, never by the restoration library).
 
 The paper does not use a network for the Gaussian selection step: it reviews
-a gating network (Sec. 5, the RoG discussion, eq. "eq:rog") that approximates
+a gating network (Sec. 4, Related methods, its RoG score) that approximates
 the selection score, and accelerates the step with a search tree instead.
 The proposal network here is a design choice of this project that takes the
 same role -- guess the few components worth scoring -- and is then checked by
-the exact score of the selection step (eq:selection_eigenspace), so the
+the exact score of the selection step (Eq. (8)), so the
 restoration stays the paper's method.  Everything below is therefore
 defined by this project, not by the paper:
 

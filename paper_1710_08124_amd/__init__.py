@@ -311,7 +311,7 @@ def restore(gmm: GMM, y, sigma: float, betas=None, init=None, precision="fp32",
     (Sec. 3.3) with its Philox seed.
     tree: select through the search tree of gmm.set_tree (Sec. 3.2; bf16).
     blur: None (denoising), or the centred odd-sized kernel of a periodic
-    convolution A (deblurring; the Sec. 6 schedule and start by default).
+    convolution A (deblurring; the Sec. 5 schedule and start by default).
     Returns the restored image (same kind and device as y) and, with
     return_labels, the (T, Np) int32 labels of every iteration (K for the
     patches an iteration did not choose).

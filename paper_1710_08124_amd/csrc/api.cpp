@@ -1460,7 +1460,7 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const fepll_opera
   if ((s = check_opt(g, &o)) != FEPLL_OK) return s;
   const int H = y->height, W = y->width;
   hipStream_t st = (hipStream_t)o.stream;
-  // deblurring: the kernel's spectrum and lambda (Sec. 6) before the schedule
+  // deblurring: the kernel's spectrum and lambda (Sec. 5) before the schedule
   double lambda = 1.0;
   if (conv) {
     if ((s = use_stream(g, st)) != FEPLL_OK) return s;
@@ -1504,7 +1504,7 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const fepll_opera
 
   float* res = nullptr;
   if (conv) {
-    // A^t y once; the Sec. 6 start unless options.init is given; then the
+    // A^t y once; the Sec. 5 start unless options.init is given; then the
     // iterations with the Fourier image estimation (eager: no capture)
     auto& D = g->db;
     const int n = H * W, m = H * (W / 2 + 1);

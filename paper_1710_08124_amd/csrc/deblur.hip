@@ -1,7 +1,7 @@
 // Image estimation of Alg. 1 for a periodic convolution A (deblurring):
 // x = (A^t A + b I)^-1 (A^t y + b x~), b = beta sigma^2, is a pointwise
 // division in the Fourier basis (A's eigenvalues are the DFT of its kernel,
-// Sec. 2.1's remark on fast transforms); the start of Sec. 6,
+// Sec. 2.1's remark on fast transforms); the start of Sec. 5,
 // x = (A^t A + c Lap)^-1 A^t y with c = 0.2 sigma^2 / lambda and Lap the
 // positive semidefinite periodic 5-point Laplacian, is the same division
 // with c Lap's eigenvalues in place of b.

@@ -1,7 +1,7 @@
 // Gaussian selection for every patch (Alg. 1, patch extraction + Gaussian
 // selection, in the eigenspace form of Sec. 2.1): per patch i and component
-// k the projection c = U_k^t z~_i (eq:projection_eigenspace) and the cost
-// L_k + sum_j c_j^2 / nu_kj (eq:selection_eigenspace), argmin over k.
+// k the projection c = U_k^t z~_i (Eq. (7)) and the cost
+// L_k + sum_j c_j^2 / nu_kj (Eq. (8)), argmin over k.
 //
 // Float32 MFMA kernel for gfx950.  The contraction is
 //   C[(k, j), i] = sum_p Ut_k[p][j] * z~_i[p],   Ut_k = U_k diag(nu_k)^-1/2,

@@ -4,7 +4,7 @@
 // AdamW.  The network is this project's replacement for the paper's search
 // tree (Sec. 3.2) in the role of limiting how many components the
 // selection step scores; its output is always rescored with the exact cost
-// of eq:selection_eigenspace.
+// of Eq. (8).
 //
 // One tiled float32 MFMA GEMM serves every product of the forward and
 // backward passes (C = op(A) op(B), A or B optionally transposed) with fused

@@ -1,5 +1,5 @@
 // Per-beta constants of the eigenspace formulation (Sec. 2.1, the terms
-// defined after eq:selection_eigenspace): nu_kj = lambda_kj + 1/beta,
+// defined after Eq. (8)): nu_kj = lambda_kj + 1/beta,
 // gamma_kj = lambda_kj / nu_kj, iota_k = -2 log w_k.  Computed in float64
 // from the float64 eigendecomposition, then rounded once to the operand
 // layouts the kernels read (see common.h).  One workgroup per (component,

@@ -4,7 +4,7 @@ construction on the host (float64 NumPy), for GMM.set_tree.
 Sec. 3.2 collapses the mixture level by level (K = 200 -> 64 -> 32 -> 16 ->
 8 -> 4 -> 2 -> 1 components), each level a partition of the one below into
 clusters of about equal size minimizing the summed symmetric Kullback-Leibler
-divergence between the zero-mean Gaussians of a cluster (eq:cost_clustering,
+divergence between the zero-mean Gaussians of a cluster (the clustering cost of Sec. 3.2,
 whose printed form compares a component with itself: the pairwise
 divergence is meant).  The paper solves each partition with a genetic
 algorithm for the multiple travelling salesmen problem; here a deterministic

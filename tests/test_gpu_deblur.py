@@ -1,5 +1,5 @@
 """Deblurring (a periodic convolution A, Alg. 1's image estimation in the
-Fourier basis, Sec. 6's schedule and start) on the GPU against the FP64
+Fourier basis, Sec. 5's schedule and start) on the GPU against the FP64
 reference (oracle/deblur.py).
 
 * float32, teacher-forced: labels bit-exact (certified), one iteration's

@@ -93,7 +93,7 @@ def test_identity_operator_is_denoising():
     got = db.restore(y, np.ones((1, 1)), c["U"], c["lam"], c["w"], c["sigma"],
                      betas=o.default_betas(c["sigma"]), init=y)
     np.testing.assert_allclose(got, want, rtol=0, atol=1e-9)
-    # and the Sec. 6 schedule reduces to the denoising one
+    # and the Sec. 5 schedule reduces to the denoising one
     np.testing.assert_allclose(db.default_betas(np.ones((1, 1)), 30, 34, c["sigma"]),
                                o.default_betas(c["sigma"]), rtol=1e-14)
 

@@ -43,7 +43,7 @@ def dense_iteration(x, y, Sig, w, beta, sigma, periodic=False, closed_form=False
     """One HQS iteration written in the matrix form of Alg. 1 with dense
     covariances: Gaussian selection by log-determinant and linear solve,
     patch estimation (Sigma + I/beta)^-1 Sigma z~, reprojection with explicit
-    P_i matrices.  ``closed_form`` uses eq:qhs_optim_imest_sol instead of
+    P_i matrices.  ``closed_form`` uses Eq. (6) instead of
     the reprojection + image estimation split."""
     H, W = x.shape
     K = Sig.shape[0]
@@ -230,7 +230,7 @@ def test_p5_counts_closed_form(H, W):
 def test_p6_periodic_equals_closed_form():
     """With wrap-around patches every pixel is covered P = 64 times and
     Alg. 1 (average, then image estimation) equals the closed-form x-update
-    eq:qhs_optim_imest_sol; both are computed densely here, and the oracle's
+    Eq. (6); both are computed densely here, and the oracle's
     periodic iteration must match."""
     U, lam, w = fs.gmm(3, 4)
     Sig = covs(U, lam)
@@ -249,7 +249,7 @@ def test_p6_periodic_equals_closed_form():
 
 
 def test_p6_valid_mode_differs_only_on_border():
-    """Valid patches: Alg. 1 and eq:qhs_optim_imest_sol agree where the
+    """Valid patches: Alg. 1 and Eq. (6) agree where the
     count is P and differ on the border band (the reading taken: Alg. 1)."""
     U, lam, w = fs.gmm(2, 6)
     Sig = covs(U, lam)
