@@ -320,7 +320,7 @@ fepll_status fepll_profile(fepll_gmm* g, double* ms, int32_t* launches, int32_t 
  * Component-proposal network.  Not part of the paper: the paper limits the
  * components scored by a search tree (Sec. 3.2) and reviews a gating network
  * that approximates the selection score (Sec. 4); here a network
- * [z~/128, log sigma_beta] (65) -> 256 -> 256 -> K, exact-erf GELU after the
+ * [z~/128, log sigma_beta] (65) -> 256 -> 256 -> K, tanh-form GELU after the
  * hidden layers, proposes components that the selection step then rescores
  * with the exact cost.  Parameters are one float32 vector
  * W1 (256x65) b1 (256) W2 (256x256) b2 (256) W3 (Kx256) b3 (K), every W

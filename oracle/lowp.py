@@ -24,13 +24,12 @@ float32, and the products are exact: this module evaluates them in float64
 from the rounded operands.  What the GPU adds on top is float32 (or wider)
 accumulation, so its costs must agree with these to within that rounding.
 
-The DC-removed patch z~ = z - m is formed in float32, with the patch mean m
-accumulated in float32 in a fixed order (part of each mode's definition):
-
-* ``"bf16"``: s_g = sum, in order, of patch rows g and 4 + g (16 pixels,
-  row g first) for g = 0..3, then m = ((s_0 + s_1) + (s_2 + s_3)) / 64;
-* ``"fp8"``:  s_h = sum, in order, of pixels 32 h .. 32 h + 31 for h = 0, 1,
-  then m = (s_0 + s_1) / 64.
+The DC-removed patch z~ is defined independently of any summation order: m
+is the sum of the patch's 64 float32 pixels, correctly rounded to float64
+(exact whenever the pixel magnitudes of the patch lie within a factor 2^23
+of each other), divided by 64 (exact), and each z~_j is the difference
+z_j - m correctly rounded to float32 (nearest, ties to even).  Both modes
+share it, and it is the float32 path's DC removal too.
 
 Ut_k is formed in float64 and rounded to float32 before the format rounding
 (for fp8: Ut_k 2^-e_k rounded to float32, then to e4m3).
@@ -47,6 +46,8 @@ float32 DC-removed patch (before the format rounding).  Components with
 r_k = 64 keep the plain form.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -100,30 +101,40 @@ def pow2_exponent(mx) -> np.ndarray:
 
 # ----------------------------------------------------------- operands
 
-def _seq_sum32(cols: np.ndarray) -> np.ndarray:
-    """float32 sum of the columns of cols, left to right."""
-    s = cols[:, 0].astype(np.float32)
-    for i in range(1, cols.shape[1]):
-        s = (s + cols[:, i]).astype(np.float32)
-    return s
+def _twosum(a: np.ndarray, b: np.ndarray):
+    """s + e == a + b exactly, s = fl(a + b) (Knuth's TwoSum)."""
+    s = a + b
+    bv = s - a
+    av = s - bv
+    return s, (a - av) + (b - bv)
 
 
-def dc_removed32(Z: np.ndarray, mode: str) -> np.ndarray:
+def round32_of_sum(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """a + b (float64 arrays) correctly rounded to float32, nearest, ties to
+    even: the float64 sum d and its error e give the exact value d + e;
+    rounding d alone is correct unless d sits exactly halfway between two
+    float32 values and e != 0, where e decides."""
+    d, e = _twosum(np.asarray(a, np.float64), np.asarray(b, np.float64))
+    r = d.astype(np.float32)
+    r64 = r.astype(np.float64)
+    # the other float32 neighbour of d (toward d), and the midpoint between
+    # the two (exact in float64)
+    nb = np.nextafter(r, np.where(d > r64, np.inf, -np.inf).astype(np.float32))
+    nb64 = nb.astype(np.float64)
+    mid = (r64 + nb64) * 0.5
+    # a tie of d went to the even neighbour r; the exact value d + e lies
+    # past the midpoint, toward nb, when e points that way
+    fix = (e != 0) & (d == mid) & ((e > 0) == (nb64 > r64))
+    return np.where(fix, nb, r)
+
+
+def dc_removed32(Z: np.ndarray, mode: str | None = None) -> np.ndarray:
     """z~ = z - m in float32 for float32 patches Z (N x 64), m as in the
-    module docstring."""
-    Z = np.asarray(Z, np.float32)
-    if mode == "bf16":
-        s = []
-        for g in range(4):
-            cols = np.concatenate([Z[:, 8 * g:8 * g + 8], Z[:, 8 * (4 + g):8 * (4 + g) + 8]], 1)
-            s.append(_seq_sum32(cols))
-        tot = ((s[0] + s[1]).astype(np.float32) + (s[2] + s[3]).astype(np.float32)).astype(np.float32)
-    elif mode == "fp8":
-        tot = (_seq_sum32(Z[:, :32]) + _seq_sum32(Z[:, 32:])).astype(np.float32)
-    else:
-        raise ValueError(mode)
-    m = (tot * np.float32(1.0 / 64.0)).astype(np.float32)
-    return (Z - m[:, None]).astype(np.float32)
+    module docstring (the same for both modes)."""
+    Z64 = np.asarray(Z, np.float32).astype(np.float64)
+    S = np.fromiter((math.fsum(row) for row in Z64), np.float64, Z64.shape[0])
+    m = S * (1.0 / 64.0)
+    return round32_of_sum(Z64, -m[:, None])
 
 
 def patch_operand(Zt32: np.ndarray, mode: str) -> np.ndarray:

@@ -14,8 +14,8 @@ defined by this project, not by the paper:
 
 * input feature of a patch: [z~ / 128, log sigma_beta] (65 values), with z~
   the DC-removed patch and sigma_beta = beta^-1/2;
-* network: 65 -> 256 -> 256 -> K, exact-erf GELU after the two hidden
-  layers, logits out;  h = W x + b with W stored (out, in) row-major;
+* network: 65 -> 256 -> 256 -> K, GELU in its tanh form (Hendrycks &
+  Gimpel, 2016) after the two hidden layers, logits out;  h = W x + b with W stored (out, in) row-major;
 * loss: mean softmax cross-entropy against the MAP label k*;
 * optimiser: AdamW with decoupled weight decay
   p <- p - lr * (m_hat / (sqrt(v_hat) + eps) + wd * p), bias-corrected moments;
@@ -44,15 +44,16 @@ def features(Zt: np.ndarray, beta: float) -> np.ndarray:
 
 
 def gelu(x):
-    """x * Phi(x) with the exact normal CDF."""
-    from scipy.special import erf
-    return 0.5 * x * (1.0 + erf(x / math.sqrt(2.0)))
+    """x * sigmoid(2 u) = 0.5 x (1 + tanh u), u = sqrt(2/pi) (x + 0.044715 x^3)."""
+    u = math.sqrt(2.0 / math.pi) * (x + 0.044715 * x ** 3)
+    return 0.5 * x * (1.0 + np.tanh(u))
 
 
 def gelu_grad(x):
-    from scipy.special import erf
-    phi = np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
-    return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * phi
+    """Derivative of ``gelu`` by the chain rule."""
+    t = np.tanh(math.sqrt(2.0 / math.pi) * (x + 0.044715 * x ** 3))
+    du = math.sqrt(2.0 / math.pi) * (1.0 + 3.0 * 0.044715 * x * x)
+    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * du
 
 
 def forward(p, X):

@@ -71,29 +71,30 @@ __device__ __forceinline__ f32x4 mfma16(uint4 a, uint4 b, f32x4 c) {
 template <bool NZ>
 __device__ __forceinline__ void load_patch(const float* __restrict__ x, int W, int r, int c,
                                            int g, uint4 zb[2], float& nz) {
-  // the mean is taken in float32: its rounding is far below the bfloat16
-  // rounding of the differences that follows
+  // the mean in float64 (exact for any order whenever the patch's pixel
+  // magnitudes lie within 2^23 of each other), each difference rounded once
+  // to float32
   float v[2][8];
-  float s = 0.f;
+  double s = 0.0;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const float* row = x + (size_t)(r + 4 * t + g) * W + c;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       v[t][e] = row[e];
-      s += v[t][e];
+      s += (double)v[t][e];
     }
   }
   s += __shfl_xor(s, 16);
   s += __shfl_xor(s, 32);
-  const float m = s * (1.f / 64.f);
+  const double m = s * (1.0 / 64.0);
   float q2 = 0.f;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     float d[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      d[e] = v[t][e] - m;
+      d[e] = (float)((double)v[t][e] - m);
       if (NZ) q2 = fmaf(d[e], d[e], q2);
     }
     zb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),

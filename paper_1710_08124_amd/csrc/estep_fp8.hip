@@ -46,21 +46,22 @@ __device__ __forceinline__ int fp8_exponent(float mx) {
 }
 
 // e4m3 B operand (32 bytes) and E8M0 scale of a patch from the lane's 32
-// pixels v (rows 4 h .. 4 h + 3 of it, row-major): the mean is a float32 sum
-// of the lane's 32 pixels in order, plus the other half's sum.  With NZ, nz
-// receives the float32 squared norm of the (unrounded) DC-removed patch,
-// the same in both lanes of its column.
+// pixels v (rows 4 h .. 4 h + 3 of it, row-major): the mean is a float64
+// sum of the 64 pixels (exact for any order whenever the patch's pixel
+// magnitudes lie within 2^23 of each other), each difference rounded once to
+// float32.  With NZ, nz receives the float32 squared norm of the (unrounded)
+// DC-removed patch, the same in both lanes of its column.
 template <bool NZ>
 __device__ __forceinline__ void quantize_patch8(float (&v)[32], i32x8& zq, int& code, float& nz) {
-  float s = v[0];
+  double s = (double)v[0];
 #pragma unroll
-  for (int i = 1; i < 32; ++i) s += v[i];
+  for (int i = 1; i < 32; ++i) s += (double)v[i];
   s += __shfl_xor(s, 32);
-  const float m = s * (1.f / 64.f);
+  const double m = s * (1.0 / 64.0);
   float mx = 0.f, q2 = 0.f;
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
-    v[i] -= m;
+    v[i] = (float)((double)v[i] - m);
     mx = fmaxf(mx, fabsf(v[i]));
     if (NZ) q2 = fmaf(v[i], v[i], q2);
   }

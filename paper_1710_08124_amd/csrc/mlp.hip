@@ -21,10 +21,18 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 namespace {
 constexpr int TM = 64, TN = 64, TK = 32;
 
-__device__ __forceinline__ float gelu(float a) { return 0.5f * a * (1.f + erff(a * 0.70710678118654752f)); }
+// GELU in its tanh form (Hendrycks & Gimpel, 2016): a sigmoid(2 u) with
+// u = sqrt(2/pi) (a + 0.044715 a^3), i.e. 0.5 a (1 + tanh u); the inference
+// kernel evaluates the same function.
+__device__ __forceinline__ float gelu(float a) {
+  const float u2 = a * fmaf(0.0713548162726f, a * a, 1.59576912161f);  // 2 u
+  return a / (1.f + expf(-u2));
+}
 __device__ __forceinline__ float gelu_grad(float a) {
-  return 0.5f * (1.f + erff(a * 0.70710678118654752f)) +
-         a * 0.39894228040143268f * expf(-0.5f * a * a);
+  const float a2 = a * a;
+  const float s = 1.f / (1.f + expf(-a * fmaf(0.0713548162726f, a2, 1.59576912161f)));
+  // d(2u)/da = 2 sqrt(2/pi) (1 + 3 * 0.044715 a^2)
+  return fmaf(a * s * (1.f - s), fmaf(0.214064448818f, a2, 1.59576912161f), s);
 }
 }  // namespace
 

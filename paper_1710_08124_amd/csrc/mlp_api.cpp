@@ -48,7 +48,7 @@ struct BlobHeader {
   uint32_t d_in;      // 65
   uint32_t hidden;    // 256
   float scale_in;     // 128
-  uint32_t gelu;      // 1 = exact erf
+  uint32_t gelu;      // 2 = tanh form (the only one inference evaluates)
   uint64_t nparam;
   uint64_t checksum;  // FNV-1a-64 of the parameter bytes
   uint8_t pad[64 - 48];
@@ -277,7 +277,7 @@ fepll_status fepll_mlp_serialize(fepll_mlp* m, void* buf, size_t cap, size_t* nb
   h.d_in = kFeat;
   h.hidden = kHidden;
   h.scale_in = kScaleIn;
-  h.gelu = 1;
+  h.gelu = 2;
   h.nparam = m->lay.n;
   h.checksum = fnv1a(p.data(), p.size() * sizeof(float));
   std::memcpy(buf, &h, sizeof(h));
@@ -300,7 +300,7 @@ fepll_status parse_proposal_blob(const void* blob, size_t nbytes, int K,
     return fail(FEPLL_EINVAL, "not a proposal network blob (magic/version)");
   if ((int)h.K != K) return fail(FEPLL_EINVAL, "network K differs from the mixture's K");
   if (h.d_in != (uint32_t)kFeat || h.hidden != (uint32_t)kHidden || h.scale_in != kScaleIn ||
-      h.gelu != 1)
+      h.gelu != 2)
     return fail(FEPLL_EINVAL, "network shape, input scale or GELU variant not supported");
   const MlpLayout L(K);
   if (h.nparam != L.n || nbytes != sizeof(BlobHeader) + L.n * sizeof(float))

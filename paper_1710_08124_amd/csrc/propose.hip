@@ -50,9 +50,8 @@ __device__ __forceinline__ f32x16 mfma_bf16(uint4 a, uint4 b, f32x16 c) {
                                                  __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 // GELU in the tanh form of Hendrycks & Gimpel (2016),
-// x * sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3)): within 5e-4 of the exact
-// x Phi(x) the network is trained with, far below the bfloat16 rounding of
-// the activations that follows, and branch-free (one exp2, one reciprocal).
+// x * sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3)), the form the network is
+// trained with: branch-free, one exp2 and one reciprocal.
 __device__ __forceinline__ float gelu(float a) {
   const float t = a * fmaf(0.0713548162726f, a * a, 1.59576912161f);  // 2 sqrt(2/pi) (a + 0.044715 a^3)
   const float e = __builtin_amdgcn_exp2f(-t * 1.44269504089f);
@@ -193,13 +192,15 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
   // (made visible by the first slab's barrier)
 
   // ---- layer-1 input: DC-removed patch / 128 and log sigma_beta.  The
-  // mean is summed in the order of the bfloat16 selection's operand (rows g
-  // and 4 + g in order into s_g, then (s_0 + s_1) + (s_2 + s_3)); lane half
-  // h holds rows 2 t + h, so s_h (rows h, 4 + h) and s_{2+h} (rows 2 + h,
-  // 6 + h).  With zop, the patch is also written as that operand
-  // (bfloat16, row dy at uint4 dy of the patch's 128 bytes) with its float32
-  // squared norm in the same order: what the rescoring of the candidates
-  // reads, bit for bit the full search's operands.
+  // mean is summed in float64 (exact in any order whenever the patch's pixel
+  // magnitudes lie within 2^23 of each other) and each difference is
+  // rounded once to float32, as in the selection kernels; lane half h holds
+  // rows 2 t + h.  With zop, the patch is also written as the bfloat16
+  // selection operand (row dy at uint4 dy of the patch's 128 bytes) with its
+  // float32 squared norm, summed in the order of the bfloat16 selection
+  // (rows g and 4 + g in order into q_g, then (q_0 + q_1) + (q_2 + q_3)):
+  // what the rescoring of the candidates reads, bit for bit the full
+  // search's operands.
   uint4 xb[5];
   {
     float v[4][8];
@@ -209,22 +210,18 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
 #pragma unroll
       for (int e = 0; e < 8; ++e) v[t][e] = row[e];
     }
-    float sa = 0.f, sb = 0.f;
+    double sd = 0.0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) sa += v[0][e];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) sa += v[2][e];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) sb += v[1][e];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) sb += v[3][e];
-    const float pa = __shfl_xor(sa, 32), pb = __shfl_xor(sb, 32);
-    const float mean = ((sa + pa) + (sb + pb)) * (1.f / 64.f);
+      for (int e = 0; e < 8; ++e) sd += (double)v[t][e];
+    sd += __shfl_xor(sd, 32);
+    const double mean = sd * (1.0 / 64.0);
     float d[4][8];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) d[t][e] = v[t][e] - mean;
+      for (int e = 0; e < 8; ++e) d[t][e] = (float)((double)v[t][e] - mean);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       float q[8];

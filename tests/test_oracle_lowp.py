@@ -61,14 +61,70 @@ def test_pow2_exponent():
     assert lowp.pow2_exponent(0.0) == 0
 
 
-@pytest.mark.parametrize("mode", ["bf16", "fp8"])
-def test_dc_removed_orders(mode):
+def _nearest_f32(q):
+    """The float32 nearest to the rational q, ties to the even significand:
+    brute force over the neighbours of a first guess."""
+    from fractions import Fraction
+    f = np.float32(float(q))
+    cands = [f, np.nextafter(f, np.float32(np.inf)), np.nextafter(f, np.float32(-np.inf))]
+    dist = [abs(Fraction(float(c)) - q) for c in cands]
+    best = min(dist)
+    ties = [c for c, d in zip(cands, dist) if d == best]
+    if len(ties) > 1:
+        ties = [c for c in ties if int(np.float32(c).view(np.uint32)) & 1 == 0]
+    return ties[0]
+
+
+def _dc_removed_brute(Z):
+    """z~ by exact rational arithmetic: the pixel sum correctly rounded to
+    float64 (int / int true division rounds correctly), divided by 64, and
+    z - m rounded to the nearest float32."""
+    from fractions import Fraction
+    out = np.empty(Z.shape, np.float32)
+    for i, row in enumerate(Z):
+        S = sum(Fraction(float(v)) for v in row)
+        m = Fraction(S.numerator / S.denominator) / 64
+        for j, v in enumerate(row):
+            out[i, j] = _nearest_f32(Fraction(float(v)) - m)
+    return out
+
+
+def test_dc_removed_exact_against_rational_brute_force():
     rng = np.random.default_rng(4)
-    Z = rng.uniform(0, 255, (500, 64)).astype(np.float32)
-    zt = lowp.dc_removed32(Z, mode)
-    # the float32 mean differs from the exact one by a few float32 ulps only
+    # ordinary pixels, pixels over a wide dynamic range with both signs, and
+    # patches built so that z - m lands exactly halfway between two float32
+    # values in float64 while the exact difference does not
+    A = rng.uniform(0, 255, (40, 64))
+    B = (np.ldexp(rng.uniform(1, 2, (40, 64)), rng.integers(-60, 10, (40, 64)))
+         * rng.choice([-1.0, 1.0], (40, 64)))
+    C = np.zeros((3, 64))
+    C[:, 0] = 1.0
+    C[:, 1] = 2.0 ** -19
+    C[:, 2] = [2.0 ** -52, -(2.0 ** -52), 0.0]
+    Z = np.concatenate([A, B, C]).astype(np.float32)
+    got = lowp.dc_removed32(Z)
+    want = _dc_removed_brute(Z)
+    np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+    # the engineered ties: 1 - 2^-6 - 2^-25 -/+ 2^-58 rounds away from the
+    # even neighbour 63/64 in the first patch, to it in the second and third
+    assert got[80, 0] == np.float32(1 - 2.0 ** -6 - 2.0 ** -24)
+    assert got[81, 0] == np.float32(1 - 2.0 ** -6) == got[82, 0]
+
+
+def test_dc_removed_order_free():
+    # the definition names no summation order: permuting a patch's pixels
+    # permutes its DC-removed values, and both modes share it
+    rng = np.random.default_rng(5)
+    Z = (rng.uniform(0, 255, (300, 64)) + rng.normal(0, 30, (300, 64))).astype(np.float32)
+    zt = lowp.dc_removed32(Z, "bf16")
+    np.testing.assert_array_equal(zt, lowp.dc_removed32(Z, "fp8"))
+    for s in range(3):
+        perm = np.random.default_rng(10 + s).permutation(64)
+        np.testing.assert_array_equal(lowp.dc_removed32(Z[:, perm]), zt[:, perm])
+    # and it is the exact difference within half a float32 ulp
     exact = Z.astype(np.float64) - Z.astype(np.float64).mean(1, keepdims=True)
-    assert np.max(np.abs(zt - exact)) < 64 * 2 ** -24 * 255 * 2
+    ulp = np.spacing(np.abs(zt)).astype(np.float64)
+    assert np.all(np.abs(zt - exact) <= 0.5 * ulp + 1e-12 * np.abs(exact))
 
 
 @pytest.mark.parametrize("mode", ["bf16", "fp8"])

@@ -1,7 +1,8 @@
-"""Pins of the proposal-network oracle (FP64): gradients against central
-finite differences, the first AdamW step against its closed form, textbook
-values of the normal CDF, and the degenerate settings of the proposal rule
-that must reduce to the plain full-K selection."""
+"""Pins of the proposal-network oracle (FP64): the forward map against
+PyTorch's float64 linear and tanh-form GELU, gradients against central
+finite differences, the first AdamW step against its closed form, the GELU
+form's identities and its distance to x Phi(x), and the degenerate settings
+of the proposal rule that must reduce to the plain full-K selection."""
 import math
 
 import numpy as np
@@ -73,14 +74,41 @@ def test_adamw_first_step_closed_form():
         np.testing.assert_allclose(p[k], want, rtol=1e-12, atol=1e-15)
 
 
-def test_gelu_textbook_values():
-    # GELU(x) = x Phi(x); Phi(1) = 0.8413447460685429, Phi(-1) = 0.15865525393145707
-    np.testing.assert_allclose(M.gelu(np.array([1.0, -1.0, 0.0])),
-                               [0.8413447460685429, -0.15865525393145707, 0.0], rtol=1e-15)
-    np.testing.assert_allclose(M.gelu(np.array([12.0, -12.0])), [12.0, 0.0], atol=1e-30)
-    x = np.linspace(-4, 4, 17)
-    fd = (M.gelu(x + 1e-6) - M.gelu(x - 1e-6)) / 2e-6
-    np.testing.assert_allclose(M.gelu_grad(x), fd, atol=1e-8)
+def test_gelu_tanh_form():
+    # the tanh form against PyTorch's own float64 implementation of it, its
+    # odd-part identity gelu(x) - gelu(-x) = x (sigmoid(t) + sigmoid(-t) = 1),
+    # its limits, its distance to the exact x Phi(x) (below 5e-4, Phi(1) =
+    # 0.8413447460685429), and its derivative against central differences
+    torch = pytest.importorskip("torch")
+    x = np.linspace(-9, 9, 3601)
+    want = torch.nn.functional.gelu(torch.from_numpy(x), approximate="tanh").numpy()
+    np.testing.assert_allclose(M.gelu(x), want, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(M.gelu(x) - M.gelu(-x), x, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(M.gelu(np.array([30.0, -30.0, 0.0])), [30.0, 0.0, 0.0], atol=1e-30)
+    exact = torch.nn.functional.gelu(torch.from_numpy(x)).numpy()
+    assert np.max(np.abs(M.gelu(x) - exact)) < 5e-4
+    assert abs(M.gelu(np.array([1.0]))[0] - 0.8413447460685429) < 5e-4
+    xs = np.linspace(-4, 4, 17)
+    fd = (M.gelu(xs + 1e-6) - M.gelu(xs - 1e-6)) / 2e-6
+    np.testing.assert_allclose(M.gelu_grad(xs), fd, atol=1e-8)
+
+
+def test_forward_against_torch_functional():
+    # the oracle's forward map against an independent evaluation by PyTorch's
+    # float64 CPU ops (linear layers and the tanh-form GELU)
+    torch = pytest.importorskip("torch")
+    F = torch.nn.functional
+    K = 13
+    p = dict(fs.mlp_init(K, 41))
+    for i, k in enumerate(("b1", "b2", "b3")):
+        p[k] = fs.rng(50 + i).normal(0, 0.3, p[k].shape)
+    X = fs.rng(42).normal(0, 1, (300, 65))
+    got, _ = M.forward(p, X)
+    t = {k: torch.from_numpy(np.asarray(v, np.float64)) for k, v in p.items()}
+    h = F.gelu(F.linear(torch.from_numpy(X), t["W1"], t["b1"]), approximate="tanh")
+    h = F.gelu(F.linear(h, t["W2"], t["b2"]), approximate="tanh")
+    want = F.linear(h, t["W3"], t["b3"]).numpy()
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
 
 
 def test_xent_uniform_logits_is_log_K():
