@@ -106,7 +106,7 @@ def evaluate(gmm, images, top_m=8, margin=0.5, log=print):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_BLOB)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=24)
     ap.add_argument("--images", type=int, default=13)
     ap.add_argument("--size", type=int, default=256)
     args = ap.parse_args(argv)
