@@ -67,19 +67,22 @@ struct fepll_gmm {
   int cmask = 0;
   size_t S_cap = 0;
   double* dbeta = nullptr;
+  float* dlogsb = nullptr;  // log sigma_beta = -log(beta) / 2 of each slot (network input)
   ConstTables tb{};
   // plan of the last call: host copies (kept for the asynchronous uploads
   // and to skip unchanged uploads) and device copies
   std::vector<ImgDesc> hd;
-  std::vector<int32_t> h_est, h_sort, h_ola;
+  std::vector<int32_t> h_est, h_sort, h_ola, h_resc;
   std::vector<float> hbvals;
   Batch batch{};
   bool plan_valid = false;
-  size_t n_cap = 0, wb_cap = 0, est_cap = 0, sort_cap = 0, ola_cap = 0, slot_cap = 0;
+  size_t n_cap = 0, wb_cap = 0, est_cap = 0, sort_cap = 0, ola_cap = 0, slot_cap = 0,
+         resc_cap = 0, fb_cap = 0;
   ImgDesc* d = nullptr;
   int32_t* est_img = nullptr;
   int32_t* sort_img = nullptr;
   int32_t* ola_img = nullptr;
+  int32_t* resc_img = nullptr;
   int32_t* wbase = nullptr;
   float* bvals = nullptr;
   // scratch, sized for the packed batch
@@ -151,14 +154,15 @@ struct fepll_gmm {
   uint16_t* pWb = nullptr;
   float* pbias = nullptr;
   bool has_proposal = false;
-  uint16_t* cand = nullptr;   // Np x 8
-  int32_t* fb_list = nullptr;  // Np
-  // exact rescoring: (patch, candidate) pairs sorted by component
-  size_t pair_cap = 0, pcost_cap = 0, phist_cap = 0, pseg_cap = 0;
+  uint16_t* cand = nullptr;   // 8 per patch, packed like the labels
+  int32_t* fb_list = nullptr;  // fallback lists, packed like the labels
+  int32_t* fbcnt = nullptr;    // fallback list length per image
+  int32_t* fbitems = nullptr;  // fallback items: first of each image, then the total
+  // the search tree's descent: patches grouped by node (pair sort scratch)
+  size_t pair_cap = 0, phist_cap = 0, pseg_cap = 0;
   int32_t* psorted = nullptr;  // 8 Np
-  float* pcost = nullptr;      // 8 Np
-  // the patches' bfloat16 selection operands and squared norms, written by
-  // the network for the rescoring and the fallback
+  // the patches' bfloat16 selection operands and squared norms, written for
+  // the search tree's sparse levels
   size_t zop_cap = 0, znz_cap = 0;
   uint16_t* zop = nullptr;  // 64 Np
   float* znz = nullptr;     // Np
@@ -349,6 +353,7 @@ fepll_status ensure_consts(fepll_gmm* g, const std::vector<double>& betas, int m
   if (S > g->S_cap) {
     HIPX(hipStreamSynchronize(st));
     dfree(g->dbeta);
+    dfree(g->dlogsb);
     dfree(g->tb.Ut);
     dfree(g->tb.Ub);
     dfree(g->tb.Wt);
@@ -362,6 +367,7 @@ fepll_status ensure_consts(fepll_gmm* g, const std::vector<double>& betas, int m
     g->cbeta.clear();
     g->cmask = 0;
     HIPX(dalloc(&g->dbeta, S));
+    HIPX(dalloc(&g->dlogsb, S));
     HIPX(dalloc(&g->tb.Wt, S * K * kTileStride));
     HIPX(dalloc(&g->tb.L32, S * K));
     HIPX(dalloc(&g->tb.Pinv, S * K));
@@ -382,6 +388,9 @@ fepll_status ensure_consts(fepll_gmm* g, const std::vector<double>& betas, int m
   // same slots: add the missing tables; new slots: these tables only
   const int build = (g->cbeta == betas) ? (mask | g->cmask) : mask;
   HIPX(hipMemcpyAsync(g->dbeta, betas.data(), sizeof(double) * S, hipMemcpyHostToDevice, st));
+  std::vector<float> logsb(S);
+  for (size_t i = 0; i < S; ++i) logsb[i] = (float)(-0.5 * std::log(betas[i]));
+  HIPX(hipMemcpyAsync(g->dlogsb, logsb.data(), sizeof(float) * S, hipMemcpyHostToDevice, st));
   {
     StageTimer tm(g, 5, st);
     HIPX(launch_prep(g->U64, g->lam64, g->w64, g->K, g->dbeta, (int)S, build, g->tb, st));
@@ -472,7 +481,7 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
   const int K = g->K;
   const int ola_rows = g->tune.ola_rows;
   std::vector<ImgDesc> hd(n);
-  std::vector<int32_t> est, sort, ola;
+  std::vector<int32_t> est, sort, ola, resc;
   int64_t px = 0, np = 0, seg = 0;
   for (int i = 0; i < n; ++i) {
     const int Hp = H[i] - 7, Wp = W[i] - 7;
@@ -487,7 +496,10 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     d.est0 = (int32_t)est.size();
     d.ola0 = (int32_t)ola.size();
     d.slot0 = i * T;
+    d.resc0 = (int32_t)resc.size();
+    d.pad = 0;
     const int64_t nb = (Np + kSortBlock - 1) / kSortBlock;
+    const int64_t nr = (Np + kRescPatches - 1) / kRescPatches;
     const int64_t ne = (int64_t)((Wp + kEstCols - 1) / kEstCols) * ((Hp + 3) / 4);
     const int64_t no =
         (int64_t)((W[i] + kOlaX - 1) / kOlaX) * ((H[i] + ola_rows - 1) / ola_rows);
@@ -496,6 +508,7 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     sort.insert(sort.end(), (size_t)nb, i);
     est.insert(est.end(), (size_t)ne, i);
     ola.insert(ola.end(), (size_t)no, i);
+    resc.insert(resc.end(), (size_t)nr, i);
     px += ((int64_t)H[i] * W[i] + 63) / 64 * 64;  // 256-byte aligned images
     np += Np;
     seg += (int64_t)seg_size(Np, K);
@@ -536,22 +549,16 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     g->jflags_dirty = false;
   }
   {
-    // pair scratch of the proposal path, sized for the largest image
+    // the search tree's pair scratch, sized for the largest image
     size_t npmax = 0;
     for (int i = 0; i < n; ++i) npmax = std::max(npmax, (size_t)(H[i] - 7) * (W[i] - 7));
     if ((s = grow(&g->psorted, g->pair_cap, 8 * npmax)) != FEPLL_OK) return s;
-    if (!g->pcost || 8 * npmax > g->pcost_cap) {
-      dfree(g->pcost);
-      g->pcost_cap = 0;
-      HIPX(dalloc(&g->pcost, 8 * npmax));
-      g->pcost_cap = 8 * npmax;
-    }
     const size_t nb2 = (npmax + kPairBlock - 1) / kPairBlock;
     // (the tree descent buckets over all its nodes)
     const int Kp = std::max(K, g->tree.Kall);
     if ((s = grow(&g->phist, g->phist_cap, (size_t)Kp * nb2)) != FEPLL_OK) return s;
     if ((s = grow(&g->pseg, g->pseg_cap, pair_seg_size(npmax, Kp))) != FEPLL_OK) return s;
-    if (g->has_proposal || g->tree.Kall) {
+    if (g->tree.Kall) {
       if ((s = grow(&g->zop, g->zop_cap, 64 * npmax)) != FEPLL_OK) return s;
       if ((s = grow(&g->znz, g->znz_cap, npmax)) != FEPLL_OK) return s;
     }
@@ -568,6 +575,8 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
   }
   if (!g->count) HIPX(dalloc(&g->count, 64));
   if ((s = grow(&g->jcount, g->jcount_cap, 4 * (size_t)n)) != FEPLL_OK) return s;
+  if ((s = grow(&g->fbcnt, g->fb_cap, 2 * (size_t)n + 1)) != FEPLL_OK) return s;
+  g->fbitems = g->fbcnt + n;
   if ((s = grow(&g->hist, g->hist_cap, (size_t)K * sort.size())) != FEPLL_OK) return s;
   if ((s = grow(&g->seg, g->seg_cap, (size_t)seg)) != FEPLL_OK) return s;
   if (!same) {
@@ -576,11 +585,13 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     if ((s = grow(&g->est_img, g->est_cap, est.size())) != FEPLL_OK) return s;
     if ((s = grow(&g->sort_img, g->sort_cap, sort.size())) != FEPLL_OK) return s;
     if ((s = grow(&g->ola_img, g->ola_cap, ola.size())) != FEPLL_OK) return s;
+    if ((s = grow(&g->resc_img, g->resc_cap, resc.size())) != FEPLL_OK) return s;
     if ((s = grow(&g->bvals, g->slot_cap, bvals.size())) != FEPLL_OK) return s;
     g->hd = std::move(hd);
     g->h_est = std::move(est);
     g->h_sort = std::move(sort);
     g->h_ola = std::move(ola);
+    g->h_resc = std::move(resc);
     g->hbvals = bvals;
     HIPX(hipMemcpyAsync(g->d, g->hd.data(), sizeof(ImgDesc) * n, hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(g->est_img, g->h_est.data(), sizeof(int32_t) * g->h_est.size(),
@@ -588,6 +599,8 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     HIPX(hipMemcpyAsync(g->sort_img, g->h_sort.data(), sizeof(int32_t) * g->h_sort.size(),
                         hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(g->ola_img, g->h_ola.data(), sizeof(int32_t) * g->h_ola.size(),
+                        hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(g->resc_img, g->h_resc.data(), sizeof(int32_t) * g->h_resc.size(),
                         hipMemcpyHostToDevice, st));
     HIPX(hipMemcpyAsync(g->bvals, g->hbvals.data(), sizeof(float) * g->hbvals.size(),
                         hipMemcpyHostToDevice, st));
@@ -598,10 +611,12 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
   b.est_img = g->est_img;
   b.sort_img = g->sort_img;
   b.ola_img = g->ola_img;
+  b.resc_img = g->resc_img;
   b.n = n;
   b.n_est = (int)g->h_est.size();
   b.n_sort = (int)g->h_sort.size();
   b.n_ola = (int)g->h_ola.size();
+  b.n_resc = (int)g->h_resc.size();
   b.n_patches = np;
   b.max_np = 0;
   for (const ImgDesc& dd : g->hd)
@@ -674,66 +689,14 @@ fepll_status select_tree(fepll_gmm* g, const float* x, int H, int W, int slot,
   return FEPLL_OK;
 }
 
-// One Gaussian selection of one image x with the tables of beta slot
-// `slot`: float32 E-step + float64 recheck, or the proposal path.
+// One float32 Gaussian selection of one image x with the tables of beta
+// slot `slot`: the certified E-step, then the float64 re-selection of the
+// uncertified patches.
 fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, double beta,
                         const fepll_options& o, int32_t* labels, float* best, float* second,
                         int32_t* flags, hipStream_t st) {
   const int Np = (H - 7) * (W - 7);
   const size_t K = g->K;
-  if (o.precision == FEPLL_BF16) {
-    // the proposal path: network, exact rescoring of the candidates, full-K
-    // selection of the fallback list
-    if (flags) {
-      hipLaunchKernelGGL(zero_i32_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, flags, Np);
-      HIPX(hipGetLastError());
-    }
-    {
-      StageTimer tm(g, 6, st);
-      HIPX(launch_propose_bf16(x, H, W, beta, g->pWb, g->pbias, g->K, o.top_m, g->cand, g->zop,
-                               g->znz, st));
-    }
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, g->count, 1);
-    HIPX(hipGetLastError());
-    const uint16_t* Ub = g->tb.Ub + (size_t)slot * K * kTileStride;
-    const float* L = g->tb.L32 + (size_t)slot * K;
-    {
-      // exact rescoring of the candidates: pairs bucketed by component
-      StageTimer tm(g, 0, st);
-      HIPX(launch_pair_bucket(g->cand, Np, o.top_m, g->K, g->phist, g->pseg, g->psorted, st));
-      HIPX(launch_pair_scores_bf16(g->zop, g->znz, Np, Ub, L, g->tb.rk,
-                                   g->tb.Pinv + (size_t)slot * K, g->K, o.top_m, g->pseg,
-                                   g->psorted, g->pcost, st));
-      HIPX(launch_pair_reduce(g->cand, g->pcost, Np, o.top_m, g->K, (float)o.margin_nats, labels,
-                              best, second, g->count, g->fb_list, st));
-    }
-    BF16Args a{};
-    a.x = x;
-    a.H = H;
-    a.W = W;
-    a.Ub = Ub;
-    a.L = L;
-    a.K = g->K;
-    a.labels = labels;
-    a.best = best;
-    a.second = second;
-    a.list_count = g->count;
-    a.list = g->fb_list;
-    a.rk = g->tb.rk;
-    a.Pinv = g->tb.Pinv + (size_t)slot * K;
-    a.zop = reinterpret_cast<const uint4*>(g->zop);
-    a.znz = g->znz;
-    {
-      StageTimer tm(g, 7, st);
-      HIPX(launch_estep_bf16_mode(kModeListFull, a, st));
-    }
-    if (flags) {
-      hipLaunchKernelGGL(mark_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, g->count,
-                         g->fb_list, flags);
-      HIPX(hipGetLastError());
-    }
-    return FEPLL_OK;
-  }
   hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, g->count, 1);
   HIPX(hipGetLastError());
   {
@@ -753,8 +716,9 @@ fepll_status select_one(fepll_gmm* g, const float* x, int H, int W, int slot, do
 
 // Selection of every image of the planned batch at iteration t.  The
 // all-K reduced-precision modes run as one persistent launch over the
-// batch; float32 (with its recheck) and the proposal path run image by
-// image.  best / second / flags: packed like labels, or NULL.
+// batch, the proposal path as one launch per stage over the batch; float32
+// (with its recheck) runs image by image.  best / second / flags: packed
+// like labels, or NULL.
 // The jittered subsets' flag set, list and counts of iteration t (float32
 // uses set 0 throughout), and the clearing of both flag sets.
 int32_t* jflags_of(fepll_gmm* g, int t) { return g->jflags + (size_t)(t % 3) * g->np_cap; }
@@ -912,6 +876,97 @@ fepll_status ensure_jitter(fepll_gmm* g, const fepll_options& o) {
   return FEPLL_OK;
 }
 
+// The proposal path over the planned batch at iteration t: the network's
+// top-m candidates of every patch (one launch over the batch's selection
+// tiles), their exact rescoring with the fallback decisions (one launch over
+// the rescoring tiles), then the full-K search of every image's fallback
+// list (one launch over the items of all lists).  flags (or NULL): 1 on the
+// patches that fell back, 0 elsewhere.
+fepll_status select_proposal(fepll_gmm* g, int t, const fepll_options& o, const float* x,
+                             int32_t* labels, float* best, float* second, int32_t* flags,
+                             hipStream_t st) {
+  const Batch& b = g->batch;
+  {
+    StageTimer tm(g, 6, st);
+    ProposeArgs p{};
+    p.x = x;
+    p.d = b.d;
+    p.est_img = b.est_img;
+    p.n_est = b.n_est;
+    p.logsb_slot = g->dlogsb;
+    p.t = t;
+    p.Wb = g->pWb;
+    p.bias = g->pbias;
+    p.K = g->K;
+    p.m = o.top_m;
+    p.cand = g->cand;
+    HIPX(launch_propose(p, st));
+  }
+  {
+    StageTimer tm(g, 0, st);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((b.n + 255) / 256), dim3(256), 0, st, g->fbcnt,
+                       b.n);
+    HIPX(hipGetLastError());
+    RescoreArgs r{};
+    r.d = b.d;
+    r.tile_img = b.resc_img;
+    r.x = x;
+    r.cand = g->cand;
+    r.m = o.top_m;
+    r.K = g->K;
+    r.t = t;
+    r.Ub = g->tb.Ub;
+    r.L = g->tb.L32;
+    r.rk = g->tb.rk;
+    r.Pinv = g->tb.Pinv;
+    r.margin = (float)o.margin_nats;
+    r.labels = labels;
+    r.best = best;
+    r.second = second;
+    r.fb_count = g->fbcnt;
+    r.fb_list = g->fb_list;
+    HIPX(launch_rescore_batch(r, b.n_resc, st));
+    HIPX(launch_fallback_items(g->fbcnt, b.n, g->fbitems, st));
+  }
+  {
+    StageTimer tm(g, 7, st);
+    BF16Args a{};
+    a.x = x;
+    a.Ub = g->tb.Ub;
+    a.L = g->tb.L32;
+    a.K = g->K;
+    a.labels = labels;
+    a.best = best;
+    a.second = second;
+    a.list_count = g->fbcnt;
+    a.list = g->fb_list;
+    a.d = b.d;
+    a.t = t;
+    a.rk = g->tb.rk;
+    a.Pinv = g->tb.Pinv;
+    a.item_pre = g->fbitems;
+    a.n_img = b.n;
+    // a fixed grid walking the items (at most every patch falls back)
+    int64_t items = 0;
+    for (const ImgDesc& d : g->hd) items += ((int64_t)(d.H - 7) * (d.W - 7) + 511) / 512;
+    a.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(items, 1024));
+    HIPX(launch_estep_bf16_mode(kModeListBatch, a, st));
+  }
+  if (flags) {
+    const int n = (int)b.n_patches;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, n);
+    HIPX(hipGetLastError());
+    for (int i = 0; i < b.n; ++i) {
+      const ImgDesc& d = g->hd[i];
+      const int Np = (d.H - 7) * (d.W - 7);
+      hipLaunchKernelGGL(mark_kernel, dim3((Np + 255) / 256), dim3(256), 0, st, g->fbcnt + i,
+                         g->fb_list + d.np, flags + d.np);
+      HIPX(hipGetLastError());
+    }
+  }
+  return FEPLL_OK;
+}
+
 fepll_status select_batch(fepll_gmm* g, int t, const fepll_options& o, const float* x,
                           int32_t* labels, float* best, float* second, int32_t* flags,
                           hipStream_t st) {
@@ -929,7 +984,9 @@ fepll_status select_batch(fepll_gmm* g, int t, const fepll_options& o, const flo
     }
     return FEPLL_OK;
   }
-  if (o.precision == FEPLL_FP8 || (o.precision == FEPLL_BF16 && !o.use_proposal)) {
+  if (o.precision == FEPLL_BF16 && o.use_proposal)
+    return select_proposal(g, t, o, x, labels, best, second, flags, st);
+  if (o.precision == FEPLL_FP8 || o.precision == FEPLL_BF16) {
     if (flags) {
       const int n = (int)b.n_patches;
       hipLaunchKernelGGL(zero_i32_kernel, dim3((n + 255) / 256), dim3(256), 0, st, flags, n);
@@ -1131,7 +1188,8 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
                         g->wbase, g->bvals,   g->labels, g->list,  g->count,  g->hist,
                         g->seg,   g->perm,    g->Zhat,  g->ybuf,   g->xa,     g->xb,
                         g->pWb,   g->pbias,   g->cand,  g->fb_list,
-                        g->psorted, g->pcost, g->phist, g->pseg,
+                        g->fbcnt, g->resc_img, g->dlogsb, g->dbeta,
+                        g->psorted, g->phist, g->pseg,
                         g->tb.rk,   g->tb.Pinv, g->zop,  g->znz,
                         g->jflags,  g->jlist,   g->jcount, g->jpart,
                         g->tree.tb.Ub, g->tree.tb.L32, g->tree.tb.Pinv, g->tree.rk,
@@ -1393,7 +1451,9 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->cand);
   dfree(g->fb_list);
   dfree(g->psorted);
-  dfree(g->pcost);
+  dfree(g->fbcnt);
+  dfree(g->resc_img);
+  dfree(g->dlogsb);
   dfree(g->zop);
   dfree(g->znz);
   dfree(g->jflags);
@@ -1911,8 +1971,17 @@ fepll_status fepll_propose(fepll_gmm* g, const fepll_image* x, double beta, int3
   const std::vector<float> bv(1, 1.f);
   if ((s = make_plan(g, 1, &H, &W, 1, bv, st)) != FEPLL_OK) return s;
   HIPX(copy_in(g->xa, x, st));
-  HIPX(launch_propose_bf16(g->xa, H, W, beta, g->pWb, g->pbias, g->K, top_m, cand, nullptr,
-                           nullptr, st));
+  ProposeArgs p{};
+  p.x = g->xa;
+  p.H = H;
+  p.W = W;
+  p.logsb = (float)(-0.5 * std::log(beta));
+  p.Wb = g->pWb;
+  p.bias = g->pbias;
+  p.K = g->K;
+  p.m = top_m;
+  p.cand = cand;
+  HIPX(launch_propose(p, st));
   return FEPLL_OK;
 }
 

@@ -72,6 +72,8 @@ struct ImgDesc {
   int64_t np;
   int64_t seg;
   int32_t sort0, est0, ola0, slot0;
+  int32_t resc0;  // first rescoring tile of the proposal
+  int32_t pad;
 };
 
 // Selection tile: 4 patch rows x kEstCols patch columns (one workgroup).
@@ -85,8 +87,9 @@ struct Batch {
   const int32_t* est_img;   // device: image of each selection tile
   const int32_t* sort_img;  // device: image of each sort block
   const int32_t* ola_img;   // device: image of each reprojection tile
+  const int32_t* resc_img;  // device: image of each rescoring tile (proposal)
   int n;
-  int n_est, n_sort, n_ola;  // tile totals
+  int n_est, n_sort, n_ola, n_resc;  // tile totals
   int64_t n_patches;         // patches of the whole batch
   int64_t max_np;            // patches of the largest image
   int ola_rows;              // rows of a reprojection tile

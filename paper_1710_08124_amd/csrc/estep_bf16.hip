@@ -215,6 +215,7 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
   const int col = lane & 15;
 
   const int nlist = (MODE == kModeListFull) ? *a.list_count : 0;
+  const int nitems = (MODE == kModeListBatch) ? a.item_pre[a.n_img] : 0;
   // work items: list mode, 512 consecutive list entries; spatial all-K
   // mode, one selection tile (4 patch rows x 128 columns) of any image of
   // the batch.  The loop is workgroup-uniform: every wave reaches every
@@ -232,6 +233,35 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
     float* bestp = a.best;
     float* secondp = a.second;
     int tr = blockIdx.y, tc = blockIdx.x;  // tile row / column (spatial modes)
+    // list modes: the list, its length and this item's first entry
+    const int32_t* list = a.list;
+    int nl = nlist, lbase = item * 512;
+    if (MODE == kModeListBatch) {
+      if (item >= nitems) break;
+      // the image of this item: the last one whose first item is <= item
+      int lo = 0, hi = a.n_img - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.item_pre[mid] <= item)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      const ImgDesc d = a.d[lo];
+      H = d.H;
+      W = d.W;
+      x += d.px;
+      const size_t slot = (size_t)(d.slot0 + a.t);
+      Ub += slot * a.K * kTileStride;
+      Lt += slot * a.K;
+      if (FLAT) Pt += slot * a.K;
+      labels += d.np;
+      if (bestp) bestp += d.np;
+      if (secondp) secondp += d.np;
+      list += d.np;
+      nl = a.list_count[lo];
+      lbase = (item - a.item_pre[lo]) * 512;
+    }
     if (MODE == kModeSpatialFull) {
       if (item >= a.n_est) break;
       const int im = a.est_img[item];
@@ -255,14 +285,13 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
     // ---- this wave's 128 patches
     int idx[PB];
     bool valid[PB];
-    if (MODE == kModeListFull) {
-      if (item * 512 >= nlist) break;
-      const int base = item * 512;
+    if (MODE != kModeSpatialFull) {
+      if (MODE == kModeListFull && lbase >= nl) break;
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) {
-        const int e = base + wave * 128 + 16 * pb + col;
-        valid[pb] = e < nlist;
-        idx[pb] = a.list[valid[pb] ? e : base];
+        const int e = lbase + wave * 128 + 16 * pb + col;
+        valid[pb] = e < nl;
+        idx[pb] = list[valid[pb] ? e : lbase];
       }
     } else {
       const int r = tr * 4 + wave;
@@ -370,64 +399,274 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
   }
 }
 
-// Exact rescoring of the proposal: one wave scores the up to 128 pairs of
-// one tile of the pair list (all of one component k) with the same
-// arithmetic as the all-K selection (score(): the cost of a (patch, k) pair
-// is bit for bit the one the full search computes), reading each pair's
-// patch operand from the network's records (one 128-byte line per patch),
-// and writes the costs at the pairs' ids.
+// ---- Exact rescoring of the proposal's candidates.  A workgroup takes
+// kRescPatches consecutive patches of one image of the batch: it builds their
+// bfloat16 operands in LDS (load_patch: bit for bit the all-K operands),
+// groups their (patch, candidate) pairs by component with a counting sort in
+// LDS, and each wave scores the pairs of every eighth component, 16 pairs
+// per MFMA block and up to 4 blocks per pass, with the all-K arithmetic
+// (same products, same squares in the same order, same lane-group sums
+// (q0 + q2) + (q1 + q3)), so every (patch, k) cost equals the full search's.
+// Per patch, the best (lowest cost, then lowest k) and the second cost are
+// kept by two LDS atomic minima on order-preserving keys: an update leaves
+// the larger of the old best and the new cost to the second minimum, and
+// every cost but the final best is that larger value exactly once, so the
+// result does not depend on the order of the updates.  Last, labels, costs
+// and the fallback list: half the exact gap of the two best below the
+// margin, or fewer than two candidates.
+
+// Order-preserving map of a float cost to uint32 (-0 taken as +0).
+__device__ __forceinline__ uint32_t cost_key(float c) {
+  const uint32_t u = __float_as_uint(c + 0.f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float key_cost(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+// LDS slot of uint4 j (0..7) of the record of local patch pl: rotated by the
+// patch, so the 16 lanes of a gather spread over the banks
+__device__ __forceinline__ int rec_slot(int pl, int j) { return pl * 8 + (j ^ (pl & 7)); }
+
 template <bool FLAT>
-__global__ __launch_bounds__(256, 3) void pairs_bf16_kernel(
-    const uint4* __restrict__ zop, const float* __restrict__ znz,
-    const uint16_t* __restrict__ Ub, const float* __restrict__ L, const int32_t* __restrict__ rkt,
-    const float* __restrict__ Pinv, int K, const int32_t* __restrict__ seg,
-    const int32_t* __restrict__ sorted, float* __restrict__ pair_cost) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int g = lane >> 4;
-  const int col = lane & 15;
-  const int32_t* start = seg;
-  const int32_t* count = seg + (K + 1);
-  const int32_t* tinfo = seg + (3 * K + 3);
-  const int total = seg[3 * K + 2];
-  const uint4* up = reinterpret_cast<const uint4*>(Ub) + lane;
-  for (int t = blockIdx.x * 4 + wave; t < total; t += gridDim.x * 4) {
-    const int info = tinfo[t];
-    const int k = info & 1023;
-    const int first = (info >> 10) * kPairTile;
-    const int n = min(kPairTile, count[k] - first);
-    const int32_t* ids = sorted + start[k] + first;
-    int idx[PB];
-    bool valid[PB];
+__global__ __launch_bounds__(512, 1) void rescore_bf16_kernel(RescoreArgs a) {
+  __shared__ uint4 rec[kRescPatches * 8];
+  __shared__ float nzs[FLAT ? kRescPatches : 1];
+  __shared__ uint16_t plist[kRescPatches * 8];
+  __shared__ unsigned long long bkey[kRescPatches];
+  __shared__ uint32_t skey[kRescPatches];
+  __shared__ int32_t hcnt[kMaxK];
+  __shared__ int32_t hend[kMaxK];
+  __shared__ int32_t wsum[8];
+  __shared__ int32_t fbase;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, col = lane & 15;
+  const int K = a.K;
+  const int im = a.tile_img[blockIdx.x];
+  const ImgDesc d = a.d[im];
+  const int W = d.W, Wp = d.W - 7;
+  const int Np = (d.H - 7) * Wp;
+  const int base = (blockIdx.x - d.resc0) * kRescPatches;
+  const int npw = min(kRescPatches, Np - base);
+  const float* x = a.x + d.px;
+  const size_t slot = (size_t)(d.slot0 + a.t);
+
+  // the candidates of the thread's two patches (in flight during the
+  // operand build)
+  const uint4* cand4 = reinterpret_cast<const uint4*>(a.cand) + d.np + base;
+  uint4 cw[2];
 #pragma unroll
-    for (int pb = 0; pb < PB; ++pb) {
-      const int e = 16 * pb + col;
-      valid[pb] = e < n;
-      idx[pb] = ids[valid[pb] ? e : 0];
-    }
-    const int own = 4 * (g >> 1) + 2 * (g & 1);
-    uint4 zb[PB][2];
-    float nzA = 0.f, nzB = 0.f;
-#pragma unroll
-    for (int pb = 0; pb < PB; ++pb) {
-      float nz = 0.f;
-      load_operand<FLAT>(zop, znz, idx[pb] >> 3, g, zb[pb], nz);
-      if (FLAT) {
-        nzA = (pb == own) ? nz : nzA;
-        nzB = (pb == own + 1) ? nz : nzB;
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    float cA, cB;
-    score<FLAT>(up + (size_t)k * 512, zb, L[k], FLAT ? rkt[k] : kP, FLAT ? Pinv[k] : 0.f, nzA,
-                nzB, cA, cB);
-#pragma unroll
-    for (int pb = 0; pb < PB; pb += 2)
-      if (pb == own) {
-        if (valid[pb]) pair_cost[idx[pb]] = cA;
-        if (valid[pb + 1]) pair_cost[idx[pb + 1]] = cB;
-      }
+  for (int h = 0; h < 2; ++h) {
+    const int pl = tid + 512 * h;
+    cw[h] = (pl < npw) ? cand4[pl] : make_uint4(~0u, ~0u, ~0u, ~0u);
   }
+  for (int k = tid; k < K; k += 512) hcnt[k] = 0;
+  for (int p = tid; p < kRescPatches; p += 512) {
+    bkey[p] = ~0ull;
+    skey[p] = ~0u;
+  }
+  // ---- operands: 16 patches per wave pass (lane group g: rows g, 4 + g);
+  // past the image's last patch, copies of it that no pair names.  (7
+  // passes per wave, unrolled: every pass's pixel loads in flight at once.)
+  static_assert(kRescPatches == 16 * 8 * 7, "seven operand passes per wave");
+#pragma unroll
+  for (int b = wave; b < kRescPatches / 16; b += 8) {
+    const int pl = 16 * b + col;
+    const int p = base + min(pl, npw - 1);
+    const int r = p / Wp;
+    uint4 zb[2];
+    float nz = 0.f;
+    load_patch<FLAT>(x, W, r, p - r * Wp, g, zb, nz);
+    rec[rec_slot(pl, g)] = zb[0];
+    rec[rec_slot(pl, 4 + g)] = zb[1];
+    if (FLAT && g == 0) nzs[pl] = nz;
+  }
+  __syncthreads();
+  // ---- the pairs by component: counts, exclusive scan, scatter
+  auto cand_k = [&](int h, int j) __attribute__((always_inline)) {
+    const uint32_t w = (j >> 1) == 0 ? cw[h].x : (j >> 1) == 1 ? cw[h].y
+                     : (j >> 1) == 2 ? cw[h].z : cw[h].w;
+    const int k = (int)((w >> (16 * (j & 1))) & 0xffffu);
+    return (j < a.m && k < K) ? k : -1;  // (an index >= K is never scored)
+  };
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = cand_k(h, j);
+      if (k >= 0) atomicAdd(&hcnt[k], 1);
+    }
+  __syncthreads();
+  {
+    // two components per thread (K <= 1024)
+    const int k0 = 2 * tid;
+    const int c0 = (k0 < K) ? hcnt[k0] : 0, c1 = (k0 + 1 < K) ? hcnt[k0 + 1] : 0;
+    int s = c0 + c1;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(s, off);
+      if (lane >= off) s += u;
+    }
+    if (lane == 63) wsum[wave] = s;
+    __syncthreads();
+    int pre = 0;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    const int excl = pre + s - (c0 + c1);
+    if (k0 < K) hend[k0] = excl;
+    if (k0 + 1 < K) hend[k0 + 1] = excl + c0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = cand_k(h, j);
+      if (k >= 0) plist[atomicAdd(&hend[k], 1)] = (uint16_t)(tid + 512 * h);
+    }
+  __syncthreads();
+  // ---- scores: component k's pairs are plist[hend[k] - hcnt[k] .. hend[k])
+  const uint4* up = reinterpret_cast<const uint4*>(a.Ub + slot * K * kTileStride) + lane;
+  const float* Lt = a.L + slot * K;
+  // the component's operand and terms, the next component's already in
+  // flight (issued before anything of the current one is waited for)
+  uint4 A[8];
+  float Lk = 0.f, Pk = 0.f;
+  int rk = kP;
+  auto fetch = [&](int k, uint4* Ad, float& Ld, int& rd, float& Pd) __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) Ad[i] = up[(size_t)k * 512 + i * 64];
+    Ld = Lt[k];
+    if (FLAT) {
+      rd = a.rk[k];
+      Pd = a.Pinv[slot * K + k];
+    }
+  };
+  if (wave < K) fetch(wave, A, Lk, rk, Pk);
+  for (int k = wave; k < K; k += 8) {
+    uint4 An[8];
+    float Ln = 0.f, Pn = 0.f;
+    int rn = kP;
+    if (k + 8 < K) fetch(k + 8, An, Ln, rn, Pn);  // (wave-uniform)
+    const int n = hcnt[k];
+    const int s0 = hend[k] - n;
+    const int nb = FLAT ? (rk + 15) >> 4 : 4;  // eigen blocks scored
+    for (int c0 = 0; c0 < n; c0 += 64) {
+      const int nblk = min(4, (n - c0 + 15) >> 4);
+      int pl[4];
+      uint4 zb[4][2];
+#pragma unroll
+      for (int pb = 0; pb < 4; ++pb) {
+        pl[pb] = plist[s0 + min(c0 + 16 * pb + col, n - 1)];
+        if (pb < nblk) {
+          zb[pb][0] = rec[rec_slot(pl[pb], g)];
+          zb[pb][1] = rec[rec_slot(pl[pb], 4 + g)];
+        } else {
+          zb[pb][0] = zb[pb][1] = make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+      float q[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb) {
+        if (rb >= nb) continue;  // (wave-uniform)
+#pragma unroll
+        for (int pb = 0; pb < 4; ++pb) {
+          if (pb >= nblk) continue;  // (wave-uniform)
+          f32x4 acc = mfma16(A[2 * rb], zb[pb][0], (f32x4){0.f, 0.f, 0.f, 0.f});
+          acc = mfma16(A[2 * rb + 1], zb[pb][1], acc);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) q[pb] = fmaf(acc[i], acc[i], q[pb]);
+        }
+      }
+      // lane group g ends with block g's column sums: (q0 + q2) + (q1 + q3)
+      const float mm = pair_sum16(pair_sum32(q[0], q[2]), pair_sum32(q[1], q[3]));
+      if (c0 + 16 * g + col < n) {
+        const int p = (g == 0) ? pl[0] : (g == 1) ? pl[1] : (g == 2) ? pl[2] : pl[3];
+        float cst;
+        if (FLAT) {
+          const float sg = (rk < kP) ? -1.f : 1.f;
+          cst = fmaf(sg, mm, fmaf(Pk, nzs[p], Lk));
+        } else {
+          cst = Lk + mm;
+        }
+        const unsigned long long kk = ((unsigned long long)cost_key(cst) << 32) | (uint32_t)k;
+        const unsigned long long old = atomicMin(&bkey[p], kk);
+        atomicMin(&skey[p], (uint32_t)(max(old, kk) >> 32));
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) A[i] = An[i];
+    Lk = Ln;
+    rk = rn;
+    Pk = Pn;
+  }
+  __syncthreads();
+  // ---- per patch: label, costs, fallback decision
+  bool fb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int pl = tid + 512 * h;
+    fb[h] = false;
+    if (pl < npw) {
+      const unsigned long long bk = bkey[pl];
+      const uint32_t sk = skey[pl];
+      const float b = (bk == ~0ull) ? INFINITY : key_cost((uint32_t)(bk >> 32));
+      const float s = (sk == ~0u) ? INFINITY : key_cost(sk);
+      const size_t i = (size_t)d.np + base + pl;
+      a.labels[i] = (bk == ~0ull) ? 0x7fffffff : (int)(uint32_t)bk;
+      if (a.best) a.best[i] = b;
+      if (a.second) a.second[i] = s;
+      const float gap = (s < INFINITY) ? 0.5f * (s - b) : -INFINITY;
+      fb[h] = !(gap >= a.margin);
+    }
+  }
+  // the image's fallback list: one global atomic per workgroup
+  const uint64_t m0 = __ballot(fb[0]), m1 = __ballot(fb[1]);
+  if (lane == 0) wsum[wave] = __popcll(m0) + __popcll(m1);
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int w = 0; w < 8; ++w) {
+      const int v = wsum[w];
+      wsum[w] = run;
+      run += v;
+    }
+    fbase = run ? atomicAdd(&a.fb_count[im], run) : 0;
+  }
+  __syncthreads();
+  const uint64_t below = (1ull << lane) - 1ull;
+  int32_t* fl = a.fb_list + d.np + fbase + wsum[wave];
+  if (fb[0]) fl[__popcll(m0 & below)] = base + tid;
+  if (fb[1]) fl[__popcll(m0) + __popcll(m1 & below)] = base + tid + 512;
+}
+
+// Items of the batched fallback search: pre[i] = sum over images j < i of
+// ceil(count[j] / 512), pre[n] the total (one workgroup).
+__global__ __launch_bounds__(1024) void fallback_items_kernel(const int32_t* __restrict__ count,
+                                                              int n, int32_t* __restrict__ pre) {
+  __shared__ int32_t part[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int carry = 0;
+  for (int i0 = 0; i0 < n; i0 += 1024) {
+    const int i = i0 + threadIdx.x;
+    const int v = (i < n) ? (count[i] + 511) / 512 : 0;
+    int s = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int u = __shfl_up(s, off);
+      if (lane >= off) s += u;
+    }
+    if (lane == 63) part[wave] = s;
+    __syncthreads();
+    int pw = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) {
+      pw += (w < wave) ? part[w] : 0;
+      tot += part[w];
+    }
+    if (i < n) pre[i] = carry + pw + s - v;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pre[n] = carry;
 }
 
 // One sparse level of the tree descent: the patches grouped by their
@@ -512,61 +751,6 @@ __global__ __launch_bounds__(256) void tree_group_kernel(const int32_t* __restri
                                                          uint4* __restrict__ cand) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < Np) cand[i] = make_uint4((uint32_t)cur[i] | 0xffff0000u, ~0u, ~0u, ~0u);
-}
-
-// Per patch: the best and second best of its m rescored candidates (ties to
-// the lower component), its label, and the fallback decision: the patch
-// goes to the full-K list when half the exact gap (in nats) is below the
-// margin, or when it has a single candidate.
-__global__ __launch_bounds__(1024) void pair_reduce_kernel(
-    const uint16_t* __restrict__ cand, const float* __restrict__ pair_cost, int Np, int m, int K,
-    float margin, int32_t* __restrict__ labels, float* __restrict__ best,
-    float* __restrict__ second, int32_t* __restrict__ fb_count, int32_t* __restrict__ fb_list) {
-  __shared__ int wcnt[16];
-  __shared__ int wbase[16];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  bool fb = false;
-  if (i < Np) {
-    // the patch's 8 candidate slots and costs in three 16-byte loads
-    const uint4 cw = reinterpret_cast<const uint4*>(cand)[i];
-    const float4 c0 = reinterpret_cast<const float4*>(pair_cost)[2 * (size_t)i];
-    const float4 c1 = reinterpret_cast<const float4*>(pair_cost)[2 * (size_t)i + 1];
-    const uint32_t kw[4] = {cw.x, cw.y, cw.z, cw.w};
-    const float cv[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-    float b = INFINITY, s = INFINITY;
-    int bk = 0x7fffffff;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = (int)((kw[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-      const bool use = (j < m) && (k < K);  // an index >= K is never scored
-      const float c = use ? cv[j] : INFINITY;
-      const bool better = use && (c < b || (c == b && k < bk));
-      s = better ? b : fminf(s, c);
-      bk = better ? k : bk;
-      b = better ? c : b;
-    }
-    labels[i] = bk;
-    if (best) best[i] = b;
-    if (second) second[i] = s;
-    const float gap = (s < INFINITY) ? 0.5f * (s - b) : -INFINITY;
-    fb = !(gap >= margin);
-  }
-  // the fallback list: one global atomic per workgroup (ballots, LDS prefix)
-  const uint64_t mask = __ballot(fb);
-  if (lane == 0) wcnt[wave] = __popcll(mask);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-      wbase[w] = run;
-      run += wcnt[w];
-    }
-    const int base = run ? atomicAdd(fb_count, run) : 0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) wbase[w] += base;
-  }
-  __syncthreads();
-  if (fb) fb_list[wbase[wave] + __popcll(mask & ((1ull << lane) - 1ull))] = i;
 }
 
 // The bfloat16 selection operand of every patch of one image as a record
@@ -753,6 +937,18 @@ hipError_t launch_tree_level_bf16(const int32_t* cur, int Np, const uint16_t* zo
 
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st) {
+  if (mode == kModeListBatch) {
+    // a fixed grid over the items of all images (their total is on the device)
+    int blocks = args.blocks;
+    if (blocks < 1) return hipSuccess;
+    if (args.rk)
+      hipLaunchKernelGGL((estep_bf16_kernel<kModeListBatch, true>), dim3(blocks), dim3(256), 0, st,
+                         args);
+    else
+      hipLaunchKernelGGL((estep_bf16_kernel<kModeListBatch, false>), dim3(blocks), dim3(256), 0,
+                         st, args);
+    return hipGetLastError();
+  }
   if (mode == kModeListFull) {
     const int Np = (args.H - 7) * (args.W - 7);
     int blocks = (Np + 511) / 512;
@@ -778,30 +974,17 @@ hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_pair_scores_bf16(const uint16_t* zop, const float* znz, int Np_,
-                                   const uint16_t* Ub_t, const float* L32_t, const int32_t* rk,
-                                   const float* Pinv_t, int K, int m, const int32_t* seg,
-                                   const int32_t* sorted, float* pair_cost, hipStream_t st) {
-  // the tile total depends on the labels: a fixed grid walks the device list
-  const int64_t Np = Np_;
-  const uint4* z4 = reinterpret_cast<const uint4*>(zop);
-  int64_t blocks = (Np * m / kPairTile + K + 3) / 4;
-  if (blocks > 1024) blocks = 1024;
-  if (blocks < 1) blocks = 1;
-  if (rk)
-    hipLaunchKernelGGL(pairs_bf16_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, z4, znz,
-                       Ub_t, L32_t, rk, Pinv_t, K, seg, sorted, pair_cost);
+hipError_t launch_rescore_batch(const RescoreArgs& a, int n_tiles, hipStream_t st) {
+  if (n_tiles < 1) return hipSuccess;
+  if (a.rk)
+    hipLaunchKernelGGL(rescore_bf16_kernel<true>, dim3((unsigned)n_tiles), dim3(512), 0, st, a);
   else
-    hipLaunchKernelGGL(pairs_bf16_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, z4,
-                       znz, Ub_t, L32_t, rk, Pinv_t, K, seg, sorted, pair_cost);
+    hipLaunchKernelGGL(rescore_bf16_kernel<false>, dim3((unsigned)n_tiles), dim3(512), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_pair_reduce(const uint16_t* cand, const float* pair_cost, int Np, int m, int K,
-                              float margin, int32_t* labels, float* best, float* second,
-                              int32_t* fb_count, int32_t* fb_list, hipStream_t st) {
-  hipLaunchKernelGGL(pair_reduce_kernel, dim3((Np + 1023) / 1024), dim3(1024), 0, st, cand,
-                     pair_cost, Np, m, K, margin, labels, best, second, fb_count, fb_list);
+hipError_t launch_fallback_items(const int32_t* count, int n, int32_t* pre, hipStream_t st) {
+  hipLaunchKernelGGL(fallback_items_kernel, dim3(1), dim3(1024), 0, st, count, n, pre);
   return hipGetLastError();
 }
 

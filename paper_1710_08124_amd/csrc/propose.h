@@ -9,7 +9,7 @@
 
 namespace fepll {
 
-enum { kModeSpatialFull = 0, kModeListFull = 2 };
+enum { kModeSpatialFull = 0, kModeListFull = 2, kModeListBatch = 3 };
 
 struct BF16Args {
   // spatial all-K mode: x, Ub, L, labels, best, second are the packed
@@ -40,22 +40,47 @@ struct BF16Args {
   // patches from the image)
   const uint4* zop;
   const float* znz;
+  // batched list mode (every image's list at list + d.np, its length
+  // list_count[i]; the tables of all slots): items of 512 list entries,
+  // image i's first item_pre[i], their total item_pre[n_img]; blocks is the
+  // grid of the launch
+  const int32_t* item_pre;
+  int n_img;
 };
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st);
 
-// Exact rescoring of the proposal (one image, tables of one beta): the cost
-// of every (patch, candidate) pair of the component-sorted pair list
-// (launch_pair_bucket) at pair_cost[8 i + j], then per patch the best /
-// second of its m candidates, its label and the fallback list (patches
-// whose half exact gap is below margin; count at *fb_count, zeroed before).
-hipError_t launch_pair_scores_bf16(const uint16_t* zop, const float* znz, int Np,
-                                   const uint16_t* Ub_t, const float* L32_t, const int32_t* rk,
-                                   const float* Pinv_t, int K, int m, const int32_t* seg,
-                                   const int32_t* sorted, float* pair_cost, hipStream_t st);
-hipError_t launch_pair_reduce(const uint16_t* cand, const float* pair_cost, int Np, int m, int K,
-                              float margin, int32_t* labels, float* best, float* second,
-                              int32_t* fb_count, int32_t* fb_list, hipStream_t st);
+// Exact rescoring of the proposal's candidates over a batch at iteration t
+// (tables of all slots; one workgroup per tile of kRescPatches consecutive
+// patches of one image, tile_img giving the image of each tile and
+// ImgDesc::resc0 its first): every pair (patch i, candidate j < m) gets the
+// bfloat16 selection cost of the all-K modes, bit for bit; per patch the best
+// (ties to the lower component) and second cost, its label (0x7fffffff
+// without candidates) and the fallback decision -- half the exact gap below
+// margin, or fewer than two candidates -- appending the patch (local index)
+// to its image's list at fb_list + d.np, fb_count[i] entries (zeroed before).
+constexpr int kRescPatches = 896;
+struct RescoreArgs {
+  const ImgDesc* d;
+  const int32_t* tile_img;
+  const float* x;         // packed images
+  const uint16_t* cand;   // packed, 8 per patch
+  int m, K, t;
+  const uint16_t* Ub;     // all slots
+  const float* L;
+  const int32_t* rk;      // flat tail, or NULL
+  const float* Pinv;
+  float margin;
+  int32_t* labels;        // packed
+  float* best;            // packed or NULL
+  float* second;          // packed or NULL
+  int32_t* fb_count;      // per image
+  int32_t* fb_list;       // packed
+};
+hipError_t launch_rescore_batch(const RescoreArgs& a, int n_tiles, hipStream_t st);
+// pre[i] = sum over images j < i of ceil(count[j] / 512), pre[n] the total:
+// the items of the batched fallback search (kModeListBatch).
+hipError_t launch_fallback_items(const int32_t* count, int n, int32_t* pre, hipStream_t st);
 
 // Search-tree descent (Sec. 3.2): every patch's bfloat16 operand record and
 // squared norm (as the network writes them).
@@ -100,15 +125,28 @@ struct TreeDenseArgs {
 };
 hipError_t launch_tree_dense_bf16(const TreeDenseArgs& a, hipStream_t st);
 
-// Network inference + top-m: cand[i] gets the m best classes of patch i in
-// decreasing logit order (ties to the lower class), 0xffff after the m-th.
-// Wb / bias: see propose.hip.  zop (Np x 64 bfloat16) / znz (Np floats):
-// NULL, or they receive every patch's bfloat16 selection operand (row dy at
-// entries 8 dy .. 8 dy + 7) and the float32 squared norm of its DC-removed
-// pixels, bit for bit as the bfloat16 selection computes them.
-hipError_t launch_propose_bf16(const float* x, int H, int W, double beta, const uint16_t* Wb,
-                               const float* bias, int K, int m, uint16_t* cand, uint16_t* zop,
-                               float* znz, hipStream_t st);
+// Network inference + top-m over selection tiles (4 patch rows x kEstCols
+// columns, two workgroups each): one image (d NULL: x, H, W, logsb, cand
+// indexed by the image's patch) or a planned batch at iteration t (d,
+// est_img, n_est; log sigma_beta of each image from logsb_slot[d.slot0 + t];
+// cand packed like the labels).  cand gets, for every patch, its m best
+// classes in decreasing logit order (ties to the lower class), 0xffff after
+// the m-th.  Wb / bias: see propose.hip.
+struct ProposeArgs {
+  const float* x;
+  int H, W;
+  float logsb;
+  const ImgDesc* d;
+  const int32_t* est_img;
+  int n_est;
+  const float* logsb_slot;
+  int t;
+  const uint16_t* Wb;
+  const float* bias;
+  int K, m;
+  uint16_t* cand;
+};
+hipError_t launch_propose(const ProposeArgs& a, hipStream_t st);
 
 // Host-side packing of float32 parameters into the inference layouts.
 // Returns the number of uint16 entries of Wb and fills wb / bias.

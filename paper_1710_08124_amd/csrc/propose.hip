@@ -11,16 +11,17 @@
 // patch row per depth step, as in the selection kernels) plus the
 // log sigma_beta feature.
 //
-// A workgroup of 8 waves owns 256 patches (8 patch rows x 32 columns) and
-// streams the 23 weight slabs (one slab = one 32-row block of a layer, all
+// A workgroup of 8 waves owns 256 patches (half of a selection tile: 4
+// patch rows x 64 columns, a wave per 32 columns of a row), of one image or
+// of any image of a planned batch, and streams the 23 weight slabs (one slab = one 32-row block of a layer, all
 // depth steps, already in MFMA operand order) through double-buffered LDS,
 // so each weight byte read from L2 serves 256 patches; each slab is fetched
 // from L2 two slabs ahead, and one barrier per slab (after its LDS store)
 // orders the buffers.
 //
 // Top-m: each lane keeps the 8 largest ranking keys (logit, then lower
-// class) of its 112 classes in sorted registers, then merges with lane
-// l ^ 32.
+// class) of its 112 classes in sorted registers (an insertion is one max and
+// seven independent medians of three), then merges with lane l ^ 32.
 #include "common.h"
 #include "mlp.h"
 #include "propose.h"
@@ -51,11 +52,12 @@ __device__ __forceinline__ f32x16 mfma_bf16(uint4 a, uint4 b, f32x16 c) {
 }
 // GELU in the tanh form of Hendrycks & Gimpel (2016),
 // x * sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3)), the form the network is
-// trained with: branch-free, one exp2 and one reciprocal.
+// trained with: branch-free, one exp2 and one reciprocal, the factor
+// -log2(e) of the exponential folded into the two constants.
 __device__ __forceinline__ float gelu(float a) {
-  const float t = a * fmaf(0.0713548162726f, a * a, 1.59576912161f);  // 2 sqrt(2/pi) (a + 0.044715 a^3)
-  const float e = __builtin_amdgcn_exp2f(-t * 1.44269504089f);
-  return a * __builtin_amdgcn_rcpf(1.f + e);
+  // -log2(e) 2 sqrt(2/pi) (a + 0.044715 a^3)
+  const float t = a * fmaf(-0.10294324f, a * a, -2.3022082f);
+  return a * __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(t));
 }
 
 // Ranking key of a logit: an order-preserving map of the float to uint32,
@@ -65,10 +67,16 @@ __device__ __forceinline__ float gelu(float a) {
 // the lower class.  Every compare-exchange is then one max and one min.
 __device__ __forceinline__ uint32_t rank_key(float v, int cls) {
   const uint32_t u = __float_as_uint(v);
-  const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  // negative: all bits flipped; otherwise the sign bit set
+  const uint32_t o = u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
   return (o & ~1023u) | (uint32_t)(1023 - cls);
 }
 __device__ __forceinline__ int key_class(uint32_t k) { return 1023 - (int)(k & 1023u); }
+
+// median of three (one v_med3_u32)
+__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
+  return max(min(a, b), min(max(a, b), c));
+}
 
 struct Top8 {
   uint32_t t[8];  // descending
@@ -76,13 +84,13 @@ struct Top8 {
 #pragma unroll
     for (int i = 0; i < 8; ++i) t[i] = 0u;
   }
+  // x lands at the first position whose key it exceeds: position i > 0 then
+  // holds the median of (old t[i - 1], old t[i], x), position 0 the maximum
   __device__ void insert(uint32_t x) {
+    const uint32_t t0 = max(t[0], x);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const uint32_t hi = max(t[i], x);
-      x = min(t[i], x);
-      t[i] = hi;
-    }
+    for (int i = 7; i >= 1; --i) t[i] = med3u(t[i - 1], t[i], x);
+    t[0] = t0;
   }
 };
 
@@ -91,16 +99,30 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kSlabU4 = 16 * 64;  // uint4 of the largest slab (16 depth steps x 64 lanes)
 static_assert(kSlabU4 == 2 * kThreads, "two uint4 of a slab per thread");
 
-// activation epilogue of one 32-row block: bias + GELU, then re-pack as
-// the two depth steps (2 nt, 2 nt + 1) of the next layer's B operand
-__device__ __forceinline__ void hidden_epilogue(const f32x16& acc, const float* __restrict__ bias,
-                                                int nt, int half, uint4& s0, uint4& s1) {
+// the accumulator of one 32-row block (units 32 nt + 8 (i >> 2) + 4 half +
+// (i & 3) of the lane's column) started at the bias of its units: the
+// matrix cores add the products to it
+__device__ __forceinline__ f32x16 bias_init(const float* __restrict__ bias, int nt, int half) {
+  f32x16 c;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float4 b = *reinterpret_cast<const float4*>(bias + 32 * nt + 8 * g + 4 * half);
+    c[4 * g] = b.x;
+    c[4 * g + 1] = b.y;
+    c[4 * g + 2] = b.z;
+    c[4 * g + 3] = b.w;
+  }
+  return c;
+}
+
+// activation epilogue of one 32-row block (bias included): GELU, then
+// re-pack as the two depth steps (2 nt, 2 nt + 1) of the next layer's B
+// operand
+__device__ __forceinline__ void hidden_epilogue(const f32x16& acc, int half, uint4& s0,
+                                                uint4& s1) {
   float h[16];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int unit = 32 * nt + 8 * (i >> 2) + 4 * half + (i & 3);
-    h[i] = gelu(acc[i] + bias[unit]);
-  }
+  for (int i = 0; i < 16; ++i) h[i] = gelu(acc[i]);
   float lo[8], hi[8];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -171,36 +193,53 @@ __device__ __forceinline__ void stage_slab(uint4* buf, SlabRegs& p, const uint4*
 // Wb: all slabs back to back, uint4 in MFMA A-operand order:
 //   layer 1: 8 slabs x 5 depth steps, layer 2: 8 x 16, layer 3: n3 x 16.
 // bias: b1 (256) b2 (256) b3 (32 n3, -inf beyond K).
-// zop / znz: NULL, or Np x 8 uint4 and Np floats receiving the selection
-// operand of every patch and its squared norm (see the input stage).
-__global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
-    const float* __restrict__ x, int H, int W, float logsb, const uint4* __restrict__ Wb,
-    const float* __restrict__ bias, int n3, int K, int m, uint16_t* __restrict__ cand,
-    uint4* __restrict__ zop, float* __restrict__ znz) {
+__global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(ProposeArgs a) {
   __shared__ uint4 slab[2][kSlabU4];  // 32 KB
-  __shared__ float bsh[2 * kHidden + 32 * 32];  // b1, b2, b3 (n3 <= 32 blocks of 32)
+  __shared__ __align__(16) float bsh[2 * kHidden + 32 * 32];  // b1, b2, b3 (n3 <= 32 blocks of 32)
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int half = lane >> 5;
   const int col = lane & 31;
+  const int n3 = (a.K + 31) / 32;
+  const int K = a.K, m = a.m;
+  const uint4* __restrict__ Wb = reinterpret_cast<const uint4*>(a.Wb);
+  // this workgroup's half selection tile
+  const int item = blockIdx.x >> 1;
+  const float* x = a.x;
+  int H = a.H, W = a.W;
+  float logsb = a.logsb;
+  size_t np0 = 0;
+  int tr, tc;
+  if (a.d) {
+    const int im = a.est_img[item];
+    const ImgDesc d = a.d[im];
+    H = d.H;
+    W = d.W;
+    x += d.px;
+    np0 = (size_t)d.np;
+    logsb = a.logsb_slot[d.slot0 + a.t];
+    const int ntx = (W - 7 + kEstCols - 1) / kEstCols;
+    const int lt = item - d.est0;
+    tr = lt / ntx;
+    tc = lt - tr * ntx;
+  } else {
+    const int ntx = (W - 7 + kEstCols - 1) / kEstCols;
+    tr = item / ntx;
+    tc = item - tr * ntx;
+  }
   const int Hp = H - 7, Wp = W - 7;
-  const int r = blockIdx.y * kWaves + wave;
-  const int c = blockIdx.x * 32 + col;
+  const int r = 4 * tr + (wave & 3);
+  const int c = kEstCols * tc + 64 * (blockIdx.x & 1) + 32 * (wave >> 2) + col;
   const int rr = min(r, Hp - 1), cc = min(c, Wp - 1);
 
-  for (int i = threadIdx.x; i < 2 * kHidden + 32 * n3; i += blockDim.x) bsh[i] = bias[i];
+  for (int i = threadIdx.x; i < 2 * kHidden + 32 * n3; i += blockDim.x) bsh[i] = a.bias[i];
   // (made visible by the first slab's barrier)
 
   // ---- layer-1 input: DC-removed patch / 128 and log sigma_beta.  The
   // mean is summed in float64 (exact in any order whenever the patch's pixel
   // magnitudes lie within 2^23 of each other) and each difference is
   // rounded once to float32, as in the selection kernels; lane half h holds
-  // rows 2 t + h.  With zop, the patch is also written as the bfloat16
-  // selection operand (row dy at uint4 dy of the patch's 128 bytes) with its
-  // float32 squared norm, summed in the order of the bfloat16 selection
-  // (rows g and 4 + g in order into q_g, then (q_0 + q_1) + (q_2 + q_3)):
-  // what the rescoring of the candidates reads, bit for bit the full
-  // search's operands.
+  // rows 2 t + h.
   uint4 xb[5];
   {
     float v[4][8];
@@ -217,41 +256,15 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
       for (int e = 0; e < 8; ++e) sd += (double)v[t][e];
     sd += __shfl_xor(sd, 32);
     const double mean = sd * (1.0 / 64.0);
-    float d[4][8];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) d[t][e] = (float)((double)v[t][e] - mean);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       float q[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) q[e] = d[t][e] * (1.f / kScaleIn);
+      for (int e = 0; e < 8; ++e) q[e] = (float)((double)v[t][e] - mean) * (1.f / kScaleIn);
       xb[t] = make_uint4(pack2(q[0], q[1]), pack2(q[2], q[3]), pack2(q[4], q[5]),
                          pack2(q[6], q[7]));
     }
     xb[4] = make_uint4(half ? 0u : bf16_rne(logsb), 0u, 0u, 0u);
-    if (zop) {  // (uniform: the shuffles see every lane)
-      const bool ok = r < Hp && c < Wp;
-      const size_t idx = (size_t)rr * Wp + cc;
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (ok)
-          zop[idx * 8 + 2 * t + half] =
-              make_uint4(pack2(d[t][0], d[t][1]), pack2(d[t][2], d[t][3]),
-                         pack2(d[t][4], d[t][5]), pack2(d[t][6], d[t][7]));
-      float qa = 0.f, qb = 0.f;  // rows h then 4 + h; rows 2 + h then 6 + h
-#pragma unroll
-      for (int e = 0; e < 8; ++e) qa = fmaf(d[0][e], d[0][e], qa);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) qa = fmaf(d[2][e], d[2][e], qa);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) qb = fmaf(d[1][e], d[1][e], qb);
-#pragma unroll
-      for (int e = 0; e < 8; ++e) qb = fmaf(d[3][e], d[3][e], qb);
-      const float oa = __shfl_xor(qa, 32), ob = __shfl_xor(qb, 32);
-      if (ok && !half) znz[idx] = (qa + oa) + (qb + ob);
-    }
   }
 
   // slabs q + 1 and q + 2 in flight in registers (preA holds the even
@@ -262,70 +275,84 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
   fetch_slab(Wb, 0, preA);
   fetch_slab(Wb, 1, preB);
   uint4 h1[16], h2[16];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
+  // Each slab's matrix products are issued before the epilogue of the slab
+  // before (the activations or the top-m of its block), so the matrix cores
+  // and the vector ALUs work at once within a wave; only the layers wait
+  // for each other.  (The buffer a slab is staged into last held the slab
+  // two before, whose operands every wave read before the barrier of the
+  // slab in between.)
+  auto mm1 = [&](int q) __attribute__((always_inline)) {
     if (q & 1)
       stage_slab(slab[1], preB, Wb, q, nslab);
     else
       stage_slab(slab[0], preA, Wb, q, nslab);
     const uint4* A = slab[q & 1] + lane;
-    f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    f32x16 acc = bias_init(bsh, q, half);
 #pragma unroll
     for (int s = 0; s < 5; ++s) acc = mfma_bf16(A[s * 64], xb[s], acc);
-    hidden_epilogue(acc, bsh, q, half, h1[2 * q], h1[2 * q + 1]);
-    // (no barrier here: slab q + 1 goes to the other buffer, and slab q + 2
-    // overwrites this one only after the next stage's barrier, which every
-    // wave reaches after its last read of this slab -- the waves of a SIMD
-    // may drift by up to one slab and overlap one's epilogue with the
-    // other's matrix products)
-  }
-#pragma unroll
-  for (int q = 8; q < 16; ++q) {
-    if (q & 1)
-      stage_slab(slab[1], preB, Wb, q, nslab);
-    else
-      stage_slab(slab[0], preA, Wb, q, nslab);
+    return acc;
+  };
+  // layers 2 and 3: two independent accumulation chains (even / odd depth
+  // steps), the first started at the bias
+  auto mm23 = [&](int q, const float* bias, int nt, const uint4* hin, SlabRegs& pre)
+      __attribute__((always_inline)) {
+    stage_slab(slab[q & 1], pre, Wb, q, nslab);
     const uint4* A = slab[q & 1] + lane;
-    // two independent accumulation chains (even / odd depth steps)
-    f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    f32x16 acc2 = acc;
+    f32x16 acc = bias_init(bias, nt, half);
+    f32x16 acc2 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < 16; s += 2) {
-      acc = mfma_bf16(A[s * 64], h1[s], acc);
-      acc2 = mfma_bf16(A[(s + 1) * 64], h1[s + 1], acc2);
+      acc = mfma_bf16(A[s * 64], hin[s], acc);
+      acc2 = mfma_bf16(A[(s + 1) * 64], hin[s + 1], acc2);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[i] += acc2[i];
-    hidden_epilogue(acc, bsh + kHidden, q - 8, half, h2[2 * (q - 8)], h2[2 * (q - 8) + 1]);
+    return acc;
+  };
+  {
+    f32x16 acc = mm1(0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      f32x16 nxt;
+      if (q + 1 < 8) nxt = mm1(q + 1);
+      hidden_epilogue(acc, half, h1[2 * q], h1[2 * q + 1]);
+      acc = nxt;
+    }
+  }
+  {
+    f32x16 acc = mm23(8, bsh + kHidden, 0, h1, preA);
+#pragma unroll
+    for (int q = 8; q < 16; ++q) {
+      f32x16 nxt;
+      if (q + 1 < 16) nxt = mm23(q + 1, bsh + kHidden, q + 1 - 8, h1, (q & 1) ? preA : preB);
+      hidden_epilogue(acc, half, h2[2 * (q - 8)], h2[2 * (q - 8) + 1]);
+      acc = nxt;
+    }
   }
   Top8 top;
   top.init();
   const float* b3 = bsh + 2 * kHidden;
-  auto layer3 = [&](int q, SlabRegs& pre) __attribute__((always_inline)) {
-    stage_slab(slab[q & 1], pre, Wb, q, nslab);
-    const uint4* A = slab[q & 1] + lane;
-    f32x16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    f32x16 acc2 = acc;
-#pragma unroll
-    for (int s = 0; s < 16; s += 2) {
-      acc = mfma_bf16(A[s * 64], h2[s], acc);
-      acc2 = mfma_bf16(A[(s + 1) * 64], h2[s + 1], acc2);
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] += acc2[i];
+  auto top_epilogue = [&](int q, const f32x16& acc) __attribute__((always_inline)) {
     const int nt = q - 16;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int cls = 32 * nt + 8 * (i >> 2) + 4 * half + (i & 3);
-      const float v = acc[i] + b3[cls];
-      const uint32_t key = rank_key(v, cls);
-      top.insert(cls < K ? key : 0u);  // (a select: classes past K rank last)
+      // (classes past K: logit -inf from their bias, below every finite key)
+      top.insert(rank_key(acc[i], cls));
     }
   };
   // layer-3 slabs in pairs: even ones in preA, odd ones in preB
-  for (int q = 16; q < nslab; q += 2) {
-    layer3(q, preA);
-    if (q + 1 < nslab) layer3(q + 1, preB);
+  {
+    f32x16 acc = mm23(16, b3, 0, h2, preA);
+    for (int q = 16; q < nslab; q += 2) {
+      f32x16 nxt;
+      if (q + 1 < nslab) nxt = mm23(q + 1, b3, q + 1 - 16, h2, preB);
+      top_epilogue(q, acc);
+      if (q + 1 < nslab) {
+        if (q + 2 < nslab) acc = mm23(q + 2, b3, q + 2 - 16, h2, preA);
+        top_epilogue(q + 1, nxt);
+      }
+    }
   }
   // merge the two halves' lists
   // take the partner's whole list before inserting, so no key comes back twice
@@ -335,7 +362,7 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
 #pragma unroll
   for (int i = 0; i < 8; ++i) top.insert(other[i]);
   if (!half && r < Hp && c < Wp) {
-    const size_t idx = (size_t)r * Wp + c;
+    const size_t idx = np0 + (size_t)r * Wp + c;
     uint32_t w[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -343,19 +370,15 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(
       const uint32_t b = (2 * i + 1 < m) ? (uint32_t)key_class(top.t[2 * i + 1]) : 0xffffu;
       w[i] = a | (b << 16);
     }
-    reinterpret_cast<uint4*>(cand)[idx] = make_uint4(w[0], w[1], w[2], w[3]);
+    reinterpret_cast<uint4*>(a.cand)[idx] = make_uint4(w[0], w[1], w[2], w[3]);
   }
 }
 
-hipError_t launch_propose_bf16(const float* x, int H, int W, double beta, const uint16_t* Wb,
-                               const float* bias, int K, int m, uint16_t* cand, uint16_t* zop,
-                               float* znz, hipStream_t st) {
-  const int Hp = H - 7, Wp = W - 7;
-  const int n3 = (K + 31) / 32;
-  dim3 grid((Wp + 31) / 32, (Hp + kWaves - 1) / kWaves);
-  hipLaunchKernelGGL(propose_bf16_kernel, grid, dim3(kThreads), 0, st, x, H, W,
-                     (float)(-0.5 * log(beta)), reinterpret_cast<const uint4*>(Wb), bias, n3, K,
-                     m, cand, reinterpret_cast<uint4*>(zop), znz);
+hipError_t launch_propose(const ProposeArgs& a, hipStream_t st) {
+  int n_est = a.n_est;
+  if (!a.d) n_est = ((a.W - 7 + kEstCols - 1) / kEstCols) * ((a.H - 7 + 3) / 4);
+  if (n_est < 1) return hipSuccess;
+  hipLaunchKernelGGL(propose_bf16_kernel, dim3((unsigned)(2 * n_est)), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 
