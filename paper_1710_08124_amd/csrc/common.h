@@ -95,6 +95,15 @@ struct Batch {
   int ola_rows;              // rows of a reprojection tile
 };
 
+// The value itself, as if just produced: a float read again after its
+// float64 conversion has fed a sum is converted afresh, so the compiler keeps
+// the 32-bit value live rather than the 64-bit conversion (half the
+// registers in the patch-loading prologues).
+__device__ __forceinline__ float fresh(float v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // ------------------------------------------------------------ launches
 // Every launcher returns hipSuccess or the launch error; none synchronises.
 

@@ -94,7 +94,7 @@ __device__ __forceinline__ void load_patch(const float* __restrict__ x, int W, i
     float d[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      d[e] = (float)((double)v[t][e] - m);
+      d[e] = (float)((double)fresh(v[t][e]) - m);
       if (NZ) q2 = fmaf(d[e], d[e], q2);
     }
     zb[t] = make_uint4(pack2(d[0], d[1]), pack2(d[2], d[3]), pack2(d[4], d[5]),
@@ -427,8 +427,44 @@ __device__ __forceinline__ float key_cost(uint32_t k) {
 // patch, so the 16 lanes of a gather spread over the banks
 __device__ __forceinline__ int rec_slot(int pl, int j) { return pl * 8 + (j ^ (pl & 7)); }
 
+// Squared projections of NBLK blocks of 16 pairs on NRB eigen blocks of one
+// component (A: its operand, 2 depth steps per eigen block): per block the
+// lane group's partial sum, accumulated in the order of project().
+// Straight-line code for each shape, so the blocks' products interleave.
+template <int NBLK, int NRB>
+__device__ __forceinline__ void square_blocks(const uint4 A[8], const uint4 zb[4][2],
+                                              float q[4]) {
+#pragma unroll
+  for (int rb = 0; rb < NRB; ++rb) {
+    f32x4 acc[NBLK];
+#pragma unroll
+    for (int pb = 0; pb < NBLK; ++pb)
+      acc[pb] = mfma16(A[2 * rb], zb[pb][0], (f32x4){0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+    for (int pb = 0; pb < NBLK; ++pb) acc[pb] = mfma16(A[2 * rb + 1], zb[pb][1], acc[pb]);
+#pragma unroll
+    for (int pb = 0; pb < NBLK; ++pb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[pb] = fmaf(acc[pb][i], acc[pb][i], q[pb]);
+  }
+}
+template <int NRB>
+__device__ __forceinline__ void square_chunk(int nblk, const uint4 A[8], const uint4 zb[4][2],
+                                             float q[4]) {
+  switch (nblk) {  // (wave-uniform)
+    case 1: square_blocks<1, NRB>(A, zb, q); break;
+    case 2: square_blocks<2, NRB>(A, zb, q); break;
+    case 3: square_blocks<3, NRB>(A, zb, q); break;
+    default: square_blocks<4, NRB>(A, zb, q); break;
+  }
+}
+
+constexpr int kRescThreads = 1024;  // 16 waves: 4 per SIMD
+constexpr int kRescWaves = kRescThreads / 64;
+static_assert(kRescPatches <= kRescThreads && kRescPatches % 16 == 0, "one patch per thread");
+
 template <bool FLAT>
-__global__ __launch_bounds__(512, 1) void rescore_bf16_kernel(RescoreArgs a) {
+__global__ __launch_bounds__(kRescThreads, 1) void rescore_bf16_kernel(RescoreArgs a) {
   __shared__ uint4 rec[kRescPatches * 8];
   __shared__ float nzs[FLAT ? kRescPatches : 1];
   __shared__ uint16_t plist[kRescPatches * 8];
@@ -436,11 +472,11 @@ __global__ __launch_bounds__(512, 1) void rescore_bf16_kernel(RescoreArgs a) {
   __shared__ uint32_t skey[kRescPatches];
   __shared__ int32_t hcnt[kMaxK];
   __shared__ int32_t hend[kMaxK];
-  __shared__ int32_t wsum[8];
+  __shared__ int32_t wsum[kRescWaves];
   __shared__ int32_t fbase;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, col = lane & 15;
-  const int K = a.K;
+  const int K = a.K, m = a.m;
   const int im = a.tile_img[blockIdx.x];
   const ImgDesc d = a.d[im];
   const int W = d.W, Wp = d.W - 7;
@@ -450,26 +486,28 @@ __global__ __launch_bounds__(512, 1) void rescore_bf16_kernel(RescoreArgs a) {
   const float* x = a.x + d.px;
   const size_t slot = (size_t)(d.slot0 + a.t);
 
-  // the candidates of the thread's two patches (in flight during the
-  // operand build)
-  const uint4* cand4 = reinterpret_cast<const uint4*>(a.cand) + d.np + base;
-  uint4 cw[2];
+  // the pairs are taken pair-major (pair e: candidate e & 7 of local patch
+  // e >> 3), so the lanes of one LDS atomic name at most 8 patches' j-th
+  // candidates (neighbouring patches often share them); the candidates are
+  // in flight during the operand build
+  const uint16_t* cand = a.cand + ((size_t)d.np + base) * 8;
+  constexpr int kPairsPerThread = kRescPatches * 8 / kRescThreads;
+  static_assert(kRescPatches * 8 % kRescThreads == 0, "whole pairs per thread");
+  int ck[kPairsPerThread];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int pl = tid + 512 * h;
-    cw[h] = (pl < npw) ? cand4[pl] : make_uint4(~0u, ~0u, ~0u, ~0u);
+  for (int i = 0; i < kPairsPerThread; ++i) {
+    const int e = tid + kRescThreads * i;
+    const int k = ((e >> 3) < npw) ? (int)cand[e] : 0xffff;
+    ck[i] = ((e & 7) < m && k < K) ? k : -1;  // (an index >= K is never scored)
   }
-  for (int k = tid; k < K; k += 512) hcnt[k] = 0;
-  for (int p = tid; p < kRescPatches; p += 512) {
-    bkey[p] = ~0ull;
-    skey[p] = ~0u;
+  for (int k = tid; k < K; k += kRescThreads) hcnt[k] = 0;
+  if (tid < kRescPatches) {
+    bkey[tid] = ~0ull;
+    skey[tid] = ~0u;
   }
   // ---- operands: 16 patches per wave pass (lane group g: rows g, 4 + g);
-  // past the image's last patch, copies of it that no pair names.  (7
-  // passes per wave, unrolled: every pass's pixel loads in flight at once.)
-  static_assert(kRescPatches == 16 * 8 * 7, "seven operand passes per wave");
-#pragma unroll
-  for (int b = wave; b < kRescPatches / 16; b += 8) {
+  // past the image's last patch, copies of it that no pair names
+  for (int b = wave; b < kRescPatches / 16; b += kRescWaves) {
     const int pl = 16 * b + col;
     const int p = base + min(pl, npw - 1);
     const int r = p / Wp;
@@ -482,73 +520,48 @@ __global__ __launch_bounds__(512, 1) void rescore_bf16_kernel(RescoreArgs a) {
   }
   __syncthreads();
   // ---- the pairs by component: counts, exclusive scan, scatter
-  auto cand_k = [&](int h, int j) __attribute__((always_inline)) {
-    const uint32_t w = (j >> 1) == 0 ? cw[h].x : (j >> 1) == 1 ? cw[h].y
-                     : (j >> 1) == 2 ? cw[h].z : cw[h].w;
-    const int k = (int)((w >> (16 * (j & 1))) & 0xffffu);
-    return (j < a.m && k < K) ? k : -1;  // (an index >= K is never scored)
-  };
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = cand_k(h, j);
-      if (k >= 0) atomicAdd(&hcnt[k], 1);
-    }
+  for (int i = 0; i < kPairsPerThread; ++i)
+    if (ck[i] >= 0) atomicAdd(&hcnt[ck[i]], 1);
   __syncthreads();
   {
-    // two components per thread (K <= 1024)
-    const int k0 = 2 * tid;
-    const int c0 = (k0 < K) ? hcnt[k0] : 0, c1 = (k0 + 1 < K) ? hcnt[k0 + 1] : 0;
-    int s = c0 + c1;
+    // one component per thread (K <= 1024)
+    const int c0 = (tid < K) ? hcnt[tid] : 0;
+    int sc = c0;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-      const int u = __shfl_up(s, off);
-      if (lane >= off) s += u;
+      const int u = __shfl_up(sc, off);
+      if (lane >= off) sc += u;
     }
-    if (lane == 63) wsum[wave] = s;
+    if (lane == 63) wsum[wave] = sc;
     __syncthreads();
     int pre = 0;
     for (int w = 0; w < wave; ++w) pre += wsum[w];
-    const int excl = pre + s - (c0 + c1);
-    if (k0 < K) hend[k0] = excl;
-    if (k0 + 1 < K) hend[k0 + 1] = excl + c0;
+    if (tid < K) hend[tid] = pre + sc - c0;
   }
   __syncthreads();
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = cand_k(h, j);
-      if (k >= 0) plist[atomicAdd(&hend[k], 1)] = (uint16_t)(tid + 512 * h);
-    }
+  for (int i = 0; i < kPairsPerThread; ++i)
+    if (ck[i] >= 0)
+      plist[atomicAdd(&hend[ck[i]], 1)] = (uint16_t)((tid + kRescThreads * i) >> 3);
   __syncthreads();
   // ---- scores: component k's pairs are plist[hend[k] - hcnt[k] .. hend[k])
   const uint4* up = reinterpret_cast<const uint4*>(a.Ub + slot * K * kTileStride) + lane;
   const float* Lt = a.L + slot * K;
-  // the component's operand and terms, the next component's already in
-  // flight (issued before anything of the current one is waited for)
-  uint4 A[8];
-  float Lk = 0.f, Pk = 0.f;
-  int rk = kP;
-  auto fetch = [&](int k, uint4* Ad, float& Ld, int& rd, float& Pd) __attribute__((always_inline)) {
+  for (int k = wave; k < K; k += kRescWaves) {
+    const int n = __builtin_amdgcn_readfirstlane(hcnt[k]);
+    if (n == 0) continue;
+    const int s0 = __builtin_amdgcn_readfirstlane(hend[k]) - n;
+    const int rk = FLAT ? a.rk[k] : kP;
+    const float Pk = FLAT ? a.Pinv[slot * K + k] : 0.f;
+    const float Lk = Lt[k];
+    // flat tail: the eigen blocks past the kept directions get a zero
+    // operand (their products add exact zeros), one block when r_k <= 16
+    const int nb = FLAT ? __builtin_amdgcn_readfirstlane((rk + 15) >> 4) : 4;
+    uint4 A[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) Ad[i] = up[(size_t)k * 512 + i * 64];
-    Ld = Lt[k];
-    if (FLAT) {
-      rd = a.rk[k];
-      Pd = a.Pinv[slot * K + k];
-    }
-  };
-  if (wave < K) fetch(wave, A, Lk, rk, Pk);
-  for (int k = wave; k < K; k += 8) {
-    uint4 An[8];
-    float Ln = 0.f, Pn = 0.f;
-    int rn = kP;
-    if (k + 8 < K) fetch(k + 8, An, Ln, rn, Pn);  // (wave-uniform)
-    const int n = hcnt[k];
-    const int s0 = hend[k] - n;
-    const int nb = FLAT ? (rk + 15) >> 4 : 4;  // eigen blocks scored
+    for (int i = 0; i < 8; ++i)
+      A[i] = (!FLAT || i < 2 * nb) ? up[(size_t)k * 512 + i * 64] : make_uint4(0u, 0u, 0u, 0u);
     for (int c0 = 0; c0 < n; c0 += 64) {
       const int nblk = min(4, (n - c0 + 15) >> 4);
       int pl[4];
@@ -556,26 +569,14 @@ __global__ __launch_bounds__(512, 1) void rescore_bf16_kernel(RescoreArgs a) {
 #pragma unroll
       for (int pb = 0; pb < 4; ++pb) {
         pl[pb] = plist[s0 + min(c0 + 16 * pb + col, n - 1)];
-        if (pb < nblk) {
-          zb[pb][0] = rec[rec_slot(pl[pb], g)];
-          zb[pb][1] = rec[rec_slot(pl[pb], 4 + g)];
-        } else {
-          zb[pb][0] = zb[pb][1] = make_uint4(0u, 0u, 0u, 0u);
-        }
+        zb[pb][0] = rec[rec_slot(pl[pb], g)];
+        zb[pb][1] = rec[rec_slot(pl[pb], 4 + g)];
       }
       float q[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int rb = 0; rb < 4; ++rb) {
-        if (rb >= nb) continue;  // (wave-uniform)
-#pragma unroll
-        for (int pb = 0; pb < 4; ++pb) {
-          if (pb >= nblk) continue;  // (wave-uniform)
-          f32x4 acc = mfma16(A[2 * rb], zb[pb][0], (f32x4){0.f, 0.f, 0.f, 0.f});
-          acc = mfma16(A[2 * rb + 1], zb[pb][1], acc);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) q[pb] = fmaf(acc[i], acc[i], q[pb]);
-        }
-      }
+      if (FLAT && nb == 1)
+        square_chunk<1>(nblk, A, zb, q);
+      else
+        square_chunk<4>(nblk, A, zb, q);
       // lane group g ends with block g's column sums: (q0 + q2) + (q1 + q3)
       const float mm = pair_sum16(pair_sum32(q[0], q[2]), pair_sum32(q[1], q[3]));
       if (c0 + 16 * g + col < n) {
@@ -592,39 +593,29 @@ __global__ __launch_bounds__(512, 1) void rescore_bf16_kernel(RescoreArgs a) {
         atomicMin(&skey[p], (uint32_t)(max(old, kk) >> 32));
       }
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) A[i] = An[i];
-    Lk = Ln;
-    rk = rn;
-    Pk = Pn;
   }
   __syncthreads();
   // ---- per patch: label, costs, fallback decision
-  bool fb[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int pl = tid + 512 * h;
-    fb[h] = false;
-    if (pl < npw) {
-      const unsigned long long bk = bkey[pl];
-      const uint32_t sk = skey[pl];
-      const float b = (bk == ~0ull) ? INFINITY : key_cost((uint32_t)(bk >> 32));
-      const float s = (sk == ~0u) ? INFINITY : key_cost(sk);
-      const size_t i = (size_t)d.np + base + pl;
-      a.labels[i] = (bk == ~0ull) ? 0x7fffffff : (int)(uint32_t)bk;
-      if (a.best) a.best[i] = b;
-      if (a.second) a.second[i] = s;
-      const float gap = (s < INFINITY) ? 0.5f * (s - b) : -INFINITY;
-      fb[h] = !(gap >= a.margin);
-    }
+  bool fb = false;
+  if (tid < npw) {
+    const unsigned long long bk = bkey[tid];
+    const uint32_t sk = skey[tid];
+    const float b = (bk == ~0ull) ? INFINITY : key_cost((uint32_t)(bk >> 32));
+    const float s = (sk == ~0u) ? INFINITY : key_cost(sk);
+    const size_t i = (size_t)d.np + base + tid;
+    a.labels[i] = (bk == ~0ull) ? 0x7fffffff : (int)(uint32_t)bk;
+    if (a.best) a.best[i] = b;
+    if (a.second) a.second[i] = s;
+    const float gap = (s < INFINITY) ? 0.5f * (s - b) : -INFINITY;
+    fb = !(gap >= a.margin);
   }
   // the image's fallback list: one global atomic per workgroup
-  const uint64_t m0 = __ballot(fb[0]), m1 = __ballot(fb[1]);
-  if (lane == 0) wsum[wave] = __popcll(m0) + __popcll(m1);
+  const uint64_t mask = __ballot(fb);
+  if (lane == 0) wsum[wave] = __popcll(mask);
   __syncthreads();
   if (tid == 0) {
     int run = 0;
-    for (int w = 0; w < 8; ++w) {
+    for (int w = 0; w < kRescWaves; ++w) {
       const int v = wsum[w];
       wsum[w] = run;
       run += v;
@@ -632,10 +623,7 @@ __global__ __launch_bounds__(512, 1) void rescore_bf16_kernel(RescoreArgs a) {
     fbase = run ? atomicAdd(&a.fb_count[im], run) : 0;
   }
   __syncthreads();
-  const uint64_t below = (1ull << lane) - 1ull;
-  int32_t* fl = a.fb_list + d.np + fbase + wsum[wave];
-  if (fb[0]) fl[__popcll(m0 & below)] = base + tid;
-  if (fb[1]) fl[__popcll(m0) + __popcll(m1 & below)] = base + tid + 512;
+  if (fb) a.fb_list[d.np + fbase + wsum[wave] + __popcll(mask & ((1ull << lane) - 1ull))] = base + tid;
 }
 
 // Items of the batched fallback search: pre[i] = sum over images j < i of
@@ -977,9 +965,11 @@ hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st
 hipError_t launch_rescore_batch(const RescoreArgs& a, int n_tiles, hipStream_t st) {
   if (n_tiles < 1) return hipSuccess;
   if (a.rk)
-    hipLaunchKernelGGL(rescore_bf16_kernel<true>, dim3((unsigned)n_tiles), dim3(512), 0, st, a);
+    hipLaunchKernelGGL(rescore_bf16_kernel<true>, dim3((unsigned)n_tiles), dim3(kRescThreads), 0, st,
+                       a);
   else
-    hipLaunchKernelGGL(rescore_bf16_kernel<false>, dim3((unsigned)n_tiles), dim3(512), 0, st, a);
+    hipLaunchKernelGGL(rescore_bf16_kernel<false>, dim3((unsigned)n_tiles), dim3(kRescThreads), 0,
+                       st, a);
   return hipGetLastError();
 }
 

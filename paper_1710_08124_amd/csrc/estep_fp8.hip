@@ -61,7 +61,7 @@ __device__ __forceinline__ void quantize_patch8(float (&v)[32], i32x8& zq, int& 
   float mx = 0.f, q2 = 0.f;
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
-    v[i] = (float)((double)v[i] - m);
+    v[i] = (float)((double)fresh(v[i]) - m);
     mx = fmaxf(mx, fabsf(v[i]));
     if (NZ) q2 = fmaf(v[i], v[i], q2);
   }

@@ -260,7 +260,8 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(ProposeArgs a
     for (int t = 0; t < 4; ++t) {
       float q[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) q[e] = (float)((double)v[t][e] - mean) * (1.f / kScaleIn);
+      for (int e = 0; e < 8; ++e)
+        q[e] = (float)((double)fresh(v[t][e]) - mean) * (1.f / kScaleIn);
       xb[t] = make_uint4(pack2(q[0], q[1]), pack2(q[2], q[3]), pack2(q[4], q[5]),
                          pack2(q[6], q[7]));
     }
