@@ -224,13 +224,21 @@ def batch_c5(n: int = 48, seed: int = 500, texture_std: float = 10.0, workers: i
         return pool.map(_c5_item, items, chunksize=1)
 
 
-def training_images(seeds=range(300, 313), size: int = 256, sigma_seed: int = 600):
+def training_images(seeds=range(300, 313), size: int = 256, sigma_seed: int = 600,
+                    stratified: bool = False):
     """Clean/noisy pairs for the proposal network's training set;
-    sigma ~ U[5, 50] per image."""
+    sigma ~ U[5, 50] per image.  stratified: image i of n draws its sigma
+    uniformly from the i-th of n equal parts of [5, 50] (still uniform over
+    the whole range, but every part of it present)."""
     g = rng(sigma_seed)
     out = []
-    for s in seeds:
-        sig = float(g.uniform(5.0, 50.0))
+    seeds = list(seeds)
+    n = len(seeds)
+    for i, s in enumerate(seeds):
+        if stratified:
+            sig = 5.0 + 45.0 * (i + float(g.uniform(0.0, 1.0))) / n
+        else:
+            sig = float(g.uniform(5.0, 50.0))
         x = test_image(size, size, s)
         out.append(dict(x=x, y=noisy(x, sig, s + 1000), sigma=sig))
     return out

@@ -280,6 +280,12 @@ fepll_status fepll_get_tuning(fepll_gmm* g, fepll_tuning* t);
  * batch (arguments as fepll_restore_batch; the results are discarded), keep
  * the fastest of each stage in the handle and return them in *best (may be
  * NULL).  Synchronises.
+ * Tuning cache: when the environment variable FEPLL_TUNING_CACHE names a
+ * file, a result found there for the same device, precision and selection
+ * path, K, flat tail and batch shape class (image count, total and largest
+ * image size, each rounded down to a power of two) is applied without any
+ * trial, and a new result is appended to it (one text line per workload; a
+ * file that cannot be read or written is no error).
  */
 fepll_status fepll_autotune(fepll_gmm* g, int32_t n, const fepll_image* y,
                             const double* sigma, const fepll_options* opt,
@@ -391,6 +397,18 @@ const char* fepll_last_error(void);
 
 /* Library version string. */
 const char* fepll_version(void);
+
+/*
+ * Device memory the library holds (every handle's buffers and scratch, in
+ * bytes), and a cap on it for testing the out-of-memory paths: once set
+ * (limit_bytes > 0; 0 removes it), an allocation that would take the
+ * holdings past the cap fails as on a full device: the call returns
+ * FEPLL_ENOMEM and leaves its outputs unwritten; the handle stays usable
+ * (buffers it grew before the failure stay with it until a later call or
+ * fepll_gmm_destroy frees them).  Process-wide.
+ */
+fepll_status fepll_set_memory_limit(size_t limit_bytes);
+size_t fepll_memory_in_use(void);
 
 #ifdef __cplusplus
 }

@@ -114,6 +114,14 @@ def hqs_iteration(xh, y, U, lam, w, sigma, beta, idx):
     """One pass of Alg. 1 over the patch subset idx (flat indices r Wp + c):
     selection and estimation of those patches, then the average of their
     overlapping estimates (every pixel covered) and the image update."""
+    xt, info = subset_estimate(xh, U, lam, w, beta, idx)
+    return o.image_update(y, xt, beta, sigma), info
+
+
+def subset_estimate(xh, U, lam, w, beta, idx):
+    """The patch steps of Alg. 1 on the subset idx: selection and estimation
+    of those patches and the average x~ of their overlapping estimates
+    (every pixel covered), before any image estimation."""
     H, W = xh.shape
     Wp = W - 7
     r, c = np.divmod(np.asarray(idx, dtype=np.int64), Wp)
@@ -129,9 +137,7 @@ def hqs_iteration(xh, y, U, lam, w, sigma, beta, idx):
         cnt[r[i]:r[i] + 8, c[i]:c[i] + 8] += 1.0
     if np.any(cnt == 0):
         raise AssertionError("a pixel is not covered by the subset")
-    xt = S / cnt
-    return o.image_update(y, xt, beta, sigma), dict(labels=lab, best=best, second=second,
-                                                    idx=np.asarray(idx), count=cnt)
+    return S / cnt, dict(labels=lab, best=best, second=second, idx=np.asarray(idx), count=cnt)
 
 
 def restore(y, U, lam, w, sigma, s, seed, betas=None, init=None, trace=False):

@@ -109,6 +109,10 @@ def lib():
     L.fepll_select.argtypes = [c_void_p, POINTER(Image), c_double, c_void_p, c_void_p, c_void_p,
                                c_void_p, POINTER(Options)]
     L.fepll_select.restype = c_int32
+    L.fepll_set_memory_limit.argtypes = [ctypes.c_size_t]
+    L.fepll_set_memory_limit.restype = c_int32
+    L.fepll_memory_in_use.argtypes = []
+    L.fepll_memory_in_use.restype = ctypes.c_size_t
     L.fepll_profile.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32), c_int32]
     L.fepll_profile.restype = c_int32
     L.fepll_mlp_param_count.argtypes = [c_int32]
@@ -421,6 +425,17 @@ def select(gmm: GMM, x, beta: float, recheck=True, precision="fp32", proposal=Fa
                               best.data_ptr(), second.data_ptr(), flags.data_ptr(),
                               ctypes.byref(o)))
     return lab, best, second, flags
+
+
+def set_memory_limit(limit_bytes: int):
+    """Cap on the device memory the library holds (0: none); allocations
+    past it fail with ENOMEM."""
+    _check(lib().fepll_set_memory_limit(int(limit_bytes)))
+
+
+def memory_in_use() -> int:
+    """Bytes of device memory the library holds."""
+    return int(lib().fepll_memory_in_use())
 
 
 def propose(gmm: GMM, x, beta: float, top_m: int = 8):

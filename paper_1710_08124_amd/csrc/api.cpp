@@ -9,6 +9,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <unordered_map>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -18,6 +21,7 @@
 #include "fepll.h"
 #include "internal.h"
 #include "propose.h"
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 using namespace fepll;
 
@@ -188,6 +192,41 @@ struct fepll_gmm {
   uint32_t profiling = 0;  // bit s: stage s is timed
 };
 
+namespace fepll {
+GmmView gmm_view(const fepll_gmm* g) { return GmmView{g->K, g->device, g->U64, g->lam64, g->w64}; }
+
+namespace {
+std::mutex g_mem_mu;
+std::unordered_map<void*, size_t> g_mem_held;
+size_t g_mem_in_use = 0;
+size_t g_mem_limit = 0;  // 0: none
+}  // namespace
+
+hipError_t dev_alloc(void** p, size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  *p = nullptr;
+  if (g_mem_limit && g_mem_in_use + bytes > g_mem_limit) return hipErrorOutOfMemory;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  g_mem_held[*p] = bytes;
+  g_mem_in_use += bytes;
+  return hipSuccess;
+}
+
+void dev_free(void* p) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  auto it = g_mem_held.find(p);
+  if (it != g_mem_held.end()) {
+    g_mem_in_use -= it->second;
+    g_mem_held.erase(it);
+  }
+  (void)hipFree(p);
+}
+}  // namespace fepll
+
 namespace {
 
 constexpr int kStages = 9;
@@ -200,6 +239,59 @@ void default_tuning(fepll_tuning* t) {
   t->wiener_blocks = 4096;
   t->ola_rows = 32;
   t->reserved = 0;
+}
+
+// The tuning cache (a text file named by FEPLL_TUNING_CACHE): one line per
+// autotuned workload, "fepll-tuning 1 <key> <est> <wiener> <ola>", the key
+// naming what the launch shapes depend on: the device, the precision and
+// selection path, K, and the batch's shape class (image count, total and
+// largest image size, each to a power of two).  The last line for a key
+// wins.
+int log2_class(int64_t v) {
+  int c = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++c;
+  }
+  return c;
+}
+std::string tuning_key(const fepll_gmm* g, const fepll_options& o, int n, int64_t total,
+                       int64_t largest) {
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, g->device) == hipSuccess) arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
+  const char* path = o.use_proposal ? "proposal" : o.use_tree ? "tree" : o.jitter ? "jitter" : "all";
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s:p%d:%s:flat%d:K%d:n%d:px%d:max%d", arch.c_str(),
+                (int)o.precision, path, g->tb.rk ? 1 : 0, g->K, log2_class(n),
+                log2_class(total), log2_class(largest));
+  return buf;
+}
+bool tuning_lookup(const char* path, const std::string& key, fepll_tuning* t) {
+  std::FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, f)) {
+    char k[300];
+    int ver = 0, e = 0, w = 0, r = 0;
+    if (std::sscanf(line, "fepll-tuning %d %299s %d %d %d", &ver, k, &e, &w, &r) == 5 &&
+        ver == 1 && key == k) {
+      *t = fepll_tuning{e, w, r, 0};
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+void tuning_store(const char* path, const std::string& key, const fepll_tuning& t) {
+  std::FILE* f = std::fopen(path, "a");
+  if (!f) return;  // a cache that cannot be written is no error
+  std::fprintf(f, "fepll-tuning 1 %s %d %d %d\n", key.c_str(), t.est_blocks, t.wiener_blocks,
+               t.ola_rows);
+  std::fclose(f);
 }
 
 hipEvent_t take_event(fepll_gmm* g) {
@@ -221,6 +313,20 @@ uint32_t profile_mask(int32_t profile) {
   if (profile & 1) return 0xffffffffu;
   return (uint32_t)profile >> 1;
 }
+
+// A named range on the host timeline of a tracer (roctx; no cost without
+// one): each HQS iteration of a restoration, and each call.
+struct TraceRange {
+  explicit TraceRange(const char* what, int t = -1) {
+    char buf[64];
+    if (t >= 0)
+      std::snprintf(buf, sizeof buf, "%s %d", what, t + 1);
+    else
+      std::snprintf(buf, sizeof buf, "%s", what);
+    roctxRangePushA(buf);
+  }
+  ~TraceRange() { roctxRangePop(); }
+};
 
 // Brackets one stage with events when profiling is on.
 // chain: the stage follows the previous timed stage with no launch between,
@@ -580,6 +686,7 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
   if ((s = grow(&g->hist, g->hist_cap, (size_t)K * sort.size())) != FEPLL_OK) return s;
   if ((s = grow(&g->seg, g->seg_cap, (size_t)seg)) != FEPLL_OK) return s;
   if (!same) {
+    g->plan_valid = false;  // (until every plan buffer is uploaded)
     if ((s = grow(&g->d, g->n_cap, (size_t)n)) != FEPLL_OK) return s;
     if ((s = grow(&g->wbase, g->wb_cap, (size_t)n + 1)) != FEPLL_OK) return s;
     if ((s = grow(&g->est_img, g->est_cap, est.size())) != FEPLL_OK) return s;
@@ -1064,7 +1171,8 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
   g->jit_hist = false;
   // one image, its list sorted, no labels returned: the reprojection of
   // iteration t also draws the subset of t + 1 (it then takes its patches
-  // from the flags; the labels of earlier lists are left as they are)
+  // from the flags, and the drawing gives the patches of the list of t - 1
+  // flag 0 and label K again)
   g->jit_fused = list_sort && b.n == 1 && labels_out == nullptr;
   if (jit_list) {
     const int n = (int)b.n_patches;
@@ -1078,6 +1186,7 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     HIPX(hipGetLastError());
   }
   for (int t = 0; t < T; ++t) {
+    TraceRange tr("fepll HQS iteration", t);
     if ((s = select_batch(g, t, o, xc, g->labels, nullptr, nullptr, nullptr, st)) != FEPLL_OK)
       return s;
     if (labels_out)
@@ -1101,14 +1210,16 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     {
       StageTimer tm(g, 4, st, true);
       if (g->jit_fused && t + 1 < T) {
-        // the drawing of t + 1: undoes the list of t - 1 (flags only), zeroes
-        // the count t + 2 appends to, clears the selection's histogram
+        // the drawing of t + 1: undoes the list of t - 1 (flags and labels;
+        // this reprojection reads neither), zeroes the count t + 2 appends
+        // to, clears the selection's histogram
         const ImgDesc& d = g->hd[0];
         JitterPrev prev;
         if (t >= 1) {
           prev.list = jlist_of(g, t - 1) + d.np;
           prev.count = jcount_of(g, t - 1);
           prev.flags = jflags_of(g, t - 1) + d.np;
+          prev.labels = g->labels + d.np;
           prev.K = g->K;
         }
         prev.zero = jcount_of(g, t + 2);
@@ -1197,6 +1308,13 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
   for (const void* p : ptrs) put(key, p);
   put(key, g->tree_gen);  // a new tree may reuse the old one's addresses
   if (g->gexec && key == g->gkey) {
+    // the graph starts from clear subset flags: after an interrupted eager
+    // call they are cleared here first
+    if (o.jitter && g->jflags_dirty) {
+      fepll_status s = clear_jflags(g, st);
+      if (s != FEPLL_OK) return s;
+      g->jflags_dirty = false;
+    }
     *result = (T % 2) ? g->xb : g->xa;
     HIPX(hipGraphLaunch(g->gexec, st));
     return FEPLL_OK;
@@ -1327,6 +1445,18 @@ void fepll_options_default(fepll_options* o) {
 const char* fepll_last_error(void) { return g_err.c_str(); }
 
 const char* fepll_version(void) { return "fepll-gfx950 0.2"; }
+
+fepll_status fepll_set_memory_limit(size_t limit_bytes) {
+  clear_error();
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  g_mem_limit = limit_bytes;
+  return FEPLL_OK;
+}
+
+size_t fepll_memory_in_use(void) {
+  std::lock_guard<std::mutex> lk(g_mem_mu);
+  return g_mem_in_use;
+}
 
 fepll_status fepll_gmm_create(const double* U, const double* lambda, const double* w, int32_t K,
                               int32_t d, fepll_gmm** out) {
@@ -1496,6 +1626,7 @@ fepll_status fepll_restore(fepll_gmm* g, const fepll_image* y, const fepll_opera
                            double sigma, const double* beta_schedule, int32_t T,
                            fepll_image* out, const fepll_options* opt, int32_t* labels_out) {
   g_err.clear();
+  TraceRange tr("fepll_restore");
   if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
   fepll_status s;
   if ((s = check_image(y, "y")) != FEPLL_OK) return s;
@@ -1599,6 +1730,7 @@ fepll_status fepll_restore_batch(fepll_gmm* g, int32_t n, const fepll_image* y,
                                  const double* sigma, fepll_image* out,
                                  const fepll_options* opt) {
   g_err.clear();
+  TraceRange tr("fepll_restore_batch");
   if (!g) return fail(FEPLL_EINVAL, "gmm handle is NULL");
   if (n < 1 || n > kMaxBatch) return fail(FEPLL_EINVAL, "n must be in 1..65536");
   if (!y || !sigma || !out) return fail(FEPLL_EINVAL, "y, sigma and out must be non-NULL");
@@ -1684,10 +1816,20 @@ fepll_status fepll_autotune(fepll_gmm* g, int32_t n, const fepll_image* y, const
   if (opt) o = *opt;
   o.profile = 1;
   fepll_status s;
-  int64_t total = 0;
+  int64_t total = 0, largest = 0;
   for (int i = 0; i < n; ++i) {
     if ((s = check_image(&y[i], "y")) != FEPLL_OK) return s;
     total += (int64_t)y[i].height * y[i].width;
+    largest = std::max<int64_t>(largest, (int64_t)y[i].height * y[i].width);
+  }
+  // a result kept for this kind of workload in the tuning cache
+  const std::string ckey = tuning_key(g, o, n, total, largest);
+  const char* cpath = std::getenv("FEPLL_TUNING_CACHE");
+  fepll_tuning cached;
+  if (cpath && *cpath && tuning_lookup(cpath, ckey, &cached)) {
+    if ((s = fepll_set_tuning(g, &cached)) != FEPLL_OK) return s;
+    if (best) *best = cached;
+    return FEPLL_OK;
   }
   // every image is restored into a device scratch image
   float* scratch = nullptr;
@@ -1736,6 +1878,7 @@ fepll_status fepll_autotune(fepll_gmm* g, int32_t n, const fepll_image* y, const
                        ola_c[std::min_element(to.begin(), to.end()) - to.begin()], 0};
   if ((s = fepll_set_tuning(g, &t)) != FEPLL_OK) return s;
   if (best) *best = t;
+  if (cpath && *cpath) tuning_store(cpath, ckey, t);
   return FEPLL_OK;
 }
 

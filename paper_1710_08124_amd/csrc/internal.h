@@ -13,18 +13,36 @@ namespace fepll {
 fepll_status fail(fepll_status s, const std::string& msg);
 void clear_error();
 
+// Every device buffer of the library goes through these two: the bytes held
+// are counted, and an allocation that would take them past the limit set by
+// fepll_set_memory_limit fails with hipErrorOutOfMemory, as a full device.
+hipError_t dev_alloc(void** p, size_t bytes);
+void dev_free(void* p);
+
 template <class T>
 hipError_t dalloc(T** p, size_t n) {
   *p = nullptr;
   if (n == 0) return hipSuccess;
-  return hipMalloc((void**)p, n * sizeof(T));
+  return dev_alloc((void**)p, n * sizeof(T));
 }
 
 template <class T>
 void dfree(T*& p) {
-  if (p) (void)hipFree(p);
+  if (p) dev_free(p);
   p = nullptr;
 }
+
+// What an entry point outside the handle's own translation unit may read of
+// a handle: its size, its device and its float64 mixture (device copies made
+// at creation, the spectra in use).
+struct GmmView {
+  int K;
+  int device;
+  const double* U64;
+  const double* lam64;
+  const double* w64;
+};
+GmmView gmm_view(const fepll_gmm* g);
 
 }  // namespace fepll
 

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const floa
     s0 += __shfl_xor(s0, 32);
     const double m0 = s0 * (1.0 / 64.0);
 #pragma unroll
-    for (int s = 0; s < 32; ++s) z0[s] = (float)((double)z0[s] - m0);
+    for (int s = 0; s < 32; ++s) z0[s] = (float)((double)fresh(z0[s]) - m0);
     const float fm0 = (float)m0;
     // one 32-row block of W_k at a time (rows q = 32 qb + ...)
 #pragma unroll
@@ -112,13 +112,17 @@ __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const floa
       // accumulator 4 g + e of lane l is pixel q = 32 qb + 8 g + 4 half + e of
       // patch col; the two halves of the wave write the 128 contiguous bytes
       // of pixels 32 qb .. 32 qb + 31 of each patch
+      // (streaming stores: the estimates are read once, by the reprojection,
+      // and must not push the image and the filters out of the L2)
       if (v0) {
         float* zp = Zhat + (size_t)id0 * kP + 32 * qb + 4 * half;
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
-          *reinterpret_cast<float4*>(zp + 8 * g) =
-              make_float4(a0[4 * g] + fm0, a0[4 * g + 1] + fm0, a0[4 * g + 2] + fm0,
-                          a0[4 * g + 3] + fm0);
+        for (int g = 0; g < 4; ++g) {
+          const f32x4 v = {a0[4 * g] + fm0, a0[4 * g + 1] + fm0, a0[4 * g + 2] + fm0,
+                           a0[4 * g + 3] + fm0};
+          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(zp + 8 * g));
+        }
       }
     }
   }

@@ -179,6 +179,33 @@ def test_autotune_and_shapes_keep_results(F, gm, small_batch):
             np.testing.assert_array_equal(a.cpu().numpy(), b)
 
 
+def test_autotune_cache(F, gm, small_batch, tmp_path, monkeypatch):
+    """FEPLL_TUNING_CACHE: a tuned workload is written once; the same kind of
+    workload is then tuned from the file with no trial (no new line), the
+    last line for a key winning; another precision is its own key."""
+    path = tmp_path / "tuning.txt"
+    monkeypatch.setenv("FEPLL_TUNING_CACHE", str(path))
+    g = F.GMM(*gm)
+    sig = [d["sigma"] for d in small_batch]
+    ys = [dev(d["y"]) for d in small_batch]
+    best = F.autotune(g, ys, sig, precision="bf16")
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("fepll-tuning 1 ")
+    key = lines[0].split()[2]
+    assert ":K200:" in key
+    F.set_tuning(g, est_blocks=1, wiener_blocks=1024, ola_rows=16)
+    assert F.autotune(g, ys, sig, precision="bf16") == best
+    assert len(path.read_text().splitlines()) == 1
+    with open(path, "a") as f:
+        f.write(f"fepll-tuning 1 {key} 512 2048 64\n")
+    assert F.autotune(g, ys, sig, precision="bf16") == dict(est_blocks=512, wiener_blocks=2048,
+                                                            ola_rows=64)
+    F.autotune(g, ys, sig, precision="fp8")
+    lines = path.read_text().splitlines()
+    assert len(lines) == 3 and lines[2].split()[2] != key
+    g.close()
+
+
 def test_batch_with_proposal_equals_single(F, gm, small_batch):
     import os
     path = os.path.join(os.path.dirname(F.__file__), "data", "proposal_k200_gmm12.bin")

@@ -109,17 +109,33 @@ def test_reduced_precision_quality(F, mode):
     assert abs(d) <= 0.05
 
 
-def test_deblur_with_flat_tail_and_jitter_runs(F):
+@pytest.mark.parametrize("mode", ["fp32", "fp8"])
+def test_deblur_with_flat_tail_and_jitter(F, mode):
+    """Deblurring on the flat-tailed mixture (Sec. 3.1) with jittered patch
+    subsets (Sec. 3.3) against the FP64 reference composed of the same
+    steps: the Sec. 5 start and schedule, at iteration t the patch steps on
+    the oracle's subset of t with the flat spectra, then the Fourier image
+    estimation.  float32: end to end within 1e-3 dB (the labels agree where
+    the trajectories do); e4m3: within 0.05 dB."""
+    from oracle import flat_tail as ft
+    from oracle import jitter as jt
     c = fs.config_deblur(size=128)
     g = F.GMM(c["U"], c["lam"], c["w"])
     g.flat_tail(0.95)
     y32 = f32(c["y"])
-    got = F.restore(g, dev(y32), c["sigma"], blur=c["h"], precision="fp8", jitter=6, seed=1)
+    H, W = y32.shape
+    lam_f, _ = ft.flat_tail(c["lam"], 0.95)
+    x = db.initial_estimate(y32, c["h"], c["sigma"])
+    for t, beta in enumerate(db.default_betas(c["h"], H, W, c["sigma"])):
+        idx, _ = jt.positions(H, W, 6, 1, t)
+        xt, _ = jt.subset_estimate(x, c["U"], lam_f, c["w"], float(beta), idx)
+        x = db.image_update(y32, xt, c["h"], float(beta), c["sigma"])
+    got = F.restore(g, dev(y32), c["sigma"], blur=c["h"], precision=mode, jitter=6, seed=1)
     got = got.cpu().numpy().astype(np.float64)
-    assert np.all(np.isfinite(got))
-    print("deblur fp8 + flat + jitter: PSNR", o.psnr(c["x"], got), "vs blurred",
-          o.psnr(c["x"], y32))
-    assert o.psnr(c["x"], got) > o.psnr(c["x"], y32) + 1.0
+    d = o.psnr(c["x"], x) - o.psnr(c["x"], got)
+    print(f"deblur {mode} + flat + jitter: dPSNR vs FP64 {d:+.5f} dB "
+          f"(blurred {o.psnr(c['x'], y32):.2f} dB, restored {o.psnr(c['x'], got):.2f} dB)")
+    assert abs(d) <= (1e-3 if mode == "fp32" else 0.05)
 
 
 def test_bad_operators_rejected(F, prob):

@@ -274,3 +274,52 @@ def test_trained_network_gain(F):
     d = o.psnr(xs, ref) - o.psnr(xs, got.astype(np.float64))
     print("trained proposal dPSNR", d)
     assert abs(d) <= 0.05
+
+
+def test_shipped_network_full_size(F):
+    """The shipped network on the 1024 x 1024 workload (first iteration, from
+    y), on 4000 sampled patches against the bfloat16 selection's definition
+    (oracle/lowp.py with its float32 accumulation bound): a patch that was
+    kept took its candidates' best and had a candidate gap above the margin,
+    a patch that fell back took the best over all K, a patch whose
+    candidates' gap is clearly below the margin fell back; and the exact FP64
+    label is among the 8 candidates of most patches."""
+    import os
+
+    from oracle import lowp
+    c = fs.config_c3(1024)
+    U, lam, w, sigma = c["U"], c["lam"], c["w"], c["sigma"]
+    x = np.asarray(c["y"], np.float32)
+    beta = 1.0 / sigma ** 2
+    g = F.GMM(U, lam, w)
+    blob = os.path.join(os.path.dirname(F.__file__), "data", "proposal_k200_gmm12.bin")
+    g.load_proposal(open(blob, "rb").read())
+    xd = dev(x)
+    cand = F.propose(g, xd, beta, 8).cpu().numpy().astype(np.int64)
+    lab, best, _, fb = F.select(g, xd, beta, precision="bf16", proposal=True, top_m=8, margin=0.5)
+    lab, best, fb = lab.cpu().numpy(), best.cpu().numpy(), fb.cpu().numpy().astype(bool)
+    idx = np.sort(fs.rng(31).choice(lab.size, 4000, replace=False))
+    cost, bnd = lowp.lowp_costs(x, U, lam, w, beta, "bf16", acc_eps=64 * 2.0 ** -24, patches=idx)
+    i = np.arange(idx.size)
+    cd, lb, f, tol = cand[idx], lab[idx], fb[idx], bnd.max(1)
+    assert all(len(set(r)) == 8 for r in cd) and np.all((cd >= 0) & (cd < 200))
+    assert np.all(np.abs(best[idx] - cost[i, lb]) <= tol)
+    cc = np.sort(np.take_along_axis(cost, cd, axis=1), axis=1)
+    gap = cc[:, 1] - cc[:, 0]          # 2 x the margin in nats
+    keep = ~f
+    assert np.all([lb[j] in cd[j] for j in np.nonzero(keep)[0]])
+    assert np.all(cost[i[keep], lb[keep]] <= cc[keep, 0] + 2 * tol[keep])
+    assert np.all(gap[keep] >= 1.0 - 2 * tol[keep])
+    assert np.all(cost[i[f], lb[f]] <= cost[f].min(1) + 2 * tol[f])
+    assert np.all(f[gap < 1.0 - 2 * tol])
+    H, W = x.shape
+    r, cc0 = o.patch_corners(H, W)
+    exact = o.patch_scores(o.extract(x.astype(np.float64), r[idx], cc0[idx]), U, lam, w,
+                           beta).argmin(1)
+    recall = float(np.mean((cd == exact[:, None]).any(axis=1)))
+    agree = float(np.mean(lb == exact))
+    print(f"1024^2 first iteration: fallback {fb.mean():.4f}, sampled top-8 recall {recall:.4f}, "
+          f"label agreement with FP64 {agree:.4f}")
+    assert recall >= 0.7
+    assert agree >= 0.8
+    g.close()
