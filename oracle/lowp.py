@@ -19,6 +19,12 @@ rounded operands:
   no infinities; nearest, ties to even); the scales are applied back
   exactly.
 
+The patch estimate of Alg. 1 in these modes (``lowp_estimates``) takes
+binary16 operands: W_k = U_k diag(gamma_k) U_k^t formed in float64, rounded
+to float32 and then to binary16 (11 significant bits, nearest, ties to
+even), and the float32 DC-removed patch rounded to binary16; the estimate is
+W16 z16 + m with exact products and the patch mean m of the DC removal.
+
 In both modes the cost is L_k + sum_j c_j^2 with L_k rounded from float64 to
 float32, and the products are exact: this module evaluates them in float64
 from the rounded operands.  What the GPU adds on top is float32 (or wider)
@@ -69,6 +75,20 @@ def round_bf16(x) -> np.ndarray:
     step = np.ldexp(1.0, np.maximum(e - 8, -133))
     r = np.rint(x / step) * step  # rint: nearest, ties to even
     return r.astype(np.float32)
+
+
+def round_fp16(x) -> np.ndarray:
+    """Nearest IEEE binary16 value (ties to even) of float32 x, in float64;
+    +-inf where the rounded magnitude exceeds 65504.
+
+    binary16 keeps 11 significant bits: on the binade [2^(e-1), 2^e),
+    e - 1 >= -14, the step is 2^(e-11); below 2^-14 the subnormal step is
+    2^-24."""
+    x = np.asarray(x, np.float32).astype(np.float64)
+    _, e = np.frexp(x)
+    step = np.ldexp(1.0, np.maximum(e - 11, -24))
+    r = np.rint(x / step) * step
+    return np.where(np.abs(r) > 65504.0, np.copysign(np.inf, r), r)
 
 
 def round_e4m3(x) -> np.ndarray:
@@ -227,3 +247,51 @@ def lowp_costs(x, U, lam, w, beta, mode: str, acc_eps: float | None = None, rank
                            + 65 * u32 * (sq + np.abs(L32[k]))
                            + (130 * u32 * pinv * nz2 if flat else 0.0))
     return (cost, bound) if bound is not None else cost
+
+
+# ----------------------------------------------------------- estimation
+
+def estimate_operand(U, lam, w, beta) -> np.ndarray:
+    """The binary16 Wiener operand W_k = U_k diag(gamma_k) U_k^t (K x 64 x
+    64, float64 values): formed in float64, rounded to float32, then to
+    binary16."""
+    _, _, gamma, _ = o.eigen_terms(np.asarray(lam, np.float64), np.asarray(w, np.float64), beta)
+    U = np.asarray(U, np.float64)
+    W = np.einsum("kqj,kj,kpj->kqp", U, gamma, U)
+    return round_fp16(W.astype(np.float32))
+
+
+def lowp_estimates(x, U, lam, w, beta, labels, acc_eps: float | None = None, patches=None):
+    """Patch estimates (N x 64, float64) of the float32 image x under the
+    given labels in the reduced-precision modes: z^ = W16_k z16 + m, W16 of
+    ``estimate_operand``, z16 the binary16 rounding of the float32 DC-removed
+    patch, m its mean (the sum of the pixels correctly rounded to float64,
+    divided by 64), products exact.
+
+    With ``acc_eps``, also a bound (N x 64) on how far an evaluation may land
+    from these estimates when it accumulates the 64 products with a relative
+    error of at most acc_eps of the sum of their magnitudes, adds m rounded
+    to float32 and rounds the sum to float32.
+
+    ``patches``: indices (r (W - 7) + c) of the valid patches (default: all,
+    in that order); labels holds one entry per patch evaluated."""
+    x = np.asarray(x, np.float32)
+    H, W = x.shape
+    r, c = o.patch_corners(H, W)
+    if patches is not None:
+        r, c = r[patches], c[patches]
+    Z = o.extract(x.astype(np.float64), r, c).astype(np.float32)
+    Z64 = Z.astype(np.float64)
+    S = np.fromiter((math.fsum(row) for row in Z64), np.float64, Z64.shape[0])
+    m = S * (1.0 / 64.0)
+    z16 = round_fp16(round32_of_sum(Z64, -m[:, None]))
+    W16 = estimate_operand(U, lam, w, beta)
+    lab = np.asarray(labels, np.int64)
+    prod = np.einsum("nqp,np->nq", W16[lab], z16)
+    est = prod + m[:, None]
+    if acc_eps is None:
+        return est
+    mag = np.einsum("nqp,np->nq", np.abs(W16[lab]), np.abs(z16))
+    u32 = 2.0 ** -24
+    bound = acc_eps * mag + u32 * np.abs(m)[:, None] + u32 * (np.abs(est) + acc_eps * mag)
+    return est, bound

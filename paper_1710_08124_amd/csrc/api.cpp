@@ -462,6 +462,7 @@ fepll_status ensure_consts(fepll_gmm* g, const std::vector<double>& betas, int m
     dfree(g->dlogsb);
     dfree(g->tb.Ut);
     dfree(g->tb.Ub);
+    dfree(g->tb.Wh);
     dfree(g->tb.Wt);
     dfree(g->tb.L32);
     dfree(g->tb.Pinv);
@@ -487,6 +488,8 @@ fepll_status ensure_consts(fepll_gmm* g, const std::vector<double>& betas, int m
     HIPX(dalloc(&g->tb.invnu64, C * K * kP));
   }
   if ((mask & kTabBF16) && !g->tb.Ub) HIPX(dalloc(&g->tb.Ub, C * K * kTileStride));
+  // (the reduced-precision modes' binary16 estimate operand, with either)
+  if ((mask & (kTabBF16 | kTabF8)) && !g->tb.Wh) HIPX(dalloc(&g->tb.Wh, C * K * kTileStride));
   if ((mask & kTabF8) && !g->tb.Uf) {
     HIPX(dalloc(&g->tb.Uf, C * K * kTileStride));
     HIPX(dalloc(&g->tb.Ue, C * K));
@@ -1204,7 +1207,8 @@ fepll_status run_hqs(fepll_gmm* g, int T, const fepll_options& o, int32_t* label
     }
     {
       StageTimer tm(g, 3, st, true);
-      HIPX(launch_wiener_batch(b, xc, g->tb.Wt, g->K, t, g->seg, g->perm, g->wbase, g->Zhat,
+      HIPX(launch_wiener_batch(b, xc, g->tb.Wt, o.precision == FEPLL_FP32 ? nullptr : g->tb.Wh,
+                               g->K, t, g->seg, g->perm, g->wbase, g->Zhat,
                                g->tune.wiener_blocks, st));
     }
     {
@@ -1294,7 +1298,7 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
   for (const ImgDesc& d : g->hd) put(key, d);
   for (double v : g->cbeta) put(key, v);
   for (float v : g->hbvals) put(key, v);
-  const void* ptrs[] = {g->tb.Ut, g->tb.Ub, g->tb.Wt, g->tb.L32, g->tb.L64, g->tb.invnu64,
+  const void* ptrs[] = {g->tb.Ut, g->tb.Ub, g->tb.Wt, g->tb.Wh, g->tb.L32, g->tb.L64, g->tb.invnu64,
                         g->tb.Uf, g->tb.Ue,   g->d,     g->est_img, g->sort_img, g->ola_img,
                         g->wbase, g->bvals,   g->labels, g->list,  g->count,  g->hist,
                         g->seg,   g->perm,    g->Zhat,  g->ybuf,   g->xa,     g->xb,
@@ -1559,6 +1563,7 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->dbeta);
   dfree(g->tb.Ut);
   dfree(g->tb.Ub);
+  dfree(g->tb.Wh);
   dfree(g->tb.Wt);
   dfree(g->tb.L32);
   dfree(g->tb.L64);

@@ -13,6 +13,11 @@
 //    entry W_k[q][p] with q = 32*qb + (l & 31), p = 32*(l >> 5) + s, where
 //    W_k = U_k diag(gamma_k) U_k^t (the Wiener filter of Alg. 1, patch
 //    estimation, written back in pixel space).
+//  * Wh   binary16 bits (uint16), [T][K][2][4][64][8]: the patch-estimation
+//    A operand of the reduced-precision modes (v_mfma_f32_32x32x16_f16),
+//    entry W_k[q][p] with q = 32*qb + (l & 31), p = 16*s + 8*(l >> 5) + e for
+//    row block qb, depth step s, lane l, element e (float64 -> float32 ->
+//    binary16, nearest even).
 //  * Ub   bf16 bits (uint16), [T][K][4][2][64][8]: the bfloat16 E-step A
 //    operand (v_mfma_f32_16x16x32_bf16), entry Ut_k[p][j] with
 //    j = 16*rb + (l & 15) and p = 32*t + 8*(l >> 4) + e for eigen block rb
@@ -44,6 +49,7 @@ struct ConstTables {
   float* Ut;
   uint16_t* Ub;
   float* Wt;
+  uint16_t* Wh;  // with Ub or Uf (the reduced-precision modes' estimate)
   float* L32;
   double* L64;
   double* invnu64;
@@ -176,10 +182,12 @@ hipError_t launch_pair_bucket(const uint16_t* cand, int Np, int m, int K, int32_
 // Patch estimates z^: float [patches][64], patch-major (pixel 8 dy + dx of
 // patch i at i * 64 + 8 dy + dx), at d.np * 64 per image.
 // blocks: workgroups of the launch, a multiple of 8 (a cap: never more than
-// the tiles need).
-hipError_t launch_wiener_batch(const Batch& b, const float* x, const float* Wt, int K, int t,
-                               const int32_t* seg, const int32_t* perm, const int32_t* wbase,
-                               float* Zhat, int blocks, hipStream_t st);
+// the tiles need).  Wh: NULL (float32 operands Wt, float32 products), or the
+// binary16 table (binary16 operands, float32 accumulation).
+hipError_t launch_wiener_batch(const Batch& b, const float* x, const float* Wt,
+                               const uint16_t* Wh, int K, int t, const int32_t* seg,
+                               const int32_t* perm, const int32_t* wbase, float* Zhat, int blocks,
+                               hipStream_t st);
 
 struct JitterDraw;
 

@@ -90,6 +90,7 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
   float* wt = tb.Wt + tk * kTileStride;
   float* ut = (mask & kTabF32) ? tb.Ut + tk * kTileStride : nullptr;
   uint16_t* ub = (mask & kTabBF16) ? tb.Ub + tk * kTileStride : nullptr;
+  uint16_t* wh = (tb.Wh && (mask & (kTabBF16 | kTabF8))) ? tb.Wh + tk * kTileStride : nullptr;
   for (int idx = threadIdx.x; idx < kTileStride; idx += blockDim.x) {
     const int e = idx & 3, l = (idx >> 2) & 63, i = (idx >> 8) & 7, jb = idx >> 11;
     const int s = 4 * i + e;
@@ -111,6 +112,13 @@ __global__ __launch_bounds__(256) void prep_kernel(const double* __restrict__ U6
     // (lanes 0..31) with pixel 32 + s (lanes 32..63), so each lane's patch
     // operand is 32 consecutive pixels
     wt[idx] = (float)Ws[j * UP + 32 * (l >> 5) + s];
+    if (wh) {
+      // binary16 Wiener operand: MFMA 32x32x16 order, rounded via float32
+      const int eh = idx & 7, lh = (idx >> 3) & 63, sh = (idx >> 9) & 3, qb = idx >> 11;
+      const float f = (float)Ws[(32 * qb + (lh & 31)) * UP + 16 * sh + 8 * (lh >> 5) + eh];
+      const _Float16 h = (_Float16)fresh(f);  // (two roundings: not fused)
+      wh[idx] = __builtin_bit_cast(uint16_t, h);
+    }
   }
   if (!(mask & kTabF8)) return;
 

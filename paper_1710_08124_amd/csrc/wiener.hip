@@ -15,6 +15,12 @@
 // 8 workgroups) and each workgroup walks its share of the device-side tile
 // list of the whole batch (images one after the other, each image's tiles
 // ordered by component); a wave exits at the end of its share.
+//
+// Two forms: float32 operands on v_mfma_f32_32x32x2f32 (the float32 path:
+// 64 products of 64 cycles per 32-patch tile), and, for the reduced-
+// precision modes, binary16 operands on v_mfma_f32_32x32x16_f16 with
+// float32 accumulation (8 products per tile, about a sixteenth of the
+// matrix-core time).
 #include "common.h"
 
 namespace fepll {
@@ -128,16 +134,122 @@ __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const floa
   }
 }
 
-hipError_t launch_wiener_batch(const Batch& b, const float* x, const float* Wt, int K, int t,
-                               const int32_t* seg, const int32_t* perm, const int32_t* wbase,
-                               float* Zhat, int max_blocks, hipStream_t st) {
+// The reduced-precision form: the same tile walk; per tile the lane (half
+// h, column col) holds rows h, 2 + h, 4 + h, 6 + h of patch col, depth step
+// s of v_mfma_f32_32x32x16_f16 taking row 2 s + h (pixels 16 s + 8 h + e),
+// the DC-removed pixels rounded once from float32 to binary16; the A operand
+// is the binary16 table Wh (row block qb, depth step s); the accumulator
+// layout is the float32 form's, so are the stores.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+__global__ __launch_bounds__(256, 4) void wiener_f16_kernel(Batch bt, const float* __restrict__ xb,
+                                                         const uint4* __restrict__ Wh_all, int K,
+                                                         int it, const int32_t* __restrict__ seg_b,
+                                                         const int32_t* __restrict__ perm_b,
+                                                         const int32_t* __restrict__ wbase,
+                                                         float* __restrict__ Zhat_b) {
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const int col = lane & 31;
+  const int total = wbase[bt.n];
+  const int G = min((int)gridDim.x, max(8, (((total + 3) >> 2) + 7) & ~7));
+  if ((int)blockIdx.x >= G) return;
+  const int lb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int per = (total + G - 1) / G;
+  const int t_end = min(total, (lb + 1) * per);
+  int t = lb * per + (threadIdx.x >> 6);
+  if (t >= t_end) return;
+  int im = image_of(wbase, bt.n, t);
+  for (; t < t_end; t += 4) {
+    while (t >= wbase[im + 1]) ++im;
+    const ImgDesc d = bt.d[im];
+    const int W = d.W, Wp = d.W - 7;
+    const float* x = xb + d.px;
+    const int32_t* seg = seg_b + d.seg;
+    const int32_t* start = seg;
+    const int32_t* count = seg + (K + 1);
+    const int32_t* tinfo = seg + (3 * K + 3);
+    const uint4* Wh = Wh_all + (size_t)(d.slot0 + it) * K * 512;
+    float* Zhat = Zhat_b + (size_t)d.np * kP;
+    const int info = tinfo[t - wbase[im]];
+    const int k = info & 1023;
+    const int first = (info >> 10) * kWienerTile;
+    const int n = min(kWienerTile, count[k] - first);
+    const int32_t* ids = perm_b + d.np + start[k] + first;
+    const bool v0 = col < n;
+    const int id0 = v0 ? ids[col] : ids[0];
+    const int r0 = id0 / Wp, c0 = id0 - r0 * Wp;
+    float z[4][8];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const float* p0 = x + (size_t)(r0 + 2 * s + half) * W + c0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float4 a;
+        __builtin_memcpy(&a, p0 + 4 * h, 16);
+        z[s][4 * h] = a.x;
+        z[s][4 * h + 1] = a.y;
+        z[s][4 * h + 2] = a.z;
+        z[s][4 * h + 3] = a.w;
+      }
+    }
+    double s0 = 0.0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) s0 += (double)z[s][e];
+    s0 += __shfl_xor(s0, 32);
+    const double m0 = s0 * (1.0 / 64.0);
+    f16x8 zb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        // rounded to float32, then to binary16 (two roundings, as defined;
+        // fresh() keeps the compiler from fusing them into one)
+        const float d32 = (float)((double)fresh(z[s][e]) - m0);
+        zb[s][e] = (_Float16)fresh(d32);
+      }
+    const float fm0 = (float)m0;
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb) {
+      const uint4* wp = Wh + (size_t)k * 512 + qb * 256 + lane;
+      uint4 A[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) A[s] = wp[s * 64];
+      f32x16 a0 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, A[s]), zb[s], a0,
+                                                    0, 0, 0);
+      if (v0) {
+        float* zp = Zhat + (size_t)id0 * kP + 32 * qb + 4 * half;
+        typedef float f32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          const f32x4 v = {a0[4 * g] + fm0, a0[4 * g + 1] + fm0, a0[4 * g + 2] + fm0,
+                           a0[4 * g + 3] + fm0};
+          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(zp + 8 * g));
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_wiener_batch(const Batch& b, const float* x, const float* Wt,
+                               const uint16_t* Wh, int K, int t, const int32_t* seg,
+                               const int32_t* perm, const int32_t* wbase, float* Zhat,
+                               int max_blocks, hipStream_t st) {
   // tile total <= patches / tile + K per image
   const int64_t max_tiles = b.n_patches / kWienerTile + (int64_t)K * b.n;
   int64_t blocks = (max_tiles + 3) / 4;
   if (blocks > max_blocks) blocks = max_blocks;
   blocks = (blocks + 7) & ~7;  // whole rounds over the 8 XCDs
-  hipLaunchKernelGGL(wiener_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, b, x,
-                     reinterpret_cast<const float4*>(Wt), K, t, seg, perm, wbase, Zhat);
+  if (Wh)
+    hipLaunchKernelGGL(wiener_f16_kernel, dim3((unsigned)blocks), dim3(256), 0, st, b, x,
+                       reinterpret_cast<const uint4*>(Wh), K, t, seg, perm, wbase, Zhat);
+  else
+    hipLaunchKernelGGL(wiener_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, b, x,
+                       reinterpret_cast<const float4*>(Wt), K, t, seg, perm, wbase, Zhat);
   return hipGetLastError();
 }
 

@@ -290,11 +290,14 @@ def test_bad_jitter_options(F):
 def test_list_iteration_sampled_pixels(F, shape, mode):
     """One iteration of a reduced-precision list path at full size (K = 200,
     sigma 25, s = 6), through the sort, the patch estimation and the
-    reprojection: at 600 sampled pixels the image equals the FP64 update
-    (Alg. 1: each covering chosen patch's Wiener estimate under the label
-    the GPU chose, their average, the image update).  The 1024^2 list (29
-    chunks of 1024 entries) sorts with the tables inside its scatter; the
-    4096 x 1024 one (116 chunks) with a launch of its own for the tables."""
+    reprojection: at 600 sampled pixels the image equals the update of
+    Alg. 1 with each covering chosen patch's estimate under the label the
+    GPU chose -- the reduced-precision modes' binary16 estimate of
+    oracle/lowp.py, within its float32 accumulation bound -- their average
+    and the image update, within 1e-4 more.  The 1024^2 list (29 chunks of
+    1024 entries) sorts with the tables inside its scatter; the 4096 x 1024
+    one (116 chunks) with a launch of its own for the tables."""
+    from oracle import lowp
     H, W = shape
     c = fs.config_c2(25.0)
     U, lam, w = c["U"], c["lam"], c["w"]
@@ -312,24 +315,32 @@ def test_list_iteration_sampled_pixels(F, shape, mode):
     Wp = W - 7
     chosen = np.zeros((H - 7) * Wp, bool)
     chosen[idx] = True
-    _, _, gamma, _ = o.eigen_terms(lam, w, beta)
     R = fs.rng(43)
     py, px = R.integers(0, H, 600), R.integers(0, W, 600)
-    worst = 0.0
+    cover = []
     for yy, xx in zip(py, px):
         rr, cc = np.meshgrid(np.arange(max(yy - 7, 0), min(yy, H - 8) + 1),
                              np.arange(max(xx - 7, 0), min(xx, W - 8) + 1), indexing="ij")
         rr, cc = rr.ravel(), cc.ravel()
         on = chosen[rr * Wp + cc]
-        rr, cc = rr[on], cc[on]
-        assert rr.size > 0  # every pixel covered
-        Zt, m = o.remove_dc(o.extract(y32, rr, cc))
-        Zh = o.patch_estimate(Zt, m, lab[rr * Wp + cc], U, gamma)
-        xt = np.mean(Zh[np.arange(rr.size), 8 * (yy - rr) + (xx - cc)])
+        assert np.any(on)  # every pixel covered
+        cover.append((rr[on], cc[on]))
+    need = np.unique(np.concatenate([r * Wp + c for r, c in cover]))
+    est, bnd = lowp.lowp_estimates(y32.astype(np.float32), U, lam, w, beta, lab[need],
+                                   acc_eps=64 * 2.0 ** -24, patches=need)
+    row = {int(p): i for i, p in enumerate(need)}
+    b = beta * 25.0 ** 2
+    worst = 0.0
+    for (yy, xx), (rr, cc) in zip(zip(py, px), cover):
+        i = np.array([row[int(p)] for p in rr * Wp + cc])
+        off = 8 * (yy - rr) + (xx - cc)
+        xt = np.mean(est[i, off])
+        tol = TOL + b / (1.0 + b) * np.mean(bnd[i, off])
         want = o.image_update(y32[yy, xx], xt, beta, 25.0)
-        worst = max(worst, abs(got[yy, xx] - want))
-    print(f"{mode} {H}x{W} list iteration: {idx.size} chosen, worst sampled pixel error {worst:.2e}")
-    assert worst <= TOL
+        worst = max(worst, abs(got[yy, xx] - want) / tol)
+    print(f"{mode} {H}x{W} list iteration: {idx.size} chosen, worst sampled pixel error / "
+          f"tolerance {worst:.3f}")
+    assert worst <= 1.0
 
 
 def test_state_between_calls(F):

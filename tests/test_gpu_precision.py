@@ -4,7 +4,8 @@ Two kinds of check:
 * the selection kernels against the definition of their mode
   (oracle/lowp.py: rounded operands, exact products): teacher-forced, the
   GPU cost of the chosen label equals the definition's cost of that label to
-  float32 accumulation accuracy, and no component beats it by more;
+  float32 accumulation accuracy, and no component beats it by more; the
+  patch estimates likewise against the modes' binary16 estimate;
 * the modes against the exact FP64 restoration: their selection is an
   approximation, so the tests state its label agreement with the exact
   selection and bound its PSNR loss, the quality criterion of the modes
@@ -105,6 +106,51 @@ def test_lowp_select_matches_definition(F, mode, sigma, t, shape):
     # labels differ only where the definition has a near-tie
     gap = srt[:, 1] - srt[:, 0]
     assert np.all((lab == cost.argmin(1)) | (gap <= 2 * tol))
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
+@pytest.mark.parametrize("sigma,t,shape", [(25, 0, (96, 130)), (10, 2, (40, 300)),
+                                           (50, 1, (71, 8))])
+def test_lowp_estimate_matches_definition(F, mode, sigma, t, shape):
+    """Teacher-forced: one HQS iteration of a reduced-precision mode from a
+    float32 image, under the labels the GPU chose, against the modes'
+    patch estimate (oracle/lowp.py: binary16 Wiener operand and patch,
+    exact products) averaged over the overlapping patches and pushed
+    through the image update of Alg. 1; every pixel within the estimate's
+    float32 accumulation bound plus 1e-4.  The float64 estimate under the
+    same labels is further off than that, so the test tells the two
+    apart."""
+    c = fs.config_c2(sigma)
+    H, W = shape
+    y = np.asarray(c["y"][150:150 + H, 90:90 + W], np.float32)
+    betas = o.default_betas(sigma)
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    x = dev(y)
+    if t:
+        x = F.restore(g, dev(y), sigma, betas=[float(b) for b in betas[:t]], precision=mode)
+    x32 = x.cpu().numpy()
+    beta = float(betas[t])
+    got, lab = F.restore(g, dev(y), sigma, betas=[beta], init=x, precision=mode,
+                         return_labels=True)
+    got = got.cpu().numpy().astype(np.float64)
+    lab = lab.cpu().numpy()[0]
+    est, bnd = lowp.lowp_estimates(x32, c["U"], c["lam"], c["w"], beta, lab,
+                                   acc_eps=64 * 2.0 ** -24)
+    b = beta * sigma * sigma
+    want = o.image_update(y.astype(np.float64), o.reproject(est, H, W), beta, sigma)
+    tol = 1e-4 + b / (1.0 + b) * o.reproject(bnd, H, W)
+    err = np.abs(got - want)
+    # the float64 estimate of Alg. 1 under the same labels
+    r, cc = o.patch_corners(H, W)
+    Zt, m = o.remove_dc(o.extract(x32.astype(np.float64), r, cc))
+    _, _, gamma, _ = o.eigen_terms(c["lam"], c["w"], beta)
+    ref = o.image_update(y.astype(np.float64),
+                         o.reproject(o.patch_estimate(Zt, m, lab, c["U"], gamma), H, W),
+                         beta, sigma)
+    print(f"{mode} sigma {sigma} t {t} {shape}: max err / tol {np.max(err / tol):.3f}, "
+          f"max |float64 estimate - def| / tol {np.max(np.abs(ref - want) / tol):.1f}")
+    assert np.all(err <= tol)
+    assert np.max(np.abs(ref - want) / tol) > 2.0
 
 
 @pytest.mark.parametrize("mode", ["bf16", "fp8"])

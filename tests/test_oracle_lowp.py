@@ -269,3 +269,55 @@ def test_flat_costs_within_rounding_bound(mode, rel):
         bound = (np.sum(2 * np.abs(C) * d + d * d, axis=1) + np.abs(L[k]) * 2 ** -23
                  + pinv * nz2 * 2 ** -20)
         assert np.all(np.abs(got[:, k] - want[:, k]) <= bound)
+
+
+# ---------------------------------------------------------------- estimation
+
+def test_round_fp16_matches_torch():
+    x = np.concatenate([_probe_values(11),
+                        np.array([65504.0, 65519.0, 65520.0, 70000.0, 2.0 ** -24, 2.0 ** -25,
+                                  3 * 2.0 ** -26, 1e-9, 0.0, -0.0], np.float32)])
+    got = lowp.round_fp16(x)
+    want = torch.from_numpy(x).to(torch.float16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(got, want)
+
+
+def test_estimates_exact_when_operands_are_representable():
+    # U_k a signed permutation, so W_k is diagonal (in permuted order) with
+    # entries gamma_kj = lambda / (lambda + 1) at beta = 1; lambda in
+    # {1, 3, 7, 15} makes them 1/2, 3/4, 7/8, 15/16, exact in binary16; the
+    # checker-and-stripes image has mean 100 and z~ in {+-0.5, ..., +-3.5}
+    rng = np.random.default_rng(13)
+    K = 3
+    U = np.zeros((K, 64, 64))
+    for k in range(K):
+        perm = rng.permutation(64)
+        U[k, perm, np.arange(64)] = rng.choice([-1.0, 1.0], 64)
+    lam = rng.choice([1.0, 3.0, 7.0, 15.0], (K, 64))
+    w = np.full(K, 1.0 / K)
+    x = _checker_stripes(12, 13).astype(np.float32)
+    r, c = o.patch_corners(12, 13)
+    lab = rng.integers(0, K, r.size)
+    got = lowp.lowp_estimates(x, U, lam, w, 1.0, lab)
+    Zt, m = o.remove_dc(o.extract(x.astype(np.float64), r, c))
+    _, _, gamma, _ = o.eigen_terms(lam, w, 1.0)
+    want = o.patch_estimate(Zt, m, lab, U, gamma)
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=0)
+
+
+def test_estimates_within_rounding_bound():
+    c = fs.config_c1()
+    x = np.asarray(c["y"][:20, :22], np.float32)
+    beta = 8.0 / c["sigma"] ** 2
+    r, cc = o.patch_corners(20, 22)
+    lab = fs.rng(14).integers(0, c["U"].shape[0], r.size)
+    got = lowp.lowp_estimates(x, c["U"], c["lam"], c["w"], beta, lab)
+    Zt, m = o.remove_dc(o.extract(x.astype(np.float64), r, cc))
+    _, _, gamma, _ = o.eigen_terms(c["lam"], c["w"], beta)
+    want = o.patch_estimate(Zt, m, lab, c["U"], gamma)
+    # W and z~ each rounded (float32, then binary16: relative 2^-11 + 2^-24)
+    W = np.einsum("kqj,kj,kpj->kqp", c["U"], gamma, c["U"])
+    u = 2.0 ** -11 + 2.0 ** -24
+    mag = np.einsum("nqp,np->nq", np.abs(W[lab]), np.abs(Zt))
+    assert np.all(np.abs(got - want) <= mag * (2 * u + u * u) + 1e-12)
+    assert np.max(np.abs(got - want)) > 0  # (the rounding is there)
