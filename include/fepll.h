@@ -308,6 +308,29 @@ fepll_status fepll_select(fepll_gmm* g, const fepll_image* x, double beta,
                           const fepll_options* opt);
 
 /*
+ * fepll_select in float32 (options: FEPLL_FP32, recheck on, the other
+ * defaults), allocating no device memory: for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * it).  Same labels, costs and flags as fepll_select, bit for bit.
+ * x: a device image, contiguous (row_stride 0 or width), on the handle's
+ * device, which must be current.  labels / best / second / flags: device
+ * buffers of Np = (H - 7)(W - 7) entries as in fepll_select (best, second,
+ * flags optional).  Asynchronous on stream (NULL: the default stream).
+ * Scratch: one 32 MiB device array per GPU inside the library, held until
+ * the process ends; a call takes the per-beta tables, 33 300 bytes per
+ * component (6.7 MB at K = 200), and 16 bytes per patch for the list of
+ * uncertified patches (16.5 MB at 1024 x 1024), each region rounded up to
+ * 256 bytes; a call that needs more returns EINVAL.  Every call on a GPU uses that
+ * GPU's one array: calls that overlap on one GPU (other streams or threads)
+ * race, the caller serialises them.
+ * Errors: EINVAL (NULL handle or buffers, host or strided image, size < 8,
+ * beta <= 0, not the handle's device, scratch exceeded), EDEVICE.
+ */
+fepll_status fepll_select_static(fepll_gmm* g, const fepll_image* x, double beta,
+                                 int32_t* labels, float* best, float* second, int32_t* flags,
+                                 void* stream);
+
+/*
  * Stage timing of the calls made with options.profile set since the last
  * read.  Stages: 0 selection (E-step; with the proposal: exact rescoring of
  * the candidates), 1 float64 re-selection, 2 bucketing, 3 patch

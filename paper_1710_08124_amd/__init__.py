@@ -109,6 +109,9 @@ def lib():
     L.fepll_select.argtypes = [c_void_p, POINTER(Image), c_double, c_void_p, c_void_p, c_void_p,
                                c_void_p, POINTER(Options)]
     L.fepll_select.restype = c_int32
+    L.fepll_select_static.argtypes = [c_void_p, POINTER(Image), c_double, c_void_p, c_void_p,
+                                      c_void_p, c_void_p, c_void_p]
+    L.fepll_select_static.restype = c_int32
     L.fepll_set_memory_limit.argtypes = [ctypes.c_size_t]
     L.fepll_set_memory_limit.restype = c_int32
     L.fepll_memory_in_use.argtypes = []
@@ -436,6 +439,28 @@ def set_memory_limit(limit_bytes: int):
 def memory_in_use() -> int:
     """Bytes of device memory the library holds."""
     return int(lib().fepll_memory_in_use())
+
+
+def select_static(gmm: GMM, x, beta: float, out=None):
+    """fepll_select_static: the float32 selection of select() without device
+    allocation inside the library, on the contiguous CUDA image x.  out: a
+    tuple (labels, best, second, flags) of preallocated CUDA tensors of
+    (H-7)*(W-7) entries (int32, float32, float32, int32), or None (allocated
+    here by PyTorch).  Returns the four tensors."""
+    import torch
+    xi = _image(x)
+    Np = (x.shape[0] - 7) * (x.shape[1] - 7)
+    if out is None:
+        dev = x.device
+        out = (torch.empty(Np, dtype=torch.int32, device=dev),
+               torch.empty(Np, dtype=torch.float32, device=dev),
+               torch.empty(Np, dtype=torch.float32, device=dev),
+               torch.empty(Np, dtype=torch.int32, device=dev))
+    lab, best, second, flags = out
+    _check(lib().fepll_select_static(gmm.handle, ctypes.byref(xi), float(beta), lab.data_ptr(),
+                                     best.data_ptr(), second.data_ptr(), flags.data_ptr(),
+                                     _stream_of(x)))
+    return lab, best, second, flags
 
 
 def propose(gmm: GMM, x, beta: float, top_m: int = 8):

@@ -85,6 +85,8 @@ int main() {
   fepll_options o;
   fepll_options_default(&o);
   CHECK(fepll_restore(nullptr, &im, nullptr, 10.0, nullptr, 5, &im, &o, nullptr) == FEPLL_EINVAL);
+  CHECK(fepll_select_static(nullptr, &im, 1.0, nullptr, nullptr, nullptr, nullptr, nullptr) ==
+        FEPLL_EINVAL);
   CHECK(fepll_restore_batch(nullptr, 1, &im, nullptr, &im, &o) == FEPLL_EINVAL);
   CHECK(fepll_set_tuning(nullptr, nullptr) == FEPLL_EINVAL);
   CHECK(fepll_gmm_load_proposal(nullptr, nullptr, 0) == FEPLL_EINVAL);
