@@ -225,20 +225,31 @@ def batch_c5(n: int = 48, seed: int = 500, texture_std: float = 10.0, workers: i
 
 
 def training_images(seeds=range(300, 313), size: int = 256, sigma_seed: int = 600,
-                    stratified: bool = False):
-    """Clean/noisy pairs for the proposal network's training set;
-    sigma ~ U[5, 50] per image.  stratified: image i of n draws its sigma
-    uniformly from the i-th of n equal parts of [5, 50] (still uniform over
-    the whole range, but every part of it present)."""
+                    sigmas: str = "uniform"):
+    """Clean/noisy pairs for the proposal network's training set.
+
+    sigmas: how image i of n draws its noise level (one uniform draw u_i of
+    the sigma_seed stream per image, in order):
+    * "uniform": sigma ~ U[5, 50];
+    * "low": the first n // 2 images log-uniform over [4.5, 10], the others
+      over [10, 50], each half stratified (image j of m takes
+      a (b / a)^((j + u_i) / m) on its interval [a, b]).  The network's
+      recall is lowest where sigma is small (sharper posteriors), so half the
+      data sits there."""
     g = rng(sigma_seed)
     out = []
     seeds = list(seeds)
     n = len(seeds)
+    h = n // 2
     for i, s in enumerate(seeds):
-        if stratified:
-            sig = 5.0 + 45.0 * (i + float(g.uniform(0.0, 1.0))) / n
-        else:
+        u = float(g.uniform(0.0, 1.0)) if sigmas == "low" else None
+        if sigmas == "low":
+            a0, a1, j, m = (4.5, 10.0, i, h) if i < h else (10.0, 50.0, i - h, n - h)
+            sig = a0 * (a1 / a0) ** ((j + u) / m)
+        elif sigmas == "uniform":
             sig = float(g.uniform(5.0, 50.0))
+        else:
+            raise ValueError(f"unknown sigma schedule {sigmas!r}")
         x = test_image(size, size, s)
         out.append(dict(x=x, y=noisy(x, sig, s + 1000), sigma=sig))
     return out

@@ -160,6 +160,7 @@ struct fepll_gmm {
   bool has_proposal = false;
   uint16_t* cand = nullptr;   // 8 per patch, packed like the labels
   int32_t* fb_list = nullptr;  // fallback lists, packed like the labels
+  int32_t* fbpart = nullptr;   // split fallback search: the parts' results (3 kFallbackSplit NP)
   int32_t* fbcnt = nullptr;    // fallback list length per image
   int32_t* fbitems = nullptr;  // fallback items: first of each image, then the total
   // the search tree's descent: patches grouped by node (pair sort scratch)
@@ -232,6 +233,11 @@ namespace {
 constexpr int kStages = 9;
 constexpr int kDenseNodes = 16;  // tree levels of at most this many nodes are scored densely
 constexpr int kDefaultT = 5;
+// The full-K search of the proposal's fallback lists runs each item of 512
+// listed patches as this many workgroups over shares of K (merged after):
+// the lists hold a sixth of the patches or fewer, too few items to fill the
+// chip otherwise.
+constexpr int kFallbackSplit = 2;
 const double kDefaultB[kDefaultT] = {1.0, 4.0, 8.0, 16.0, 32.0};
 
 void default_tuning(fepll_tuning* t) {
@@ -639,6 +645,7 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     dfree(g->Zhat);
     dfree(g->cand);
     dfree(g->fb_list);
+    dfree(g->fbpart);
     dfree(g->jflags);
     dfree(g->jlist);
     g->np_cap = 0;
@@ -648,6 +655,7 @@ fepll_status make_plan(fepll_gmm* g, int n, const int* H, const int* W, int T,
     HIPX(dalloc(&g->Zhat, NP * kP));
     HIPX(dalloc(&g->cand, NP * 8));
     HIPX(dalloc(&g->fb_list, NP));
+    HIPX(dalloc(&g->fbpart, 3 * kFallbackSplit * NP));
     HIPX(dalloc(&g->jflags, 3 * NP));
     HIPX(dalloc(&g->jlist, 3 * NP));
     g->np_cap = NP;
@@ -1056,11 +1064,16 @@ fepll_status select_proposal(fepll_gmm* g, int t, const fepll_options& o, const 
     a.Pinv = g->tb.Pinv;
     a.item_pre = g->fbitems;
     a.n_img = b.n;
+    a.ksplit = kFallbackSplit;
+    a.part_out = g->fbpart;
+    a.part_stride = g->np_cap;
     // a fixed grid walking the items (at most every patch falls back)
     int64_t items = 0;
     for (const ImgDesc& d : g->hd) items += ((int64_t)(d.H - 7) * (d.W - 7) + 511) / 512;
-    a.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(items, 1024));
+    a.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(items * kFallbackSplit, 1024));
     HIPX(launch_estep_bf16_mode(kModeListBatch, a, st));
+    a.blocks = (int)std::max<int64_t>(1, std::min<int64_t>(items, 1024));
+    HIPX(launch_fallback_merge(a, st));
   }
   if (flags) {
     const int n = (int)b.n_patches;
@@ -1302,7 +1315,7 @@ fepll_status run_hqs_graph(fepll_gmm* g, int T, const fepll_options& o, float** 
                         g->tb.Uf, g->tb.Ue,   g->d,     g->est_img, g->sort_img, g->ola_img,
                         g->wbase, g->bvals,   g->labels, g->list,  g->count,  g->hist,
                         g->seg,   g->perm,    g->Zhat,  g->ybuf,   g->xa,     g->xb,
-                        g->pWb,   g->pbias,   g->cand,  g->fb_list,
+                        g->pWb,   g->pbias,   g->cand,  g->fb_list, g->fbpart,
                         g->fbcnt, g->resc_img, g->dlogsb, g->dbeta,
                         g->psorted, g->phist, g->pseg,
                         g->tb.rk,   g->tb.Pinv, g->zop,  g->znz,
@@ -1585,6 +1598,7 @@ void fepll_gmm_destroy(fepll_gmm* g) {
   dfree(g->Zhat);
   dfree(g->cand);
   dfree(g->fb_list);
+  dfree(g->fbpart);
   dfree(g->psorted);
   dfree(g->fbcnt);
   dfree(g->resc_img);

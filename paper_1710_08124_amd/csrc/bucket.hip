@@ -170,28 +170,80 @@ __global__ __launch_bounds__(1024) void seg_total_kernel(Batch b, int32_t* __res
   }
 }
 
+// The tile table.  For the pair sort (BATCH false) in component order.  For
+// the patch-estimation tiles of a batch (BATCH true) octile-major: tile j of
+// component k (n_k tiles, its patches in sort-block order, so in image
+// order up to a block) lies in octile x when floor(x n_k / 8) <= j <
+// floor((x + 1) n_k / 8), and an image's list holds octile 0 of every
+// component, then octile 1, and so on.  The patch-estimation launch hands
+// consecutive eighths of the list to the workgroups of one XCD each, so an
+// XCD gathers its patches from about one eighth of the image's rows, which
+// stay in its L2, instead of from the whole image.
 template <bool BATCH>
 __global__ __launch_bounds__(256) void seg_info_kernel(Batch b, int32_t* __restrict__ hist_a,
                                                        int32_t* __restrict__ seg_a, int nb_a,
                                                        int K) {
-  __shared__ int32_t tp[kMaxK + 1];
+  constexpr int kParts = BATCH ? 8 : 1;
+  __shared__ int32_t tp[kParts][kMaxK + 1];
+  __shared__ int32_t base[kParts + 1];
+  static_assert(kParts == 1 || kParts == 8, "two octiles per wave of 256 threads");
   const SegProblem p = seg_problem<BATCH>(b, hist_a, seg_a, nb_a, K);
   const int32_t* tpre = p.seg + (2 * K + 1);
   const int32_t total = p.seg[3 * K + 2];
   const int tl = blockIdx.x * 256 + threadIdx.x;
   if ((int)(blockIdx.x * 256) >= total) return;  // (workgroup-uniform)
-  for (int k = threadIdx.x; k <= K; k += 256) tp[k] = tpre[k];
+  if (kParts == 1) {
+    for (int k = threadIdx.x; k <= K; k += 256) tp[0][k] = tpre[k];
+    if (threadIdx.x == 0) base[0] = 0;
+  } else {
+    // per octile, the exclusive prefix over the components of its tiles:
+    // wave w scans octiles 2 w and 2 w + 1, 64 components per step
+    const int lane = threadIdx.x & 63;
+    for (int x = 2 * (threadIdx.x >> 6); x < 2 * (threadIdx.x >> 6) + 2; ++x) {
+      int32_t carry = 0;
+      for (int k0 = 0; k0 < K; k0 += 64) {
+        const int k = k0 + lane;
+        int32_t c = 0;
+        if (k < K) {
+          const int32_t n = tpre[k + 1] - tpre[k];
+          c = (((x + 1) * n) >> 3) - ((x * n) >> 3);
+        }
+        int32_t v = c;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int32_t u = __shfl_up(v, off);
+          if (lane >= off) v += u;
+        }
+        if (k < K) tp[x][k] = carry + v - c;
+        carry += __shfl(v, 63);
+      }
+      if (lane == 0) tp[x][K] = carry;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int32_t s = 0;
+      for (int x = 0; x < kParts; ++x) {
+        base[x] = s;
+        s += tp[x][K];
+      }
+      base[kParts] = s;
+    }
+  }
   __syncthreads();
   if (tl >= total) return;
-  int lo = 0, hi = K - 1;  // the last k with tp[k] <= tl
+  int x = 0;  // the last octile starting at or before tl
+  while (x + 1 < kParts && base[x + 1] <= tl) ++x;
+  const int r = tl - base[x];
+  int lo = 0, hi = K - 1;  // the last k with tp[x][k] <= r
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (tp[mid] <= tl)
+    if (tp[x][mid] <= r)
       lo = mid;
     else
       hi = mid - 1;
   }
-  p.seg[(3 * K + 3) + tl] = lo | ((tl - tp[lo]) << 10);
+  const int32_t first = kParts == 1 ? 0 : ((x * (tpre[lo + 1] - tpre[lo])) >> 3);
+  p.seg[(3 * K + 3) + tl] = lo | ((first + r - tp[x][lo]) << 10);
 }
 
 // A, B and C for `nprob` problems (BATCH: the images of b); max_tiles bounds

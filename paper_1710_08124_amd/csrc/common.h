@@ -9,14 +9,15 @@
 //    U_k[p][j] / sqrt(nu_kj) with p = 2*s + (l >> 5) and j = 32*jb + (l & 31).
 //    Scaling the eigenvectors by nu^-1/2 turns the Mahalanobis term
 //    sum_j c_j^2 / nu_kj of the selection cost into a plain sum of squares.
-//  * Wt   float,  [T][K][2][8][64][4]: the patch-estimation A operand,
-//    entry W_k[q][p] with q = 32*qb + (l & 31), p = 32*(l >> 5) + s, where
+//  * Wt   float,  [T][K][2][8][64][4]: the patch-estimation B operand
+//    (pixels of the estimate as columns), entry W_k[q][p] with
+//    q = 32*qb + (l & 31), p = 32*(l >> 5) + s, where
 //    W_k = U_k diag(gamma_k) U_k^t (the Wiener filter of Alg. 1, patch
 //    estimation, written back in pixel space).
 //  * Wh   binary16 bits (uint16), [T][K][2][4][64][8]: the patch-estimation
-//    A operand of the reduced-precision modes (v_mfma_f32_32x32x16_f16),
+//    B operand of the reduced-precision modes (v_mfma_f32_32x32x16_f16),
 //    entry W_k[q][p] with q = 32*qb + (l & 31), p = 16*s + 8*(l >> 5) + e for
-//    row block qb, depth step s, lane l, element e (float64 -> float32 ->
+//    column block qb, depth step s, lane l, element e (float64 -> float32 ->
 //    binary16, nearest even).
 //  * Ub   bf16 bits (uint16), [T][K][4][2][64][8]: the bfloat16 E-step A
 //    operand (v_mfma_f32_16x16x32_bf16), entry Ut_k[p][j] with

@@ -215,11 +215,13 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
   const int col = lane & 15;
 
   const int nlist = (MODE == kModeListFull) ? *a.list_count : 0;
-  const int nitems = (MODE == kModeListBatch) ? a.item_pre[a.n_img] : 0;
-  // work items: list mode, 512 consecutive list entries; spatial all-K
-  // mode, one selection tile (4 patch rows x 128 columns) of any image of
-  // the batch.  The loop is workgroup-uniform: every wave reaches every
-  // barrier of the K loop.
+  // batched list mode: S workgroups per item, each over a share of K
+  const int S = (MODE == kModeListBatch) ? max(1, a.ksplit) : 1;
+  const int nitems = (MODE == kModeListBatch) ? a.item_pre[a.n_img] * S : 0;
+  // work items: list mode, 512 consecutive list entries (batched: times
+  // the component parts); spatial all-K mode, one selection tile (4 patch
+  // rows x 128 columns) of any image of the batch.  The loop is
+  // workgroup-uniform: every wave reaches every barrier of the K loop.
   int item = blockIdx.y * gridDim.x + blockIdx.x;
   const int nwg = gridDim.x * gridDim.y;
   for (;; item += nwg) {
@@ -236,13 +238,19 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
     // list modes: the list, its length and this item's first entry
     const int32_t* list = a.list;
     int nl = nlist, lbase = item * 512;
+    // the components this item searches, and where a split part's results go
+    int kb_l = 0, ke_l = 0;
+    int32_t* pout = nullptr;
     if (MODE == kModeListBatch) {
       if (item >= nitems) break;
-      // the image of this item: the last one whose first item is <= item
+      const int li = item / S, part = item - li * S;
+      kb_l = part * a.K / S;
+      ke_l = (part + 1) * a.K / S;
+      // the image of this item: the last one whose first item is <= li
       int lo = 0, hi = a.n_img - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (a.item_pre[mid] <= item)
+        if (a.item_pre[mid] <= li)
           lo = mid;
         else
           hi = mid - 1;
@@ -260,7 +268,8 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       if (secondp) secondp += d.np;
       list += d.np;
       nl = a.list_count[lo];
-      lbase = (item - a.item_pre[lo]) * 512;
+      lbase = (li - a.item_pre[lo]) * 512;
+      if (S > 1) pout = a.part_out + (size_t)part * a.part_stride + d.np;
     }
     if (MODE == kModeSpatialFull) {
       if (item >= a.n_est) break;
@@ -344,19 +353,23 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       // directions)
       const uint4* gsrc = reinterpret_cast<const uint4*>(Ub);
       const int tid = threadIdx.x;
+      const int kb = (MODE == kModeListBatch) ? kb_l : 0;
+      const int ke = (MODE == kModeListBatch) ? ke_l : a.K;
       int rn = kP, nu4 = 512;
       uint4 pre0, pre1;
+      // (kb < K whenever the range is not empty; an empty one prefetches
+      // component kb < K all the same and searches nothing)
       if (FLAT) {
-        rn = a.rk[0];
+        rn = a.rk[kb];
         nu4 = 128 * ((rn + 15) >> 4);
         pre0 = pre1 = make_uint4(0, 0, 0, 0);
-        if (tid < nu4) pre0 = gsrc[tid];
-        if (256 + tid < nu4) pre1 = gsrc[256 + tid];
+        if (tid < nu4) pre0 = gsrc[(size_t)kb * 512 + tid];
+        if (256 + tid < nu4) pre1 = gsrc[(size_t)kb * 512 + 256 + tid];
       } else {
-        pre0 = gsrc[tid];
-        pre1 = gsrc[256 + tid];
+        pre0 = gsrc[(size_t)kb * 512 + tid];
+        pre1 = gsrc[(size_t)kb * 512 + 256 + tid];
       }
-      for (int k = 0; k < a.K; ++k) {
+      for (int k = kb; k < ke; ++k) {
         uint4* As = Ash[k & 1];
         const int rk = rn;
         if (FLAT) {
@@ -367,7 +380,7 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
           As[256 + tid] = pre1;
         }
         __syncthreads();
-        if (k + 1 < a.K) {
+        if (k + 1 < ke) {
           if (FLAT) {
             rn = a.rk[k + 1];
             nu4 = 128 * ((rn + 15) >> 4);
@@ -385,13 +398,20 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       }
       __syncthreads();  // the staging buffers are reused by the next pass
     }
-    // ---- outputs
+    // ---- outputs (a split part's to its slots, for the merge)
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const bool v = p ? vB : vA;
       if (!v) continue;
       const int i = p ? iB : iA;
       const float b = p ? bB : bA, s = p ? sB : sA;
+      if (MODE == kModeListBatch && pout) {
+        const size_t ps = (size_t)S * a.part_stride;
+        pout[i] = p ? kB : kA;
+        pout[ps + i] = __float_as_int(b);
+        pout[2 * ps + i] = __float_as_int(s);
+        continue;
+      }
       labels[i] = p ? kB : kA;
       if (bestp) bestp[i] = b;
       if (secondp) secondp[i] = s;
@@ -923,6 +943,59 @@ hipError_t launch_tree_level_bf16(const int32_t* cur, int Np, const uint16_t* zo
   return hipGetLastError();
 }
 
+
+// The parts of a split list search, merged in component order: part p + 1
+// holds higher components than part p, so over the parts in order the best
+// is the first strict improvement (ties stay with the lower component) and
+// the second is the second smallest of all the costs, exactly as one
+// keep_best pass over all K would leave them.
+__global__ __launch_bounds__(256) void fallback_merge_kernel(BF16Args a) {
+  const int nitems = a.item_pre[a.n_img];
+  const int S = a.ksplit;
+  const size_t ps = (size_t)S * a.part_stride;
+  for (int li = blockIdx.x; li < nitems; li += gridDim.x) {
+    int lo = 0, hi = a.n_img - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (a.item_pre[mid] <= li)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const ImgDesc d = a.d[lo];
+    const int nl = a.list_count[lo];
+    const int lbase = (li - a.item_pre[lo]) * 512;
+    for (int j = threadIdx.x; j < 512; j += 256) {
+      const int e = lbase + j;
+      if (e >= nl) continue;
+      const int i = a.list[d.np + e];
+      const int32_t* q = a.part_out + d.np + i;
+      int k = q[0];
+      float b = __int_as_float(q[ps]), s = __int_as_float(q[2 * ps]);
+      for (int p = 1; p < S; ++p) {
+        const int kp = q[p * a.part_stride];
+        const float bp = __int_as_float(q[ps + p * a.part_stride]);
+        const float sp = __int_as_float(q[2 * ps + p * a.part_stride]);
+        if (bp < b) {
+          s = fminf(b, sp);
+          b = bp;
+          k = kp;
+        } else {
+          s = fminf(s, bp);
+        }
+      }
+      a.labels[d.np + i] = k;
+      if (a.best) a.best[d.np + i] = b;
+      if (a.second) a.second[d.np + i] = s;
+    }
+  }
+}
+
+hipError_t launch_fallback_merge(const BF16Args& args, hipStream_t st) {
+  if (args.ksplit < 2 || args.blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(fallback_merge_kernel, dim3((unsigned)args.blocks), dim3(256), 0, st, args);
+  return hipGetLastError();
+}
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st) {
   if (mode == kModeListBatch) {

@@ -46,9 +46,23 @@ struct BF16Args {
   // grid of the launch
   const int32_t* item_pre;
   int n_img;
+  // batched list mode split over the components (ksplit >= 2): ksplit
+  // workgroups per item, part p searching components [p K / ksplit,
+  // (p + 1) K / ksplit) and writing, for patch i of image d, its label to
+  // part_out[p * part_stride + d.np + i], its best and second cost (float
+  // bits) ksplit * part_stride and 2 ksplit * part_stride further on;
+  // launch_fallback_merge then writes labels, best and second.  0 or 1: one
+  // workgroup per item, outputs written directly.
+  int ksplit;
+  int32_t* part_out;
+  size_t part_stride;
 };
 
 hipError_t launch_estep_bf16_mode(int mode, const BF16Args& args, hipStream_t st);
+// The batched list mode's merge of its ksplit parts (ksplit >= 2), in
+// component order: the labels, costs and second costs of one search over all
+// K, bit for bit.
+hipError_t launch_fallback_merge(const BF16Args& args, hipStream_t st);
 
 // Exact rescoring of the proposal's candidates over a batch at iteration t
 // (tables of all slots; one workgroup per tile of kRescPatches consecutive

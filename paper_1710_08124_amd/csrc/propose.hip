@@ -336,10 +336,16 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(ProposeArgs a
   auto top_epilogue = [&](int q, const f32x16& acc) __attribute__((always_inline)) {
     const int nt = q - 16;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int cls = 32 * nt + 8 * (i >> 2) + 4 * half + (i & 3);
-      // (classes past K: logit -inf from their bias, below every finite key)
-      top.insert(rank_key(acc[i], cls));
+    for (int g = 0; g < 4; ++g) {
+      // a group of 8 classes wholly past K is skipped (a wave-uniform
+      // branch); in a group that straddles K the classes past it have the
+      // logit -inf from their bias, below every finite key
+      if (32 * nt + 8 * g >= K) break;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int cls = 32 * nt + 8 * g + 4 * half + e;
+        top.insert(rank_key(acc[4 * g + e], cls));
+      }
     }
   };
   // layer-3 slabs in pairs: even ones in preA, odd ones in preB

@@ -6,10 +6,11 @@
 // patches that share a component, recomputes their DC-removed pixels from
 // the current image, multiplies by W_k on MFMA and writes z^ patch-major,
 // Zhat[patch][dy][dx].  The patches of a tile lie anywhere in the image, so
-// every store goes to a different patch; patch-major, each patch's 256 bytes
-// are two whole cache lines written by one wave within a few cycles, where a
-// plane-per-row layout would leave 32-byte pieces of many lines for the
-// memory to merge.
+// each patch's 256 bytes are the unit of the output.  The patches are the
+// matrix product's rows and the pixels its columns (D = Z~ W_k^t), so each
+// accumulator register of a half-wave holds 32 consecutive pixels of one
+// patch and every store instruction writes two whole 128-byte lines: no
+// line is left partly written for the memory to merge or to read back.
 //
 // The tile count depends on the labels, so the grid is fixed (a multiple of
 // 8 workgroups) and each workgroup walks its share of the device-side tile
@@ -27,6 +28,23 @@ namespace fepll {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// Accumulator register r of lane (half, col) is pixel 32 qb + col of tile
+// row i = 8 (r / 4) + 4 half + r % 4: the 32 lanes of a half write that
+// patch's 128 contiguous bytes, one whole line per half per instruction.
+// Lanes i and 32 + i hold row i's patch id and mean (id0, m0); the writing
+// lanes fetch them by lane permutes, which keeps them out of long-lived
+// registers.
+__device__ inline void store_rows(float* __restrict__ Zhat, const f32x16& a, int id0, float m0,
+                                  int n, int half, int col, int qb) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = 8 * (r >> 2) + 4 * half + (r & 3);
+    const int id = __shfl(id0, i);
+    const float m = __shfl(m0, i);
+    if (i < n) Zhat[(size_t)id * kP + 32 * qb + col] = a[r] + m;
+  }
+}
+
 __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const float* __restrict__ xb,
                                                          const float4* __restrict__ Wt_all,
                                                          int K, int it,
@@ -39,10 +57,11 @@ __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const floa
   const int col = lane & 31;
   const int total = wbase[bt.n];
   // Each workgroup takes a contiguous range of tiles (tiles are ordered by
-  // image, then component, so a range mostly shares one W_k, which then
-  // stays in the CU's L1), and consecutive ranges go to workgroups of the
-  // same XCD (workgroups are dealt round-robin over the 8 XCDs), so each
-  // XCD's L2 holds only the filters of its part of the list.
+  // image, then octile of the image's rows, then component, so a range
+  // mostly shares one W_k, which then stays in the CU's L1), and
+  // consecutive ranges go to workgroups of the same XCD (workgroups are
+  // dealt round-robin over the 8 XCDs), so each XCD's L2 holds the filters
+  // and the image rows of only its part of the list.
   // With fewer tiles than the grid has waves (a patch subset), only the
   // workgroups needed for one tile per wave take part, still dealt over all
   // 8 XCDs.  (The grid is a multiple of 8.)
@@ -100,7 +119,7 @@ __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const floa
 #pragma unroll
     for (int s = 0; s < 32; ++s) z0[s] = (float)((double)fresh(z0[s]) - m0);
     const float fm0 = (float)m0;
-    // one 32-row block of W_k at a time (rows q = 32 qb + ...)
+    // one 32-column block of W_k^t at a time (pixels q = 32 qb + col)
 #pragma unroll
     for (int qb = 0; qb < 2; ++qb) {
       const float4* wp = Wt + (size_t)k * 1024 + qb * 512 + lane;
@@ -110,26 +129,12 @@ __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const floa
       f32x16 a0 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].x, z0[4 * i + 0], a0, 0, 0, 0);
-        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].y, z0[4 * i + 1], a0, 0, 0, 0);
-        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].z, z0[4 * i + 2], a0, 0, 0, 0);
-        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(A[i].w, z0[4 * i + 3], a0, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(z0[4 * i + 0], A[i].x, a0, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(z0[4 * i + 1], A[i].y, a0, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(z0[4 * i + 2], A[i].z, a0, 0, 0, 0);
+        a0 = __builtin_amdgcn_mfma_f32_32x32x2f32(z0[4 * i + 3], A[i].w, a0, 0, 0, 0);
       }
-      // accumulator 4 g + e of lane l is pixel q = 32 qb + 8 g + 4 half + e of
-      // patch col; the two halves of the wave write the 128 contiguous bytes
-      // of pixels 32 qb .. 32 qb + 31 of each patch
-      // (streaming stores: the estimates are read once, by the reprojection,
-      // and must not push the image and the filters out of the L2)
-      if (v0) {
-        float* zp = Zhat + (size_t)id0 * kP + 32 * qb + 4 * half;
-        typedef float f32x4 __attribute__((ext_vector_type(4)));
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const f32x4 v = {a0[4 * g] + fm0, a0[4 * g + 1] + fm0, a0[4 * g + 2] + fm0,
-                           a0[4 * g + 3] + fm0};
-          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(zp + 8 * g));
-        }
-      }
+      store_rows(Zhat, a0, id0, fm0, n, half, col, qb);
     }
   }
 }
@@ -137,11 +142,11 @@ __global__ __launch_bounds__(256, 4) void wiener_f32_kernel(Batch bt, const floa
 // The reduced-precision form: the same tile walk; per tile the lane (half
 // h, column col) holds rows h, 2 + h, 4 + h, 6 + h of patch col, depth step
 // s of v_mfma_f32_32x32x16_f16 taking row 2 s + h (pixels 16 s + 8 h + e),
-// the DC-removed pixels rounded once from float32 to binary16; the A operand
-// is the binary16 table Wh (row block qb, depth step s); the accumulator
+// the DC-removed pixels rounded once from float32 to binary16; the B operand
+// is the binary16 table Wh (column block qb, depth step s); the accumulator
 // layout is the float32 form's, so are the stores.
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-__global__ __launch_bounds__(256, 4) void wiener_f16_kernel(Batch bt, const float* __restrict__ xb,
+__global__ __launch_bounds__(256, 5) void wiener_f16_kernel(Batch bt, const float* __restrict__ xb,
                                                          const uint4* __restrict__ Wh_all, int K,
                                                          int it, const int32_t* __restrict__ seg_b,
                                                          const int32_t* __restrict__ perm_b,
@@ -219,18 +224,9 @@ __global__ __launch_bounds__(256, 4) void wiener_f16_kernel(Batch bt, const floa
       f32x16 a0 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < 4; ++s)
-        a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, A[s]), zb[s], a0,
+        a0 = __builtin_amdgcn_mfma_f32_32x32x16_f16(zb[s], __builtin_bit_cast(f16x8, A[s]), a0,
                                                     0, 0, 0);
-      if (v0) {
-        float* zp = Zhat + (size_t)id0 * kP + 32 * qb + 4 * half;
-        typedef float f32x4 __attribute__((ext_vector_type(4)));
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          const f32x4 v = {a0[4 * g] + fm0, a0[4 * g + 1] + fm0, a0[4 * g + 2] + fm0,
-                           a0[4 * g + 3] + fm0};
-          __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(zp + 8 * g));
-        }
-      }
+      store_rows(Zhat, a0, id0, fm0, n, half, col, qb);
     }
   }
 }

@@ -2,8 +2,10 @@
 
 The training pairs are produced by the method itself: the plain float32
 path (exact labels: certified float32 selection with float64 re-selection)
-runs the five HQS iterations on seeded synthetic images with sigma ~ U[5, 50]
-and records, for every patch and iteration, the network input
+runs the five HQS iterations on seeded synthetic images (32 of 256 x 256,
+half of them with sigma in [4.5, 10], half in [10, 50], log-uniform: the
+network's recall is lowest at small sigma, where the posteriors are
+sharpest) and records, for every patch and iteration, the network input
 [z~/128, log sigma_beta] and the selected component.  Training runs on the
 GPU through the library's own kernels (forward, softmax cross-entropy,
 backward, AdamW); PyTorch only holds the buffers and draws the minibatch
@@ -106,8 +108,8 @@ def evaluate(gmm, images, top_m=8, margin=0.5, log=print):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_BLOB)
-    ap.add_argument("--epochs", type=int, default=24)
-    ap.add_argument("--images", type=int, default=13)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--images", type=int, default=32)
     ap.add_argument("--size", type=int, default=256)
     args = ap.parse_args(argv)
 
@@ -122,7 +124,7 @@ def main(argv=None):
 
     U, lam, w = fs.gmm(200, 12)
     g = GMM(U, lam, w)
-    imgs = fs.training_images(range(300, 300 + args.images), args.size)
+    imgs = fs.training_images(range(300, 300 + args.images), args.size, sigmas="low")
     X, y = training_pairs(g, imgs, log)
     log(f"training pairs: {X.shape[0]}")
     net = train(200, X, y, epochs=args.epochs, log=log)
