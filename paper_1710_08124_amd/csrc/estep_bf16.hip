@@ -353,21 +353,27 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       // directions)
       const uint4* gsrc = reinterpret_cast<const uint4*>(Ub);
       const int tid = threadIdx.x;
-      const int kb = (MODE == kModeListBatch) ? kb_l : 0;
-      const int ke = (MODE == kModeListBatch) ? ke_l : a.K;
+      int kb = 0, ke = a.K;
+      if constexpr (MODE == kModeListBatch) {
+        kb = kb_l;
+        ke = ke_l;
+      }
       int rn = kP, nu4 = 512;
       uint4 pre0, pre1;
-      // (kb < K whenever the range is not empty; an empty one prefetches
-      // component kb < K all the same and searches nothing)
+      // component kb's operand (kb < K whenever the range is not empty; an
+      // empty one prefetches component kb < K all the same and searches
+      // nothing)
+      const uint4* gb = gsrc;
+      if constexpr (MODE == kModeListBatch) gb += (size_t)kb * 512;
       if (FLAT) {
         rn = a.rk[kb];
         nu4 = 128 * ((rn + 15) >> 4);
         pre0 = pre1 = make_uint4(0, 0, 0, 0);
-        if (tid < nu4) pre0 = gsrc[(size_t)kb * 512 + tid];
-        if (256 + tid < nu4) pre1 = gsrc[(size_t)kb * 512 + 256 + tid];
+        if (tid < nu4) pre0 = gb[tid];
+        if (256 + tid < nu4) pre1 = gb[256 + tid];
       } else {
-        pre0 = gsrc[(size_t)kb * 512 + tid];
-        pre1 = gsrc[(size_t)kb * 512 + 256 + tid];
+        pre0 = gb[tid];
+        pre1 = gb[256 + tid];
       }
       for (int k = kb; k < ke; ++k) {
         uint4* As = Ash[k & 1];
@@ -405,12 +411,16 @@ __global__ __launch_bounds__(256, 3) void estep_bf16_kernel(BF16Args a) {
       if (!v) continue;
       const int i = p ? iB : iA;
       const float b = p ? bB : bA, s = p ? sB : sA;
-      if (MODE == kModeListBatch && pout) {
-        const size_t ps = (size_t)S * a.part_stride;
-        pout[i] = p ? kB : kA;
-        pout[ps + i] = __float_as_int(b);
-        pout[2 * ps + i] = __float_as_int(s);
-        continue;
+      if constexpr (MODE == kModeListBatch) {
+        if (pout) {
+          // by list entry: the lane group's 16 entries are contiguous
+          const int e = lbase + wave * 128 + 16 * (own + p) + col;
+          const size_t ps = (size_t)S * a.part_stride;
+          pout[e] = p ? kB : kA;
+          pout[ps + e] = __float_as_int(b);
+          pout[2 * ps + e] = __float_as_int(s);
+          continue;
+        }
       }
       labels[i] = p ? kB : kA;
       if (bestp) bestp[i] = b;
@@ -969,7 +979,7 @@ __global__ __launch_bounds__(256) void fallback_merge_kernel(BF16Args a) {
       const int e = lbase + j;
       if (e >= nl) continue;
       const int i = a.list[d.np + e];
-      const int32_t* q = a.part_out + d.np + i;
+      const int32_t* q = a.part_out + d.np + e;
       int k = q[0];
       float b = __int_as_float(q[ps]), s = __int_as_float(q[2 * ps]);
       for (int p = 1; p < S; ++p) {

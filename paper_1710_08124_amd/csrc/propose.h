@@ -48,8 +48,8 @@ struct BF16Args {
   int n_img;
   // batched list mode split over the components (ksplit >= 2): ksplit
   // workgroups per item, part p searching components [p K / ksplit,
-  // (p + 1) K / ksplit) and writing, for patch i of image d, its label to
-  // part_out[p * part_stride + d.np + i], its best and second cost (float
+  // (p + 1) K / ksplit) and writing, for list entry e of image d, its label
+  // to part_out[p * part_stride + d.np + e], its best and second cost (float
   // bits) ksplit * part_stride and 2 ksplit * part_stride further on;
   // launch_fallback_merge then writes labels, best and second.  0 or 1: one
   // workgroup per item, outputs written directly.
