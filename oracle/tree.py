@@ -15,7 +15,8 @@ smallest selection cost, and so on down to a leaf (ties to the lower
 index), the leaf being its label.  The selection cost of a node is Alg. 1's,
 in the eigenspace form of Sec. 2.1, with the node's weight, eigenvectors and
 eigenvalues.  Optionally every node's spectrum is flat-tailed (Sec. 3.1;
-the paper flat-tails all Gaussians of the tree).
+in the paper the flat tail applies to every node of the tree, inner nodes
+included).
 """
 from __future__ import annotations
 
