@@ -274,15 +274,15 @@ def main():
             return {"bound": "hbm", "kernel": kern, "achieved": round(gbs, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(kern) if args.size == 1024 else None}
+        wiener = (("wiener_f32_kernel", MFMA_F32_PEAK_TFLOPS) if name == "fp32"
+                  else ("wiener_f16_kernel", MFMA_BF16_PEAK_TFLOPS))
         kern, peak = {"select": (sel_kernel, sel_peak),
                       "propose": ("propose_bf16_kernel", MFMA_BF16_PEAK_TFLOPS),
-                      "wiener": ("wiener_f32_kernel", MFMA_F32_PEAK_TFLOPS)}.get(
-                          dom, (dom, sel_peak))
+                      "wiener": wiener}.get(dom, (dom, sel_peak))
         tf = pr["dominant_tflops"] or 0.0
         return {"bound": "mfma", "kernel": kern, "achieved": round(tf, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(tf / peak, 4),
-                "traffic": (measured_traffic(kern) if dom == "select" and args.size == 1024
-                            else None)}
+                "traffic": measured_traffic(kern) if args.size == 1024 else None}
 
     blob_path = os.path.join(os.path.dirname(F.__file__), "data", "proposal_k200_gmm12.bin")
     if K == 200 and os.path.exists(blob_path):
