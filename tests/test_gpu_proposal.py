@@ -207,6 +207,26 @@ def test_margin_inf_is_bitwise_the_full_search(F):
     np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
 
 
+def test_margin_inf_full_size_select(F):
+    """Threshold +inf at 1024^2 (K = 200): every one of the 1 034 289
+    patches falls back, so the full-K search of the fallback list runs its
+    2 036 items as 4 072 half-K parts over a grid of 1 024 workgroups (each
+    takes several parts) and the merge joins the halves.  Labels, best and
+    second costs equal the bfloat16 all-K selection's bit for bit, and
+    every patch is flagged."""
+    c = fs.config_c3(1024)
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    g.load_proposal(F.MLP(200, fs.mlp_init(200, 18)).serialize())
+    x = dev(c["y"])
+    beta = float(o.default_betas(25.0)[2])
+    la, ba, sa, _ = F.select(g, x, beta, precision="bf16")
+    lb, bb, sb, fb = F.select(g, x, beta, precision="bf16", proposal=True, margin=math.inf)
+    np.testing.assert_array_equal(la.cpu().numpy(), lb.cpu().numpy())
+    np.testing.assert_array_equal(ba.cpu().numpy(), bb.cpu().numpy())
+    np.testing.assert_array_equal(sa.cpu().numpy(), sb.cpu().numpy())
+    assert bool(fb.cpu().numpy().all())
+
+
 def test_top_m_equal_K_is_the_full_search(F):
     U, lam, w = fs.gmm(8, 19)
     y = fs.noisy(fs.test_image(48, 80, 20), 20.0, 21)
