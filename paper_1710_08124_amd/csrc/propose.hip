@@ -11,13 +11,18 @@
 // patch row per depth step, as in the selection kernels) plus the
 // log sigma_beta feature.
 //
-// A workgroup of 8 waves owns 256 patches (half of a selection tile: 4
-// patch rows x 64 columns, a wave per 32 columns of a row), of one image or
-// of any image of a planned batch, and streams the 23 weight slabs (one slab = one 32-row block of a layer, all
-// depth steps, already in MFMA operand order) through double-buffered LDS,
-// so each weight byte read from L2 serves 256 patches; each slab is fetched
-// from L2 two slabs ahead, and one barrier per slab (after its LDS store)
-// orders the buffers.
+// A workgroup of 4 waves owns 128 patches (a quarter of a selection tile:
+// 32 columns of each of its 4 patch rows, a wave per row), of one image or
+// of any image of a planned batch, and streams the 23 weight slabs (one
+// slab = one 32-row block of a layer, all depth steps, already in MFMA
+// operand order) through double-buffered LDS, each slab fetched from L2
+// into registers one slab ahead; one barrier per slab (after its LDS store)
+// orders the buffers.  The kernel is latency-bound (neither its matrix
+// cores, its vector ALUs nor its LDS saturate), so it is shaped for
+// occupancy: one accumulation chain per slab, no products of the next slab
+// held across an epilogue and one prefetched slab keep a wave within 168
+// registers (the bf16 activations of 32 patches alone take 128), three
+// workgroups per compute unit, three waves per SIMD.
 //
 // Top-m: each lane keeps the 8 largest ranking keys (logit, then lower
 // class) of its 112 classes in sorted registers (an insertion is one max and
@@ -94,10 +99,12 @@ struct Top8 {
   }
 };
 
-constexpr int kWaves = 8;
+constexpr int kWaves = 4;                // per workgroup, three workgroups per CU
 constexpr int kThreads = 64 * kWaves;
+constexpr int kWgPerTile = 16 / kWaves;  // a selection tile is 16 waves of 32 patches
 constexpr int kSlabU4 = 16 * 64;  // uint4 of the largest slab (16 depth steps x 64 lanes)
-static_assert(kSlabU4 == 2 * kThreads, "two uint4 of a slab per thread");
+constexpr int kSlabPer = kSlabU4 / kThreads;  // uint4 of a slab per thread
+static_assert(kSlabU4 % kThreads == 0, "whole uint4 of a slab per thread");
 
 // the accumulator of one 32-row block (units 32 nt + 8 (i >> 2) + 4 half +
 // (i & 3) of the lane's column) started at the bias of its units: the
@@ -164,7 +171,7 @@ __device__ __forceinline__ void hidden_epilogue(const f32x16& acc, int half, uin
 // the pair in private memory)
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 struct SlabRegs {
-  u32x4 a, b;
+  u32x4 v[kSlabPer];
 };
 __device__ __forceinline__ int slab_offset(int q) {
   if (q < 8) return q * 5 * 64;
@@ -173,19 +180,19 @@ __device__ __forceinline__ int slab_offset(int q) {
 }
 __device__ __forceinline__ void fetch_slab(const uint4* __restrict__ Wb, int q, SlabRegs& p) {
   const u32x4* w = reinterpret_cast<const u32x4*>(Wb) + slab_offset(q) + threadIdx.x;
-  p.a = w[0];
-  p.b = w[kThreads];
+#pragma unroll
+  for (int i = 0; i < kSlabPer; ++i) p.v[i] = w[i * kThreads];
 }
-// make slab q resident in the LDS buffer buf and start fetching slab q + 2
+// make slab q resident in the LDS buffer buf and start fetching slab q + 1
 // into the same registers (past the last slab, the last one again: no
 // branch, so every wait stays exact)
 __device__ __forceinline__ void stage_slab(uint4* buf, SlabRegs& p, const uint4* __restrict__ Wb,
                                            int q, int nslab) {
   u32x4* d = reinterpret_cast<u32x4*>(buf) + threadIdx.x;
-  d[0] = p.a;
-  d[kThreads] = p.b;
+#pragma unroll
+  for (int i = 0; i < kSlabPer; ++i) d[i * kThreads] = p.v[i];
   __syncthreads();
-  fetch_slab(Wb, min(q + 2, nslab - 1), p);
+  fetch_slab(Wb, min(q + 1, nslab - 1), p);
 }
 
 }  // namespace
@@ -193,7 +200,7 @@ __device__ __forceinline__ void stage_slab(uint4* buf, SlabRegs& p, const uint4*
 // Wb: all slabs back to back, uint4 in MFMA A-operand order:
 //   layer 1: 8 slabs x 5 depth steps, layer 2: 8 x 16, layer 3: n3 x 16.
 // bias: b1 (256) b2 (256) b3 (32 n3, -inf beyond K).
-__global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(ProposeArgs a) {
+__global__ __launch_bounds__(kThreads, 3) void propose_bf16_kernel(ProposeArgs a) {
   __shared__ uint4 slab[2][kSlabU4];  // 32 KB
   __shared__ __align__(16) float bsh[2 * kHidden + 32 * 32];  // b1, b2, b3 (n3 <= 32 blocks of 32)
   const int lane = threadIdx.x & 63;
@@ -204,7 +211,7 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(ProposeArgs a
   const int K = a.K, m = a.m;
   const uint4* __restrict__ Wb = reinterpret_cast<const uint4*>(a.Wb);
   // this workgroup's half selection tile
-  const int item = blockIdx.x >> 1;
+  const int item = blockIdx.x / kWgPerTile;
   const float* x = a.x;
   int H = a.H, W = a.W;
   float logsb = a.logsb;
@@ -228,8 +235,10 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(ProposeArgs a
     tc = item - tr * ntx;
   }
   const int Hp = H - 7, Wp = W - 7;
-  const int r = 4 * tr + (wave & 3);
-  const int c = kEstCols * tc + 64 * (blockIdx.x & 1) + 32 * (wave >> 2) + col;
+  // wave gw of the tile's 16: patch row gw % 4, columns 32 (gw / 4) + 0..31
+  const int gw = (blockIdx.x % kWgPerTile) * kWaves + wave;
+  const int r = 4 * tr + (gw & 3);
+  const int c = kEstCols * tc + 32 * (gw >> 2) + col;
   const int rr = min(r, Hp - 1), cc = min(c, Wp - 1);
 
   for (int i = threadIdx.x; i < 2 * kHidden + 32 * n3; i += blockDim.x) bsh[i] = a.bias[i];
@@ -268,66 +277,45 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(ProposeArgs a
     xb[4] = make_uint4(half ? 0u : bf16_rne(logsb), 0u, 0u, 0u);
   }
 
-  // slabs q + 1 and q + 2 in flight in registers (preA holds the even
-  // slabs, preB the odd ones; each call below names its pair at compile
-  // time, so both stay in registers)
+  // the next slab in flight in registers
   const int nslab = 16 + n3;
-  SlabRegs preA, preB;
-  fetch_slab(Wb, 0, preA);
-  fetch_slab(Wb, 1, preB);
+  SlabRegs pre;
+  fetch_slab(Wb, 0, pre);
   uint4 h1[16], h2[16];
-  // Each slab's matrix products are issued before the epilogue of the slab
-  // before (the activations or the top-m of its block), so the matrix cores
-  // and the vector ALUs work at once within a wave; only the layers wait
-  // for each other.  (The buffer a slab is staged into last held the slab
-  // two before, whose operands every wave read before the barrier of the
-  // slab in between.)
+  // Per slab: stage it, its matrix products, its epilogue (the activations
+  // or the top-m of its block); the other waves of the SIMD fill the gaps.
+  // (The buffer a slab is staged into last held the slab two before, whose
+  // operands every wave read before the barrier of the slab in between.)
   auto mm1 = [&](int q) __attribute__((always_inline)) {
-    if (q & 1)
-      stage_slab(slab[1], preB, Wb, q, nslab);
-    else
-      stage_slab(slab[0], preA, Wb, q, nslab);
+    stage_slab(slab[q & 1], pre, Wb, q, nslab);
     const uint4* A = slab[q & 1] + lane;
     f32x16 acc = bias_init(bsh, q, half);
 #pragma unroll
     for (int s = 0; s < 5; ++s) acc = mfma_bf16(A[s * 64], xb[s], acc);
     return acc;
   };
-  // layers 2 and 3: two independent accumulation chains (even / odd depth
-  // steps), the first started at the bias
-  auto mm23 = [&](int q, const float* bias, int nt, const uint4* hin, SlabRegs& pre)
+  // layers 2 and 3: one accumulation chain started at the bias
+  auto mm23 = [&](int q, const float* bias, int nt, const uint4* hin)
       __attribute__((always_inline)) {
     stage_slab(slab[q & 1], pre, Wb, q, nslab);
     const uint4* A = slab[q & 1] + lane;
     f32x16 acc = bias_init(bias, nt, half);
-    f32x16 acc2 = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < 16; s += 2) {
-      acc = mfma_bf16(A[s * 64], hin[s], acc);
-      acc2 = mfma_bf16(A[(s + 1) * 64], hin[s + 1], acc2);
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] += acc2[i];
+    for (int s = 0; s < 16; ++s) acc = mfma_bf16(A[s * 64], hin[s], acc);
     return acc;
   };
   {
-    f32x16 acc = mm1(0);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      f32x16 nxt;
-      if (q + 1 < 8) nxt = mm1(q + 1);
+      f32x16 acc = mm1(q);
       hidden_epilogue(acc, half, h1[2 * q], h1[2 * q + 1]);
-      acc = nxt;
     }
   }
   {
-    f32x16 acc = mm23(8, bsh + kHidden, 0, h1, preA);
 #pragma unroll
     for (int q = 8; q < 16; ++q) {
-      f32x16 nxt;
-      if (q + 1 < 16) nxt = mm23(q + 1, bsh + kHidden, q + 1 - 8, h1, (q & 1) ? preA : preB);
+      f32x16 acc = mm23(q, bsh + kHidden, q - 8, h1);
       hidden_epilogue(acc, half, h2[2 * (q - 8)], h2[2 * (q - 8) + 1]);
-      acc = nxt;
     }
   }
   Top8 top;
@@ -348,16 +336,14 @@ __global__ __launch_bounds__(kThreads, 1) void propose_bf16_kernel(ProposeArgs a
       }
     }
   };
-  // layer-3 slabs in pairs: even ones in preA, odd ones in preB
+  // layer 3, two slabs per pass
   {
-    f32x16 acc = mm23(16, b3, 0, h2, preA);
     for (int q = 16; q < nslab; q += 2) {
-      f32x16 nxt;
-      if (q + 1 < nslab) nxt = mm23(q + 1, b3, q + 1 - 16, h2, preB);
+      f32x16 acc = mm23(q, b3, q - 16, h2);
       top_epilogue(q, acc);
       if (q + 1 < nslab) {
-        if (q + 2 < nslab) acc = mm23(q + 2, b3, q + 2 - 16, h2, preA);
-        top_epilogue(q + 1, nxt);
+        acc = mm23(q + 1, b3, q + 1 - 16, h2);
+        top_epilogue(q + 1, acc);
       }
     }
   }
@@ -385,7 +371,8 @@ hipError_t launch_propose(const ProposeArgs& a, hipStream_t st) {
   int n_est = a.n_est;
   if (!a.d) n_est = ((a.W - 7 + kEstCols - 1) / kEstCols) * ((a.H - 7 + 3) / 4);
   if (n_est < 1) return hipSuccess;
-  hipLaunchKernelGGL(propose_bf16_kernel, dim3((unsigned)(2 * n_est)), dim3(kThreads), 0, st, a);
+  hipLaunchKernelGGL(propose_bf16_kernel, dim3((unsigned)(kWgPerTile * n_est)), dim3(kThreads), 0,
+                     st, a);
   return hipGetLastError();
 }
 
