@@ -270,7 +270,8 @@ def main():
             # algorithmic bytes: the chosen patches' estimates, y and x
             npat = n_sub.get(name, Np)
             gbs = (256.0 * npat + 8.0 * H * W) / (pr["dominant_ms"] / 1e3) / 1e9
-            kern = ("ola_subset_kernel<16>" if "jitter" in name else "ola_update_kernel<32>")
+            kern = ("ola_subset_kernel<16>" if "jitter" in name
+                    else "ola_update_kernel<%d>" % F.get_tuning(g)["ola_rows"])
             return {"bound": "hbm", "kernel": kern, "achieved": round(gbs, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                     "traffic": measured_traffic(kern) if args.size == 1024 else None}

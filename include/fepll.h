@@ -264,7 +264,7 @@ typedef struct {
                             0 = one per tile (default 768: 3 per CU)       */
   int32_t wiener_blocks; /* cap on the patch-estimation workgroups, a
                             multiple of 8 (default 4096)                   */
-  int32_t ola_rows;      /* rows of a reprojection tile: 16, 32 (default)
+  int32_t ola_rows;      /* rows of a reprojection tile: 16 (default), 32
                             or 64                                          */
   int32_t reserved;      /* 0                                              */
 } fepll_tuning;

@@ -386,7 +386,7 @@ def restore_batch(gmm: GMM, ys, sigmas, precision="bf16", recheck=True, outs=Non
     return outs
 
 
-def set_tuning(gmm: GMM, est_blocks=768, wiener_blocks=4096, ola_rows=32):
+def set_tuning(gmm: GMM, est_blocks=768, wiener_blocks=4096, ola_rows=16):
     t = Tuning(int(est_blocks), int(wiener_blocks), int(ola_rows), 0)
     _check(lib().fepll_set_tuning(gmm.handle, ctypes.byref(t)))
 
