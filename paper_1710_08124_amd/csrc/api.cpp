@@ -1018,13 +1018,12 @@ fepll_status select_proposal(fepll_gmm* g, int t, const fepll_options& o, const 
     p.K = g->K;
     p.m = o.top_m;
     p.cand = g->cand;
+    p.zero = g->fbcnt;  // the fallback counts the rescoring appends to
+    p.n_zero = b.n;
     HIPX(launch_propose(p, st));
   }
   {
     StageTimer tm(g, 0, st);
-    hipLaunchKernelGGL(zero_i32_kernel, dim3((b.n + 255) / 256), dim3(256), 0, st, g->fbcnt,
-                       b.n);
-    HIPX(hipGetLastError());
     RescoreArgs r{};
     r.d = b.d;
     r.tile_img = b.resc_img;

@@ -134,7 +134,8 @@ __global__ __launch_bounds__(256) void seg_comp_kernel(Batch b, int32_t* __restr
 template <bool BATCH>
 __global__ __launch_bounds__(1024) void seg_total_kernel(Batch b, int32_t* __restrict__ hist_a,
                                                          int32_t* __restrict__ seg_a, int nb_a,
-                                                         int K, int tile) {
+                                                         int K, int tile,
+                                                         int32_t* __restrict__ wbase1) {
   __shared__ int32_t part[1024];
   const SegProblem p = seg_problem<BATCH>(b, hist_a, seg_a, nb_a, K);
   int32_t* start = p.seg;
@@ -167,6 +168,11 @@ __global__ __launch_bounds__(1024) void seg_total_kernel(Batch b, int32_t* __res
   if (t == 1023) {
     tpre[K] = part[1023];
     p.seg[3 * K + 2] = part[1023];
+    // a batch of one image: its tile base too (0, then the total)
+    if (wbase1) {
+      wbase1[0] = 0;
+      wbase1[1] = part[1023];
+    }
   }
 }
 
@@ -248,15 +254,17 @@ __global__ __launch_bounds__(256) void seg_info_kernel(Batch b, int32_t* __restr
 
 // A, B and C for `nprob` problems (BATCH: the images of b); max_tiles bounds
 // the tile count of every problem
+// (wbase1: a batch of one image's tile bases, written with the totals, or NULL)
 template <bool BATCH>
 hipError_t launch_seg_tables(const Batch& b, int32_t* hist, int32_t* seg, int nb, int K,
-                             int tile, int nprob, int64_t max_tiles, hipStream_t st) {
+                             int tile, int nprob, int64_t max_tiles, hipStream_t st,
+                             int32_t* wbase1 = nullptr) {
   hipLaunchKernelGGL(seg_comp_kernel<BATCH>, dim3(K, nprob), dim3(256), 0, st, b, hist, seg, nb,
                      K);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(seg_total_kernel<BATCH>, dim3(1, nprob), dim3(1024), 0, st, b, hist, seg, nb,
-                     K, tile);
+                     K, tile, wbase1);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t gx = (max_tiles + 255) / 256;
@@ -512,13 +520,13 @@ hipError_t launch_bucket_batch(const Batch& b, const int32_t* labels, int K, int
     e = hipGetLastError();
   } else {
     e = launch_seg_tables<true>(b, hist, seg, 0, K, kWienerTile, b.n,
-                                b.max_np / kWienerTile + K, st);
+                                b.max_np / kWienerTile + K, st, b.n == 1 ? wbase : nullptr);
   }
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(scatter_kernel, dim3(b.n_sort), dim3(1024), K * sizeof(int32_t), st, b,
                      labels, K, hist, seg, perm);
   e = hipGetLastError();
-  if (e != hipSuccess || (small && b.n == 1)) return e;
+  if (e != hipSuccess || b.n == 1) return e;  // (one image: the tables wrote its bases)
   hipLaunchKernelGGL(wbase_kernel, dim3(1), dim3(1024), 0, st, b, K, seg, wbase);
   return hipGetLastError();
 }

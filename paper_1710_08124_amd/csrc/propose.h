@@ -159,6 +159,10 @@ struct ProposeArgs {
   const float* bias;
   int K, m;
   uint16_t* cand;
+  // n_zero int32 set to 0 by the launch before any later kernel runs (the
+  // rescoring's per-image fallback counts), or NULL
+  int32_t* zero;
+  int n_zero;
 };
 hipError_t launch_propose(const ProposeArgs& a, hipStream_t st);
 

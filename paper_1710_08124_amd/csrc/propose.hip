@@ -241,6 +241,8 @@ __global__ __launch_bounds__(kThreads, 3) void propose_bf16_kernel(ProposeArgs a
   const int c = kEstCols * tc + 32 * (gw >> 2) + col;
   const int rr = min(r, Hp - 1), cc = min(c, Wp - 1);
 
+  if (a.zero && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < a.n_zero; i += blockDim.x) a.zero[i] = 0;
   for (int i = threadIdx.x; i < 2 * kHidden + 32 * n3; i += blockDim.x) bsh[i] = a.bias[i];
   // (made visible by the first slab's barrier)
 
