@@ -154,6 +154,47 @@ def test_lowp_estimate_matches_definition(F, mode, sigma, t, shape):
 
 
 @pytest.mark.parametrize("mode", ["bf16", "fp8"])
+def test_full_size_iteration_sampled_pixels(F, mode):
+    """One full-set iteration of a reduced-precision mode at 1024^2 (K = 200,
+    sigma 25, the second beta, from the noisy image): the tile list of the
+    patch estimation is the octile-major one (about 33 000 tiles), the
+    reprojection the default 16-row tiles.  At 150 sampled pixels the image
+    equals Alg. 1's update of the average of the covering patches' binary16
+    estimates (oracle/lowp.py) under the GPU's labels, within their
+    accumulation bound plus 1e-4."""
+    c = fs.config_c3()
+    y32 = np.asarray(c["y"], np.float32)
+    H, W = y32.shape
+    beta = float(o.default_betas(25.0)[1])
+    g = F.GMM(c["U"], c["lam"], c["w"])
+    got, lab = F.restore(g, dev(y32), 25.0, betas=[beta], precision=mode, return_labels=True)
+    got = got.cpu().numpy().astype(np.float64)
+    lab = lab.cpu().numpy()[0]
+    Wp = W - 7
+    R = fs.rng(44)
+    py, px = R.integers(0, H, 150), R.integers(0, W, 150)
+    cover = []
+    for yy, xx in zip(py, px):
+        rr, cc = np.meshgrid(np.arange(max(yy - 7, 0), min(yy, H - 8) + 1),
+                             np.arange(max(xx - 7, 0), min(xx, W - 8) + 1), indexing="ij")
+        cover.append((rr.ravel(), cc.ravel()))
+    need = np.unique(np.concatenate([r * Wp + cc for r, cc in cover]))
+    est, bnd = lowp.lowp_estimates(y32, c["U"], c["lam"], c["w"], beta, lab[need],
+                                   acc_eps=64 * 2.0 ** -24, patches=need)
+    row = {int(p): i for i, p in enumerate(need)}
+    b = beta * 25.0 ** 2
+    worst = 0.0
+    for (yy, xx), (rr, cc) in zip(zip(py, px), cover):
+        i = np.array([row[int(p)] for p in rr * Wp + cc])
+        off = 8 * (yy - rr) + (xx - cc)
+        want = o.image_update(float(y32[yy, xx]), np.mean(est[i, off]), beta, 25.0)
+        tol = 1e-4 + b / (1.0 + b) * np.mean(bnd[i, off])
+        worst = max(worst, abs(got[yy, xx] - want) / tol)
+    print(f"1024^2 {mode} full-set iteration: worst sampled pixel error / tolerance {worst:.3f}")
+    assert worst <= 1.0
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp8"])
 @pytest.mark.parametrize("rho", [None, 0.95])
 def test_full_size_select_sampled(F, mode, rho):
     """The benchmarked configuration: the all-K selection of the 1024^2,
