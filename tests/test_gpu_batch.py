@@ -220,9 +220,15 @@ def test_batch_with_proposal_equals_single(F, gm, small_batch):
 
 
 def test_large_uneven_batch_sampled(F, gm):
-    """Image sizes of the 48-image workload (256^2 up to 1024 x 1536): the
-    batch against single-image restorations of the same images."""
+    """Image sizes of the 48-image workload (256^2 up to 1024 x 1536, so the
+    octile-major tile tables of several images in one launch): the batch
+    against single-image restorations of the same images, bit for bit, in
+    every precision and with the learned proposal (its fallback search
+    split over halves of K across images)."""
+    import os
     g = F.GMM(*gm)
+    g.load_proposal(open(os.path.join(os.path.dirname(F.__file__), "data",
+                                      "proposal_k200_gmm12.bin"), "rb").read())
     shapes = [(256, 256), (1024, 1536), (517, 901), (300, 1200)]
     sig = [7.5, 42.0, 25.0, 13.0]
     b = []
@@ -230,9 +236,10 @@ def test_large_uneven_batch_sampled(F, gm):
         x = fs.test_image(H, W, 700 + i)
         b.append(dict(y=fs.noisy(x, sig[i], 800 + i), sigma=sig[i]))
     ys = [dev(d["y"]) for d in b]
-    for mode in ("bf16", "fp8"):
-        got = F.restore_batch(g, ys, sig, precision=mode)
-        want = single(F, g, b, precision=mode)
+    for kw in (dict(precision="bf16"), dict(precision="fp8"), dict(precision="fp32"),
+               dict(precision="bf16", proposal=True, top_m=8, margin=0.5)):
+        got = F.restore_batch(g, ys, sig, **kw)
+        want = single(F, g, b, **kw)
         for a, w in zip(got, want):
             np.testing.assert_array_equal(a.cpu().numpy(), w)
 
